@@ -1,0 +1,808 @@
+/*
+ * perrk_oracle.c -- plain FP64 CPU oracle for one P-ERRK step on a periodic
+ * Cartesian DGSEM (degree 3) discretisation of the compressible Euler
+ * equations.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  The product path
+ * (the HIP library behind include/perrk.h) shares no code with it.
+ *
+ * Everything is written as slow, obvious loops in double precision, in the
+ * order of the paper:
+ *   - Sec. 2.1: semidiscretisation U' = F(U) by DGSEM on LGL nodes;
+ *     entropy-conservative flux differencing in the volume, entropy-conservative
+ *     or entropy-stable surface fluxes (the paper cites these; their formulas are
+ *     restated here from the published mathematics: Ranocha's EC/KEP flux, the
+ *     HLL two-wave solver with Davis speeds).
+ *   - Sec. 2.2: partitioned RK in Butcher form (PartitionedRKSystem), the
+ *     archetype tableaux of Appendix A, the active-stage rule and the cheap
+ *     update of inactive partitions.
+ *   - Sec. 2.3: entropy s(u) = -rho log(p / rho^gamma) (EntropyMathematical).
+ *   - Sec. 2.4 / 3: relaxed update U_{n+1} = U_n + gamma dt d, entropy change
+ *     Delta H from the stage entropy production (EntropyChangeDefinition,
+ *     its rearranged node-wise form), relaxation residual r(gamma) and its
+ *     derivative (RelaxationEquation), Newton with unit step, bisection.
+ *
+ * Layout at the interface: structure of arrays U[v][elem][node], node fastest,
+ * node = i + 4 j + 16 k (x index fastest), elem = ix + nx (iy + ny iz).
+ * Conserved variables per node: rho, rho v_1..rho v_dim, rho e.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_N 4            /* LGL nodes per direction */
+#define OR_MAXS 64        /* maximum number of stages */
+#define OR_MAXR 32        /* maximum number of levels */
+
+enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2, OR_ENONPHYS = -4, OR_ENONFINITE = -5 };
+enum { OR_FLAG_BISECT = 1, OR_FLAG_FALLBACK = 2, OR_FLAG_TRIVIAL = 4 };
+
+typedef struct {
+    int dim;              /* 2 or 3 */
+    int n[3];             /* elements per direction; n[2] = 1 in 2D */
+    const double *faces;  /* face coordinates, direction 0 then 1 (then 2): n[d]+1 each */
+    double gam;           /* ratio of specific heats */
+    int surface_flux;     /* 0: Ranocha EC flux, 1: HLL with Davis wave speeds */
+} or_mesh;
+
+typedef struct {
+    int order;            /* 2, 3 or 4 (informational) */
+    int S;                /* number of stages */
+    int R;                /* number of levels */
+    const int *E;         /* [R] stage evaluations of each level */
+    const double *c;      /* [S] abscissae, shared by all levels */
+    const double *b;      /* [S] weights, shared by all levels (Conservation) */
+    const double *a_sub;  /* [R][S] a^{(r)}_{i,i-1}; a^{(r)}_{i,1} = c_i - a^{(r)}_{i,i-1} */
+} or_tableau;
+
+typedef struct {
+    int relax;            /* 0: plain P-ERK step, gamma = 1 */
+    int max_newton;
+    double tol_r;         /* accept gamma only when |r(gamma)| <= tol_r */
+    double tol_step;      /* a Newton step below this ends the Newton loop */
+    int anchor;           /* 0: H(U_{n+1}) = H(U_n) + gamma dH ; 1: ... = H0 + gamma dH */
+    double H0;
+    double bis_lo, bis_hi;
+    int max_bisect;
+    double gamma0;        /* initial guess of the Newton iteration */
+} or_relax;
+
+typedef struct {
+    double gamma, r, dH, H_old, H_new;
+    int passes, newton_iters, flags, pad;
+    double e[OR_MAXS];    /* stage entropy production <W(U_{n,i}), K_i> for b_i != 0 */
+} or_info;
+
+/* ------------------------------------------------------------------------ */
+/* LGL nodes, weights, derivative matrix, split-form matrix (degree 3)       */
+/* ------------------------------------------------------------------------ */
+
+/* Nodes: roots of (1 - x^2) P_3'(x); weights 2/(N(N+1) P_3(x)^2), N = 3.
+ * D_ij = l_j'(xi_i) from the barycentric form of the Lagrange basis.
+ * Dsplit = 2 D - W^{-1} B, B = diag(-1, 0, 0, 1): the flux-differencing form
+ * of the DGSEM volume term (its diagonal vanishes). */
+void or_lgl(double *xi, double *q, double *D, double *Dsplit)
+{
+    const double s = 1.0 / sqrt(5.0);
+    double x[OR_N] = { -1.0, -s, s, 1.0 };
+    double w[OR_N] = { 1.0 / 6.0, 5.0 / 6.0, 5.0 / 6.0, 1.0 / 6.0 };
+    double lam[OR_N];
+    for (int j = 0; j < OR_N; ++j) {
+        double p = 1.0;
+        for (int k = 0; k < OR_N; ++k)
+            if (k != j) p *= (x[j] - x[k]);
+        lam[j] = 1.0 / p;
+    }
+    for (int i = 0; i < OR_N; ++i) {
+        double diag = 0.0;
+        for (int j = 0; j < OR_N; ++j) {
+            if (j == i) continue;
+            double dij = (lam[j] / lam[i]) / (x[i] - x[j]);
+            D[i * OR_N + j] = dij;
+            diag -= dij;
+        }
+        D[i * OR_N + i] = diag;
+    }
+    for (int i = 0; i < OR_N; ++i) {
+        xi[i] = x[i];
+        q[i] = w[i];
+        for (int j = 0; j < OR_N; ++j) {
+            double bij = 0.0;
+            if (i == j && i == 0) bij = -1.0;
+            if (i == j && i == OR_N - 1) bij = 1.0;
+            Dsplit[i * OR_N + j] = 2.0 * D[i * OR_N + j] - bij / w[i];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Thermodynamics                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Logarithmic mean (a - b) / (log a - log b).  With z = (a-b)/(a+b),
+ * log(a/b) = 2 (z + z^3/3 + z^5/5 + z^7/7 + ...), hence for small z the mean
+ * equals (a+b) / (2 + 2z^2/3 + 2z^4/5 + 2z^6/7 + ...), truncated after z^6
+ * (omitted term < z^8 / 9 < 1.2e-17 relative for z^2 < 1e-4).  Otherwise the
+ * logarithm of the ratio is taken as log1p((a-b)/b), which avoids the
+ * cancellation of log a - log b for nearby arguments. */
+double or_logmean(double a, double b)
+{
+    double z = (a - b) / (a + b);
+    double z2 = z * z;
+    if (z2 < 1.0e-4)
+        return (a + b) / (2.0 + z2 * (2.0 / 3.0 + z2 * (2.0 / 5.0 + z2 * (2.0 / 7.0))));
+    return (a - b) / log1p((a - b) / b);
+}
+
+/* Primitive variables of a node state; returns 0, ENONPHYS or ENONFINITE. */
+static int or_prim(int dim, const double *u, double gam, double *rho, double *v, double *p)
+{
+    for (int k = 0; k < dim + 2; ++k)
+        if (!isfinite(u[k])) return OR_ENONFINITE;
+    *rho = u[0];
+    if (!(*rho > 0.0)) return OR_ENONPHYS;
+    double kin = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        v[d] = u[1 + d] / u[0];
+        kin += 0.5 * u[1 + d] * v[d];
+    }
+    *p = (gam - 1.0) * (u[dim + 1] - kin);
+    if (!(*p > 0.0)) return OR_ENONPHYS;
+    return OR_OK;
+}
+
+/* Physical Euler flux in direction dir. */
+void or_flux_phys(int dim, int dir, const double *u, double gam, double *f)
+{
+    double rho, v[3], p;
+    or_prim(dim, u, gam, &rho, v, &p);
+    double vn = v[dir];
+    f[0] = u[0] * vn;
+    for (int d = 0; d < dim; ++d) f[1 + d] = u[1 + d] * vn + (d == dir ? p : 0.0);
+    f[dim + 1] = (u[dim + 1] + p) * vn;
+}
+
+/* Ranocha's entropy-conservative, kinetic-energy-preserving two-point flux
+ * (the EC volume and surface flux of Sec. 4.1).  With arithmetic means {.}
+ * and logarithmic means {.}_log:
+ *   f_rho = {rho}_log {v_n}
+ *   f_m   = f_rho {v} + {p} n
+ *   f_E   = f_rho ( v_L . v_R / 2 + 1 / ((gamma-1) {rho/p}_log) )
+ *           + (p_L v_n,R + p_R v_n,L) / 2                                   */
+void or_flux_ec(int dim, int dir, const double *uL, const double *uR, double gam, double *f)
+{
+    double rl, rr, vl[3], vr[3], pl, pr;
+    or_prim(dim, uL, gam, &rl, vl, &pl);
+    or_prim(dim, uR, gam, &rr, vr, &pr);
+    double rho_log = or_logmean(rl, rr);
+    double beta_log = or_logmean(rl / pl, rr / pr);
+    double vn_avg = 0.5 * (vl[dir] + vr[dir]);
+    double p_avg = 0.5 * (pl + pr);
+    double vv = 0.0;
+    for (int d = 0; d < dim; ++d) vv += vl[d] * vr[d];
+    double frho = rho_log * vn_avg;
+    f[0] = frho;
+    for (int d = 0; d < dim; ++d) f[1 + d] = frho * 0.5 * (vl[d] + vr[d]) + (d == dir ? p_avg : 0.0);
+    f[dim + 1] = frho * (0.5 * vv + 1.0 / ((gam - 1.0) * beta_log)) + 0.5 * (pl * vr[dir] + pr * vl[dir]);
+}
+
+/* HLL two-wave flux with Davis wave-speed estimates
+ *   lmin = min(vn_L - c_L, vn_R - c_R),  lmax = max(vn_L + c_L, vn_R + c_R). */
+void or_flux_hll(int dim, int dir, const double *uL, const double *uR, double gam, double *f)
+{
+    double rl, rr, vl[3], vr[3], pl, pr;
+    or_prim(dim, uL, gam, &rl, vl, &pl);
+    or_prim(dim, uR, gam, &rr, vr, &pr);
+    double cl = sqrt(gam * pl / rl), cr = sqrt(gam * pr / rr);
+    double lmin = fmin(vl[dir] - cl, vr[dir] - cr);
+    double lmax = fmax(vl[dir] + cl, vr[dir] + cr);
+    double fl[5], fr[5];
+    or_flux_phys(dim, dir, uL, gam, fl);
+    or_flux_phys(dim, dir, uR, gam, fr);
+    int V = dim + 2;
+    if (lmin >= 0.0) {
+        for (int k = 0; k < V; ++k) f[k] = fl[k];
+    } else if (lmax <= 0.0) {
+        for (int k = 0; k < V; ++k) f[k] = fr[k];
+    } else {
+        for (int k = 0; k < V; ++k)
+            f[k] = (lmax * fl[k] - lmin * fr[k] + lmin * lmax * (uR[k] - uL[k])) / (lmax - lmin);
+    }
+}
+
+/* Mathematical entropy s(u) = -rho log(p / rho^gamma) (Sec. 2.3). */
+double or_entropy(int dim, const double *u, double gam)
+{
+    double rho, v[3], p;
+    or_prim(dim, u, gam, &rho, v, &p);
+    return -rho * (log(p) - gam * log(rho));
+}
+
+/* Entropy variables w = ds/du for the entropy above:
+ *   w_rho = gamma - log(p rho^-gamma) - (gamma-1) rho |v|^2 / (2p)
+ *   w_m   = (gamma-1) rho v / p
+ *   w_E   = -(gamma-1) rho / p                                               */
+void or_entropy_vars(int dim, const double *u, double gam, double *w)
+{
+    double rho, v[3], p;
+    or_prim(dim, u, gam, &rho, v, &p);
+    double v2 = 0.0;
+    for (int d = 0; d < dim; ++d) v2 += v[d] * v[d];
+    double rp = rho / p;
+    w[0] = gam - (log(p) - gam * log(rho)) - 0.5 * (gam - 1.0) * rp * v2;
+    for (int d = 0; d < dim; ++d) w[1 + d] = (gam - 1.0) * rp * v[d];
+    w[dim + 1] = -(gam - 1.0) * rp;
+}
+
+/* s(u + du) - s(u) without cancellation.  With rho' = rho + drho and
+ *   dp = (gamma-1) [ dE - (m.dm + |dm|^2/2) / rho' + drho |m|^2 / (2 rho rho') ]
+ * (exactly p(u+du) - p(u)), one has
+ *   s(u+du) - s(u) = -drho (log p' - gamma log rho')
+ *                    - rho [ log1p(dp/p) - gamma log1p(drho/rho) ].          */
+double or_entropy_diff(int dim, const double *u, const double *du, double gam)
+{
+    double rho, v[3], p;
+    or_prim(dim, u, gam, &rho, v, &p);
+    double drho = du[0];
+    double rho1 = rho + drho;
+    double mdm = 0.0, dm2 = 0.0, m2 = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        mdm += u[1 + d] * du[1 + d];
+        dm2 += du[1 + d] * du[1 + d];
+        m2 += u[1 + d] * u[1 + d];
+    }
+    double dp = (gam - 1.0) * (du[dim + 1] - (mdm + 0.5 * dm2) / rho1 + drho * m2 / (2.0 * rho * rho1));
+    double p1 = p + dp;
+    return -drho * (log(p1) - gam * log(rho1)) - rho * (log1p(dp / p) - gam * log1p(drho / rho));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh helpers                                                              */
+/* ------------------------------------------------------------------------ */
+
+static int or_npe(int dim) { return dim == 2 ? 16 : 64; }
+static int or_nelem(const or_mesh *m) { return m->n[0] * m->n[1] * (m->dim == 3 ? m->n[2] : 1); }
+
+static const double *or_faces(const or_mesh *m, int d)
+{
+    const double *f = m->faces;
+    for (int k = 0; k < d; ++k) f += m->n[k] + 1;
+    return f;
+}
+
+static void or_elem_ijk(const or_mesh *m, int e, int *ix)
+{
+    ix[0] = e % m->n[0];
+    ix[1] = (e / m->n[0]) % m->n[1];
+    ix[2] = (m->dim == 3) ? e / (m->n[0] * m->n[1]) : 0;
+}
+
+static int or_elem_index(const or_mesh *m, const int *ix)
+{
+    return ix[0] + m->n[0] * (ix[1] + m->n[1] * ix[2]);
+}
+
+static double or_width(const or_mesh *m, int e, int d)
+{
+    int ix[3];
+    or_elem_ijk(m, e, ix);
+    const double *f = or_faces(m, d);
+    return f[ix[d] + 1] - f[ix[d]];
+}
+
+/* Jacobian of the reference-to-physical map of a Cartesian element. */
+static double or_jac(const or_mesh *m, int e)
+{
+    double J = 1.0;
+    for (int d = 0; d < m->dim; ++d) J *= 0.5 * or_width(m, e, d);
+    return J;
+}
+
+static void or_node_ijk(int l, int *il)
+{
+    il[0] = l % 4;
+    il[1] = (l / 4) % 4;
+    il[2] = l / 16;
+}
+
+static int or_node_index(const int *il) { return il[0] + 4 * (il[1] + 4 * il[2]); }
+
+static void or_get(const or_mesh *m, const double *U, int e, int l, double *u)
+{
+    int ne = or_nelem(m), npe = or_npe(m->dim);
+    for (int v = 0; v < m->dim + 2; ++v) u[v] = U[((size_t)v * ne + e) * npe + l];
+}
+
+static void or_put(const or_mesh *m, double *U, int e, int l, const double *u)
+{
+    int ne = or_nelem(m), npe = or_npe(m->dim);
+    for (int v = 0; v < m->dim + 2; ++v) U[((size_t)v * ne + e) * npe + l] = u[v];
+}
+
+/* Quadrature weight of node l (tensor product of the 1D LGL weights). */
+static double or_qnode(int dim, int l)
+{
+    double xi[4], q[4], D[16], Ds[16];
+    or_lgl(xi, q, D, Ds);
+    int il[3];
+    or_node_ijk(l, il);
+    double w = q[il[0]] * q[il[1]];
+    if (dim == 3) w *= q[il[2]];
+    return w;
+}
+
+/* Validate every node state of U. */
+int or_check_state(const or_mesh *m, const double *U)
+{
+    int ne = or_nelem(m), npe = or_npe(m->dim);
+    for (int e = 0; e < ne; ++e)
+        for (int l = 0; l < npe; ++l) {
+            double u[5], rho, v[3], p;
+            or_get(m, U, e, l, u);
+            int st = or_prim(m->dim, u, m->gam, &rho, v, &p);
+            if (st) return st;
+        }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Semidiscretisation F(U) on a set of elements                             */
+/* ------------------------------------------------------------------------ */
+
+/* For every node of every element with active[e] != 0:
+ *   dU/dt = - sum_d (2/h_d) [ sum_{m != i_d} Dsplit[i_d][m] f#_d(u, u_m)
+ *                             + (1/q_{i_d}) (delta_{i_d,3} f*_d(u, u+)
+ *                                            - delta_{i_d,0} f*_d(u-, u)) ]
+ * where u_m runs along the line of direction d through the node, u+ / u- are
+ * the traces of the periodic neighbour across the right / left face, f# is
+ * the EC volume flux and f* the selected surface flux.  active == NULL means
+ * all elements.  Inactive elements' K entries are left untouched. */
+int or_rhs(const or_mesh *m, const double *U, const unsigned char *active, double *K)
+{
+    double xi[4], q[4], D[16], Ds[16];
+    or_lgl(xi, q, D, Ds);
+    int dim = m->dim, V = dim + 2, npe = or_npe(dim), ne = or_nelem(m);
+    int st = or_check_state(m, U);
+    if (st) return st;
+    for (int e = 0; e < ne; ++e) {
+        if (active && !active[e]) continue;
+        int ix[3];
+        or_elem_ijk(m, e, ix);
+        for (int l = 0; l < npe; ++l) {
+            int il[3];
+            or_node_ijk(l, il);
+            double u[5], du[5] = { 0, 0, 0, 0, 0 };
+            or_get(m, U, e, l, u);
+            for (int d = 0; d < dim; ++d) {
+                double scale = 2.0 / or_width(m, e, d);
+                double acc[5] = { 0, 0, 0, 0, 0 };
+                /* volume: flux differencing along the line */
+                for (int mm = 0; mm < 4; ++mm) {
+                    if (mm == il[d]) continue;
+                    int jl[3] = { il[0], il[1], il[2] };
+                    jl[d] = mm;
+                    double um[5], f[5];
+                    or_get(m, U, e, or_node_index(jl), um);
+                    or_flux_ec(dim, d, u, um, m->gam, f);
+                    for (int v = 0; v < V; ++v) acc[v] += Ds[il[d] * 4 + mm] * f[v];
+                }
+                /* surface: right face (i_d = 3) and left face (i_d = 0) */
+                if (il[d] == 3 || il[d] == 0) {
+                    int right = (il[d] == 3);
+                    int jx[3] = { ix[0], ix[1], ix[2] };
+                    jx[d] = right ? (ix[d] + 1) % m->n[d] : (ix[d] + m->n[d] - 1) % m->n[d];
+                    int jl[3] = { il[0], il[1], il[2] };
+                    jl[d] = right ? 0 : 3;
+                    double un[5], f[5];
+                    or_get(m, U, or_elem_index(m, jx), or_node_index(jl), un);
+                    if (right) {
+                        if (m->surface_flux == 1) or_flux_hll(dim, d, u, un, m->gam, f);
+                        else or_flux_ec(dim, d, u, un, m->gam, f);
+                        for (int v = 0; v < V; ++v) acc[v] += f[v] / q[3];
+                    } else {
+                        if (m->surface_flux == 1) or_flux_hll(dim, d, un, u, m->gam, f);
+                        else or_flux_ec(dim, d, un, u, m->gam, f);
+                        for (int v = 0; v < V; ++v) acc[v] -= f[v] / q[0];
+                    }
+                }
+                for (int v = 0; v < V; ++v) du[v] += scale * acc[v];
+            }
+            double k[5];
+            for (int v = 0; v < V; ++v) k[v] = -du[v];
+            or_put(m, K, e, l, k);
+        }
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integrals                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Discrete total entropy H(U) = sum_e J_e sum_l q_l s(u_l). */
+double or_total_entropy(const or_mesh *m, const double *U)
+{
+    int npe = or_npe(m->dim), ne = or_nelem(m);
+    double H = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        double J = or_jac(m, e), He = 0.0;
+        for (int l = 0; l < npe; ++l) {
+            double u[5];
+            or_get(m, U, e, l, u);
+            He += or_qnode(m->dim, l) * or_entropy(m->dim, u, m->gam);
+        }
+        H += J * He;
+    }
+    return H;
+}
+
+/* Discrete integrals of the conserved variables, out[v] = sum_e J_e sum_l q_l u_v. */
+void or_total_conserved(const or_mesh *m, const double *U, double *out)
+{
+    int npe = or_npe(m->dim), ne = or_nelem(m), V = m->dim + 2;
+    for (int v = 0; v < V; ++v) out[v] = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        double J = or_jac(m, e);
+        for (int v = 0; v < V; ++v) {
+            double s = 0.0;
+            for (int l = 0; l < npe; ++l) s += or_qnode(m->dim, l) * U[((size_t)v * ne + e) * npe + l];
+            out[v] += J * s;
+        }
+    }
+}
+
+/* Entropy production <W(U), K> = sum_e J_e sum_l q_l w(u_l) . k_l
+ * (EntropyChange_EntropyVariables_ReArranged without the dt b_i factor). */
+double or_entropy_production(const or_mesh *m, const double *U, const double *K)
+{
+    int npe = or_npe(m->dim), ne = or_nelem(m), V = m->dim + 2;
+    double s = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        double J = or_jac(m, e), se = 0.0;
+        for (int l = 0; l < npe; ++l) {
+            double u[5], k[5], w[5];
+            or_get(m, U, e, l, u);
+            or_get(m, K, e, l, k);
+            or_entropy_vars(m->dim, u, m->gam, w);
+            double dot = 0.0;
+            for (int v = 0; v < V; ++v) dot += w[v] * k[v];
+            se += or_qnode(m->dim, l) * dot;
+        }
+        s += J * se;
+    }
+    return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Relaxation (Sec. 3.1)                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* r(gamma) = H(U_n + gamma dt d) - H(U_n) - gamma dH + offset, evaluated as the
+ * quadrature of the stable per-node entropy difference, and
+ * r'(gamma) = <W(U_n + gamma dt d), dt d> - dH. */
+void or_relax_eval(const or_mesh *m, const double *Un, const double *d, double dt, double gamma,
+                   double dH, double offset, double *r, double *rp)
+{
+    int npe = or_npe(m->dim), ne = or_nelem(m), V = m->dim + 2;
+    double sr = 0.0, srp = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        double J = or_jac(m, e), er = 0.0, erp = 0.0;
+        for (int l = 0; l < npe; ++l) {
+            double u[5], dd[5], du[5], u1[5], w[5];
+            or_get(m, Un, e, l, u);
+            or_get(m, d, e, l, dd);
+            for (int v = 0; v < V; ++v) {
+                du[v] = gamma * dt * dd[v];
+                u1[v] = u[v] + du[v];
+            }
+            or_entropy_vars(m->dim, u1, m->gam, w);
+            double dot = 0.0;
+            for (int v = 0; v < V; ++v) dot += w[v] * dt * dd[v];
+            double ql = or_qnode(m->dim, l);
+            er += ql * or_entropy_diff(m->dim, u, du, m->gam);
+            erp += ql * dot;
+        }
+        sr += J * er;
+        srp += J * erp;
+    }
+    *r = sr - gamma * dH + offset;
+    *rp = srp - dH;
+}
+
+/* True when the candidate state U_n + gamma dt d is admissible at every node. */
+static int or_candidate_ok(const or_mesh *m, const double *Un, const double *d, double dt, double gamma)
+{
+    int npe = or_npe(m->dim), ne = or_nelem(m), V = m->dim + 2;
+    for (int e = 0; e < ne; ++e)
+        for (int l = 0; l < npe; ++l) {
+            double u[5], dd[5], rho, v[3], p;
+            or_get(m, Un, e, l, u);
+            or_get(m, d, e, l, dd);
+            for (int k = 0; k < V; ++k) u[k] += gamma * dt * dd[k];
+            if (or_prim(m->dim, u, m->gam, &rho, v, &p)) return 0;
+        }
+    return 1;
+}
+
+/* Solve r(gamma) = 0: Newton with unit step from opt->gamma0; accept the first
+ * iterate with |r| <= tol_r.  If Newton fails, bisection on [bis_lo, bis_hi]
+ * (the bracket is widened once to [bis_lo/2, 2 bis_hi] when r does not change
+ * sign; gamma = 0, the trivial root, is never bracketed).  If that fails too,
+ * gamma = 1 and the fallback flag (the paper's non-relaxed step). */
+void or_relax_solve(const or_mesh *m, const double *Un, const double *d, double dt, double dH,
+                    double offset, const or_relax *opt, or_info *info)
+{
+    double g = opt->gamma0, r = 0.0, rp = 0.0;
+    int passes = 0, iters = 0;
+    info->flags = 0;
+    /* trivial direction: any gamma is a root */
+    int npe = or_npe(m->dim), ne = or_nelem(m), V = m->dim + 2, nonzero = 0;
+    for (size_t k = 0; k < (size_t)V * ne * npe; ++k)
+        if (d[k] != 0.0) { nonzero = 1; break; }
+    if (!nonzero) {
+        info->gamma = 1.0;
+        info->r = offset;
+        info->passes = 0;
+        info->newton_iters = 0;
+        info->flags = OR_FLAG_TRIVIAL;
+        return;
+    }
+    for (int k = 0; k < opt->max_newton; ++k) {
+        if (!(g > 0.0) || !or_candidate_ok(m, Un, d, dt, g)) break;
+        or_relax_eval(m, Un, d, dt, g, dH, offset, &r, &rp);
+        ++passes;
+        if (fabs(r) <= opt->tol_r) {
+            info->gamma = g;
+            info->r = r;
+            info->passes = passes;
+            info->newton_iters = iters;
+            return;
+        }
+        if (!(rp != 0.0) || !isfinite(r) || !isfinite(rp)) break;
+        double step = r / rp;
+        g -= step;
+        ++iters;
+        if (fabs(step) < opt->tol_step) {
+            /* no further progress possible at this precision */
+            if (!(g > 0.0) || !or_candidate_ok(m, Un, d, dt, g)) break;
+            or_relax_eval(m, Un, d, dt, g, dH, offset, &r, &rp);
+            ++passes;
+            if (fabs(r) <= opt->tol_r) {
+                info->gamma = g;
+                info->r = r;
+                info->passes = passes;
+                info->newton_iters = iters;
+                return;
+            }
+            break;
+        }
+    }
+    info->newton_iters = iters;
+    /* bisection */
+    info->flags |= OR_FLAG_BISECT;
+    double lo = opt->bis_lo, hi = opt->bis_hi, rlo, rhi, dummy;
+    for (int widen = 0; widen < 2; ++widen) {
+        int ok_lo = or_candidate_ok(m, Un, d, dt, lo), ok_hi = or_candidate_ok(m, Un, d, dt, hi);
+        if (ok_lo && ok_hi) {
+            or_relax_eval(m, Un, d, dt, lo, dH, offset, &rlo, &dummy);
+            or_relax_eval(m, Un, d, dt, hi, dH, offset, &rhi, &dummy);
+            passes += 2;
+            if (rlo < 0.0 && rhi > 0.0) {
+                for (int k = 0; k < opt->max_bisect; ++k) {
+                    double mid = 0.5 * (lo + hi), rm;
+                    or_relax_eval(m, Un, d, dt, mid, dH, offset, &rm, &dummy);
+                    ++passes;
+                    if (fabs(rm) <= opt->tol_r) {
+                        info->gamma = mid;
+                        info->r = rm;
+                        info->passes = passes;
+                        return;
+                    }
+                    if (rm < 0.0) lo = mid;
+                    else hi = mid;
+                }
+                break;
+            }
+        }
+        lo = 0.5 * opt->bis_lo;
+        hi = 2.0 * opt->bis_hi;
+    }
+    /* non-relaxed step */
+    info->flags |= OR_FLAG_FALLBACK;
+    info->gamma = 1.0;
+    or_relax_eval(m, Un, d, dt, 1.0, dH, offset, &r, &rp);
+    info->r = r;
+    info->passes = passes;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tableau                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Dense Butcher matrix of level r: row i has c_i - a_{i,i-1} in column 1 and
+ * a_{i,i-1} in column i-1 (for i = 2 both land in column 1 and sum to c_2). */
+void or_dense_A(const or_tableau *t, int r, double *A)
+{
+    int S = t->S;
+    memset(A, 0, sizeof(double) * S * S);
+    for (int i = 1; i < S; ++i) {
+        double a = t->a_sub[r * S + i];
+        A[i * S + 0] += t->c[i] - a;
+        A[i * S + (i - 1)] += a;
+    }
+}
+
+/* Stage i (zero-based) is evaluated by level r iff i == 0 or i >= S - E_r + 1:
+ * a level with E evaluations computes K_1 and K_{S-E+2}, ..., K_S. */
+int or_stage_active(const or_tableau *t, int r, int i)
+{
+    return i == 0 || i >= t->S - t->E[r] + 1;
+}
+
+static int or_validate(const or_mesh *m, const or_tableau *t, const int *level)
+{
+    if (!(m->dim == 2 || m->dim == 3)) return OR_EINVAL;
+    if (t->S < 2 || t->S > OR_MAXS || t->R < 1 || t->R > OR_MAXR) return OR_EINVAL;
+    for (int r = 0; r < t->R; ++r) {
+        if (t->E[r] < 2 || t->E[r] > t->S) return OR_EINVAL;
+        /* archetype structure: no sub-diagonal coupling into a stage the level
+         * does not evaluate, nor into its first evaluated stage after K_1 */
+        for (int i = 1; i <= t->S - t->E[r] + 1 && i < t->S; ++i)
+            if (t->a_sub[r * t->S + i] != 0.0) return OR_EINVAL;
+    }
+    int ne = or_nelem(m);
+    for (int e = 0; e < ne; ++e)
+        if (level[e] < 0 || level[e] >= t->R) return OR_EINVAL;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One step                                                                  */
+/* ------------------------------------------------------------------------ */
+
+static int or_finish_step(const or_mesh *m, const or_tableau *t, const or_relax *opt, double *U,
+                          const double *d, double dt, double dH, or_info *info)
+{
+    size_t M = (size_t)(m->dim + 2) * or_nelem(m) * or_npe(m->dim);
+    info->dH = dH;
+    info->H_old = or_total_entropy(m, U);
+    if (opt->relax) {
+        double offset = (opt->anchor == 1) ? (info->H_old - opt->H0) : 0.0;
+        or_relax_solve(m, U, d, dt, dH, offset, opt, info);
+    } else {
+        info->gamma = 1.0;
+        info->r = 0.0;
+        info->passes = 0;
+        info->newton_iters = 0;
+        info->flags = 0;
+    }
+    for (size_t k = 0; k < M; ++k) U[k] = U[k] + info->gamma * dt * d[k];
+    info->H_new = or_total_entropy(m, U);
+    (void)t;
+    return OR_OK;
+}
+
+/* Literal partitioned RK step (PartitionedRKSystem): every stage is evaluated
+ * on every element, U_{n,i} = U_n + dt sum_j a^{(r)}_{ij} K_j with the dense
+ * A^{(r)} of the element's level; d = sum_i b_i K_i; relaxation; update.
+ * U is overwritten with U_{n+1} (relaxed solution at t_n + gamma dt). */
+int or_step_dense(const or_mesh *m, const or_tableau *t, const int *level, const or_relax *opt,
+                  double *U, double dt, or_info *info)
+{
+    int st = or_validate(m, t, level);
+    if (st) return st;
+    st = or_check_state(m, U);
+    if (st) return st;
+    int S = t->S, ne = or_nelem(m), npe = or_npe(m->dim), V = m->dim + 2;
+    size_t M = (size_t)V * ne * npe;
+    double *Kall = (double *)calloc(M * S, sizeof(double));
+    double *Ui = (double *)malloc(M * sizeof(double));
+    double *d = (double *)calloc(M, sizeof(double));
+    double *A = (double *)malloc(sizeof(double) * S * S * t->R);
+    if (!Kall || !Ui || !d || !A) {
+        free(Kall); free(Ui); free(d); free(A);
+        return OR_ENOMEM;
+    }
+    for (int r = 0; r < t->R; ++r) or_dense_A(t, r, A + (size_t)r * S * S);
+    memset(info->e, 0, sizeof(info->e));
+    for (int i = 0; i < S; ++i) {
+        for (int v = 0; v < V; ++v)
+            for (int e = 0; e < ne; ++e) {
+                const double *Ar = A + (size_t)level[e] * S * S;
+                for (int l = 0; l < npe; ++l) {
+                    size_t idx = ((size_t)v * ne + e) * npe + l;
+                    double s = 0.0;
+                    for (int j = 0; j < i; ++j) s += Ar[i * S + j] * Kall[(size_t)j * M + idx];
+                    Ui[idx] = U[idx] + dt * s;
+                }
+            }
+        st = or_rhs(m, Ui, NULL, Kall + (size_t)i * M);
+        if (st) break;
+        if (t->b[i] != 0.0) info->e[i] = or_entropy_production(m, Ui, Kall + (size_t)i * M);
+    }
+    if (!st) {
+        double dH = 0.0;
+        for (int i = 0; i < S; ++i)
+            if (t->b[i] != 0.0) {
+                for (size_t k = 0; k < M; ++k) d[k] += t->b[i] * Kall[(size_t)i * M + k];
+                dH += t->b[i] * info->e[i];
+            }
+        st = or_finish_step(m, t, opt, U, d, dt, dt * dH, info);
+    }
+    free(Kall); free(Ui); free(d); free(A);
+    return st;
+}
+
+/* The same step in the form the paper's schemes are built for: only the
+ * stages a level evaluates are computed on its elements (K_1 everywhere,
+ * K_{S-E+2..S} on a level with E evaluations), and U_{n,i} is formed from
+ * U_n, K_1 and K_{i-1} only; inactive levels take the cheap update
+ * U_n + dt c_i K_1.  Two stage registers plus K_1 and K_{S-1} are kept. */
+int or_step(const or_mesh *m, const or_tableau *t, const int *level, const or_relax *opt,
+            double *U, double dt, or_info *info)
+{
+    int st = or_validate(m, t, level);
+    if (st) return st;
+    st = or_check_state(m, U);
+    if (st) return st;
+    int S = t->S, ne = or_nelem(m), npe = or_npe(m->dim), V = m->dim + 2;
+    size_t M = (size_t)V * ne * npe;
+    double *K1 = (double *)calloc(M, sizeof(double));
+    double *Kp = (double *)calloc(M, sizeof(double));
+    double *Kc = (double *)calloc(M, sizeof(double));
+    double *Ksm1 = (double *)calloc(M, sizeof(double));
+    double *Ui = (double *)malloc(M * sizeof(double));
+    double *d = (double *)calloc(M, sizeof(double));
+    unsigned char *act = (unsigned char *)malloc(ne);
+    if (!K1 || !Kp || !Kc || !Ksm1 || !Ui || !d || !act) {
+        free(K1); free(Kp); free(Kc); free(Ksm1); free(Ui); free(d); free(act);
+        return OR_ENOMEM;
+    }
+    memset(info->e, 0, sizeof(info->e));
+    for (int i = 0; i < S && !st; ++i) {
+        double *Kout = (i == 0) ? K1 : Kc;
+        for (int e = 0; e < ne; ++e) {
+            int r = level[e];
+            double a = (i >= 1) ? t->a_sub[r * S + i] : 0.0;
+            double a1 = (i >= 1) ? t->c[i] - a : 0.0;
+            if (i == 1) { a1 = t->c[1]; a = 0.0; }
+            act[e] = (unsigned char)or_stage_active(t, r, i);
+            for (int v = 0; v < V; ++v)
+                for (int l = 0; l < npe; ++l) {
+                    size_t idx = ((size_t)v * ne + e) * npe + l;
+                    double s = a1 * K1[idx];
+                    if (a != 0.0) s += a * Kp[idx];
+                    Ui[idx] = U[idx] + dt * s;
+                }
+        }
+        st = or_rhs(m, Ui, act, Kout);
+        if (st) break;
+        if (t->b[i] != 0.0) info->e[i] = or_entropy_production(m, Ui, Kout);
+        if (i == S - 2) memcpy(Ksm1, Kout, M * sizeof(double));
+        if (i >= 1) {
+            double *tmp = Kp;
+            Kp = Kc;
+            Kc = tmp;
+        }
+    }
+    if (!st) {
+        /* after the loop Kp holds K_S (S >= 2) */
+        const double *KS = Kp;
+        double dH = 0.0;
+        for (size_t k = 0; k < M; ++k) {
+            double s = t->b[S - 1] * KS[k];
+            if (S >= 3 && t->b[S - 2] != 0.0) s += t->b[S - 2] * Ksm1[k];
+            if (t->b[0] != 0.0) s += t->b[0] * K1[k];
+            d[k] = s;
+        }
+        for (int i = 0; i < S; ++i)
+            if (t->b[i] != 0.0) dH += t->b[i] * info->e[i];
+        /* b may only be nonzero in positions 1, S-1, S for these archetypes */
+        for (int i = 1; i < S - 2; ++i)
+            if (t->b[i] != 0.0) st = OR_EINVAL;
+        if (!st) st = or_finish_step(m, t, opt, U, d, dt, dt * dH, info);
+    }
+    free(K1); free(Kp); free(Kc); free(Ksm1); free(Ui); free(d); free(act);
+    return st;
+}
