@@ -1,0 +1,232 @@
+/*
+ * perrk.h -- C ABI of libperrk: one Paired Explicit Relaxation Runge-Kutta
+ * (P-ERRK) step of a degree-3 DGSEM discretisation of the compressible Euler
+ * equations on periodic Cartesian meshes, on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (arXiv 2507.04991):
+ *   - Sec. 2.2: partitioned RK in Butcher form; each element belongs to one
+ *     level r with E^(r) stage evaluations; the archetype tableaux of
+ *     Appendix A (second, third, fourth order) with shared c and b and
+ *     per-level sub-diagonal a^(r)_{i,i-1}; a level evaluates K_1 and
+ *     K_{S-E+2}..K_S, inactive levels take the cheap update U_n + dt c_i K_1.
+ *   - Sec. 2.4 and 3: relaxed update U_{n+1} = U_n + gamma dt d,
+ *     d = sum_i b_i K_i, entropy change dH = dt sum_i b_i <W(U_{n,i}), K_i>
+ *     accumulated stage by stage, gamma the root of
+ *     r(gamma) = H(U_n + gamma dt d) - H(U_n) - gamma dH (Sec. 3.1), found by
+ *     Newton with unit steps from the previous gamma; bisection, then the
+ *     non-relaxed step gamma = 1, as fallbacks.
+ *   - Sec. 2.1 / 4.1: DGSEM on Legendre-Gauss-Lobatto nodes with
+ *     entropy-conservative flux differencing (Ranocha's EC/KEP two-point flux)
+ *     in the volume, and the same flux or HLL (Davis wave speeds) at faces.
+ *   - Sec. 2.3: entropy s(u) = -rho log(p / rho^gamma), H its quadrature.
+ *
+ * Data layout of every state array (caller's and library's): structure of
+ * arrays [v][elem][node], node fastest; v = rho, rho v_1..rho v_dim, rho e
+ * (V = dim + 2 fields); node = i + 4 j (+ 16 k) with i along x; elements of a
+ * case numbered ix + nx (iy + ny iz), cases concatenated.  Every pointer
+ * named *_dev is device memory; everything else is host memory.
+ *
+ * Errors: every call returns a perrk_status.  Negative values are errors;
+ * after an error perrk_last_error(ctx) describes it (when ctx exists).
+ * Positive values are warnings (the call completed).  Calls never throw
+ * across the boundary.  The library is thread-compatible, not thread-safe:
+ * one context must not be used from two host threads at once.
+ */
+#ifndef PERRK_H
+#define PERRK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct perrk_ctx perrk_ctx; /* opaque; owned by the library */
+
+typedef enum {
+    PERRK_OK = 0,
+    PERRK_EINVAL = -1,      /* invalid argument or descriptor; no side effects */
+    PERRK_ENOMEM = -2,      /* device or host allocation failed */
+    PERRK_EHIP = -3,        /* a HIP runtime call failed (e.g. no GPU) */
+    PERRK_ENONPHYS = -4,    /* rho <= 0 or p <= 0 in a state the step formed; u left unmodified */
+    PERRK_ENONFINITE = -5,  /* NaN or Inf in a state the step formed; u left unmodified */
+    PERRK_WARN_FALLBACK = 1 /* some case took the non-relaxed step gamma = 1 (see flags) */
+} perrk_status;
+
+enum { PERRK_FLUX_EC = 0, PERRK_FLUX_HLL = 1 };
+/* FP64: every operation in double precision.
+ * MIXED: volume and surface fluxes in single precision with single-precision
+ * accumulation and single-precision stage storage; stage-state formation,
+ * direction d, entropy sums and the gamma solve stay double precision. */
+enum { PERRK_FP64 = 0, PERRK_MIXED = 1 };
+/* STEP: r anchored to H(U_n) (first equality of the discrete entropy balance);
+ * INITIAL: to H(U_0) at the time of perrk_init / perrk_reset_relaxation. */
+enum { PERRK_ANCHOR_STEP = 0, PERRK_ANCHOR_INITIAL = 1 };
+/* Initial guess of the Newton iteration: previous accepted gamma (1 at the
+ * first step), or the learned guess (perrk_set_guess_model). */
+enum { PERRK_GUESS_PREV = 0, PERRK_GUESS_MLP = 1 };
+/* Per-case step flags (perrk_step_info.flags). */
+enum {
+    PERRK_FLAG_BISECT = 1,   /* Newton failed, bisection was used */
+    PERRK_FLAG_FALLBACK = 2, /* no root found: gamma = 1 was taken */
+    PERRK_FLAG_TRIVIAL = 4   /* d == 0 everywhere: gamma = 1 without a solve */
+};
+
+typedef struct {
+    int32_t dim;               /* 2 or 3 */
+    int32_t n_cases;           /* >= 1: independent meshes advanced together */
+    const int32_t *n_elem_dir; /* [n_cases][3] elements per direction, >= 2 each (third = 1 in 2D) */
+    const double *face_coords; /* per case, per direction: n+1 increasing face positions, concatenated;
+                                  the domain is periodic in every direction */
+    double gas_gamma;          /* ratio of specific heats (> 1) */
+    int32_t surface_flux;      /* PERRK_FLUX_EC or PERRK_FLUX_HLL */
+    int32_t precision;         /* PERRK_FP64 or PERRK_MIXED */
+} perrk_mesh_desc;
+
+typedef struct {
+    int32_t n_levels;          /* must equal the tableau's n_levels */
+    const int32_t *elem_level; /* [total elements] level index 0..n_levels-1 (natural order) */
+} perrk_partition_desc;
+
+typedef struct {
+    int32_t order;             /* 2, 3 or 4 */
+    int32_t S;                 /* stages, 2..64 */
+    int32_t n_levels;          /* 1..16 */
+    const int32_t *E;          /* [n_levels] stage evaluations, 2..S */
+    const double *c;           /* [S] abscissae shared by all levels */
+    const double *b;           /* [S] weights shared by all levels; nonzero only at i = 1, S-1, S */
+    const double *a_sub;       /* [n_levels][S]: a^(r)_{i,i-1}; a^(r)_{i,1} = c_i - a^(r)_{i,i-1}.
+                                  Must vanish for stages a level skips and for its first
+                                  evaluated stage after K_1. */
+} perrk_tableau_desc;
+
+typedef struct {
+    int32_t relax;             /* 0: plain P-ERK step (gamma = 1), 1: relaxation */
+    int32_t max_newton;        /* Newton evaluations before bisection (>= 0) */
+    double tol_r;              /* accept gamma only when |r(gamma)| <= tol_r */
+    double tol_step;           /* a Newton step below this ends Newton after one more check */
+    int32_t anchor;            /* PERRK_ANCHOR_STEP or PERRK_ANCHOR_INITIAL */
+    int32_t max_bisect;        /* bisection steps before gamma = 1 (>= 0) */
+    double bisect_lo, bisect_hi; /* bracket, 0 < lo < 1 < hi; widened once to [lo/2, 2 hi] */
+    int32_t guess;             /* PERRK_GUESS_PREV or PERRK_GUESS_MLP */
+    int32_t fast_passes;       /* residual passes launched without host involvement (1..16);
+                                  further passes run in one per-case completion kernel */
+    int32_t use_graph;         /* 1: capture each step's launch sequence into a hipGraph */
+    int32_t tune;              /* 1: time the stage-kernel variants once and keep the fastest */
+} perrk_options;
+
+typedef struct {
+    double gamma;      /* accepted relaxation parameter; the solution is at t_n + gamma dt */
+    double r;          /* relaxation residual at the accepted gamma */
+    double dH;         /* dt sum_i b_i <W(U_{n,i}), K_i> */
+    double H_delta;    /* H(U_{n+1}) - H(U_n) as integrated by the residual */
+    double e[3];       /* <W(U_{n,i}), K_i> of the stages with b_i != 0, in stage order */
+    double t;          /* accumulated relaxed time sum gamma dt since init */
+    int32_t passes;    /* residual evaluations (full-mesh reductions) of the solve */
+    int32_t flags;     /* PERRK_FLAG_* */
+} perrk_step_info;
+
+/* Default options: relax = 1, max_newton = 10, tol_r = 1e-12, tol_step = 1e-15,
+ * anchor = STEP, max_bisect = 60, bracket [0.8, 1.2], guess = PREV,
+ * fast_passes = 3, use_graph = 1, tune = 0. */
+void perrk_default_options(perrk_options *opts);
+
+/* Validates every descriptor on the host (no GPU call): tableau structure,
+ * internal consistency sum_j a_ij = c_i (Sec. 2.2), shared b (conservation),
+ * order conditions up to `order`, level and mesh ranges.  Returns PERRK_OK or
+ * PERRK_EINVAL and writes a message into msg (may be NULL). */
+int perrk_validate(const perrk_mesh_desc *mesh, const perrk_partition_desc *part,
+                   const perrk_tableau_desc *tab, const perrk_options *opts, char *msg,
+                   size_t msg_len);
+
+/* Creates a context: validates (as perrk_validate), builds element tables and
+ * the level-sorted active lists, allocates the stage registers and reduction
+ * buffers on the current HIP device, and binds `stream` (hipStream_t; NULL =
+ * default stream) for all later work.  Host descriptors may be freed after
+ * return.  On error *out is NULL. */
+int perrk_init(const perrk_mesh_desc *mesh, const perrk_partition_desc *part,
+               const perrk_tableau_desc *tab, const perrk_options *opts, void *stream,
+               perrk_ctx **out);
+
+/* One P-ERRK step of every case, in place on u_dev (FP64, layout above,
+ * caller-owned).  dt: [n_cases] host array of step sizes (> 0).  Work is
+ * enqueued on the context's stream.  info: [n_cases] host array or NULL; with
+ * NULL the call does not synchronise (errors are then reported by the next
+ * call that synchronises); with info the call waits for the step and fills it.
+ * A step that forms a non-physical state leaves u_dev unmodified and returns
+ * PERRK_ENONPHYS or PERRK_ENONFINITE (when it synchronises). */
+int perrk_step(perrk_ctx *ctx, void *u_dev, const double *dt, perrk_step_info *info);
+
+/* H[c] = discrete total entropy of case c of u_dev: sum over elements of
+ * J_e sum_nodes q s(u) (Sec. 2.3).  Synchronises.  H: [n_cases] host. */
+int perrk_entropy(perrk_ctx *ctx, const void *u_dev, double *H);
+
+/* k_dev = F(u_dev) on every element: the semidiscretisation the stages
+ * evaluate.  k_dev has the stage storage type: double (FP64) or float
+ * (MIXED), same layout as u_dev.  Asynchronous on the context's stream. */
+int perrk_rhs(perrk_ctx *ctx, const void *u_dev, void *k_dev);
+
+/* Previous accepted gamma per case (the Newton starting value) and the
+ * accumulated entropy offset H(U_n) - H(U_0) used by PERRK_ANCHOR_INITIAL:
+ * read or restore (checkpoint / resume).  Arrays are [n_cases] host. */
+int perrk_get_relaxation_state(perrk_ctx *ctx, double *gamma_prev, double *h_offset, double *t);
+int perrk_set_relaxation_state(perrk_ctx *ctx, const double *gamma_prev, const double *h_offset,
+                               const double *t);
+
+/* Learned initial guess (guess = PERRK_GUESS_MLP): a multilayer perceptron
+ * 8 -> 32 -> 32 -> 1 (tanh hidden layers), float32 weights in the order
+ * W1[32][8], b1[32], W2[32][32], b2[32], W3[1][32], b3[1] (1377 values), plus
+ * feature normalisation mean[8], scale[8].  Features per case: the last three
+ * accepted gamma - 1, dt, and the stage entropy-production terms of the step
+ * normalised by their sum of magnitudes (padded to four).  The output is a
+ * prediction of gamma - 1; Newton/bisection still decide the accepted gamma. */
+int perrk_set_guess_model(perrk_ctx *ctx, const float *weights, const float *mean,
+                          const float *scale);
+
+/* Kernel classes of the per-launch statistics. */
+enum {
+    PERRK_K_STAGE_FIRST = 0, /* stage 1: K_1 = F(U_n) on every element */
+    PERRK_K_STAGE_MID = 1,   /* stages 2..S-1 on their active elements */
+    PERRK_K_STAGE_LAST = 2,  /* stage S, writes the direction d */
+    PERRK_K_RESIDUAL = 3,    /* relaxation residual passes (full mesh) */
+    PERRK_K_SOLVER = 4,      /* per-case reductions and the Newton / bisection updates */
+    PERRK_K_UPDATE = 5,      /* U_{n+1} = U_n + gamma dt d */
+    PERRK_K_CLASSES = 6
+};
+
+/* Accumulated statistics of one kernel class: summed launch durations
+ * (HIP events around each launch on the library's stream), summed algorithmic
+ * bytes (compulsory HBM traffic of the launch: the arrays it must read and
+ * write once; neighbour face reads are not counted) and launch count. */
+typedef struct {
+    double ms;
+    double bytes;
+    int64_t launches;
+} perrk_kernel_stat;
+
+/* on = 1: later steps are launched without the graph, each launch bracketed by
+ * HIP events, and every step synchronises; on = 0 restores normal launches. */
+int perrk_set_profiling(perrk_ctx *ctx, int on);
+
+/* Copies the statistics of the PERRK_K_CLASSES classes into stats[] and, if
+ * reset != 0, clears them. */
+int perrk_get_kernel_stats(perrk_ctx *ctx, perrk_kernel_stat *stats, int reset);
+
+/* Writes a short text describing the launch configuration in use. */
+int perrk_get_tuning(perrk_ctx *ctx, char *buf, size_t len);
+
+/* Last error message of ctx ("" if none). */
+const char *perrk_last_error(const perrk_ctx *ctx);
+
+/* Library version string. */
+const char *perrk_version(void);
+
+/* Frees every resource of ctx (waits for its stream first).  NULL is allowed. */
+void perrk_destroy(perrk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERRK_H */

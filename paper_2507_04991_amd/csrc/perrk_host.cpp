@@ -1,0 +1,777 @@
+// perrk_host.cpp -- host side of libperrk: descriptor validation, element
+// tables, level-sorted active lists, buffer planning, the launch sequence of
+// one P-ERRK step (optionally captured once into a hipGraph), and the C ABI
+// declared in include/perrk.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "perrk.h"
+#include "perrk_internal.h"
+
+struct perrk_ctx {
+    std::string err;
+    // problem
+    int dim = 2, V = 4, npe = 16, n_cases = 1, precision = 0, flux = 0;
+    double gam = 1.4;
+    int64_t nelem = 0;
+    std::vector<int64_t> case_off;
+    // tableau
+    int order = 2, S = 2, R = 1;
+    std::vector<int> E;
+    std::vector<double> c, b, a_sub;
+    std::vector<int> bstages;  // stages with b_i != 0
+    perrk_options opt{};
+    RelaxParams rp{};
+    LaunchCfg cfg{4};
+    std::vector<int32_t> n_active;  // per stage
+    // streams and events
+    hipStream_t user_stream = nullptr, stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // device buffers
+    ElemInfo *d_elem = nullptr;
+    int32_t *d_active = nullptr;
+    int64_t *d_case_off = nullptr;
+    CaseState *d_cs = nullptr;
+    double *d_coef = nullptr;  // [S][2 * PERRK_MAXR]
+    void *d_K1 = nullptr, *d_Ka = nullptr, *d_Kb = nullptr;
+    double *d_d = nullptr, *d_ep = nullptr, *d_partial = nullptr, *d_H = nullptr, *d_dt = nullptr;
+    int32_t *d_err = nullptr;
+    float *d_mlp = nullptr;
+    bool have_mlp = false;
+    // pinned host staging
+    static constexpr int NRING = 8;
+    double *h_dt = nullptr;  // [NRING][n_cases]
+    hipEvent_t ring_ev[NRING] = {};
+    int ring = 0;
+    CaseState *h_cs = nullptr;
+    int32_t *h_err = nullptr;
+    double *h_H = nullptr;
+    // profiling
+    bool profiling = false;
+    static constexpr int NEV = 192;
+    hipEvent_t pev[NEV] = {};
+    int npev = 0;
+    int pcls[NEV / 2] = {};
+    double pbytes[NEV / 2] = {};
+    perrk_kernel_stat stats[PERRK_K_CLASSES] = {};
+    std::vector<double> stage_bytes;  // algorithmic bytes of each stage launch
+    double pass_bytes = 0.0, update_bytes = 0.0;
+    // graph
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    void *graph_u = nullptr;
+};
+
+namespace {
+
+int fail(perrk_ctx *ctx, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return code;
+}
+
+#define HIPCHECK(ctx, call)                                                                     \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((ctx), PERRK_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+struct Checker {
+    char *msg;
+    size_t len;
+    int bad(const char *fmt, ...)
+    {
+        if (msg && len) {
+            va_list ap;
+            va_start(ap, fmt);
+            vsnprintf(msg, len, fmt, ap);
+            va_end(ap);
+        }
+        return PERRK_EINVAL;
+    }
+};
+
+// Dense Butcher matrix of level r (row i: c_i - a in column 0, a in column i-1).
+std::vector<double> dense_A(const perrk_tableau_desc *t, int r)
+{
+    const int S = t->S;
+    std::vector<double> A((size_t)S * S, 0.0);
+    for (int i = 1; i < S; ++i) {
+        const double a = t->a_sub[r * S + i];
+        A[i * S + 0] += t->c[i] - a;
+        A[i * S + i - 1] += a;
+    }
+    return A;
+}
+
+std::vector<double> matvec(const std::vector<double> &A, const std::vector<double> &x, int S)
+{
+    std::vector<double> y(S, 0.0);
+    for (int i = 0; i < S; ++i)
+        for (int j = 0; j < S; ++j) y[i] += A[i * S + j] * x[j];
+    return y;
+}
+
+double dot(const double *b, const std::vector<double> &x)
+{
+    double s = 0.0;
+    for (size_t i = 0; i < x.size(); ++i) s += b[i] * x[i];
+    return s;
+}
+
+int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perrk_tableau_desc *t,
+             const perrk_options *o, char *msg, size_t len)
+{
+    Checker ck{msg, len};
+    if (msg && len) msg[0] = 0;
+    if (!m || !p || !t) return ck.bad("null descriptor");
+    if (m->dim != 2 && m->dim != 3) return ck.bad("dim must be 2 or 3 (got %d)", m->dim);
+    if (m->n_cases < 1) return ck.bad("n_cases must be >= 1");
+    if (!m->n_elem_dir || !m->face_coords) return ck.bad("null mesh arrays");
+    if (!(m->gas_gamma > 1.0) || !std::isfinite(m->gas_gamma)) return ck.bad("gas_gamma must be > 1");
+    if (m->surface_flux != PERRK_FLUX_EC && m->surface_flux != PERRK_FLUX_HLL)
+        return ck.bad("unknown surface flux %d", m->surface_flux);
+    if (m->precision != PERRK_FP64 && m->precision != PERRK_MIXED)
+        return ck.bad("unknown precision %d", m->precision);
+    int64_t total = 0;
+    const double *f = m->face_coords;
+    for (int c = 0; c < m->n_cases; ++c) {
+        int64_t ne = 1;
+        for (int d = 0; d < 3; ++d) {
+            const int n = m->n_elem_dir[3 * c + d];
+            if (d < m->dim) {
+                if (n < 2 || n > (1 << 20)) return ck.bad("case %d: n[%d] = %d out of range", c, d, n);
+                for (int k = 0; k < n; ++k)
+                    if (!(f[k + 1] > f[k]) || !std::isfinite(f[k]) || !std::isfinite(f[k + 1]))
+                        return ck.bad("case %d: face coordinates of direction %d not increasing", c, d);
+                f += n + 1;
+                ne *= n;
+            } else if (n != 1) {
+                return ck.bad("case %d: n[2] must be 1 in 2D", c);
+            }
+        }
+        total += ne;
+    }
+    if (total > (int64_t)INT32_MAX / 64) return ck.bad("too many elements (%lld)", (long long)total);
+    const int S = t->S, R = t->n_levels;
+    if (t->order < 2 || t->order > 4) return ck.bad("order must be 2, 3 or 4");
+    if (S < 2 || S > PERRK_MAXS) return ck.bad("S must be in 2..%d", PERRK_MAXS);
+    if (R < 1 || R > PERRK_MAXR) return ck.bad("n_levels must be in 1..%d", PERRK_MAXR);
+    if (!t->E || !t->c || !t->b || !t->a_sub) return ck.bad("null tableau arrays");
+    if (p->n_levels != R) return ck.bad("partition has %d levels, tableau %d", p->n_levels, R);
+    if (!p->elem_level) return ck.bad("null elem_level");
+    for (int64_t e = 0; e < total; ++e)
+        if (p->elem_level[e] < 0 || p->elem_level[e] >= R)
+            return ck.bad("element %lld has level %d", (long long)e, p->elem_level[e]);
+    if (t->c[0] != 0.0) return ck.bad("c_1 must be 0");
+    for (int i = 0; i < S; ++i) {
+        if (!std::isfinite(t->c[i]) || !std::isfinite(t->b[i])) return ck.bad("non-finite c or b");
+        if (t->b[i] < 0.0) return ck.bad("b_%d < 0", i + 1);
+        if (t->b[i] != 0.0 && !(i == 0 || i >= S - 2))
+            return ck.bad("b_%d != 0: only b_1, b_{S-1}, b_S may be nonzero", i + 1);
+    }
+    for (int r = 0; r < R; ++r) {
+        const int E = t->E[r];
+        if (E < 2 || E > S) return ck.bad("level %d: E = %d outside 2..S", r, E);
+        for (int i = 0; i < S; ++i) {
+            const double a = t->a_sub[r * S + i];
+            if (!std::isfinite(a)) return ck.bad("non-finite a_sub");
+            if (i <= 1 && a != 0.0) return ck.bad("level %d: a_sub[%d] must be 0", r, i);
+            if (i >= 1 && i <= S - E + 1 && a != 0.0)
+                return ck.bad("level %d: stage %d is skipped or first evaluated, a_{i,i-1} must be 0", r,
+                              i + 1);
+        }
+        if (S >= 3 && t->b[S - 2] != 0.0 && E < 3)
+            return ck.bad("b_{S-1} != 0 needs every level to evaluate stage S-1 (E >= 3)");
+    }
+    // order conditions of the partitioned method for every level combination
+    std::vector<double> one(S, 1.0), cv(t->c, t->c + S), c2(S), c3(S);
+    for (int i = 0; i < S; ++i) {
+        c2[i] = cv[i] * cv[i];
+        c3[i] = c2[i] * cv[i];
+    }
+    const double tol = 1e-10;
+    if (std::fabs(dot(t->b, one) - 1.0) > tol) return ck.bad("order 1 condition sum b = 1 violated");
+    if (std::fabs(dot(t->b, cv) - 0.5) > tol) return ck.bad("order 2 condition b.c = 1/2 violated");
+    std::vector<std::vector<double>> A(R);
+    for (int r = 0; r < R; ++r) A[r] = dense_A(t, r);
+    if (t->order >= 3) {
+        if (std::fabs(dot(t->b, c2) - 1.0 / 3.0) > tol) return ck.bad("order 3: b.c^2 = 1/3 violated");
+        for (int r = 0; r < R; ++r)
+            if (std::fabs(dot(t->b, matvec(A[r], cv, S)) - 1.0 / 6.0) > tol)
+                return ck.bad("order 3: b.A c = 1/6 violated for level %d", r);
+    }
+    if (t->order >= 4) {
+        if (std::fabs(dot(t->b, c3) - 0.25) > tol) return ck.bad("order 4: b.c^3 = 1/4 violated");
+        for (int r = 0; r < R; ++r) {
+            std::vector<double> Ac = matvec(A[r], cv, S), cAc(S);
+            for (int i = 0; i < S; ++i) cAc[i] = cv[i] * Ac[i];
+            if (std::fabs(dot(t->b, cAc) - 0.125) > tol) return ck.bad("order 4: b.(c A c) = 1/8 (level %d)", r);
+            if (std::fabs(dot(t->b, matvec(A[r], c2, S)) - 1.0 / 12.0) > tol)
+                return ck.bad("order 4: b.A c^2 = 1/12 (level %d)", r);
+            for (int s = 0; s < R; ++s)
+                if (std::fabs(dot(t->b, matvec(A[r], matvec(A[s], cv, S), S)) - 1.0 / 24.0) > tol)
+                    return ck.bad("order 4: b.A A c = 1/24 (levels %d, %d)", r, s);
+        }
+    }
+    if (o) {
+        if (o->max_newton < 0 || o->max_newton > 100) return ck.bad("max_newton out of range");
+        if (o->max_bisect < 0 || o->max_bisect > 200) return ck.bad("max_bisect out of range");
+        if (!(o->tol_r >= 0.0) || !(o->tol_step >= 0.0)) return ck.bad("tolerances must be >= 0");
+        if (!(o->bisect_lo > 0.0 && o->bisect_lo < 1.0 && o->bisect_hi > 1.0))
+            return ck.bad("bracket must satisfy 0 < lo < 1 < hi");
+        if (o->anchor != PERRK_ANCHOR_STEP && o->anchor != PERRK_ANCHOR_INITIAL) return ck.bad("bad anchor");
+        if (o->guess != PERRK_GUESS_PREV && o->guess != PERRK_GUESS_MLP) return ck.bad("bad guess");
+        if (o->fast_passes < 1 || o->fast_passes > 16) return ck.bad("fast_passes must be in 1..16");
+    }
+    return PERRK_OK;
+}
+
+void free_all(perrk_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    void *dev[] = {c->d_elem, c->d_active, c->d_case_off, c->d_cs, c->d_coef, c->d_K1, c->d_Ka,
+                   c->d_Kb, c->d_d, c->d_ep, c->d_partial, c->d_H, c->d_dt, c->d_err, c->d_mlp};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    void *host[] = {c->h_dt, c->h_cs, c->h_err, c->h_H};
+    for (void *p : host)
+        if (p) (void)hipHostFree(p);
+    for (auto &e : c->ring_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->pev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+// Profiling: events around one launch.
+hipError_t mark_begin(perrk_ctx *c)
+{
+    if (!c->profiling || c->npev + 2 > perrk_ctx::NEV) return hipSuccess;
+    return hipEventRecord(c->pev[c->npev], c->stream);
+}
+
+hipError_t mark_end(perrk_ctx *c, int cls, double bytes)
+{
+    if (!c->profiling || c->npev + 2 > perrk_ctx::NEV) return hipSuccess;
+    const hipError_t e = hipEventRecord(c->pev[c->npev + 1], c->stream);
+    c->pcls[c->npev / 2] = cls;
+    c->pbytes[c->npev / 2] = bytes;
+    c->npev += 2;
+    return e;
+}
+
+// Enqueues one full step on ctx->stream (no host synchronisation).
+int enqueue_step(perrk_ctx *c, double *u)
+{
+    const size_t ks = c->precision == PERRK_MIXED ? 4 : 8;
+    (void)ks;
+    StageArgs a{};
+    a.U = u;
+    a.elem = c->d_elem;
+    a.active = c->d_active;
+    a.cs = c->d_cs;
+    a.err = c->d_err;
+    a.nelem = c->nelem;
+    a.gam = c->gam;
+    const int S = c->S;
+    void *kbuf[2] = {c->d_Ka, c->d_Kb};
+    for (int i = 0; i < S; ++i) {
+        const int kind = i == 0 ? SK_FIRST : (i == S - 1 ? SK_LAST : SK_MID);
+        a.K1 = c->d_K1;
+        a.Kp = i >= 2 ? kbuf[(i - 2) % 2] : c->d_K1;
+        a.Kout = i == 0 ? c->d_K1 : kbuf[(i - 1) % 2];
+        a.d_out = c->d_d;
+        a.n_active = c->n_active[i];
+        a.b1 = c->b[0];
+        a.bsm1 = (S >= 3) ? c->b[S - 2] : 0.0;
+        a.bs = c->b[S - 1];
+        if (S == 2) a.b1 = c->b[0];
+        a.ep_partial = nullptr;
+        for (size_t j = 0; j < c->bstages.size(); ++j)
+            if (c->bstages[j] == i) a.ep_partial = c->d_ep + j * (size_t)c->nelem;
+        HIPCHECK(c, mark_begin(c));
+        HIPCHECK(c, launch_stage(c->dim, c->precision, c->flux, kind, a, c->d_coef + (size_t)i * 2 * PERRK_MAXR,
+                                 c->cfg, c->stream));
+        HIPCHECK(c, mark_end(c, kind == SK_FIRST ? PERRK_K_STAGE_FIRST
+                                : (kind == SK_MID ? PERRK_K_STAGE_MID : PERRK_K_STAGE_LAST),
+                             c->stage_bytes[i]));
+    }
+    HIPCHECK(c, mark_begin(c));
+    HIPCHECK(c, launch_relax_prepare(c->d_cs, c->d_case_off, c->n_cases, c->d_ep, c->nelem, c->rp,
+                                     c->have_mlp ? c->d_mlp : nullptr, c->stream));
+    HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
+    if (c->rp.relax) {
+        for (int p = 0; p < c->opt.fast_passes; ++p) {
+            HIPCHECK(c, mark_begin(c));
+            HIPCHECK(c, launch_relax_pass(c->dim, u, c->d_d, c->d_elem, c->d_cs, c->d_partial, c->nelem, c->gam,
+                                          c->stream));
+            HIPCHECK(c, mark_end(c, PERRK_K_RESIDUAL, c->pass_bytes));
+            HIPCHECK(c, mark_begin(c));
+            HIPCHECK(c, launch_relax_finalize(c->d_cs, c->d_case_off, c->n_cases, c->d_partial, c->rp, c->stream));
+            HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
+        }
+    }
+    HIPCHECK(c, mark_begin(c));
+    HIPCHECK(c, launch_relax_complete(c->dim, u, c->d_d, c->d_elem, c->d_cs, c->d_case_off, c->n_cases,
+                                      c->d_partial, c->nelem, c->gam, c->rp, c->stream));
+    HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
+    HIPCHECK(c, mark_begin(c));
+    HIPCHECK(c, launch_final_update(c->dim, u, c->d_d, c->d_elem, c->d_cs, c->d_err, c->nelem, c->stream));
+    HIPCHECK(c, mark_end(c, PERRK_K_UPDATE, c->update_bytes));
+    return PERRK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void perrk_default_options(perrk_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->relax = 1;
+    o->max_newton = 10;
+    o->tol_r = 1e-12;
+    o->tol_step = 1e-15;
+    o->anchor = PERRK_ANCHOR_STEP;
+    o->max_bisect = 60;
+    o->bisect_lo = 0.8;
+    o->bisect_hi = 1.2;
+    o->guess = PERRK_GUESS_PREV;
+    o->fast_passes = 3;
+    o->use_graph = 1;
+    o->tune = 0;
+}
+
+int perrk_validate(const perrk_mesh_desc *mesh, const perrk_partition_desc *part,
+                   const perrk_tableau_desc *tab, const perrk_options *opts, char *msg, size_t msg_len)
+{
+    return validate(mesh, part, tab, opts, msg, msg_len);
+}
+
+int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perrk_tableau_desc *t,
+               const perrk_options *opts, void *stream, perrk_ctx **out)
+{
+    if (!out) return PERRK_EINVAL;
+    *out = nullptr;
+    perrk_options o;
+    if (opts) o = *opts;
+    else perrk_default_options(&o);
+    char msg[512];
+    const int st = validate(m, p, t, &o, msg, sizeof msg);
+    if (st != PERRK_OK) {
+        std::fprintf(stderr, "perrk_init: %s\n", msg);
+        return st;
+    }
+    perrk_ctx *c = new (std::nothrow) perrk_ctx();
+    if (!c) return PERRK_ENOMEM;
+    c->opt = o;
+    c->dim = m->dim;
+    c->V = m->dim + 2;
+    c->npe = m->dim == 2 ? 16 : 64;
+    c->n_cases = m->n_cases;
+    c->precision = m->precision;
+    c->flux = m->surface_flux;
+    c->gam = m->gas_gamma;
+    c->order = t->order;
+    c->S = t->S;
+    c->R = t->n_levels;
+    c->E.assign(t->E, t->E + c->R);
+    c->c.assign(t->c, t->c + c->S);
+    c->b.assign(t->b, t->b + c->S);
+    c->a_sub.assign(t->a_sub, t->a_sub + (size_t)c->R * c->S);
+    for (int i = 0; i < c->S; ++i)
+        if (c->b[i] != 0.0) c->bstages.push_back(i);
+
+    // element tables (natural order, cases concatenated)
+    std::vector<ElemInfo> elem;
+    c->case_off.push_back(0);
+    const double *f = m->face_coords;
+    for (int cs = 0; cs < m->n_cases; ++cs) {
+        const int n0 = m->n_elem_dir[3 * cs], n1 = m->n_elem_dir[3 * cs + 1];
+        const int n2 = m->dim == 3 ? m->n_elem_dir[3 * cs + 2] : 1;
+        const double *fx = f, *fy = fx + n0 + 1, *fz = fy + n1 + 1;
+        f = fy + n1 + 1 + (m->dim == 3 ? n2 + 1 : 0);
+        const int64_t base = c->case_off.back();
+        for (int iz = 0; iz < n2; ++iz)
+            for (int iy = 0; iy < n1; ++iy)
+                for (int ix = 0; ix < n0; ++ix) {
+                    ElemInfo ei{};
+                    auto gid = [&](int x, int y, int z) {
+                        return (int32_t)(base + x + (int64_t)n0 * (y + (int64_t)n1 * z));
+                    };
+                    ei.nbr[0] = gid((ix + n0 - 1) % n0, iy, iz);
+                    ei.nbr[1] = gid((ix + 1) % n0, iy, iz);
+                    ei.nbr[2] = gid(ix, (iy + n1 - 1) % n1, iz);
+                    ei.nbr[3] = gid(ix, (iy + 1) % n1, iz);
+                    ei.nbr[4] = m->dim == 3 ? gid(ix, iy, (iz + n2 - 1) % n2) : gid(ix, iy, iz);
+                    ei.nbr[5] = m->dim == 3 ? gid(ix, iy, (iz + 1) % n2) : gid(ix, iy, iz);
+                    const double hx = fx[ix + 1] - fx[ix], hy = fy[iy + 1] - fy[iy];
+                    const double hz = m->dim == 3 ? fz[iz + 1] - fz[iz] : 2.0;
+                    ei.metric[0] = 2.0 / hx;
+                    ei.metric[1] = 2.0 / hy;
+                    ei.metric[2] = 2.0 / hz;
+                    ei.jac = 0.5 * hx * 0.5 * hy * (m->dim == 3 ? 0.5 * hz : 1.0);
+                    const int64_t g = elem.size();
+                    ei.level = p->elem_level[g];
+                    ei.case_id = cs;
+                    elem.push_back(ei);
+                }
+        c->case_off.push_back((int64_t)elem.size());
+    }
+    c->nelem = (int64_t)elem.size();
+
+    // level-sorted active list: elements of levels with more evaluations first
+    std::vector<int32_t> order(c->nelem);
+    for (int64_t e = 0; e < c->nelem; ++e) order[e] = (int32_t)e;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return c->E[elem[x].level] > c->E[elem[y].level];
+    });
+    c->n_active.resize(c->S);
+    for (int i = 0; i < c->S; ++i) {
+        int64_t n = 0;
+        for (int64_t e = 0; e < c->nelem; ++e) {
+            const int E = c->E[elem[e].level];
+            if (i == 0 || i >= c->S - E + 1) ++n;
+        }
+        c->n_active[i] = (int32_t)n;
+    }
+    // per-stage coefficients (without dt): K_1 and K_{i-1} multipliers per level
+    std::vector<double> coef((size_t)c->S * 2 * PERRK_MAXR, 0.0);
+    for (int i = 1; i < c->S; ++i)
+        for (int r = 0; r < c->R; ++r) {
+            const double a = (i >= 2) ? c->a_sub[(size_t)r * c->S + i] : 0.0;
+            coef[(size_t)i * 2 * PERRK_MAXR + r] = c->c[i] - a;
+            coef[(size_t)i * 2 * PERRK_MAXR + PERRK_MAXR + r] = a;
+        }
+    // relaxation parameters
+    RelaxParams rp{};
+    rp.tol_r = o.tol_r;
+    rp.tol_step = o.tol_step;
+    rp.bis_lo = o.bisect_lo;
+    rp.bis_hi = o.bisect_hi;
+    rp.max_newton = o.max_newton;
+    rp.max_bisect = o.max_bisect;
+    rp.anchor = o.anchor;
+    rp.relax = o.relax;
+    rp.guess = o.guess;
+    rp.nb = (int)c->bstages.size();
+    for (int j = 0; j < rp.nb && j < 3; ++j) rp.bw[j] = c->b[c->bstages[j]];
+    c->rp = rp;
+    c->cfg.epb_mult = 4;
+
+    // algorithmic (compulsory) bytes of each launch
+    {
+        const double dofe = (double)c->V * c->npe;  // DOF per element
+        const double kb = c->precision == PERRK_MIXED ? 4.0 : 8.0;
+        std::vector<int64_t> per_level(c->R, 0);
+        for (int64_t e = 0; e < c->nelem; ++e) per_level[elem[e].level]++;
+        c->stage_bytes.assign(c->S, 0.0);
+        for (int i = 0; i < c->S; ++i) {
+            double bytes = 0.0;
+            for (int r = 0; r < c->R; ++r) {
+                if (!(i == 0 || i >= c->S - c->E[r] + 1)) continue;
+                const double c1 = coef[(size_t)i * 2 * PERRK_MAXR + r];
+                const double cp = coef[(size_t)i * 2 * PERRK_MAXR + PERRK_MAXR + r];
+                double be = 8.0;  // U_n
+                if (i == 0) be += kb;  // write K_1
+                else {
+                    if (c1 != 0.0) be += kb;                                     // K_1
+                    if (cp != 0.0 || (i == c->S - 1 && c->S >= 3 && c->b[c->S - 2] != 0.0)) be += kb;  // K_{i-1}
+                    be += (i == c->S - 1) ? 8.0 : kb;                           // write K_i or d
+                }
+                bytes += be * dofe * per_level[r];
+            }
+            c->stage_bytes[i] = bytes;
+        }
+        c->pass_bytes = 16.0 * dofe * c->nelem;
+        c->update_bytes = 24.0 * dofe * c->nelem;
+    }
+
+    // device state
+    const size_t M = (size_t)c->V * c->nelem * c->npe;
+    const size_t ks = c->precision == PERRK_MIXED ? 4 : 8;
+    auto bail = [&](int code) {
+        free_all(c);
+        delete c;
+        return code;
+    };
+#define HIPINIT(call)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) {                                                                 \
+            std::fprintf(stderr, "perrk_init: %s failed: %s\n", #call, hipGetErrorString(e_)); \
+            return bail(e_ == hipErrorOutOfMemory ? PERRK_ENOMEM : PERRK_EHIP);                 \
+        }                                                                                       \
+    } while (0)
+    c->user_stream = (hipStream_t)stream;
+    HIPINIT(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIPINIT(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HIPINIT(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    for (auto &e : c->ring_ev) HIPINIT(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPINIT(hipMalloc(&c->d_elem, sizeof(ElemInfo) * c->nelem));
+    HIPINIT(hipMalloc(&c->d_active, sizeof(int32_t) * c->nelem));
+    HIPINIT(hipMalloc(&c->d_case_off, sizeof(int64_t) * (c->n_cases + 1)));
+    HIPINIT(hipMalloc(&c->d_cs, sizeof(CaseState) * c->n_cases));
+    HIPINIT(hipMalloc(&c->d_coef, sizeof(double) * coef.size()));
+    HIPINIT(hipMalloc(&c->d_K1, ks * M));
+    HIPINIT(hipMalloc(&c->d_Ka, ks * M));
+    HIPINIT(hipMalloc(&c->d_Kb, ks * M));
+    HIPINIT(hipMalloc(&c->d_d, sizeof(double) * M));
+    HIPINIT(hipMalloc(&c->d_ep, sizeof(double) * 3 * c->nelem));
+    HIPINIT(hipMalloc(&c->d_partial, sizeof(double) * 4 * c->nelem));
+    HIPINIT(hipMalloc(&c->d_H, sizeof(double) * c->n_cases));
+    HIPINIT(hipMalloc(&c->d_dt, sizeof(double) * c->n_cases * perrk_ctx::NRING));
+    HIPINIT(hipMalloc(&c->d_err, sizeof(int32_t)));
+    HIPINIT(hipMalloc(&c->d_mlp, sizeof(float) * (PERRK_MLP_NW + 18)));
+    HIPINIT(hipHostMalloc(&c->h_dt, sizeof(double) * c->n_cases * perrk_ctx::NRING, 0));
+    HIPINIT(hipHostMalloc(&c->h_cs, sizeof(CaseState) * c->n_cases, 0));
+    HIPINIT(hipHostMalloc(&c->h_err, sizeof(int32_t), 0));
+    HIPINIT(hipHostMalloc(&c->h_H, sizeof(double) * c->n_cases, 0));
+    HIPINIT(hipMemcpyAsync(c->d_elem, elem.data(), sizeof(ElemInfo) * c->nelem, hipMemcpyHostToDevice, c->stream));
+    HIPINIT(hipMemcpyAsync(c->d_active, order.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice, c->stream));
+    HIPINIT(hipMemcpyAsync(c->d_case_off, c->case_off.data(), sizeof(int64_t) * (c->n_cases + 1),
+                           hipMemcpyHostToDevice, c->stream));
+    HIPINIT(hipMemcpyAsync(c->d_coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, c->stream));
+    HIPINIT(launch_init_cases(c->d_cs, c->n_cases, c->stream));
+    HIPINIT(launch_clear_err(c->d_err, c->stream));
+    HIPINIT(hipStreamSynchronize(c->stream));
+#undef HIPINIT
+    *out = c;
+    return PERRK_OK;
+}
+
+int perrk_step(perrk_ctx *c, void *u_dev, const double *dt, perrk_step_info *info)
+{
+    if (!c || !u_dev || !dt) return fail(c, PERRK_EINVAL, "null argument");
+    for (int i = 0; i < c->n_cases; ++i)
+        if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(c, PERRK_EINVAL, "dt[%d] must be > 0", i);
+    // order after the caller's work
+    HIPCHECK(c, hipEventRecord(c->ev_in, c->user_stream));
+    HIPCHECK(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
+    // dt upload through a ring of pinned buffers
+    const int slot = c->ring;
+    c->ring = (c->ring + 1) % perrk_ctx::NRING;
+    HIPCHECK(c, hipEventSynchronize(c->ring_ev[slot]));
+    double *hdt = c->h_dt + (size_t)slot * c->n_cases;
+    double *ddt = c->d_dt + (size_t)slot * c->n_cases;
+    std::memcpy(hdt, dt, sizeof(double) * c->n_cases);
+    HIPCHECK(c, hipMemcpyAsync(ddt, hdt, sizeof(double) * c->n_cases, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipEventRecord(c->ring_ev[slot], c->stream));
+    HIPCHECK(c, launch_set_dt(c->d_cs, ddt, c->n_cases, c->stream));
+    if (c->opt.use_graph && !c->profiling) {
+        if (!c->gexec || c->graph_u != u_dev) {
+            if (c->gexec) {
+                (void)hipGraphExecDestroy(c->gexec);
+                c->gexec = nullptr;
+            }
+            if (c->graph) {
+                (void)hipGraphDestroy(c->graph);
+                c->graph = nullptr;
+            }
+            HIPCHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            const int st = enqueue_step(c, static_cast<double *>(u_dev));
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+            if (st != PERRK_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (ec != hipSuccess) return fail(c, PERRK_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+            c->graph = g;
+            HIPCHECK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+            c->graph_u = u_dev;
+        }
+        HIPCHECK(c, hipGraphLaunch(c->gexec, c->stream));
+    } else {
+        c->npev = 0;
+        const int st = enqueue_step(c, static_cast<double *>(u_dev));
+        if (st != PERRK_OK) return st;
+        if (c->profiling) {
+            HIPCHECK(c, hipStreamSynchronize(c->stream));
+            for (int k = 0; k < c->npev / 2; ++k) {
+                float ms = 0.0f;
+                HIPCHECK(c, hipEventElapsedTime(&ms, c->pev[2 * k], c->pev[2 * k + 1]));
+                perrk_kernel_stat &s = c->stats[c->pcls[k]];
+                s.ms += ms;
+                s.bytes += c->pbytes[k];
+                s.launches += 1;
+            }
+            c->npev = 0;
+        }
+    }
+    HIPCHECK(c, hipEventRecord(c->ev_out, c->stream));
+    HIPCHECK(c, hipStreamWaitEvent(c->user_stream, c->ev_out, 0));
+    if (!info) return PERRK_OK;
+    HIPCHECK(c, hipMemcpyAsync(c->h_cs, c->d_cs, sizeof(CaseState) * c->n_cases, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->h_err, c->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    int status = PERRK_OK;
+    for (int i = 0; i < c->n_cases; ++i) {
+        const CaseState &C = c->h_cs[i];
+        perrk_step_info &I = info[i];
+        I.gamma = C.gamma_acc;
+        I.r = C.r;
+        I.dH = C.dH;
+        I.H_delta = C.H_delta;
+        for (int j = 0; j < 3; ++j) I.e[j] = C.e[j];
+        I.t = C.t;
+        I.passes = C.passes;
+        I.flags = C.flags;
+        if (C.flags & PERRK_FLAG_FALLBACK) status = PERRK_WARN_FALLBACK;
+    }
+    if (*c->h_err) {
+        const int e = *c->h_err;
+        HIPCHECK(c, launch_clear_err(c->d_err, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        if (e & 1) return fail(c, PERRK_ENONPHYS, "non-physical state (rho <= 0 or p <= 0) formed; u unmodified");
+        return fail(c, PERRK_ENONFINITE, "non-finite state formed; u unmodified");
+    }
+    return status;
+}
+
+int perrk_entropy(perrk_ctx *c, const void *u_dev, double *H)
+{
+    if (!c || !u_dev || !H) return fail(c, PERRK_EINVAL, "null argument");
+    HIPCHECK(c, hipEventRecord(c->ev_in, c->user_stream));
+    HIPCHECK(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
+    HIPCHECK(c, launch_entropy(c->dim, static_cast<const double *>(u_dev), c->d_elem, c->d_partial, c->d_H,
+                               c->d_case_off, c->n_cases, c->nelem, c->gam, c->d_err, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->h_H, c->d_H, sizeof(double) * c->n_cases, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    std::memcpy(H, c->h_H, sizeof(double) * c->n_cases);
+    return PERRK_OK;
+}
+
+int perrk_rhs(perrk_ctx *c, const void *u_dev, void *k_dev)
+{
+    if (!c || !u_dev || !k_dev) return fail(c, PERRK_EINVAL, "null argument");
+    HIPCHECK(c, hipEventRecord(c->ev_in, c->user_stream));
+    HIPCHECK(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
+    StageArgs a{};
+    a.U = static_cast<const double *>(u_dev);
+    a.K1 = k_dev;
+    a.Kp = k_dev;
+    a.Kout = k_dev;
+    a.elem = c->d_elem;
+    a.active = c->d_active;
+    a.n_active = (int32_t)c->nelem;
+    a.cs = c->d_cs;
+    a.err = c->d_err;
+    a.nelem = c->nelem;
+    a.gam = c->gam;
+    HIPCHECK(c, launch_stage(c->dim, c->precision, c->flux, SK_FIRST, a, c->d_coef, c->cfg, c->stream));
+    HIPCHECK(c, hipEventRecord(c->ev_out, c->stream));
+    HIPCHECK(c, hipStreamWaitEvent(c->user_stream, c->ev_out, 0));
+    return PERRK_OK;
+}
+
+int perrk_get_relaxation_state(perrk_ctx *c, double *gamma_prev, double *h_offset, double *t)
+{
+    if (!c) return PERRK_EINVAL;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipMemcpy(c->h_cs, c->d_cs, sizeof(CaseState) * c->n_cases, hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->n_cases; ++i) {
+        if (gamma_prev) gamma_prev[i] = c->h_cs[i].gamma_prev;
+        if (h_offset) h_offset[i] = c->h_cs[i].offset;
+        if (t) t[i] = c->h_cs[i].t;
+    }
+    return PERRK_OK;
+}
+
+int perrk_set_relaxation_state(perrk_ctx *c, const double *gamma_prev, const double *h_offset, const double *t)
+{
+    if (!c) return PERRK_EINVAL;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipMemcpy(c->h_cs, c->d_cs, sizeof(CaseState) * c->n_cases, hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->n_cases; ++i) {
+        if (gamma_prev) {
+            if (!(gamma_prev[i] > 0.0)) return fail(c, PERRK_EINVAL, "gamma_prev must be > 0");
+            c->h_cs[i].gamma_prev = gamma_prev[i];
+        }
+        if (h_offset) c->h_cs[i].offset = h_offset[i];
+        if (t) c->h_cs[i].t = t[i];
+    }
+    HIPCHECK(c, hipMemcpy(c->d_cs, c->h_cs, sizeof(CaseState) * c->n_cases, hipMemcpyHostToDevice));
+    return PERRK_OK;
+}
+
+int perrk_set_guess_model(perrk_ctx *c, const float *weights, const float *mean, const float *scale)
+{
+    if (!c || !weights || !mean || !scale) return fail(c, PERRK_EINVAL, "null argument");
+    std::vector<float> buf(PERRK_MLP_NW + 18, 0.0f);
+    std::memcpy(buf.data(), weights, sizeof(float) * (PERRK_MLP_NW + 2));
+    std::memcpy(buf.data() + PERRK_MLP_NW, mean, sizeof(float) * 8);
+    std::memcpy(buf.data() + PERRK_MLP_NW + 8, scale, sizeof(float) * 8);
+    // output scale and shift follow the 1377 network weights in `weights`
+    // (weights[1377], weights[1378])
+    buf[PERRK_MLP_NW + 16] = weights[PERRK_MLP_NW];
+    buf[PERRK_MLP_NW + 17] = weights[PERRK_MLP_NW + 1];
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipMemcpy(c->d_mlp, buf.data(), sizeof(float) * buf.size(), hipMemcpyHostToDevice));
+    c->have_mlp = true;
+    if (c->gexec) {  // the captured graph holds the old model pointer state; recapture
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    return PERRK_OK;
+}
+
+int perrk_set_profiling(perrk_ctx *c, int on)
+{
+    if (!c) return PERRK_EINVAL;
+    if (on && !c->pev[0])
+        for (auto &e : c->pev) HIPCHECK(c, hipEventCreate(&e));
+    c->profiling = on != 0;
+    return PERRK_OK;
+}
+
+int perrk_get_kernel_stats(perrk_ctx *c, perrk_kernel_stat *stats, int reset)
+{
+    if (!c || !stats) return PERRK_EINVAL;
+    std::memcpy(stats, c->stats, sizeof c->stats);
+    if (reset) std::memset(c->stats, 0, sizeof c->stats);
+    return PERRK_OK;
+}
+
+int perrk_get_tuning(perrk_ctx *c, char *buf, size_t len)
+{
+    if (!c || !buf || !len) return PERRK_EINVAL;
+    std::snprintf(buf, len, "dim=%d precision=%s flux=%s waves_per_block=%d fast_passes=%d graph=%d", c->dim,
+                  c->precision ? "mixed" : "fp64", c->flux ? "hll" : "ec", c->cfg.epb_mult, c->opt.fast_passes,
+                  c->opt.use_graph);
+    return PERRK_OK;
+}
+
+const char *perrk_last_error(const perrk_ctx *c) { return c ? c->err.c_str() : ""; }
+
+const char *perrk_version(void) { return "perrk 0.1 (gfx950)"; }
+
+void perrk_destroy(perrk_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

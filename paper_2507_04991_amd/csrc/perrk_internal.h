@@ -1,0 +1,110 @@
+// Internal declarations shared by the host side (perrk_host.cpp) and the
+// kernels (perrk_kernels.hip) of libperrk.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "perrk.h"
+
+#define PERRK_MAXR 16        // levels
+#define PERRK_MAXS 64        // stages
+#define PERRK_RED_THREADS 256  // block size of every per-case reduction (fixed: results depend on it)
+#define PERRK_MLP_NW 1377
+
+// Per-element geometry and bookkeeping (natural element order, all cases).
+struct ElemInfo {
+    int32_t nbr[6];     // periodic neighbours: -x, +x, -y, +y, -z, +z (global element index)
+    int32_t level;      // level index r
+    int32_t case_id;    // owning case
+    double metric[3];   // 2 / h_d
+    double jac;         // prod_d h_d / 2
+};
+
+// Relaxation solver states.
+enum {
+    RS_NEWTON = 0,
+    RS_NEWTON_LAST = 1,  // one more evaluation after a step below tol_step
+    RS_BIS_INIT = 2,     // evaluate both bracket ends
+    RS_BIS = 3,
+    RS_DONE = 4,
+    RS_FALLBACK = 5,
+    RS_EVAL1 = 6         // one evaluation at gamma = 1 (bookkeeping of non-relaxed steps)
+};
+
+// Per-case state of the step (device resident, persists across steps).
+struct CaseState {
+    double dt;
+    double gamma;       // current evaluation point
+    double gamma_b;     // second evaluation point (bracket end)
+    double gamma_prev;  // accepted gamma of the previous step
+    double gamma_acc;   // accepted gamma of this step
+    double dH;
+    double r, rp;       // residual and derivative at the last evaluation
+    double lo, hi;      // bisection bracket
+    double offset;      // H(U_n) - H(U_0) (initial anchoring)
+    double H_delta;     // H(U_{n+1}) - H(U_n) at the accepted gamma
+    double e[3];        // stage entropy production of the b_i != 0 stages
+    double t;           // accumulated relaxed time
+    double ghist[3];    // last three accepted gamma - 1 (learned guess features)
+    int32_t state, k, iters, passes, flags, bis_count, widen, trivial;
+};
+
+struct RelaxParams {
+    double tol_r, tol_step, bis_lo, bis_hi;
+    int32_t max_newton, max_bisect, anchor, relax;
+    int32_t guess;
+    int32_t nb;          // number of b != 0 stages (entropy-production slots)
+    double bw[3];        // their weights
+};
+
+// Arguments of one stage launch.  The per-level coefficients of the stage live
+// in device memory: coef[r] multiplies K_1, coef[PERRK_MAXR + r] multiplies K_{i-1}.
+struct StageArgs {
+    const double *U;          // U_n (caller state)
+    const void *K1;           // K_1 (stage storage type)
+    const void *Kp;           // K_{i-1}
+    void *Kout;               // K_i (stage storage type); unused for the last stage
+    double *d_out;            // last stage: d = b_1 K_1 + b_{S-1} K_{S-1} + b_S K_S
+    const ElemInfo *elem;
+    const int32_t *active;    // level-sorted element list; the first n_active are active
+    int32_t n_active;
+    const CaseState *cs;      // dt per case
+    double *ep_partial;       // [nelem] per-element J sum q w.K, or NULL
+    int32_t *err;             // bit 1: non-physical, bit 2: non-finite state formed
+    int64_t nelem;
+    double gam;
+    double b1, bsm1, bs;      // last stage weights
+};
+
+// Stage kernel variants.
+enum { SK_FIRST = 0, SK_MID = 1, SK_LAST = 2 };
+
+struct LaunchCfg {
+    int epb_mult;   // wavefronts (of 64 lanes) per workgroup
+};
+
+// Kernel launchers (perrk_kernels.hip).
+hipError_t launch_stage(int dim, int mixed, int flux, int kind, const StageArgs &a, const double *coef,
+                        LaunchCfg cfg, hipStream_t s);
+hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases,
+                                const double *ep_partial, int64_t nelem, RelaxParams rp,
+                                const float *mlp, hipStream_t s);
+hipError_t launch_relax_pass(int dim, const double *U, const double *d, const ElemInfo *elem,
+                             const CaseState *cs, double *partial, int64_t nelem, double gam,
+                             hipStream_t s);
+hipError_t launch_relax_finalize(CaseState *cs, const int64_t *case_off, int n_cases,
+                                 const double *partial, RelaxParams rp, hipStream_t s);
+hipError_t launch_relax_complete(int dim, const double *U, const double *d, const ElemInfo *elem,
+                                 CaseState *cs, const int64_t *case_off, int n_cases,
+                                 double *partial, int64_t nelem, double gam, RelaxParams rp,
+                                 hipStream_t s);
+hipError_t launch_final_update(int dim, double *U, const double *d, const ElemInfo *elem,
+                               const CaseState *cs, const int32_t *err, int64_t nelem,
+                               hipStream_t s);
+hipError_t launch_entropy(int dim, const double *U, const ElemInfo *elem, double *partial,
+                          double *H_out, const int64_t *case_off, int n_cases, int64_t nelem,
+                          double gam, int32_t *err, hipStream_t s);
+hipError_t launch_init_cases(CaseState *cs, int n_cases, hipStream_t s);
+hipError_t launch_set_dt(CaseState *cs, const double *dt, int n_cases, hipStream_t s);
+hipError_t launch_clear_err(int32_t *err, hipStream_t s);

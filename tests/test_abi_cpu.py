@@ -1,0 +1,75 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and its host-side validation accepts good descriptors and
+rejects bad ones with PERRK_EINVAL."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_04991_amd import perrk as P
+from paper_2507_04991_amd import tableau as T
+from paper_2507_04991_amd import workloads as W
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "perrk.h")
+
+
+def declared_functions():
+    src = open(HDR).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(perrk_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(P.EXPORTS)
+    assert b"gfx950" in L.perrk_version()
+
+
+def desc(**over):
+    f = [W.graded_faces(6, 0, 10), W.graded_faces(4, 0, 10)]
+    tab = dict(T.get_tableau(2, [3, 6]))
+    tab.update(over.pop("tab", {}))
+    lev = over.pop("lev", np.zeros(24, dtype=np.int32))
+    return P.Descriptors([f], [lev], tab, **over)
+
+
+def test_validate_accepts_good_descriptors():
+    st, msg = desc().validate(P.default_options())
+    assert st == P.OK, msg
+    for order, E in [(3, [4, 6, 8, 12]), (4, [5, 9, 14])]:
+        d = desc(tab=T.get_tableau(order, E))
+        assert d.validate()[0] == P.OK
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (lambda t: t["b"].__setitem__(-1, 0.9), "order 1"),
+    (lambda t: t["c"].__setitem__(-1, 0.51), "order 2"),
+    (lambda t: t["a_sub"].__setitem__((0, 2), 0.1), "skipped or first evaluated"),
+    (lambda t: t["b"].__setitem__(2, 0.1), "only b_1"),
+    (lambda t: t["E"].__setitem__(0, 7), "outside"),
+])
+def test_validate_rejects_bad_tableaux(mutate, expect):
+    t = {k: (np.array(v, copy=True) if isinstance(v, (list, np.ndarray)) else v)
+         for k, v in T.get_tableau(2, [3, 6]).items()}
+    mutate(t)
+    st, msg = desc(tab=t).validate()
+    assert st == P.EINVAL and expect in msg, msg
+
+
+def test_validate_rejects_bad_mesh_and_levels():
+    d = desc(lev=np.full(24, 5, dtype=np.int32))
+    assert d.validate()[0] == P.EINVAL
+    d = desc()
+    d.faces[3] = d.faces[2]  # non-increasing faces
+    assert d.validate()[0] == P.EINVAL
+    d = desc(gas_gamma=0.9)
+    assert d.validate()[0] == P.EINVAL
+    d = desc(surface_flux=7)
+    assert d.validate()[0] == P.EINVAL
+    d = desc()
+    assert d.validate(P.default_options(fast_passes=0))[0] == P.EINVAL
+    assert d.validate(P.default_options(bisect_lo=1.1))[0] == P.EINVAL

@@ -1,0 +1,227 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Double precision: U and K agree to 1e-12 relative error of the whole state
+vector (max |a - b| / max |b| over all DOF), entropy sums to 1e-13 relative,
+gamma to 1e-12 absolute, pass counts and solver flags exactly.  Mixed
+precision: bounds derived from single-precision flux arithmetic (see
+test_mixed_precision_bounds).  Random and round-robin level assignments use
+the largest step every assigned level is stable for.
+"""
+import numpy as np
+import pytest
+
+from tests.helpers import field_errors, flux_scale, problem_2d, problem_3d, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_04991_amd import perrk
+    perrk.lib()
+    return perrk
+
+
+def make(P, f, U0, tab, lev, flux=0, precision=0, **opt):
+    d = P.Descriptors([f], [lev], tab, surface_flux=flux, precision=precision)
+    st = P.Stepper(d, P.default_options(**opt))
+    u = torch.tensor(U0, dtype=torch.float64, device="cuda").contiguous()
+    return st, u
+
+
+def omesh(oracle, f, flux=0):
+    return oracle.Mesh(f, surface_flux=flux)
+
+
+def otab(oracle, tab):
+    return oracle.Tableau(tab["order"], tab["c"], tab["b"], tab["a_sub"], tab["E"])
+
+
+CASES_RHS = [("2d", 0), ("2d", 1), ("3d", 0), ("3d", 1)]
+
+
+@pytest.mark.parametrize("dim,flux", CASES_RHS)
+def test_rhs_matches_oracle(P, oracle, dim, flux):
+    f, U0, tab, dt, lev = problem_2d() if dim == "2d" else problem_3d()
+    if dim == "2d":
+        U0 = problem_2d(ic="blast")[1] if flux else U0
+    st, u = make(P, f, U0, tab, lev, flux=flux)
+    K = st.rhs(u).cpu().numpy()
+    Kref = oracle.rhs(omesh(oracle, f, flux), U0)
+    assert rel_err(K, Kref) < 1e-12
+
+
+@pytest.mark.parametrize("order,E,levels", [(2, (3, 6), "cfl"), (2, (3, 6), "random"),
+                                            (3, (4, 6, 8, 12), "cfl"), (3, (4, 6, 8, 12), "roundrobin"),
+                                            (4, (5, 9, 14), "cfl"), (4, (5, 9, 14), "random")])
+def test_steps_match_oracle_2d(P, oracle, order, E, levels):
+    f, U0, tab, dt, lev = problem_2d(order=order, E=E, levels=levels)
+    st, u = make(P, f, U0, tab, lev)
+    m, t = omesh(oracle, f), otab(oracle, tab)
+    Uref = U0.copy()
+    g = 1.0
+    for n in range(5):
+        info = st.step(u, dt)[0]
+        Uref, iref = oracle.step(m, t, lev, Uref, dt, oracle.relax_options(gamma0=g))
+        g = iref["gamma"]
+        assert info["flags"] == iref["flags"] == 0
+        assert info["passes"] == iref["passes"]
+        assert abs(info["gamma"] - iref["gamma"]) <= 1e-12
+        assert abs(info["r"]) <= 1e-12
+        assert abs(info["dH"] - iref["dH"]) <= 1e-13 * max(1.0, abs(iref["dH"]))
+        assert rel_err(u.cpu().numpy(), Uref) < 1e-12, n
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+def test_steps_match_oracle_3d(P, oracle, flux):
+    f, U0, tab, dt, lev = problem_3d()
+    st, u = make(P, f, U0, tab, lev, flux=flux)
+    m, t = omesh(oracle, f, flux), otab(oracle, tab)
+    Uref = U0.copy()
+    g = 1.0
+    for n in range(2):
+        info = st.step(u, dt)[0]
+        Uref, iref = oracle.step(m, t, lev, Uref, dt, oracle.relax_options(gamma0=g))
+        g = iref["gamma"]
+        assert info["passes"] == iref["passes"]
+        assert abs(info["gamma"] - iref["gamma"]) <= 1e-12
+        assert rel_err(u.cpu().numpy(), Uref) < 1e-12
+
+
+def test_entropy_matches_oracle(P, oracle):
+    for f, U0, tab, dt, lev in (problem_2d(ic="random"), problem_3d()):
+        st, u = make(P, f, U0, tab, lev)
+        H = st.entropy(u)[0]
+        Href = oracle.total_entropy(omesh(oracle, f), U0)
+        assert abs(H - Href) <= 1e-13 * max(1.0, abs(Href))
+
+
+def test_graph_and_eager_bitwise_identical_and_deterministic(P):
+    f, U0, tab, dt, lev = problem_2d(order=3, E=(4, 6, 8, 12))
+    outs = []
+    for graph in (1, 0, 1):
+        st, u = make(P, f, U0, tab, lev, use_graph=graph)
+        infos = [st.step(u, dt)[0] for _ in range(3)]
+        outs.append((u.cpu().numpy(), [i["gamma"] for i in infos]))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert o[1] == outs[0][1]
+
+
+def test_async_steps_equal_synchronous_steps(P):
+    f, U0, tab, dt, lev = problem_2d(order=4, E=(5, 9, 14))
+    st, u = make(P, f, U0, tab, lev)
+    for _ in range(4):
+        st.step(u, dt)
+    st2, u2 = make(P, f, U0, tab, lev)
+    for _ in range(4):
+        st2.step(u2, dt, info=False)
+    torch.cuda.synchronize()
+    assert torch.equal(u, u2)
+    assert np.array_equal(st.relaxation_state()[0], st2.relaxation_state()[0])
+
+
+def test_nonphysical_state_rejected_and_u_unmodified(P):
+    f, U0, tab, dt, lev = problem_2d()
+    bad = U0.copy()
+    bad[0, 7, 5] = -0.5
+    st, u = make(P, f, bad, tab, lev)
+    before = u.clone()
+    with pytest.raises(P.PerrkError) as ei:
+        st.step(u, dt)
+    assert ei.value.status == P.ENONPHYS
+    assert torch.equal(u, before)
+    nan = U0.copy()
+    nan[3, 2, 1] = np.nan
+    st, u = make(P, f, nan, tab, lev)
+    with pytest.raises(P.PerrkError) as ei:
+        st.step(u, dt)
+    assert ei.value.status == P.ENONFINITE
+    # the context recovers once the error has been reported
+    u.copy_(torch.tensor(U0, device="cuda"))
+    assert st.step(u, dt)[0]["flags"] == 0
+
+
+def test_solver_fallbacks_match_oracle(P, oracle):
+    f, U0, tab, dt, lev = problem_2d(order=3, E=(4, 6, 8, 12))
+    m, t = omesh(oracle, f), otab(oracle, tab)
+    for opt, oopt in [(dict(max_newton=0), dict(max_newton=0)),
+                      (dict(max_newton=2, tol_r=0.0, max_bisect=5), dict(max_newton=2, tol_r=0.0, max_bisect=5)),
+                      (dict(relax=0), dict(relax=False))]:
+        st, u = make(P, f, U0, tab, lev, **opt)
+        info = st.step(u, dt)[0]
+        Uref, iref = oracle.step(m, t, lev, U0, dt, oracle.relax_options(**oopt))
+        assert info["flags"] == iref["flags"], (opt, info, iref)
+        assert abs(info["gamma"] - iref["gamma"]) <= 1e-12
+        assert rel_err(u.cpu().numpy(), Uref) < 1e-12
+        if opt.get("max_newton") == 0:
+            assert info["passes"] == iref["passes"]
+
+
+def test_free_stream_is_trivial(P):
+    from paper_2507_04991_amd import workloads as W
+    f, _, tab, dt, lev = problem_2d()
+    U0 = W.free_stream_state(W.node_coords(f))
+    st, u = make(P, f, U0, tab, lev)
+    info = st.step(u, dt)[0]
+    assert info["gamma"] == 1.0
+    assert np.abs(u.cpu().numpy() - U0).max() < 1e-13
+
+
+def test_ensemble_matches_oracle_per_case(P, oracle):
+    from paper_2507_04991_amd import workloads as W
+    from paper_2507_04991_amd import tableau as T
+    tab = T.get_tableau(3, [4, 6, 8, 12])
+    rng = np.random.default_rng(5)
+    faces, U0s, levs, dts = [], [], [], []
+    for n in (6, 8, 10):
+        f = [W.graded_faces(n, 0, 10)] * 2
+        U0 = W.vortex_state(W.node_coords(f), strength=rng.uniform(1, 6), centre=tuple(rng.uniform(3, 7, 2)))
+        dt, lev = T.assign_levels(tab, W.element_widths(f).min(axis=1), W.max_wave_speed(U0, 2))
+        faces.append(f), U0s.append(U0), levs.append(lev), dts.append(dt)
+    d = P.Descriptors(faces, levs, tab)
+    st = P.Stepper(d)
+    u = torch.tensor(np.concatenate(U0s, axis=1), device="cuda").contiguous()
+    for _ in range(2):
+        infos = st.step(u, np.array(dts))
+    Ug = u.cpu().numpy()
+    off = 0
+    for k, (f, U0, lev, dt) in enumerate(zip(faces, U0s, levs, dts)):
+        m = oracle.Mesh(f)
+        Uref, _, hist = oracle.run(m, otab(oracle, tab), lev, U0, dt, 2)
+        ne = U0.shape[1]
+        assert rel_err(Ug[:, off:off + ne], Uref) < 1e-12
+        assert abs(infos[k]["gamma"] - hist[-1]["gamma"]) <= 1e-12
+        off += ne
+
+
+@pytest.mark.parametrize("dim", ["2d", "3d"])
+def test_mixed_precision_bounds(P, oracle, dim):
+    """FP32 fluxes with FP32 accumulation: the stage RHS agrees with the FP64
+    oracle to single-precision accuracy (relative 1e-5 of the field scale); after a
+    step the state agrees to 1e-6 relative and gamma stays a certified root."""
+    f, U0, tab, dt, lev = problem_2d() if dim == "2d" else problem_3d()
+    ndim = 2 if dim == "2d" else 3
+    st, u = make(P, f, U0, tab, lev, precision=1)
+    K = st.rhs(u).cpu().numpy().astype(np.float64)
+    Kref = oracle.rhs(omesh(oracle, f), U0)
+    # each node sums O(10) products Dsplit * f and a lifted face flux in FP32 with
+    # |Dsplit| <= 8.1, 1/q = 6, scaled by 2/h: error <= ~32 eps32 (2/h)_max F, with F the
+    # largest physical flux magnitude (the pressure term dominates at low Mach)
+    from paper_2507_04991_amd import workloads as W
+    hmin = W.element_widths(f).min()
+    bound_K = 32 * np.finfo(np.float32).eps * (2.0 / hmin) * flux_scale(U0, ndim)
+    errK = np.abs(K - Kref).max()
+    print("mixed rhs: max abs err", errK, "bound", bound_K, "per field", field_errors(K, Kref))
+    assert errK <= bound_K
+    info = st.step(u, dt)[0]
+    assert abs(info["r"]) <= 1e-12 and info["flags"] == 0
+    Uref, iref = oracle.step(omesh(oracle, f), otab(oracle, tab), lev, U0, dt)
+    errU = np.abs(u.cpu().numpy() - Uref).max()
+    # one step: U_n + gamma dt sum b_i K_i, each K_i within bound_K (plus stage propagation)
+    print("mixed step: max abs err", errU, "bound", 4 * dt * bound_K)
+    assert errU <= 4 * dt * bound_K
