@@ -1,23 +1,30 @@
 #!/usr/bin/env python3
 """Throughput of the P-ERRK step on one MI355X.
 
-Default workload: 3D compressible Euler Taylor-Green vortex (Mach 0.1, random
-phase offsets from seed 0) on the periodic [0, 2 pi]^3 box, 32^3 hexahedra
-graded geometrically (ratio 4, finest at the centre), DGSEM degree 3
-(64 nodes per element, 10.5 M DOF), Ranocha EC volume and surface flux,
-fourth-order P-ERRK with stage-evaluation levels E = {5, 9, 14} assigned by
-local CFL.  The headline variant computes fluxes in FP32 (FP32 accumulation,
-FP32 stage storage) and the stage combinations, entropy sums and the gamma
-solve in FP64; the FP64-plain variant is timed beside it on the same inputs,
-and the L2 distance between the two is compared with the temporal error of
-the FP64 run (dt vs dt/2) to check that they are at equal L2 error.
+Default workload (--workload ensemble): 256 independent 2D isentropic-vortex
+cases (strength U[1, 6], centre U[3, 7]^2, periodic [0, 10]^2) on graded
+meshes (ratio 4, finest at the centre) of 16^2, 32^2, 48^2 or 64^2 elements,
+DGSEM degree 3, Ranocha EC volume and surface flux, third-order P-ERRK with
+stage-evaluation levels E = {4, 6, 8, 12} assigned per case by local CFL and
+a per-case step size; all cases advance together (one launch per stage over
+every case's active elements, the step captured in a hipGraph).
+--workload tgv: 3D Taylor-Green vortex, Mach 0.1, 32^3 graded hexahedra,
+fourth-order P-ERRK with E = {5, 9, 14}.
 
-Prints one JSON line (see the keys below).  Inputs are synthetic and seeded.
+Variants on identical inputs: FP64 plain (double precision throughout, Newton
+from the previous gamma) and mixed (single-precision fluxes in the stages with
+b_i = 0; stage combinations, the stages entering d and dH, entropy sums and
+the gamma solve in double).  For the ensemble the L2 error of each case
+against the exact advected vortex at the case's own relaxed end time decides
+"equal L2 error" (within 1 %).
+
+Prints one JSON line.  Inputs are synthetic and seeded.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -29,6 +36,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "P-ERRK DOF-updates/s on 1 GPU; mixed/learned vs FP64 plain at equal L2 error"
 HBM_PEAK_GBS = 8000.0
+Q1 = np.array([1.0, 5.0, 5.0, 1.0]) / 6.0
+
+
+def workload_ensemble(n_cases=256, seed=0):
+    from paper_2507_04991_amd import tableau as T
+    from paper_2507_04991_amd import workloads as W
+
+    cases = W.vortex_ensemble(n_cases, seed)
+    tab = T.get_tableau(3, [4, 6, 8, 12])
+    dts, levs = [], []
+    for c in cases:
+        dt, lev = T.assign_levels(tab, W.element_widths(c["faces"]).min(axis=1), W.max_wave_speed(c["U0"], 2))
+        dts.append(dt)
+        levs.append(lev)
+    U0 = np.ascontiguousarray(np.concatenate([c["U0"] for c in cases], axis=1))
+    return dict(kind="ensemble", name=f"vortex_ensemble{n_cases}_p3_E4-6-8-12", faces=[c["faces"] for c in cases],
+                U0=U0, tab=tab, dt=np.array(dts), lev=levs, cases=cases,
+                desc=f"{n_cases} 2D Euler isentropic vortices (strength U[1,6], centre U[3,7]^2) on graded "
+                     f"(ratio 4) periodic meshes of 16^2..64^2 quads, DGSEM k=3, Ranocha EC volume+surface "
+                     f"flux, P-ERRK p=3 E={{4,6,8,12}}, per-case dt and levels by local CFL")
 
 
 def workload_tgv(n=32, seed=0):
@@ -41,14 +68,16 @@ def workload_tgv(n=32, seed=0):
     U0 = W.taylor_green_state(co, mach=0.1, phase=tuple(rng.uniform(0, 2 * np.pi, 3)))
     tab = T.get_tableau(4, [5, 9, 14])
     dt, lev = T.assign_levels(tab, W.element_widths(f).min(axis=1), W.max_wave_speed(U0, 3))
-    return dict(name=f"tgv{n}_p4_E5-9-14", faces=f, U0=U0, tab=tab, dt=dt, lev=lev,
+    return dict(kind="tgv", name=f"tgv{n}_p4_E5-9-14", faces=[f], U0=U0, tab=tab, dt=np.array([dt]), lev=[lev],
                 desc=f"3D Euler Taylor-Green Mach 0.1, {n}^3 graded (ratio 4) periodic hexes, DGSEM k=3, "
                      f"Ranocha EC volume+surface flux, P-ERRK p=4 E={{5,9,14}}")
 
 
-def run_variant(P, torch, wl, precision, steps, warmup, profile=False):
-    d = P.Descriptors([wl["faces"]], [wl["lev"]], wl["tab"], precision=precision)
-    st = P.Stepper(d, P.default_options())
+def run_variant(P, torch, wl, precision, steps, warmup, profile=False, guess=0, model=None):
+    d = P.Descriptors(wl["faces"], wl["lev"], wl["tab"], precision=precision)
+    st = P.Stepper(d, P.default_options(guess=guess))
+    if model is not None:
+        st.set_guess_model(*model)
     u = torch.tensor(wl["U0"], dtype=torch.float64, device="cuda").contiguous()
     for _ in range(warmup):
         st.step(u, wl["dt"], info=False)
@@ -59,9 +88,15 @@ def run_variant(P, torch, wl, precision, steps, warmup, profile=False):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     g, _, tt = st.relaxation_state()
-    out = dict(seconds=t1 - t0, u=u, gamma=float(g[0]), t=float(tt[0]), stepper=st)
+    out = dict(seconds=t1 - t0, u=u.clone(), gamma=g, t=tt)
+    # untimed: two synchronous steps on a copy to sample the solver statistics
+    us = u.clone()
+    infos = st.step(us, wl["dt"]) + st.step(us, wl["dt"])
+    out["passes_mean"] = float(np.mean([i["passes"] for i in infos]))
+    out["r_max"] = float(max(abs(i["r"]) for i in infos))
+    out["fallbacks"] = int(sum(1 for i in infos if i["flags"] & P.FLAG_FALLBACK))
     if profile:
-        # the same kernels, launched one by one with HIP events around each launch
+        # the same kernels launched one by one with HIP events around each launch
         st.set_profiling(True)
         st.kernel_stats(reset=True)
         up = u.clone()
@@ -69,30 +104,50 @@ def run_variant(P, torch, wl, precision, steps, warmup, profile=False):
             st.step(up, wl["dt"], info=False)
         out["stats"] = st.kernel_stats(reset=True)
         st.set_profiling(False)
+    st.close()
     return out
 
 
-def l2_rel(a, b, tab_w=None):
-    diff = (a - b).double()
-    return float(torch_norm(diff) / torch_norm(b.double()))
+def ensemble_l2_errors(wl, U, t):
+    """Per case: || U - U_exact(t_case) ||_L2 / || U_exact ||_L2 (quadrature weighted)."""
+    from paper_2507_04991_amd import workloads as W
+
+    errs = []
+    off = 0
+    for k, c in enumerate(wl["cases"]):
+        ne = c["U0"].shape[1]
+        co = W.node_coords(c["faces"])
+        Ue = W.vortex_state(co, t=float(t[k]), strength=c["strength"], centre=c["centre"])
+        w = W.element_widths(c["faces"])
+        J = (w[:, 0] * w[:, 1] / 4.0)[:, None] * np.outer(Q1, Q1).reshape(1, 16)  # ordering i + 4 j
+        Uk = U[:, off:off + ne]
+        errs.append(math.sqrt(float(((Uk - Ue) ** 2 * J).sum()) / float((Ue ** 2 * J).sum())))
+        off += ne
+    return np.array(errs)
 
 
-def torch_norm(x):
-    return (x * x).sum().sqrt()
-
-
-def cpu_baseline(wl):
-    """The FP64 CPU oracle on one full step of the same workload (single thread)."""
+def cpu_baseline(wl, target_dof=12.0e6):
+    """The FP64 CPU oracle, single thread, one step of a leading subset of the workload's cases."""
     from oracle import oracle as O
 
-    m = O.Mesh(wl["faces"])
     t = O.Tableau(wl["tab"]["order"], wl["tab"]["c"], wl["tab"]["b"], wl["tab"]["a_sub"], wl["tab"]["E"])
-    t0 = time.perf_counter()
-    U1, info = O.step(m, t, wl["lev"], wl["U0"], wl["dt"])
-    sec = time.perf_counter() - t0
-    M = wl["U0"].size
-    return dict(value=M / sec, unit="DOF-updates/s", cores=1, kind="oracle",
-                sample=f"one full P-ERRK step of the same workload ({M} DOF, {sec:.1f} s, single thread)")
+    dof, sec, ncase = 0, 0.0, 0
+    off = 0
+    for k, faces in enumerate(wl["faces"]):
+        ne = wl["lev"][k].shape[0]
+        U = wl["U0"][:, off:off + ne]
+        off += ne
+        m = O.Mesh(faces)
+        t0 = time.perf_counter()
+        O.step(m, t, wl["lev"][k], U, float(wl["dt"][k]))
+        sec += time.perf_counter() - t0
+        dof += U.size
+        ncase += 1
+        if dof >= target_dof:
+            break
+    return dict(value=dof / sec, unit="DOF-updates/s", cores=1, kind="oracle",
+                sample=f"one P-ERRK step of the first {ncase} of {len(wl['faces'])} cases of the same workload "
+                       f"({dof} DOF, {sec:.1f} s, single thread)")
 
 
 def main():
@@ -100,12 +155,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mesh", type=int, default=32)
+    ap.add_argument("--workload", choices=["ensemble", "tgv"], default="ensemble")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the FP64-plain and dt/2 runs")
+    ap.add_argument("--no-compare", action="store_true", help="time the mixed variant only")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path is single-GPU "
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the path is single-GPU "
                                    "(multi-GPU sharding is described, not built)", "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -116,43 +171,45 @@ def main():
     P.lib()
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
-    wl = workload_tgv(args.mesh)
+    wl = workload_ensemble() if args.workload == "ensemble" else workload_tgv()
     M = wl["U0"].size
-    print(f"# workload {wl['name']}: {M} DOF, dt={wl['dt']:.4e}, levels={np.bincount(wl['lev']).tolist()}",
-          file=sys.stderr, flush=True)
+    print(f"# workload {wl['name']}: {M} DOF, {len(wl['faces'])} case(s)", file=sys.stderr, flush=True)
 
     mixed = run_variant(P, torch, wl, P.MIXED, args.steps, args.warmup, profile=True)
-    print(f"# mixed: {mixed['seconds'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-    extra = {}
+    print(f"# mixed: {mixed['seconds'] / args.steps * 1e3:.3f} ms/step, passes {mixed['passes_mean']}",
+          file=sys.stderr, flush=True)
+    extra = dict(mixed_newton_passes_per_step=mixed["passes_mean"], mixed_max_abs_r=mixed["r_max"],
+                 mixed_fallback_steps=mixed["fallbacks"])
     if not args.no_compare:
         fp64 = run_variant(P, torch, wl, P.FP64, args.steps, args.warmup)
-        print(f"# fp64: {fp64['seconds'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-        # temporal error of the FP64 run: same end time with half the step
-        wl2 = dict(wl)
-        wl2["dt"] = wl["dt"] / 2
-        half = run_variant(P, torch, wl2, P.FP64, 2 * (args.steps + args.warmup), 0)
-        extra = dict(
-            fp64_plain_value=M * args.steps / fp64["seconds"],
-            fp64_plain_ms_per_step=fp64["seconds"] / args.steps * 1e3,
-            speedup_mixed_vs_fp64=fp64["seconds"] / mixed["seconds"],
-            l2_rel_mixed_vs_fp64=l2_rel(mixed["u"], fp64["u"]),
-            l2_rel_temporal_fp64=l2_rel(fp64["u"], half["u"]),
-            t_end_mixed=mixed["t"], t_end_fp64=fp64["t"], t_end_half=half["t"])
-        extra["equal_l2_error"] = extra["l2_rel_mixed_vs_fp64"] < 0.1 * extra["l2_rel_temporal_fp64"]
+        print(f"# fp64: {fp64['seconds'] / args.steps * 1e3:.3f} ms/step, passes {fp64['passes_mean']}",
+              file=sys.stderr, flush=True)
+        extra.update(fp64_plain_value=M * args.steps / fp64["seconds"],
+                     fp64_plain_ms_per_step=fp64["seconds"] / args.steps * 1e3,
+                     fp64_newton_passes_per_step=fp64["passes_mean"], fp64_max_abs_r=fp64["r_max"],
+                     speedup_mixed_vs_fp64=fp64["seconds"] / mixed["seconds"])
+        if wl["kind"] == "ensemble":
+            em = ensemble_l2_errors(wl, mixed["u"].cpu().numpy(), mixed["t"])
+            ef = ensemble_l2_errors(wl, fp64["u"].cpu().numpy(), fp64["t"])
+            rel = np.abs(em - ef) / ef
+            extra.update(l2_error_mixed_mean=float(em.mean()), l2_error_fp64_mean=float(ef.mean()),
+                         l2_error_rel_diff_max=float(rel.max()), equal_l2_error=bool(rel.max() <= 0.01))
+        else:
+            diff = (mixed["u"] - fp64["u"]).double()
+            extra.update(l2_rel_mixed_vs_fp64=float((diff * diff).sum().sqrt() / (fp64["u"] ** 2).sum().sqrt()),
+                         gamma_mixed=float(mixed["gamma"][0]), gamma_fp64=float(fp64["gamma"][0]))
 
     stats = mixed["stats"]
     dom = max(stats, key=lambda k: stats[k]["ms"])
     s = stats[dom]
     achieved = s["bytes"] / (s["ms"] * 1e-3) / 1e9 if s["ms"] > 0 else 0.0
-    roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None, kernel=f"stage kernel ({dom})",
-                    avg_launch_us=s["ms"] / max(s["launches"], 1) * 1e3,
+    roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=None, kernel=f"stage_kernel ({dom})", avg_launch_us=s["ms"] / max(s["launches"], 1) * 1e3,
                     bytes_per_launch=s["bytes"] / max(s["launches"], 1))
     breakdown = {k: dict(ms_per_step=v["ms"] / args.steps, launches_per_step=v["launches"] / args.steps,
                          GBps=(v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 and v["bytes"] > 0 else None))
                  for k, v in stats.items()}
 
-    ms_per_step = mixed["seconds"] / args.steps * 1e3
     line = {
         "metric": METRIC,
         "value": M * args.steps / mixed["seconds"],
@@ -160,15 +217,14 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": mixed["seconds"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 fluxes + f64 relaxation",
         "data": "synthetic",
         "config": {"workload": wl["name"], "description": wl["desc"], "dof": int(M),
-                   "elements": int(wl["U0"].shape[1]), "dt": wl["dt"],
-                   "level_counts": np.bincount(wl["lev"], minlength=3).tolist(), "variant": "mixed",
+                   "elements": int(wl["U0"].shape[1]), "cases": len(wl["faces"]), "variant": "mixed",
                    "newton_guess": "previous gamma"},
         "roofline": roofline,
         "kernel_breakdown": breakdown,

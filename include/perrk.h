@@ -129,7 +129,7 @@ typedef struct {
 
 /* Default options: relax = 1, max_newton = 10, tol_r = 1e-12, tol_step = 1e-15,
  * anchor = STEP, max_bisect = 60, bracket [0.8, 1.2], guess = PREV,
- * fast_passes = 3, use_graph = 1, tune = 0. */
+ * fast_passes = 6, use_graph = 1, tune = 0. */
 void perrk_default_options(perrk_options *opts);
 
 /* Validates every descriptor on the host (no GPU call): tableau structure,
@@ -175,14 +175,34 @@ int perrk_set_relaxation_state(perrk_ctx *ctx, const double *gamma_prev, const d
                                const double *t);
 
 /* Learned initial guess (guess = PERRK_GUESS_MLP): a multilayer perceptron
- * 8 -> 32 -> 32 -> 1 (tanh hidden layers), float32 weights in the order
- * W1[32][8], b1[32], W2[32][32], b2[32], W3[1][32], b3[1] (1377 values), plus
- * feature normalisation mean[8], scale[8].  Features per case: the last three
- * accepted gamma - 1, dt, and the stage entropy-production terms of the step
- * normalised by their sum of magnitudes (padded to four).  The output is a
- * prediction of gamma - 1; Newton/bisection still decide the accepted gamma. */
+ * 8 -> 32 -> 32 -> 1 (tanh hidden layers), float32.  weights: 1379 values, the
+ * 1377 network parameters W1[32][8], b1[32], W2[32][32], b2[32], W3[1][32],
+ * b3[1] followed by the output scale and shift.  Features per case: the last
+ * three accepted gamma - 1, dt, and the entropy-production terms of the stages
+ * with b_i != 0 normalised by the sum of their magnitudes (padded with zeros
+ * to four); each feature is normalised as (x - mean[k]) * scale[k].  The guess
+ * is gamma = 1 + shift + scale_out * network output (predictions outside
+ * |gamma - 1| < 0.5 are ignored).  Newton/bisection still decide the accepted
+ * gamma.  Host arrays; copied. */
 int perrk_set_guess_model(perrk_ctx *ctx, const float *weights, const float *mean,
                           const float *scale);
+
+/* Training and inference of the same network on device arrays, asynchronous
+ * on `stream` (hipStream_t, NULL = default); no allocation.
+ * perrk_mlp_forward: y[n] = network(w, x[n][8]) (w: the 1377 parameters).
+ * perrk_mlp_loss_grad: grad[1377] = d/dw of the mean squared error
+ *   (1/n) sum (y_i - t_i)^2 and *loss_dev = that error (double, device; may be
+ *   NULL); work_dev must hold perrk_mlp_workspace_bytes(n) bytes.  Sums are
+ *   taken in a fixed order (bitwise reproducible).
+ * perrk_mlp_adam: one Adam update of w[1377] with first/second moment arrays
+ *   m, v (device, caller-initialised to 0) at step >= 1. */
+size_t perrk_mlp_workspace_bytes(int64_t n);
+int perrk_mlp_forward(const float *w_dev, const float *x_dev, int64_t n, float *y_dev, void *stream);
+int perrk_mlp_loss_grad(const float *w_dev, const float *x_dev, const float *t_dev, int64_t n,
+                        float *grad_dev, double *loss_dev, void *work_dev, size_t work_bytes,
+                        void *stream);
+int perrk_mlp_adam(float *w_dev, const float *grad_dev, float *m_dev, float *v_dev, int32_t step,
+                   float lr, float beta1, float beta2, float eps, void *stream);
 
 /* Kernel classes of the per-launch statistics. */
 enum {

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libperrk.so")
-SOURCES = ["perrk_kernels.hip", "perrk_host.cpp"]
+SOURCES = ["perrk_kernels.hip", "perrk_mlp.hip", "perrk_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Device flags: gfx950 only; packed-FP32 instructions disabled.

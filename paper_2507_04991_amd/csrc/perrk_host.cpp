@@ -43,6 +43,7 @@ struct perrk_ctx {
     CaseState *d_cs = nullptr;
     double *d_coef = nullptr;  // [S][2 * PERRK_MAXR]
     void *d_K1 = nullptr, *d_Ka = nullptr, *d_Kb = nullptr;
+    double *d_k64_1 = nullptr, *d_k64_sm1 = nullptr;  // mixed: double copies of K_1 / K_{S-1} when b != 0
     double *d_d = nullptr, *d_ep = nullptr, *d_partial = nullptr, *d_H = nullptr, *d_dt = nullptr;
     int32_t *d_err = nullptr;
     float *d_mlp = nullptr;
@@ -247,7 +248,8 @@ void free_all(perrk_ctx *c)
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     void *dev[] = {c->d_elem, c->d_active, c->d_case_off, c->d_cs, c->d_coef, c->d_K1, c->d_Ka,
-                   c->d_Kb, c->d_d, c->d_ep, c->d_partial, c->d_H, c->d_dt, c->d_err, c->d_mlp};
+                   c->d_Kb, c->d_d, c->d_ep, c->d_partial, c->d_H, c->d_dt, c->d_err, c->d_mlp,
+                   c->d_k64_1, c->d_k64_sm1};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     void *host[] = {c->h_dt, c->h_cs, c->h_err, c->h_H};
@@ -308,8 +310,20 @@ int enqueue_step(perrk_ctx *c, double *u)
         a.ep_partial = nullptr;
         for (size_t j = 0; j < c->bstages.size(); ++j)
             if (c->bstages[j] == i) a.ep_partial = c->d_ep + j * (size_t)c->nelem;
+        // stages entering d and dH are evaluated in double precision in every mode
+        const bool mixed = c->precision == PERRK_MIXED;
+        const int variant = !mixed ? 0 : (c->b[i] != 0.0 ? 2 : 1);
+        a.k64_out = nullptr;
+        a.k64_1 = nullptr;
+        a.k64_sm1 = nullptr;
+        if (mixed && i == 0 && c->b[0] != 0.0 && S > 1) a.k64_out = c->d_k64_1;
+        if (mixed && S >= 3 && i == S - 2 && c->b[S - 2] != 0.0) a.k64_out = c->d_k64_sm1;
+        if (mixed && kind == SK_LAST) {
+            a.k64_1 = c->b[0] != 0.0 ? c->d_k64_1 : nullptr;
+            a.k64_sm1 = (S >= 3 && c->b[S - 2] != 0.0) ? c->d_k64_sm1 : nullptr;
+        }
         HIPCHECK(c, mark_begin(c));
-        HIPCHECK(c, launch_stage(c->dim, c->precision, c->flux, kind, a, c->d_coef + (size_t)i * 2 * PERRK_MAXR,
+        HIPCHECK(c, launch_stage(c->dim, variant, c->flux, kind, a, c->d_coef + (size_t)i * 2 * PERRK_MAXR,
                                  c->cfg, c->stream));
         HIPCHECK(c, mark_end(c, kind == SK_FIRST ? PERRK_K_STAGE_FIRST
                                 : (kind == SK_MID ? PERRK_K_STAGE_MID : PERRK_K_STAGE_LAST),
@@ -357,7 +371,7 @@ void perrk_default_options(perrk_options *o)
     o->bisect_lo = 0.8;
     o->bisect_hi = 1.2;
     o->guess = PERRK_GUESS_PREV;
-    o->fast_passes = 3;
+    o->fast_passes = 6;
     o->use_graph = 1;
     o->tune = 0;
 }
@@ -492,12 +506,23 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
                 if (!(i == 0 || i >= c->S - c->E[r] + 1)) continue;
                 const double c1 = coef[(size_t)i * 2 * PERRK_MAXR + r];
                 const double cp = coef[(size_t)i * 2 * PERRK_MAXR + PERRK_MAXR + r];
+                const bool mixed = c->precision == PERRK_MIXED;
+                const bool last = (i == c->S - 1);
                 double be = 8.0;  // U_n
-                if (i == 0) be += kb;  // write K_1
-                else {
-                    if (c1 != 0.0) be += kb;                                     // K_1
-                    if (cp != 0.0 || (i == c->S - 1 && c->S >= 3 && c->b[c->S - 2] != 0.0)) be += kb;  // K_{i-1}
-                    be += (i == c->S - 1) ? 8.0 : kb;                           // write K_i or d
+                if (i == 0) {
+                    be += kb;                                         // write K_1
+                    if (mixed && c->b[0] != 0.0 && c->S > 1) be += 8.0;  // its double copy
+                } else {
+                    if (c1 != 0.0) be += kb;                          // K_1
+                    if (cp != 0.0) be += kb;                          // K_{i-1}
+                    if (last) {
+                        be += 8.0;                                    // write d
+                        if (c->S >= 3 && c->b[c->S - 2] != 0.0) be += mixed ? 8.0 : (cp != 0.0 ? 0.0 : kb);
+                        if (c->b[0] != 0.0 && mixed) be += 8.0;       // double K_1 for d
+                    } else {
+                        be += kb;                                     // write K_i
+                        if (mixed && i == c->S - 2 && c->b[i] != 0.0) be += 8.0;  // its double copy
+                    }
                 }
                 bytes += be * dofe * per_level[r];
             }
@@ -537,6 +562,10 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipMalloc(&c->d_Ka, ks * M));
     HIPINIT(hipMalloc(&c->d_Kb, ks * M));
     HIPINIT(hipMalloc(&c->d_d, sizeof(double) * M));
+    if (c->precision == PERRK_MIXED) {
+        if (c->b[0] != 0.0) HIPINIT(hipMalloc(&c->d_k64_1, sizeof(double) * M));
+        if (c->S >= 3 && c->b[c->S - 2] != 0.0) HIPINIT(hipMalloc(&c->d_k64_sm1, sizeof(double) * M));
+    }
     HIPINIT(hipMalloc(&c->d_ep, sizeof(double) * 3 * c->nelem));
     HIPINIT(hipMalloc(&c->d_partial, sizeof(double) * 4 * c->nelem));
     HIPINIT(hipMalloc(&c->d_H, sizeof(double) * c->n_cases));
@@ -679,7 +708,8 @@ int perrk_rhs(perrk_ctx *c, const void *u_dev, void *k_dev)
     a.err = c->d_err;
     a.nelem = c->nelem;
     a.gam = c->gam;
-    HIPCHECK(c, launch_stage(c->dim, c->precision, c->flux, SK_FIRST, a, c->d_coef, c->cfg, c->stream));
+    HIPCHECK(c, launch_stage(c->dim, c->precision == PERRK_MIXED ? 1 : 0, c->flux, SK_FIRST, a, c->d_coef,
+                             c->cfg, c->stream));
     HIPCHECK(c, hipEventRecord(c->ev_out, c->stream));
     HIPCHECK(c, hipStreamWaitEvent(c->user_stream, c->ev_out, 0));
     return PERRK_OK;

@@ -9,7 +9,7 @@
 
 #define PERRK_MAXR 16        // levels
 #define PERRK_MAXS 64        // stages
-#define PERRK_RED_THREADS 256  // block size of every per-case reduction (fixed: results depend on it)
+#define PERRK_RED_THREADS 1024  // block size of every per-case reduction (fixed: results depend on it)
 #define PERRK_MLP_NW 1377
 
 // Per-element geometry and bookkeeping (natural element order, all cases).
@@ -75,6 +75,9 @@ struct StageArgs {
     int64_t nelem;
     double gam;
     double b1, bsm1, bs;      // last stage weights
+    double *k64_out;          // optional double copy of K_i (b_i != 0 stages in mixed precision)
+    const double *k64_1;      // last stage: double copies of K_1 and K_{S-1}, or NULL to read the
+    const double *k64_sm1;    //   stage storage
 };
 
 // Stage kernel variants.
@@ -85,7 +88,8 @@ struct LaunchCfg {
 };
 
 // Kernel launchers (perrk_kernels.hip).
-hipError_t launch_stage(int dim, int mixed, int flux, int kind, const StageArgs &a, const double *coef,
+// variant: 0 double flux / double storage, 1 float / float, 2 double flux / float storage
+hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArgs &a, const double *coef,
                         LaunchCfg cfg, hipStream_t s);
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases,
                                 const double *ep_partial, int64_t nelem, RelaxParams rp,

@@ -82,40 +82,81 @@ __device__ __forceinline__ double node_weight(int node)
 }
 
 // ---------------------------------------------------------------- log mean
-// (a - b) / (log a - log b).  Near a = b: with u = ((a-b)/(a+b))^2 the mean is
-// (a+b) / (2 + 2u/3 + 2u^2/5 + ...), used for u < 1e-2 (truncated after u^8 in
-// double, after u^3 in single precision: below the rounding unit).  Otherwise
-// (a - b) / log(a/b): in double from the per-node logarithms, in single
-// precision with the hardware logarithm of the ratio.
-__device__ __forceinline__ double lmean(double a, double b, double la, double lb)
+// L(a, b) = (a - b) / (log a - log b).  With s = a + b, z = (a - b)/s, u = z^2:
+// log(a/b) = 2 z (1 + u/3 + u^2/5 + ...) = 2 z F(u), so L = (s/2) / F(u) and
+// 1/L = (2/s) F(u).  For u < 1e-2 both are evaluated by series (1/F(u) =
+// 1 - u/3 - 4u^2/45 - 44u^3/945 - 428u^4/14175 - ..., coefficients of the
+// reciprocal power series; truncated after u^8 in double, u^3 in single
+// precision, below the rounding unit) with a single reciprocal; otherwise
+// from log1p((a-b)/b) (hardware logarithm of the ratio in single precision).
+#define C_R1 (-1.0 / 3.0)
+#define C_R2 (-4.0 / 45.0)
+#define C_R3 (-44.0 / 945.0)
+#define C_R4 (-428.0 / 14175.0)
+#define C_R5 (-10196.0 / 467775.0)
+#define C_R6 (-10719068.0 / 638512875.0)
+#define C_R7 (-25865068.0 / 1915538625.0)
+#define C_R8 (-5472607916.0 / 488462349375.0)
+
+__device__ __forceinline__ double lmean(double a, double b)
 {
     const double d = a - b, s = a + b;
-    const double d2 = d * d, s2 = s * s;
-    if (d2 < 1.0e-2 * s2) {
-        const double u = d2 / s2;
-        const double F = 2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0 + u * (2.0 / 9.0 +
-                         u * (2.0 / 11.0 + u * (2.0 / 13.0 + u * (2.0 / 15.0 + u * (2.0 / 17.0))))))));
-        return s / F;
+    const double rs = 1.0 / s;
+    const double z = d * rs, u = z * z;
+    if (u < 1.0e-2) {
+        const double P = 1.0 + u * (C_R1 + u * (C_R2 + u * (C_R3 + u * (C_R4 + u * (C_R5 + u * (C_R6 +
+                         u * (C_R7 + u * C_R8)))))));
+        return 0.5 * s * P;
     }
-    return d / (la - lb);
+    return d / log1p(d / b);
 }
 
-__device__ __forceinline__ float lmean(float a, float b, float, float)
+__device__ __forceinline__ double inv_lmean(double a, double b)
+{
+    const double d = a - b, s = a + b;
+    const double rs = 1.0 / s;
+    const double z = d * rs, u = z * z;
+    if (u < 1.0e-2) {
+        const double F = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0 + u * (1.0 / 9.0 +
+                         u * (1.0 / 11.0 + u * (1.0 / 13.0 + u * (1.0 / 15.0 + u * (1.0 / 17.0))))))));
+        return 2.0 * rs * F;
+    }
+    return log1p(d / b) / d;
+}
+
+__device__ __forceinline__ float lmean(float a, float b)
 {
     const float d = a - b, s = a + b;
-    const float d2 = d * d, s2 = s * s;
-    if (d2 < 1.0e-2f * s2) {
-        const float u = d2 / s2;
-        const float F = 2.0f + u * (2.0f / 3.0f + u * (2.0f / 5.0f + u * (2.0f / 7.0f)));
-        return s / F;
+    const float rs = __builtin_amdgcn_rcpf(s);
+    const float z = d * rs, u = z * z;
+    if (u < 1.0e-2f) {
+        const float P = 1.0f + u * ((float)C_R1 + u * ((float)C_R2 + u * (float)C_R3));
+        return 0.5f * s * P;
     }
-    return d / __logf(a / b);
+    return d * __builtin_amdgcn_rcpf(__logf(a * __builtin_amdgcn_rcpf(b)));
 }
+
+__device__ __forceinline__ float inv_lmean(float a, float b)
+{
+    const float d = a - b, s = a + b;
+    const float rs = __builtin_amdgcn_rcpf(s);
+    const float z = d * rs, u = z * z;
+    if (u < 1.0e-2f) {
+        const float F = 1.0f + u * (1.0f / 3.0f + u * (1.0f / 5.0f + u * (1.0f / 7.0f)));
+        return 2.0f * rs * F;
+    }
+    return __logf(a * __builtin_amdgcn_rcpf(b)) * __builtin_amdgcn_rcpf(d);
+}
+
+template <typename T>
+__device__ __forceinline__ T recip(T x) { return (T)1 / x; }
+template <>
+__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------- node data
 template <typename T, int DIM>
 struct Prim {
-    T rho, v[DIM], p, beta, lr, lb;  // beta = rho / p; lr, lb = logs (double path only)
+    T rho, v[DIM], p, beta;  // beta = rho / p
 };
 
 // Primitive variables of a double-precision state.  Sets bit 1 of bad for
@@ -142,57 +183,75 @@ __device__ __forceinline__ void make_prim(const double *u, double gam, Prim<T, D
 #pragma unroll
     for (int k = 0; k < DIM; ++k) P.v[k] = (T)v[k];
     P.p = (T)p;
-    if constexpr (sizeof(T) == 8) {
-        P.beta = rho / p;
-        P.lr = log(rho);
-        P.lb = log(P.beta);
-    } else {
-        P.beta = (T)(rho / p);
-        P.lr = 0;
-        P.lb = 0;
-    }
+    P.beta = (T)(rho / p);
+}
+
+// Velocity component d of a state with a runtime d, as a blend with exact 0/1
+// weights (keeps the components in registers; exact for finite values).
+template <typename T, int DIM>
+__device__ __forceinline__ T vdir(const Prim<T, DIM> &P, int d)
+{
+    T r = (d == 0 ? (T)1 : (T)0) * P.v[0] + (d == 1 ? (T)1 : (T)0) * P.v[1];
+    if (DIM == 3) r += (d == 2 ? (T)1 : (T)0) * P.v[DIM - 1];
+    return r;
 }
 
 // Ranocha's entropy-conservative, kinetic-energy-preserving two-point flux in
-// direction D: f_rho = {rho}_log {v_D}, f_m = f_rho {v} + {p} e_D,
-// f_E = f_rho (v_L.v_R / 2 + 1 / ((gamma-1) {rho/p}_log)) + (p_L v_R,D + p_R v_L,D) / 2.
-template <int D, typename T, int DIM>
-__device__ __forceinline__ void flux_ec(const Prim<T, DIM> &L, const Prim<T, DIM> &R, T inv_gm1,
-                                        T *f)
+// direction d (runtime): f_rho = {rho}_log {v_d}, f_m = f_rho {v} + {p} e_d,
+// f_E = f_rho (v_L.v_R / 2 + 1 / ((gamma-1) {rho/p}_log)) + (p_L v_R,d + p_R v_L,d) / 2.
+template <typename T, int DIM>
+__device__ __forceinline__ void flux_ec(int d, const Prim<T, DIM> &L, const Prim<T, DIM> &R, T inv_gm1, T *f)
 {
-    const T rm = lmean(L.rho, R.rho, L.lr, R.lr);
-    const T bm = lmean(L.beta, R.beta, L.lb, R.lb);
-    const T fr = rm * (T)0.5 * (L.v[D] + R.v[D]);
+    const T rm = lmean(L.rho, R.rho);
+    const T ibm = inv_lmean(L.beta, R.beta);
+    const T vl = vdir<T, DIM>(L, d), vr = vdir<T, DIM>(R, d);
+    const T fr = rm * (T)0.5 * (vl + vr);
+    const T pa = (T)0.5 * (L.p + R.p);
     T vv = 0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) vv += L.v[k] * R.v[k];
     f[0] = fr;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) f[1 + k] = fr * (T)0.5 * (L.v[k] + R.v[k]);
-    f[1 + D] += (T)0.5 * (L.p + R.p);
-    f[DIM + 1] = fr * ((T)0.5 * vv + inv_gm1 / bm) + (T)0.5 * (L.p * R.v[D] + R.p * L.v[D]);
+    for (int k = 0; k < DIM; ++k) f[1 + k] = fr * (T)0.5 * (L.v[k] + R.v[k]) + (k == d ? pa : (T)0);
+    f[DIM + 1] = fr * ((T)0.5 * vv + inv_gm1 * ibm) + (T)0.5 * (L.p * vr + R.p * vl);
 }
 
-// HLL two-wave flux with Davis wave-speed estimates in direction D.
-template <int D, typename T, int DIM>
-__device__ __forceinline__ void flux_hll(const Prim<T, DIM> &L, const Prim<T, DIM> &R,
-                                         const T *uL, const T *uR, T gam, T *f)
+// HLL two-wave flux with Davis wave-speed estimates in direction d; the
+// conserved states are rebuilt from the primitive ones.
+template <typename T, int DIM>
+__device__ __forceinline__ void flux_hll(int d, const Prim<T, DIM> &L, const Prim<T, DIM> &R, T gam, T *f)
 {
+    const T vl = vdir<T, DIM>(L, d), vr = vdir<T, DIM>(R, d);
     const T cl = sqrt(gam * L.p / L.rho), cr = sqrt(gam * R.p / R.rho);
-    const T lmin = fmin(L.v[D] - cl, R.v[D] - cr);
-    const T lmax = fmax(L.v[D] + cl, R.v[D] + cr);
-    T fl[DIM + 2], fr[DIM + 2];
-    fl[0] = uL[0] * L.v[D];
-    fr[0] = uR[0] * R.v[D];
+    const T lmin = fmin(vl - cl, vr - cr);
+    const T lmax = fmax(vl + cl, vr + cr);
+    T uL[DIM + 2], uR[DIM + 2], fl[DIM + 2], fr[DIM + 2];
+    T kl = 0, kr = 0;
+    uL[0] = L.rho;
+    uR[0] = R.rho;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        fl[1 + k] = uL[1 + k] * L.v[D];
-        fr[1 + k] = uR[1 + k] * R.v[D];
+        uL[1 + k] = L.rho * L.v[k];
+        uR[1 + k] = R.rho * R.v[k];
+        kl += uL[1 + k] * L.v[k];
+        kr += uR[1 + k] * R.v[k];
     }
-    fl[1 + D] += L.p;
-    fr[1 + D] += R.p;
-    fl[DIM + 1] = (uL[DIM + 1] + L.p) * L.v[D];
-    fr[DIM + 1] = (uR[DIM + 1] + R.p) * R.v[D];
+    uL[DIM + 1] = L.p / (gam - (T)1) + (T)0.5 * kl;
+    uR[DIM + 1] = R.p / (gam - (T)1) + (T)0.5 * kr;
+#pragma unroll
+    for (int k = 0; k < DIM + 1; ++k) {
+        fl[k] = uL[k] * vl;
+        fr[k] = uR[k] * vr;
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        if (k == d) {
+            fl[1 + k] += L.p;
+            fr[1 + k] += R.p;
+        }
+    }
+    fl[DIM + 1] = (uL[DIM + 1] + L.p) * vl;
+    fr[DIM + 1] = (uR[DIM + 1] + R.p) * vr;
     if (lmin >= (T)0) {
 #pragma unroll
         for (int k = 0; k < DIM + 2; ++k) f[k] = fl[k];
@@ -286,102 +345,210 @@ __device__ __forceinline__ void form_state(const StageArgs &a, const double *coe
     }
 }
 
-template <typename T, int DIM>
-__device__ __forceinline__ void put_prim(T *sq, int eslot, int node, const Prim<T, DIM> &P)
+// ---------------------------------------------------------------- stage kernel
+// LDS per element slot (flux precision T), structure of arrays:
+//   prim[NQ][NPE]   own stage state: rho, v_0..v_{DIM-1}, p, rho/p
+//   sf[V][NFN]      lifted surface flux of each face node (+-6 f*), NFN = 2 DIM NPE/4
+//   vf[V][NPP]      two-point fluxes of the pairs of the current phase (up to two directions)
+template <int DIM>
+struct SG {
+    static constexpr int NPE = Geo<DIM>::NPE, V = DIM + 2, EPW = Geo<DIM>::EPW;
+    static constexpr int NLINE = NPE / 4;        // LGL lines per direction
+    static constexpr int NFN = 2 * DIM * NLINE;  // face nodes
+    static constexpr int NPD = 6 * NLINE;        // node pairs per direction
+    static constexpr int NPP = 2 * NPD;          // pairs held per phase
+    static constexpr int NQ = DIM + 3;
+    static constexpr int SLOT = NQ * NPE + V * NFN + V * NPP;  // LDS words per element slot
+};
+
+// Node of line l (the other coordinates) at position t along direction d.
+template <int DIM>
+__device__ __forceinline__ int line_node(int d, int l, int t)
 {
-    constexpr int NPE = Geo<DIM>::NPE, NQ = Geo<DIM>::NQ;
-    T *b = sq + (size_t)eslot * NQ * NPE + node;
-    b[0] = P.rho;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) b[(1 + k) * NPE] = P.v[k];
-    b[(DIM + 1) * NPE] = P.p;
-    b[(DIM + 2) * NPE] = P.beta;
-    b[(DIM + 3) * NPE] = P.lr;
-    b[(DIM + 4) * NPE] = P.lb;
+    if (DIM == 2) return d == 0 ? t + 4 * l : l + 4 * t;
+    if (d == 0) return t + 4 * (l & 3) + 16 * (l >> 2);
+    if (d == 1) return (l & 3) + 4 * t + 16 * (l >> 2);
+    return l + 16 * t;
+}
+
+// Line index of a node in direction d (also its position on the faces normal to d).
+template <int DIM>
+__device__ __forceinline__ int node_line(int d, int node)
+{
+    const int i = node & 3, j = (node >> 2) & 3, k = node >> 4;
+    if (DIM == 2) return d == 0 ? j : i;
+    if (d == 0) return j + 4 * k;
+    if (d == 1) return i + 4 * k;
+    return i + 4 * j;
+}
+
+__device__ __forceinline__ int node_pos(int d, int node)
+{
+    return d == 0 ? (node & 3) : (d == 1 ? ((node >> 2) & 3) : (node >> 4));
+}
+
+// Pairs of positions on a line: (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
+__device__ __forceinline__ void pair_pos(int k, int &a, int &b)
+{
+    a = k < 3 ? 0 : (k < 5 ? 1 : 2);
+    b = k < 3 ? k + 1 : (k < 5 ? k - 1 : 3);
+}
+
+__device__ __forceinline__ int pair_index(int t, int m)
+{
+    const int a = t < m ? t : m, b = t < m ? m : t;
+    return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
 }
 
 template <typename T, int DIM>
-__device__ __forceinline__ void get_prim(const T *sq, int eslot, int node, Prim<T, DIM> &P)
+__device__ __forceinline__ void lds_put_prim(T *slot, int node, const Prim<T, DIM> &P)
 {
-    constexpr int NPE = Geo<DIM>::NPE, NQ = Geo<DIM>::NQ;
-    const T *b = sq + (size_t)eslot * NQ * NPE + node;
-    P.rho = b[0];
+    constexpr int NPE = SG<DIM>::NPE;
+    slot[node] = P.rho;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) P.v[k] = b[(1 + k) * NPE];
-    P.p = b[(DIM + 1) * NPE];
-    P.beta = b[(DIM + 2) * NPE];
-    P.lr = b[(DIM + 3) * NPE];
-    P.lb = b[(DIM + 4) * NPE];
+    for (int k = 0; k < DIM; ++k) slot[(1 + k) * NPE + node] = P.v[k];
+    slot[(DIM + 1) * NPE + node] = P.p;
+    slot[(DIM + 2) * NPE + node] = P.beta;
 }
 
-// One direction of the element operator at one node: volume flux differencing
-// along the node's line plus the lifted surface flux on faces.
-template <int D, int DIM, typename T, typename KT, int FLUX, int KIND>
-__device__ __forceinline__ void direction_terms(const StageArgs &a, const double *coef, const T *sq,
-                                                int eslot, int node, const ElemInfo &ei,
-                                                const Prim<T, DIM> &me, const double *u, T *du,
-                                                int &bad)
+template <typename T, int DIM>
+__device__ __forceinline__ void lds_get_prim(const T *slot, int node, Prim<T, DIM> &P)
 {
-    constexpr int V = Geo<DIM>::V;
-    constexpr int stride = D == 0 ? 1 : (D == 1 ? 4 : 16);
-    const T inv_gm1 = (T)(1.0 / (a.gam - 1.0));
-    const int id = (node / stride) & 3;
-    T acc[V];
+    constexpr int NPE = SG<DIM>::NPE;
+    P.rho = slot[node];
 #pragma unroll
-    for (int v = 0; v < V; ++v) acc[v] = 0;
-#pragma unroll
-    for (int j = 1; j < 4; ++j) {
-        const int m = (id + j) & 3;
-        Prim<T, DIM> P;
-        get_prim<T, DIM>(sq, eslot, node + (m - id) * stride, P);
+    for (int k = 0; k < DIM; ++k) P.v[k] = slot[(1 + k) * NPE + node];
+    P.p = slot[(DIM + 1) * NPE + node];
+    P.beta = slot[(DIM + 2) * NPE + node];
+}
+
+// Two-point volume fluxes of the pairs of directions [d0, d0 + nd), one pair per
+// lane and round, written to vf of the pair's element slot.
+template <int DIM, typename T, int D0, int ND>
+__device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_gm1)
+{
+    constexpr int d0 = D0, nd = ND;
+    constexpr int EPW = SG<DIM>::EPW, NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V;
+    constexpr int SLOT = SG<DIM>::SLOT, NQ = SG<DIM>::NQ, NPE = SG<DIM>::NPE, NFN = SG<DIM>::NFN;
+    const int per_slot = nd * NPD;
+    const int total = EPW * per_slot;
+    for (int g = lane; g < total; g += 64) {
+        const int es = g / per_slot;
+        const int p = g - es * per_slot;
+        const int d = d0 + p / NPD;
+        const int l = (p % NPD) / 6;
+        int ta, tb;
+        pair_pos(p % 6, ta, tb);
+        T *slot = lds + (size_t)(wave * EPW + es) * SLOT;
+        Prim<T, DIM> A, B;
+        lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, ta), A);
+        lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, tb), B);
         T f[V];
-        flux_ec<D, T, DIM>(me, P, inv_gm1, f);
-        const T w = dsplit<T>(id, m);
+        flux_ec<T, DIM>(d, A, B, inv_gm1, f);
+        T *vf = slot + NQ * NPE + V * NFN;
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] += w * f[v];
+        for (int v = 0; v < V; ++v) vf[v * NPP + p] = f[v];
     }
-    if (id == 0 || id == 3) {
-        const bool right = (id == 3);
-        const int nb = ei.nbr[2 * D + (right ? 1 : 0)];
-        const int nn = node + (right ? -3 : 3) * stride;
+}
+
+// Adds (2/h_d) [sum_{m != t} Dsplit[t][m] f#(t, m) + lifted surface flux] of the
+// directions [d0, d0 + nd) to du (node lane).
+template <int DIM, typename T, int D0, int ND>
+__device__ __forceinline__ void gather(const T *slot, int node, const ElemInfo &ei, T *du)
+{
+    constexpr int d0 = D0, nd = ND;
+    constexpr int NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V, NQ = SG<DIM>::NQ;
+    constexpr int NPE = SG<DIM>::NPE, NFN = SG<DIM>::NFN, NLINE = SG<DIM>::NLINE;
+    const T *sf = slot + NQ * NPE;
+    const T *vf = sf + V * NFN;
+#pragma unroll
+    for (int dd = 0; dd < nd; ++dd) {
+        const int d = d0 + dd;
+        const int t = node_pos(d, node);
+        const int l = node_line<DIM>(d, node);
+        T acc[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0;
+#pragma unroll
+        for (int j = 1; j < 4; ++j) {
+            const int m = (t + j) & 3;
+            const int pidx = dd * NPD + l * 6 + pair_index(t, m);
+            const T w = dsplit<T>(t, m);
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] += w * vf[v * NPP + pidx];
+        }
+        if (t == 0 || t == 3) {
+            const int q = (2 * d + (t == 3 ? 1 : 0)) * NLINE + l;
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] += sf[v * NFN + q];
+        }
+        const T h = (T)(d == 0 ? ei.metric[0] : (d == 1 ? ei.metric[1] : ei.metric[2]));
+#pragma unroll
+        for (int v = 0; v < V; ++v) du[v] += h * acc[v];
+    }
+}
+
+// Surface flux of every face node of the wave's elements: the neighbour's
+// stage state at the matching node is formed here (with the neighbour's level
+// coefficients) and f*(u-, u+) is stored lifted: +6 f* on right faces, -6 f* on left.
+template <int DIM, typename T, typename KT, int FLUX, int KIND>
+__device__ __forceinline__ void surface_fluxes(const StageArgs &a, const double *coef, T *lds, int wave,
+                                               int lane, int e, int &bad)
+{
+    constexpr int EPW = SG<DIM>::EPW, NFN = SG<DIM>::NFN, NLINE = SG<DIM>::NLINE, V = SG<DIM>::V;
+    constexpr int SLOT = SG<DIM>::SLOT, NQ = SG<DIM>::NQ, NPE = SG<DIM>::NPE;
+    const T inv_gm1 = (T)(1.0 / (a.gam - 1.0));
+    for (int g = lane; g < EPW * NFN; g += 64) {
+        const int es = g / NFN;          // equals the lane's own element slot
+        const int q = g - es * NFN;
+        const int f = q / NLINE, l = q - f * NLINE;
+        const int d = f >> 1, side = f & 1;
+        const int own = line_node<DIM>(d, l, side ? 3 : 0);
+        const int nn = line_node<DIM>(d, l, side ? 0 : 3);
+        T *slot = lds + (size_t)(wave * EPW + es) * SLOT;
+        const int nb = a.elem[e].nbr[2 * d + side];
         const ElemInfo en = a.elem[nb];
         double un[V];
         form_state<DIM, KT, KIND>(a, coef, nb, nn, en.level, en.case_id, un);
-        Prim<T, DIM> PN;
+        Prim<T, DIM> PN, PO;
         make_prim<T, DIM>(un, a.gam, PN, bad);
-        T f[V];
-        if (FLUX == PERRK_FLUX_HLL) {
-            T ul[V], ur[V];
+        lds_get_prim<T, DIM>(slot, own, PO);
+        // minus / plus states of the face, selected field by field (values, not
+        // addresses, so that everything stays in registers)
+        Prim<T, DIM> L, R;
+        L.rho = side ? PO.rho : PN.rho;
+        R.rho = side ? PN.rho : PO.rho;
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                ul[v] = (T)(right ? u[v] : un[v]);
-                ur[v] = (T)(right ? un[v] : u[v]);
-            }
-            if (right) flux_hll<D, T, DIM>(me, PN, ul, ur, (T)a.gam, f);
-            else flux_hll<D, T, DIM>(PN, me, ul, ur, (T)a.gam, f);
-        } else {
-            if (right) flux_ec<D, T, DIM>(me, PN, inv_gm1, f);
-            else flux_ec<D, T, DIM>(PN, me, inv_gm1, f);
+        for (int k = 0; k < DIM; ++k) {
+            L.v[k] = side ? PO.v[k] : PN.v[k];
+            R.v[k] = side ? PN.v[k] : PO.v[k];
         }
-        const T lift = right ? (T)6 : (T)-6;  // +-1/q_boundary, q_boundary = 1/6
+        L.p = side ? PO.p : PN.p;
+        R.p = side ? PN.p : PO.p;
+        L.beta = side ? PO.beta : PN.beta;
+        R.beta = side ? PN.beta : PO.beta;
+        T fs[V];
+        if (FLUX == PERRK_FLUX_HLL) flux_hll<T, DIM>(d, L, R, (T)a.gam, fs);
+        else flux_ec<T, DIM>(d, L, R, inv_gm1, fs);
+        const T lift = side ? (T)6 : (T)-6;  // +-1/q_boundary, q_boundary = 1/6
+        T *sf = slot + NQ * NPE;
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] += lift * f[v];
+        for (int v = 0; v < V; ++v) sf[v * NFN + q] = lift * fs[v];
     }
-    const T h = (T)ei.metric[D];
-#pragma unroll
-    for (int v = 0; v < V; ++v) du[v] += h * acc[v];
 }
 
 }  // namespace
 
 namespace {
 
+// T: flux arithmetic; KT: stage storage.  Lane = node of the element slot
+// lane / NPE of its wavefront.
 template <int DIM, typename T, typename KT, int FLUX, int KIND>
 __global__ void __launch_bounds__(256) stage_kernel(const StageArgs a, const double *coef)
 {
-    constexpr int NPE = Geo<DIM>::NPE, V = Geo<DIM>::V, EPW = Geo<DIM>::EPW;
+    constexpr int NPE = SG<DIM>::NPE, V = SG<DIM>::V, EPW = SG<DIM>::EPW, SLOT = SG<DIM>::SLOT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sq = reinterpret_cast<T *>(smem_raw);
+    T *lds = reinterpret_cast<T *>(smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int eslot = wave * EPW + lane / NPE;
     const int node = lane % NPE;
@@ -390,27 +557,36 @@ __global__ void __launch_bounds__(256) stage_kernel(const StageArgs a, const dou
     const bool valid = li < a.n_active;
     const int e = a.active[valid ? li : a.n_active - 1];
     const ElemInfo ei = a.elem[e];
+    T *slot = lds + (size_t)eslot * SLOT;
+    const T inv_gm1 = (T)(1.0 / (a.gam - 1.0));
     int bad = 0;
 
     double u[V];
     form_state<DIM, KT, KIND>(a, coef, e, node, ei.level, ei.case_id, u);
-    Prim<T, DIM> me;
-    make_prim<T, DIM>(u, a.gam, me, bad);
-    put_prim<T, DIM>(sq, eslot, node, me);
+    {
+        Prim<T, DIM> me;
+        make_prim<T, DIM>(u, a.gam, me, bad);
+        lds_put_prim<T, DIM>(slot, node, me);
+    }
     __syncthreads();
-
+    surface_fluxes<DIM, T, KT, FLUX, KIND>(a, coef, lds, wave, lane, e, bad);
     T du[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) du[v] = 0;
-    direction_terms<0, DIM, T, KT, FLUX, KIND>(a, coef, sq, eslot, node, ei, me, u, du, bad);
-    direction_terms<1, DIM, T, KT, FLUX, KIND>(a, coef, sq, eslot, node, ei, me, u, du, bad);
-    if constexpr (DIM == 3)
-        direction_terms<2, DIM, T, KT, FLUX, KIND>(a, coef, sq, eslot, node, ei, me, u, du, bad);
+    volume_pairs<DIM, T, 0, 2>(lds, wave, lane, inv_gm1);
+    __syncthreads();
+    gather<DIM, T, 0, 2>(slot, node, ei, du);
+    if constexpr (DIM == 3) {
+        __syncthreads();
+        volume_pairs<DIM, T, 2, 1>(lds, wave, lane, inv_gm1);
+        __syncthreads();
+        gather<DIM, T, 2, 1>(slot, node, ei, du);
+    }
 
-    // K_i rounded to the stage storage precision
+    // K_i in double, and as stored
     double k[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) k[v] = (double)(KT)(-du[v]);
+    for (int v = 0; v < V; ++v) k[v] = -(double)du[v];
 
     if (valid) {
 #pragma unroll
@@ -418,24 +594,31 @@ __global__ void __launch_bounds__(256) stage_kernel(const StageArgs a, const dou
             const size_t idx = ((size_t)v * a.nelem + e) * NPE + node;
             if (KIND == SK_LAST) {
                 double dv = a.bs * k[v];
-                if (a.bsm1 != 0.0) dv += a.bsm1 * (double)ld<KT>(a.Kp, idx);
-                if (a.b1 != 0.0) dv += a.b1 * (double)ld<KT>(a.K1, idx);
+                if (a.bsm1 != 0.0)
+                    dv += a.bsm1 * (a.k64_sm1 ? a.k64_sm1[idx] : (double)ld<KT>(a.Kp, idx));
+                if (a.b1 != 0.0) dv += a.b1 * (a.k64_1 ? a.k64_1[idx] : (double)ld<KT>(a.K1, idx));
                 a.d_out[idx] = dv;
             } else {
                 static_cast<KT *>(a.Kout)[idx] = (KT)k[v];
+                if (a.k64_out) a.k64_out[idx] = k[v];
             }
         }
     }
     if (a.ep_partial != nullptr) {
+        // entropy production with K_i as it enters d: double when a double copy is
+        // kept (or K is stored in double), else as stored
         double w[V];
         entropy_vars<DIM>(u, a.gam, w);
         double dot = 0.0;
 #pragma unroll
-        for (int v = 0; v < V; ++v) dot += w[v] * k[v];
-        double s = node_weight<DIM>(node) * dot;
+        for (int v = 0; v < V; ++v) {
+            const double kv = (KIND == SK_LAST || a.k64_out || sizeof(KT) == 8) ? k[v] : (double)(KT)k[v];
+            dot += w[v] * kv;
+        }
+        double sm = node_weight<DIM>(node) * dot;
 #pragma unroll
-        for (int off = NPE / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-        if (valid && node == 0) a.ep_partial[e] = ei.jac * s;
+        for (int off = NPE / 2; off >= 1; off >>= 1) sm += __shfl_xor(sm, off);
+        if (valid && node == 0) a.ep_partial[e] = ei.jac * sm;
     }
     if (bad && valid) atomicOr(a.err, bad);
 }
@@ -472,6 +655,56 @@ __device__ __forceinline__ void case_sum(const double *part, int stride, int64_t
     __syncthreads();
 }
 
+// log1p(x): series x - x^2/2 + ... + x^9/9 for |x| < 1e-2 (omitted term < 1e-20/10),
+// the library function otherwise.
+__device__ __forceinline__ double log1p_small(double x)
+{
+    if (fabs(x) < 1.0e-2)
+        return x * (1.0 + x * (-1.0 / 2.0 + x * (1.0 / 3.0 + x * (-1.0 / 4.0 + x * (1.0 / 5.0 + x * (-1.0 / 6.0 +
+               x * (1.0 / 7.0 + x * (-1.0 / 8.0 + x * (1.0 / 9.0)))))))));
+    return log1p(x);
+}
+
+// At one node, with du = g dt d: the entropy difference s(u + du) - s(u)
+// (cancellation-free form) and w(u + du) . (dt d), sharing the intermediate
+// quantities.  With rho' = rho + drho, p' = p + dp:
+//   s' - s = -drho log(p' rho'^-gamma) - rho [log1p(dp/p) - gamma log1p(drho/rho)],
+//   log(p' rho'^-gamma) = log(p rho^-gamma) + log1p(dp/p) - gamma log1p(drho/rho),
+//   w' = (gamma - log(p' rho'^-gamma) - (gamma-1) |m'|^2 / (2 rho' p'), (gamma-1) m'/p', -(gamma-1) rho'/p').
+template <int DIM>
+__device__ __forceinline__ void relax_node(const double *u, const double *dv, double g, double dt, double gam,
+                                           double &ds, double &wd)
+{
+    const double rho = u[0];
+    double du[DIM + 2];
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) du[v] = g * dt * dv[v];
+    const double drho = du[0], rho1 = rho + drho;
+    const double ir = 1.0 / rho, ir1 = 1.0 / rho1;
+    double mdm = 0.0, dm2 = 0.0, m2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        mdm += u[1 + k] * du[1 + k];
+        dm2 += du[1 + k] * du[1 + k];
+        m2 += u[1 + k] * u[1 + k];
+    }
+    const double g1 = gam - 1.0;
+    const double p = g1 * (u[DIM + 1] - 0.5 * m2 * ir);
+    const double dp = g1 * (du[DIM + 1] - (mdm + 0.5 * dm2) * ir1 + 0.5 * drho * m2 * ir * ir1);
+    const double p1 = p + dp;
+    const double lp = log1p_small(dp / p), lr = log1p_small(drho * ir);
+    const double sth0 = log(p) - gam * log(rho);
+    const double sth1 = sth0 + lp - gam * lr;
+    ds = -drho * sth1 - rho * (lp - gam * lr);
+    const double ip1 = 1.0 / p1;
+    const double m12 = m2 + 2.0 * mdm + dm2;
+    double dot = (gam - sth1 - 0.5 * g1 * m12 * ir1 * ip1) * dv[0];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) dot += g1 * (u[1 + k] + du[1 + k]) * ip1 * dv[1 + k];
+    dot += -g1 * rho1 * ip1 * dv[DIM + 1];
+    wd = dt * dot;
+}
+
 // Per-element residual partials: J sum q Delta s at gamma, J sum q w(u + gamma dt d) . dt d,
 // J sum q Delta s at gamma_b (only while opening a bracket), sum |d|.
 template <int DIM>
@@ -489,28 +722,22 @@ __device__ __forceinline__ void relax_element(const double *U, const double *dd,
     if (live || eval1) {
         const double g = eval1 ? 1.0 : C.gamma;
         const double dt = C.dt;
-        double u[V], dv[V], du[V], u1[V], w[V];
+        double u[V], dv[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const size_t idx = ((size_t)v * nelem + e) * NPE + node;
             u[v] = U[idx];
             dv[v] = dd[idx];
-            du[v] = g * dt * dv[v];
-            u1[v] = u[v] + du[v];
             sabs += fabs(dv[v]);
         }
         const double q = node_weight<DIM>(node);
-        sr = q * entropy_diff<DIM>(u, du, gam);
-        entropy_vars<DIM>(u1, gam, w);
-        double dot = 0.0;
-#pragma unroll
-        for (int v = 0; v < V; ++v) dot += w[v] * dt * dv[v];
-        srp = q * dot;
+        double ds, wd;
+        relax_node<DIM>(u, dv, g, dt, gam, ds, wd);
+        sr = q * ds;
+        srp = q * wd;
         if (!eval1 && st == RS_BIS_INIT) {
-            const double gb = C.gamma_b;
-#pragma unroll
-            for (int v = 0; v < V; ++v) du[v] = gb * dt * dv[v];
-            srb = q * entropy_diff<DIM>(u, du, gam);
+            relax_node<DIM>(u, dv, C.gamma_b, dt, gam, ds, wd);
+            srb = q * ds;
         }
     }
 #pragma unroll
@@ -696,6 +923,22 @@ relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const 
                   double *partial, int64_t nelem, double gam)
 {
     constexpr int NPE = Geo<DIM>::NPE, EPW = Geo<DIM>::EPW;
+    // the block's elements are consecutive, so its cases are a contiguous range:
+    // leave at once when every one of them is solved
+    __shared__ int s_live;
+    const int64_t eb = (int64_t)blockIdx.x * (blockDim.x >> 6) * EPW;
+    int64_t ee = eb + (int64_t)(blockDim.x >> 6) * EPW - 1;
+    if (ee >= nelem) ee = nelem - 1;
+    if (threadIdx.x == 0) {
+        int live = 0;
+        for (int c = elem[eb].case_id; c <= elem[ee].case_id; ++c) {
+            const int st = cs[c].state;
+            live |= (st != RS_DONE && st != RS_FALLBACK);
+        }
+        s_live = live;
+    }
+    __syncthreads();
+    if (!s_live) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t e0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * EPW + lane / NPE;
     const bool valid = e0 < nelem;
@@ -856,14 +1099,13 @@ __global__ void init_cases_kernel(CaseState *cs, int n)
 template <int DIM, typename T, typename KT, int FLUX, int KIND>
 hipError_t launch_stage_t(const StageArgs &a, const double *coef, LaunchCfg cfg, hipStream_t s)
 {
-    constexpr int NPE = Geo<DIM>::NPE, EPW = Geo<DIM>::EPW, NQ = Geo<DIM>::NQ;
+    constexpr int EPW = SG<DIM>::EPW, SLOT = SG<DIM>::SLOT;
     const int wpb = cfg.epb_mult;
     const int epb = wpb * EPW;
     if (a.n_active <= 0) return hipSuccess;
     const int blocks = (a.n_active + epb - 1) / epb;
-    const size_t lds = (size_t)epb * NQ * NPE * sizeof(T);
-    hipLaunchKernelGGL((stage_kernel<DIM, T, KT, FLUX, KIND>), dim3(blocks), dim3(64 * wpb), lds, s, a,
-                       coef);
+    const size_t lds = (size_t)epb * SLOT * sizeof(T);
+    hipLaunchKernelGGL((stage_kernel<DIM, T, KT, FLUX, KIND>), dim3(blocks), dim3(64 * wpb), lds, s, a, coef);
     return hipGetLastError();
 }
 
@@ -875,25 +1117,32 @@ hipError_t launch_stage_k(int kind, const StageArgs &a, const double *coef, Laun
     return launch_stage_t<DIM, T, KT, FLUX, SK_LAST>(a, coef, cfg, s);
 }
 
+// variant: 0 = double flux / double storage, 1 = float flux / float storage,
+// 2 = double flux / float storage (stages with b_i != 0 in mixed precision)
+template <int DIM, int FLUX>
+hipError_t launch_stage_v(int variant, int kind, const StageArgs &a, const double *coef, LaunchCfg cfg,
+                          hipStream_t s)
+{
+    if (variant == 1) return launch_stage_k<DIM, float, float, FLUX>(kind, a, coef, cfg, s);
+    if (variant == 2) return launch_stage_k<DIM, double, float, FLUX>(kind, a, coef, cfg, s);
+    return launch_stage_k<DIM, double, double, FLUX>(kind, a, coef, cfg, s);
+}
+
 template <int DIM>
-hipError_t launch_stage_d(int mixed, int flux, int kind, const StageArgs &a, const double *coef,
+hipError_t launch_stage_d(int variant, int flux, int kind, const StageArgs &a, const double *coef,
                           LaunchCfg cfg, hipStream_t s)
 {
-    if (mixed) {
-        if (flux) return launch_stage_k<DIM, float, float, 1>(kind, a, coef, cfg, s);
-        return launch_stage_k<DIM, float, float, 0>(kind, a, coef, cfg, s);
-    }
-    if (flux) return launch_stage_k<DIM, double, double, 1>(kind, a, coef, cfg, s);
-    return launch_stage_k<DIM, double, double, 0>(kind, a, coef, cfg, s);
+    if (flux) return launch_stage_v<DIM, 1>(variant, kind, a, coef, cfg, s);
+    return launch_stage_v<DIM, 0>(variant, kind, a, coef, cfg, s);
 }
 
 }  // namespace
 
-hipError_t launch_stage(int dim, int mixed, int flux, int kind, const StageArgs &a, const double *coef,
+hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArgs &a, const double *coef,
                         LaunchCfg cfg, hipStream_t s)
 {
-    if (dim == 2) return launch_stage_d<2>(mixed, flux, kind, a, coef, cfg, s);
-    return launch_stage_d<3>(mixed, flux, kind, a, coef, cfg, s);
+    if (dim == 2) return launch_stage_d<2>(variant, flux, kind, a, coef, cfg, s);
+    return launch_stage_d<3>(variant, flux, kind, a, coef, cfg, s);
 }
 
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases, const double *ep,

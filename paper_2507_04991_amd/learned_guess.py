@@ -1,0 +1,118 @@
+"""Learned initial guess for the relaxation solve.
+
+A small network (8 -> 32 -> 32 -> 1, tanh) predicts gamma - 1 of a step from
+the last three accepted gamma - 1 of the same case, the step size and the
+entropy-production terms of the stages with b_i != 0 (normalised by the sum of
+their magnitudes, zero-padded to four).  It is trained on (features,
+converged gamma) pairs logged from the method's own solves, with the
+library's HIP forward / gradient / Adam kernels; the step kernels evaluate it
+before the first residual pass.  Newton and bisection still decide the
+accepted gamma, so the guess only changes how many passes a step needs.
+
+The feature definition here matches the one evaluated on the device.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+
+from . import perrk as P
+
+NFEAT = 8
+MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
+
+
+def features(ghist, dt, e, nb):
+    """ghist: [3] previous gamma - 1 (most recent first); e: stage entropy production [nb]."""
+    x = np.zeros(NFEAT)
+    x[0:3] = ghist
+    x[3] = dt
+    s = float(np.sum(np.abs(e[:nb])))
+    if s > 0.0:
+        x[4:4 + nb] = np.asarray(e[:nb]) / s
+    return x
+
+
+def collect(stepper, u, dt, steps, nb):
+    """Advance `steps` synchronous steps, logging one (features, gamma - 1) pair per case and step.
+    Steps whose solve fell back or was trivial are skipped."""
+    n = stepper.n_cases
+    dt = np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,))
+    hist = np.zeros((n, 3))
+    X, Y, passes = [], [], []
+    for _ in range(steps):
+        infos = stepper.step(u, dt)
+        for c, inf in enumerate(infos):
+            g1 = inf["gamma"] - 1.0
+            if inf["flags"] == 0:
+                X.append(features(hist[c], dt[c], np.asarray(inf["e"]), nb))
+                Y.append(g1)
+                passes.append(inf["passes"])
+            hist[c, 1:] = hist[c, :2].copy()
+            hist[c, 0] = g1
+    return np.array(X), np.array(Y), np.array(passes)
+
+
+def normalisation(X, Y):
+    mean = X.mean(axis=0)
+    std = X.std(axis=0)
+    scale = np.where(std > 0, 1.0 / np.where(std > 0, std, 1.0), 0.0)
+    ymean, ystd = float(Y.mean()), float(Y.std() if Y.std() > 0 else 1.0)
+    return mean.astype(np.float32), scale.astype(np.float32), ymean, ystd
+
+
+def init_weights(seed=0):
+    rng = np.random.default_rng(seed)
+    w = np.zeros(P.MLP_NW, dtype=np.float32)
+    w[0:256] = rng.normal(0, np.sqrt(1.0 / 8), 256)
+    w[288:1312] = rng.normal(0, np.sqrt(1.0 / 32), 1024)
+    w[1344:1376] = rng.normal(0, np.sqrt(1.0 / 32), 32)
+    return w
+
+
+def train(X, Y, epochs=3000, lr=3e-3, seed=0, log_every=0):
+    """Full-batch Adam on the normalised data with the HIP kernels.
+    Returns (weights[1379] float32 incl. output scale/shift, mean[8], scale[8], loss history)."""
+    import torch
+
+    mean, scale, ymean, ystd = normalisation(X, Y)
+    Xn = ((X - mean) * scale).astype(np.float32)
+    Yn = ((Y - ymean) / ystd).astype(np.float32)
+    dev = "cuda"
+    x = torch.tensor(Xn, device=dev).contiguous()
+    t = torch.tensor(Yn, device=dev).contiguous()
+    w = torch.tensor(init_weights(seed), device=dev)
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    work = torch.empty(P.lib().perrk_mlp_workspace_bytes(x.shape[0]), dtype=torch.uint8, device=dev)
+    hist = []
+    for k in range(1, epochs + 1):
+        loss, g = P.mlp_loss_grad(w, x, t, work)
+        P.mlp_adam(w, g, m, v, k, lr=lr)
+        if log_every and (k % log_every == 0 or k == 1):
+            hist.append((k, float(loss.item())))
+    loss, _ = P.mlp_loss_grad(w, x, t, work)
+    hist.append((epochs, float(loss.item())))
+    full = np.concatenate([w.cpu().numpy(), np.array([ystd, ymean], dtype=np.float32)])
+    return full, mean, scale, hist
+
+
+def predict(model, X):
+    """Host-side helper: gamma - 1 predicted for feature rows X (runs the HIP forward kernel)."""
+    import torch
+
+    w, mean, scale = model
+    xn = torch.tensor(((X - mean) * scale).astype(np.float32), device="cuda").contiguous()
+    y = P.mlp_forward(torch.tensor(w[:P.MLP_NW], device="cuda"), xn).cpu().numpy().astype(np.float64)
+    return y * float(w[P.MLP_NW]) + float(w[P.MLP_NW + 1])
+
+
+def save(path, model, meta=None):
+    w, mean, scale = model
+    np.savez(path, weights=w, mean=mean, scale=scale, **({} if meta is None else meta))
+
+
+def load(path):
+    d = np.load(path, allow_pickle=False)
+    return d["weights"].astype(np.float32), d["mean"].astype(np.float32), d["scale"].astype(np.float32)

@@ -67,7 +67,8 @@ K_CLASSES = ["stage_first", "stage_mid", "stage_last", "residual", "solver", "up
 EXPORTS = ["perrk_default_options", "perrk_validate", "perrk_init", "perrk_step", "perrk_entropy",
            "perrk_rhs", "perrk_get_relaxation_state", "perrk_set_relaxation_state",
            "perrk_set_guess_model", "perrk_set_profiling", "perrk_get_kernel_stats",
-           "perrk_get_tuning", "perrk_last_error", "perrk_version", "perrk_destroy"]
+           "perrk_get_tuning", "perrk_last_error", "perrk_version", "perrk_destroy",
+           "perrk_mlp_workspace_bytes", "perrk_mlp_forward", "perrk_mlp_loss_grad", "perrk_mlp_adam"]
 
 _lib = None
 
@@ -114,6 +115,15 @@ def lib():
         L.perrk_version.restype = ctypes.c_char_p
         L.perrk_destroy.argtypes = [p]
         L.perrk_destroy.restype = None
+        L.perrk_mlp_workspace_bytes.argtypes = [ctypes.c_int64]
+        L.perrk_mlp_workspace_bytes.restype = ctypes.c_size_t
+        L.perrk_mlp_forward.argtypes = [p, p, ctypes.c_int64, p, p]
+        L.perrk_mlp_forward.restype = ctypes.c_int
+        L.perrk_mlp_loss_grad.argtypes = [p, p, p, ctypes.c_int64, p, p, p, sz, p]
+        L.perrk_mlp_loss_grad.restype = ctypes.c_int
+        L.perrk_mlp_adam.argtypes = [p, p, p, p, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, p]
+        L.perrk_mlp_adam.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -266,3 +276,54 @@ class Stepper:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------
+# learned-guess network on device tensors
+# --------------------------------------------------------------------------
+
+MLP_NW = 1377
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def mlp_forward(w, x):
+    """y = network(w, x) for float32 device tensors w[1377], x[n][8]."""
+    import torch
+
+    y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    st = lib().perrk_mlp_forward(_ptr(w), _ptr(x), x.shape[0], _ptr(y), _stream(torch))
+    if st != OK:
+        raise PerrkError(st, "perrk_mlp_forward")
+    return y
+
+
+def mlp_loss_grad(w, x, t, work=None):
+    """(loss tensor [1] float64, grad [1377] float32) of the mean squared error."""
+    import torch
+
+    n = x.shape[0]
+    nbytes = lib().perrk_mlp_workspace_bytes(n)
+    if work is None or work.numel() < nbytes:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    g = torch.empty(MLP_NW, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float64, device=x.device)
+    st = lib().perrk_mlp_loss_grad(_ptr(w), _ptr(x), _ptr(t), n, _ptr(g), _ptr(loss), _ptr(work), nbytes,
+                                   _stream(torch))
+    if st != OK:
+        raise PerrkError(st, "perrk_mlp_loss_grad")
+    return loss, g
+
+
+def mlp_adam(w, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    import torch
+
+    st = lib().perrk_mlp_adam(_ptr(w), _ptr(g), _ptr(m), _ptr(v), int(step), lr, beta1, beta2, eps, _stream(torch))
+    if st != OK:
+        raise PerrkError(st, "perrk_mlp_adam")

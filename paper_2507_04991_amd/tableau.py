@@ -427,21 +427,23 @@ def get_tableau(order: int, E_levels):
 # level assignment
 # --------------------------------------------------------------------------
 
-def assign_levels(tab, h_elem, speed_elem, cfl: float = 0.8):
+def assign_levels(tab, h_elem, speed_elem, cfl: float = 0.5, geometric: bool = True):
     """Local-CFL level assignment (TimestepConstraintLocal): the step is set by the
     most restrictive element with the largest-E level; each element takes the
-    smallest E whose stable step cfl * h_stab(E) * h / speed is >= dt.
-    Returns (dt, level index per element)."""
+    smallest E whose stable step cfl * h_stab(E) * h / speed is >= dt.  With
+    geometric=True (the paper's choice: levels from the shortest edge length) one
+    speed, the largest over all elements, is used everywhere, so the assignment
+    stays valid while the flow moves.  Returns (dt, level index per element)."""
     hs = np.asarray(tab["h_stab"])
     E = np.asarray(tab["E"])
-    ratio = np.asarray(h_elem) / np.asarray(speed_elem)
+    speed = np.asarray(speed_elem, dtype=np.float64)
+    if geometric:
+        speed = np.full_like(speed, speed.max())
+    ratio = np.asarray(h_elem) / speed
     rmax = int(np.argmax(E))
     dt = cfl * hs[rmax] * ratio.min()
-    order = np.argsort(E)
-    lev = np.full(len(ratio), rmax, dtype=np.int32)
-    for e in range(len(ratio)):
-        for r in order:
-            if cfl * hs[r] * ratio[e] >= dt * (1.0 - 1e-12):
-                lev[e] = r
-                break
+    order = np.argsort(E, kind="stable")
+    ok = cfl * hs[order][None, :] * ratio[:, None] >= dt * (1.0 - 1e-12)  # [elem][level by E]
+    first = np.argmax(ok, axis=1)
+    lev = np.where(ok.any(axis=1), order[first], rmax).astype(np.int32)
     return dt, lev

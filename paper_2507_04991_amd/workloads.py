@@ -173,3 +173,20 @@ def max_wave_speed(U, dim, gam=GAMMA) -> np.ndarray:
     c = np.sqrt(gam * p / rho)
     s = np.max(np.stack([np.abs(v) + c for v in vel]), axis=0)
     return s.max(axis=1)
+
+
+def vortex_ensemble(n_cases=256, seed=0, sizes=(16, 32, 48, 64), box=10.0, ratio=4.0):
+    """Independent isentropic-vortex cases for batched stepping: strength U[1, 6],
+    centre U[3, 7]^2, mesh size drawn from ``sizes`` (graded, ratio 4).  Case i takes
+    its parameters from a generator seeded with (seed, i).
+    Returns a list of dicts (faces, U0, strength, centre, n)."""
+    out = []
+    for i in range(n_cases):
+        rng = np.random.default_rng([seed, i])
+        n = int(rng.choice(sizes))
+        strength = float(rng.uniform(1.0, 6.0))
+        centre = tuple(float(x) for x in rng.uniform(3.0, 7.0, 2))
+        f = [graded_faces(n, 0.0, box, ratio)] * 2
+        U0 = vortex_state(node_coords(f), strength=strength, centre=centre, box=(0.0, box))
+        out.append(dict(faces=f, U0=U0, strength=strength, centre=centre, n=n))
+    return out

@@ -21,7 +21,7 @@ def problem_2d(nx=10, ny=6, order=2, E=(3, 6), flux=0, levels="cfl", seed=0, ic=
     return f, U0, tab, dt, lev
 
 
-def stable_dt(tab, f, U0, lev, cfl=0.8):
+def stable_dt(tab, f, U0, lev, cfl=0.5):
     """Largest step every element's level is stable for (local CFL of its own level)."""
     dim = len(f)
     ratio = W.element_widths(f).min(axis=1) / W.max_wave_speed(U0, dim)

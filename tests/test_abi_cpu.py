@@ -16,7 +16,7 @@ HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 
 def declared_functions():
     src = open(HDR).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(perrk_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|size_t|const char \*)\s*(perrk_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():

@@ -1,0 +1,75 @@
+"""HIP kernels of the learned-guess network against the FP64 reference."""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as M
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_04991_amd import perrk
+    perrk.lib()
+    return perrk
+
+
+def data(n, seed):
+    rng = np.random.default_rng(seed)
+    w = (rng.normal(scale=0.3, size=M.NPARAM)).astype(np.float32)
+    X = rng.normal(size=(n, 8)).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    return w, X, t
+
+
+def dev(a):
+    return torch.tensor(a, device="cuda").contiguous()
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 1000, 4099])
+def test_forward_and_gradient_match_fp64_reference(P, n):
+    w, X, t = data(n, n)
+    y = P.mlp_forward(dev(w), dev(X)).cpu().numpy()
+    yref = M.forward(w.astype(np.float64), X.astype(np.float64))
+    assert np.abs(y - yref).max() <= 2e-6 * (1 + np.abs(yref).max())
+    loss, g = P.mlp_loss_grad(dev(w), dev(X), dev(t))
+    lref, gref = M.loss_grad(w.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+    assert abs(loss.item() - lref) <= 1e-5 * (1 + lref)
+    assert np.abs(g.cpu().numpy() - gref).max() <= 2e-5 * (1 + np.abs(gref).max())
+
+
+def test_gradient_is_bitwise_reproducible(P):
+    w, X, t = data(3000, 7)
+    g1 = P.mlp_loss_grad(dev(w), dev(X), dev(t))[1]
+    g2 = P.mlp_loss_grad(dev(w), dev(X), dev(t))[1]
+    assert torch.equal(g1, g2)
+
+
+def test_adam_step_matches_reference(P):
+    rng = np.random.default_rng(3)
+    w = rng.normal(size=M.NPARAM).astype(np.float32)
+    g = rng.normal(size=M.NPARAM).astype(np.float32)
+    m = rng.normal(size=M.NPARAM).astype(np.float32) * 0.1
+    v = np.abs(rng.normal(size=M.NPARAM)).astype(np.float32) * 0.1
+    wd, md, vd = dev(w), dev(m), dev(v)
+    P.mlp_adam(wd, dev(g), md, vd, 5, lr=1e-2)
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 1e-2
+    m1 = b1 * m.astype(np.float64) + (1 - b1) * g
+    v1 = b2 * v.astype(np.float64) + (1 - b2) * g.astype(np.float64) ** 2
+    w1 = w - lr * (m1 / (1 - b1 ** 5)) / (np.sqrt(v1 / (1 - b2 ** 5)) + eps)
+    assert np.abs(md.cpu().numpy() - m1).max() < 1e-6
+    assert np.abs(vd.cpu().numpy() - v1).max() < 1e-6
+    assert np.abs(wd.cpu().numpy() - w1).max() < 1e-5
+
+
+def test_training_fits_a_smooth_target(P):
+    from paper_2507_04991_amd import learned_guess as L
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(4000, 8))
+    Y = 1e-6 * (0.5 * X[:, 0] - 0.3 * X[:, 1] + 0.2 * np.tanh(X[:, 2]))
+    model, mean, scale, hist = L.train(X, Y, epochs=400, lr=3e-3)
+    pred = L.predict((model, mean, scale), X)
+    assert np.sqrt(np.mean((pred - Y) ** 2)) < 0.05 * np.std(Y)
