@@ -40,37 +40,22 @@ Q1 = np.array([1.0, 5.0, 5.0, 1.0]) / 6.0
 
 
 def workload_ensemble(n_cases=256, seed=0):
-    from paper_2507_04991_amd import tableau as T
-    from paper_2507_04991_amd import workloads as W
+    from paper_2507_04991_amd import problems
 
-    cases = W.vortex_ensemble(n_cases, seed)
-    tab = T.get_tableau(3, [4, 6, 8, 12])
-    dts, levs = [], []
-    for c in cases:
-        dt, lev = T.assign_levels(tab, W.element_widths(c["faces"]).min(axis=1), W.max_wave_speed(c["U0"], 2))
-        dts.append(dt)
-        levs.append(lev)
-    U0 = np.ascontiguousarray(np.concatenate([c["U0"] for c in cases], axis=1))
-    return dict(kind="ensemble", name=f"vortex_ensemble{n_cases}_p3_E4-6-8-12", faces=[c["faces"] for c in cases],
-                U0=U0, tab=tab, dt=np.array(dts), lev=levs, cases=cases,
-                desc=f"{n_cases} 2D Euler isentropic vortices (strength U[1,6], centre U[3,7]^2) on graded "
-                     f"(ratio 4) periodic meshes of 16^2..64^2 quads, DGSEM k=3, Ranocha EC volume+surface "
-                     f"flux, P-ERRK p=3 E={{4,6,8,12}}, per-case dt and levels by local CFL")
+    wl = problems.ensemble(seed, n_cases)
+    wl["desc"] = (f"{n_cases} 2D Euler isentropic vortices (strength U[1,6], centre U[3,7]^2) on graded "
+                  f"(ratio 4) periodic meshes of 16^2..64^2 quads, DGSEM k=3, Ranocha EC volume+surface "
+                  f"flux, P-ERRK p=3 E={{4,6,8,12}}, per-case dt and levels (shortest edge, CFL 0.5)")
+    return wl
 
 
 def workload_tgv(n=32, seed=0):
-    from paper_2507_04991_amd import tableau as T
-    from paper_2507_04991_amd import workloads as W
+    from paper_2507_04991_amd import problems
 
-    f = [W.graded_faces(n, 0.0, 2 * np.pi, 4.0)] * 3
-    co = W.node_coords(f)
-    rng = np.random.default_rng(seed)
-    U0 = W.taylor_green_state(co, mach=0.1, phase=tuple(rng.uniform(0, 2 * np.pi, 3)))
-    tab = T.get_tableau(4, [5, 9, 14])
-    dt, lev = T.assign_levels(tab, W.element_widths(f).min(axis=1), W.max_wave_speed(U0, 3))
-    return dict(kind="tgv", name=f"tgv{n}_p4_E5-9-14", faces=[f], U0=U0, tab=tab, dt=np.array([dt]), lev=[lev],
-                desc=f"3D Euler Taylor-Green Mach 0.1, {n}^3 graded (ratio 4) periodic hexes, DGSEM k=3, "
-                     f"Ranocha EC volume+surface flux, P-ERRK p=4 E={{5,9,14}}")
+    wl = problems.tgv32(seed, n)
+    wl["desc"] = (f"3D Euler Taylor-Green Mach 0.1, {n}^3 graded (ratio 4) periodic hexes, DGSEM k=3, "
+                  f"Ranocha EC volume+surface flux, P-ERRK p=4 E={{5,9,14}}")
+    return wl
 
 
 def run_variant(P, torch, wl, precision, steps, warmup, profile=False, guess=0, model=None):

@@ -33,6 +33,7 @@ struct perrk_ctx {
     RelaxParams rp{};
     LaunchCfg cfg{4};
     std::vector<int32_t> n_active;  // per stage
+    std::vector<int64_t> active_off;  // start of each stage's list in d_active
     // streams and events
     hipStream_t user_stream = nullptr, stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -302,6 +303,7 @@ int enqueue_step(perrk_ctx *c, double *u)
         a.Kp = i >= 2 ? kbuf[(i - 2) % 2] : c->d_K1;
         a.Kout = i == 0 ? c->d_K1 : kbuf[(i - 1) % 2];
         a.d_out = c->d_d;
+        a.active = c->d_active + c->active_off[i];
         a.n_active = c->n_active[i];
         a.b1 = c->b[0];
         a.bsm1 = (S >= 3) ? c->b[S - 2] : 0.0;
@@ -454,21 +456,21 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     }
     c->nelem = (int64_t)elem.size();
 
-    // level-sorted active list: elements of levels with more evaluations first
-    std::vector<int32_t> order(c->nelem);
-    for (int64_t e = 0; e < c->nelem; ++e) order[e] = (int32_t)e;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-        return c->E[elem[x].level] > c->E[elem[y].level];
-    });
+    // active element list of every stage, in natural element order (spatial
+    // neighbours are processed together): stage i evaluates the levels with
+    // E >= S - i + 1, stage 1 every element
+    std::vector<int32_t> order;
     c->n_active.resize(c->S);
+    c->active_off.resize(c->S + 1);
     for (int i = 0; i < c->S; ++i) {
-        int64_t n = 0;
+        c->active_off[i] = (int64_t)order.size();
         for (int64_t e = 0; e < c->nelem; ++e) {
             const int E = c->E[elem[e].level];
-            if (i == 0 || i >= c->S - E + 1) ++n;
+            if (i == 0 || i >= c->S - E + 1) order.push_back((int32_t)e);
         }
-        c->n_active[i] = (int32_t)n;
+        c->n_active[i] = (int32_t)(order.size() - c->active_off[i]);
     }
+    c->active_off[c->S] = (int64_t)order.size();
     // per-stage coefficients (without dt): K_1 and K_{i-1} multipliers per level
     std::vector<double> coef((size_t)c->S * 2 * PERRK_MAXR, 0.0);
     for (int i = 1; i < c->S; ++i)
@@ -554,7 +556,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
     for (auto &e : c->ring_ev) HIPINIT(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPINIT(hipMalloc(&c->d_elem, sizeof(ElemInfo) * c->nelem));
-    HIPINIT(hipMalloc(&c->d_active, sizeof(int32_t) * c->nelem));
+    HIPINIT(hipMalloc(&c->d_active, sizeof(int32_t) * order.size()));
     HIPINIT(hipMalloc(&c->d_case_off, sizeof(int64_t) * (c->n_cases + 1)));
     HIPINIT(hipMalloc(&c->d_cs, sizeof(CaseState) * c->n_cases));
     HIPINIT(hipMalloc(&c->d_coef, sizeof(double) * coef.size()));
@@ -577,7 +579,8 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipHostMalloc(&c->h_err, sizeof(int32_t), 0));
     HIPINIT(hipHostMalloc(&c->h_H, sizeof(double) * c->n_cases, 0));
     HIPINIT(hipMemcpyAsync(c->d_elem, elem.data(), sizeof(ElemInfo) * c->nelem, hipMemcpyHostToDevice, c->stream));
-    HIPINIT(hipMemcpyAsync(c->d_active, order.data(), sizeof(int32_t) * c->nelem, hipMemcpyHostToDevice, c->stream));
+    HIPINIT(hipMemcpyAsync(c->d_active, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice,
+                           c->stream));
     HIPINIT(hipMemcpyAsync(c->d_case_off, c->case_off.data(), sizeof(int64_t) * (c->n_cases + 1),
                            hipMemcpyHostToDevice, c->stream));
     HIPINIT(hipMemcpyAsync(c->d_coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, c->stream));
@@ -637,12 +640,23 @@ int perrk_step(perrk_ctx *c, void *u_dev, const double *dt, perrk_step_info *inf
         if (st != PERRK_OK) return st;
         if (c->profiling) {
             HIPCHECK(c, hipStreamSynchronize(c->stream));
+            // a residual pass moves bytes only for the cases still being solved
+            HIPCHECK(c, hipMemcpy(c->h_cs, c->d_cs, sizeof(CaseState) * c->n_cases, hipMemcpyDeviceToHost));
+            int pass = 0;
             for (int k = 0; k < c->npev / 2; ++k) {
                 float ms = 0.0f;
                 HIPCHECK(c, hipEventElapsedTime(&ms, c->pev[2 * k], c->pev[2 * k + 1]));
+                double bytes = c->pbytes[k];
+                if (c->pcls[k] == PERRK_K_RESIDUAL) {
+                    bytes = 0.0;
+                    for (int cs = 0; cs < c->n_cases; ++cs)
+                        if (c->h_cs[cs].passes > pass)
+                            bytes += 16.0 * c->V * c->npe * (double)(c->case_off[cs + 1] - c->case_off[cs]);
+                    ++pass;
+                }
                 perrk_kernel_stat &s = c->stats[c->pcls[k]];
                 s.ms += ms;
-                s.bytes += c->pbytes[k];
+                s.bytes += bytes;
                 s.launches += 1;
             }
             c->npev = 0;

@@ -161,9 +161,16 @@ struct Prim {
 
 // Primitive variables of a double-precision state.  Sets bit 1 of bad for
 // rho <= 0 or p <= 0, bit 2 for non-finite input.
+template <int DIM>
+__device__ __forceinline__ void make_prim_f32(const double *u, double gam, Prim<float, DIM> &P, int &bad);
+
 template <typename T, int DIM>
 __device__ __forceinline__ void make_prim(const double *u, double gam, Prim<T, DIM> &P, int &bad)
 {
+    if constexpr (sizeof(T) == 4) {
+        make_prim_f32<DIM>(u, gam, P, bad);
+        return;
+    }
     const double rho = u[0];
     const double ir = 1.0 / rho;
     double ke = 0.0;
@@ -184,6 +191,34 @@ __device__ __forceinline__ void make_prim(const double *u, double gam, Prim<T, D
     for (int k = 0; k < DIM; ++k) P.v[k] = (T)v[k];
     P.p = (T)p;
     P.beta = (T)(rho / p);
+}
+
+// Single-precision variant: the state is rounded to single precision first and
+// the primitive variables are formed in single precision (reciprocals by the
+// hardware instruction); admissibility is judged on the double state.
+template <int DIM>
+__device__ __forceinline__ void make_prim_f32(const double *u, double gam, Prim<float, DIM> &P, int &bad)
+{
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < DIM + 2; ++k) fin = fin && isfinite(u[k]);
+    float uf[DIM + 2];
+#pragma unroll
+    for (int k = 0; k < DIM + 2; ++k) uf[k] = (float)u[k];
+    const float rho = uf[0];
+    const float ir = __builtin_amdgcn_rcpf(rho);
+    float ke = 0.0f;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        P.v[k] = uf[1 + k] * ir;
+        ke += uf[1 + k] * P.v[k];
+    }
+    const float p = (float)(gam - 1.0) * (uf[DIM + 1] - 0.5f * ke);
+    if (!fin) bad |= 2;
+    else if (!(rho > 0.0f) || !(p > 0.0f)) bad |= 1;
+    P.rho = rho;
+    P.p = p;
+    P.beta = rho * __builtin_amdgcn_rcpf(p);
 }
 
 // Velocity component d of a state with a runtime d, as a blend with exact 0/1
@@ -343,6 +378,15 @@ __device__ __forceinline__ void form_state(const StageArgs &a, const double *coe
         }
         u[v] = x;
     }
+}
+
+// Workgroups are handed to the 8 XCDs of the device round-robin; renumber them
+// so that each XCD works on one contiguous range of logical blocks (neighbouring
+// elements then share that XCD's L2).
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
 }
 
 // ---------------------------------------------------------------- stage kernel
@@ -553,7 +597,7 @@ __global__ void __launch_bounds__(256) stage_kernel(const StageArgs a, const dou
     const int eslot = wave * EPW + lane / NPE;
     const int node = lane % NPE;
     const int epb = (int)(blockDim.x >> 6) * EPW;
-    const int li = blockIdx.x * epb + eslot;
+    const int li = xcd_block(blockIdx.x, gridDim.x) * epb + eslot;
     const bool valid = li < a.n_active;
     const int e = a.active[valid ? li : a.n_active - 1];
     const ElemInfo ei = a.elem[e];
@@ -926,7 +970,8 @@ relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const 
     // the block's elements are consecutive, so its cases are a contiguous range:
     // leave at once when every one of them is solved
     __shared__ int s_live;
-    const int64_t eb = (int64_t)blockIdx.x * (blockDim.x >> 6) * EPW;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t eb = (int64_t)blk * (blockDim.x >> 6) * EPW;
     int64_t ee = eb + (int64_t)(blockDim.x >> 6) * EPW - 1;
     if (ee >= nelem) ee = nelem - 1;
     if (threadIdx.x == 0) {
@@ -940,7 +985,7 @@ relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const 
     __syncthreads();
     if (!s_live) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t e0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * EPW + lane / NPE;
+    const int64_t e0 = ((int64_t)blk * (blockDim.x >> 6) + wave) * EPW + lane / NPE;
     const bool valid = e0 < nelem;
     relax_element<DIM>(U, d, elem, cs, partial, nelem, gam, valid ? e0 : nelem - 1, lane % NPE, valid);
 }

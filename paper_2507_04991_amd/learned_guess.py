@@ -116,3 +116,70 @@ def save(path, model, meta=None):
 def load(path):
     d = np.load(path, allow_pickle=False)
     return d["weights"].astype(np.float32), d["mean"].astype(np.float32), d["scale"].astype(np.float32)
+
+
+def evaluate(problem, model, steps, precision=P.MIXED):
+    """Mean residual passes per step with the previous-gamma guess and with the
+    learned guess on the same problem (synchronous steps, fresh contexts)."""
+    import torch
+
+    out = {}
+    for name, guess in (("prev", P.GUESS_PREV), ("learned", P.GUESS_MLP)):
+        d = P.Descriptors(problem["faces"], problem["lev"], problem["tab"], precision=precision)
+        st = P.Stepper(d, P.default_options(guess=guess))
+        if guess == P.GUESS_MLP:
+            st.set_guess_model(*model)
+        u = torch.tensor(problem["U0"], device="cuda").contiguous()
+        passes, rmax, flags = [], 0.0, 0
+        for _ in range(steps):
+            infos = st.step(u, problem["dt"])
+            passes += [i["passes"] for i in infos]
+            rmax = max(rmax, max(abs(i["r"]) for i in infos))
+            flags |= int(np.bitwise_or.reduce([i["flags"] for i in infos]))
+        out[name] = dict(passes_mean=float(np.mean(passes)), r_max=rmax, flags=flags,
+                         gamma=st.relaxation_state()[0].tolist())
+        st.close()
+    return out
+
+
+def main(argv=None):
+    """Log training pairs on an ensemble with training seeds, train the network on the
+    GPU and write the model; evaluate on a held-out seed."""
+    import argparse
+    import json
+
+    import torch
+
+    from . import problems
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--train-seed", type=int, default=1000)
+    ap.add_argument("--eval-seed", type=int, default=7)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--epochs", type=int, default=3000)
+    ap.add_argument("--cases", type=int, default=256)
+    args = ap.parse_args(argv)
+    P.lib()
+    prob = problems.ensemble(args.train_seed, args.cases)
+    d = P.Descriptors(prob["faces"], prob["lev"], prob["tab"], precision=P.MIXED)
+    st = P.Stepper(d, P.default_options())
+    u = torch.tensor(prob["U0"], device="cuda").contiguous()
+    X, Y, passes = collect(st, u, prob["dt"], args.steps, nb=int(np.count_nonzero(prob["tab"]["b"])))
+    st.close()
+    print(f"# collected {len(Y)} pairs, gamma-1 in [{Y.min():.3e}, {Y.max():.3e}], passes {passes.mean():.3f}",
+          flush=True)
+    model_w, mean, scale, hist = train(X, Y, epochs=args.epochs, log_every=500)
+    print("# loss", hist, flush=True)
+    model = (model_w, mean, scale)
+    pred = predict(model, X)
+    res = dict(pairs=int(len(Y)), train_rmse=float(np.sqrt(np.mean((pred - Y) ** 2))),
+               prev_rmse=float(np.sqrt(np.mean((X[:, 0] - Y) ** 2))), y_std=float(Y.std()), loss=hist)
+    evalp = problems.ensemble(args.eval_seed, args.cases)
+    res["heldout"] = evaluate(evalp, model, 40)
+    save(args.out, model, dict(train_seed=np.array(args.train_seed), steps=np.array(args.steps)))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,67 @@
+"""Complete synthetic problem set-ups: mesh, initial state, tableau, levels and step.
+
+  vortex16   2D isentropic vortex (strength 5, centre (5, 5)) on [0, 10]^2, 16^2 graded
+             quads, p = 2 with E = {3, 6}.
+  kh64       2D Kelvin-Helmholtz shear layer on [-1, 1]^2, 64^2 graded quads, HLL surface
+             flux, p = 3 with E = {4, 6, 8, 12}; perturbation phase from the seed.
+  tgv32      3D Taylor-Green vortex, Mach 0.1, [0, 2 pi]^3, 32^3 graded hexahedra,
+             p = 4 with E = {5, 9, 14}; phase offsets from the seed.
+  ensemble   256 isentropic vortices (strength U[1, 6], centre U[3, 7]^2) on graded
+             16^2..64^2 meshes, p = 3 with E = {4, 6, 8, 12}, per-case step and levels.
+
+Levels by the shortest edge with one speed per case, step at 0.5 of the optimised
+stable step of the largest level.  Every mesh is graded geometrically (ratio 4,
+finest at the centre).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import tableau as T
+from . import workloads as W
+
+
+def _levels(tab, faces, U, dim):
+    return T.assign_levels(tab, W.element_widths(faces).min(axis=1), W.max_wave_speed(U, dim))
+
+
+def vortex16(seed=0):
+    f = [W.graded_faces(16, 0.0, 10.0)] * 2
+    U0 = W.vortex_state(W.node_coords(f))
+    tab = T.get_tableau(2, [3, 6])
+    dt, lev = _levels(tab, f, U0, 2)
+    return dict(kind="vortex", name="vortex16_p2_E3-6", faces=[f], U0=U0, tab=tab, dt=np.array([dt]), lev=[lev],
+                flux=0, cases=[dict(faces=f, U0=U0, strength=5.0, centre=(5.0, 5.0), n=16)])
+
+
+def kh64(seed=0):
+    f = [W.graded_faces(64, -1.0, 1.0)] * 2
+    rng = np.random.default_rng(seed)
+    U0 = W.kelvin_helmholtz_state(W.node_coords(f), phase=float(rng.uniform(0, 2 * np.pi)))
+    tab = T.get_tableau(3, [4, 6, 8, 12])
+    dt, lev = _levels(tab, f, U0, 2)
+    return dict(kind="kh", name="kh64_p3_E4-6-8-12_hll", faces=[f], U0=U0, tab=tab, dt=np.array([dt]), lev=[lev],
+                flux=1)
+
+
+def tgv32(seed=0, n=32):
+    f = [W.graded_faces(n, 0.0, 2 * np.pi)] * 3
+    rng = np.random.default_rng(seed)
+    U0 = W.taylor_green_state(W.node_coords(f), mach=0.1, phase=tuple(rng.uniform(0, 2 * np.pi, 3)))
+    tab = T.get_tableau(4, [5, 9, 14])
+    dt, lev = _levels(tab, f, U0, 3)
+    return dict(kind="tgv", name=f"tgv{n}_p4_E5-9-14", faces=[f], U0=U0, tab=tab, dt=np.array([dt]), lev=[lev],
+                flux=0)
+
+
+def ensemble(seed=0, n_cases=256):
+    cases = W.vortex_ensemble(n_cases, seed)
+    tab = T.get_tableau(3, [4, 6, 8, 12])
+    dts, levs = [], []
+    for c in cases:
+        dt, lev = _levels(tab, c["faces"], c["U0"], 2)
+        dts.append(dt)
+        levs.append(lev)
+    U0 = np.ascontiguousarray(np.concatenate([c["U0"] for c in cases], axis=1))
+    return dict(kind="ensemble", name=f"vortex_ensemble{n_cases}_p3_E4-6-8-12", faces=[c["faces"] for c in cases],
+                U0=U0, tab=tab, dt=np.array(dts), lev=levs, cases=cases, flux=0)
