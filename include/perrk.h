@@ -61,7 +61,8 @@ enum { PERRK_FLUX_EC = 0, PERRK_FLUX_HLL = 1 };
  * direction d, entropy sums and the gamma solve stay double precision. */
 enum { PERRK_FP64 = 0, PERRK_MIXED = 1 };
 /* STEP: r anchored to H(U_n) (first equality of the discrete entropy balance);
- * INITIAL: to H(U_0) at the time of perrk_init / perrk_reset_relaxation. */
+ * INITIAL: to H(U_0), the entropy of the first state stepped (its offset is
+ * part of the relaxation state, see perrk_get_relaxation_state). */
 enum { PERRK_ANCHOR_STEP = 0, PERRK_ANCHOR_INITIAL = 1 };
 /* Initial guess of the Newton iteration: previous accepted gamma (1 at the
  * first step), or the learned guess (perrk_set_guess_model). */
@@ -76,7 +77,10 @@ enum {
 typedef struct {
     int32_t dim;               /* 2 or 3 */
     int32_t n_cases;           /* >= 1: independent meshes advanced together */
-    const int32_t *n_elem_dir; /* [n_cases][3] elements per direction, >= 2 each (third = 1 in 2D) */
+    const int32_t *n_elem_dir; /* [n_cases][3] elements per direction, >= 2 each (third = 1 in 2D);
+                                  all cases together at most 2^29 nodes (elements x 4^dim), so
+                                  that the byte offset of a node in one field fits in 32 bits:
+                                  33.5 M quadrilaterals or 8.4 M hexahedra */
     const double *face_coords; /* per case, per direction: n+1 increasing face positions, concatenated;
                                   the domain is periodic in every direction */
     double gas_gamma;          /* ratio of specific heats (> 1) */
@@ -113,7 +117,9 @@ typedef struct {
     int32_t fast_passes;       /* residual passes launched without host involvement (1..16);
                                   further passes run in one per-case completion kernel */
     int32_t use_graph;         /* 1: capture each step's launch sequence into a hipGraph */
-    int32_t tune;              /* 1: time the stage-kernel variants once and keep the fastest */
+    int32_t tune;              /* 1: at the first perrk_step, time every stage launch with 1, 2, 4 and 8
+                                  wavefronts per workgroup on the caller's state and keep the fastest
+                                  per stage (results do not depend on the choice); 0: 4 for all */
 } perrk_options;
 
 typedef struct {
@@ -129,7 +135,7 @@ typedef struct {
 
 /* Default options: relax = 1, max_newton = 10, tol_r = 1e-12, tol_step = 1e-15,
  * anchor = STEP, max_bisect = 60, bracket [0.8, 1.2], guess = PREV,
- * fast_passes = 6, use_graph = 1, tune = 0. */
+ * fast_passes = 6, use_graph = 1, tune = 1. */
 void perrk_default_options(perrk_options *opts);
 
 /* Validates every descriptor on the host (no GPU call): tableau structure,
@@ -233,7 +239,12 @@ int perrk_set_profiling(perrk_ctx *ctx, int on);
  * reset != 0, clears them. */
 int perrk_get_kernel_stats(perrk_ctx *ctx, perrk_kernel_stat *stats, int reset);
 
-/* Writes a short text describing the launch configuration in use. */
+/* Copies per-stage statistics (entry i = stage i + 1, n_stages = S entries)
+ * collected while profiling into stats[] and, if reset != 0, clears them. */
+int perrk_get_stage_stats(perrk_ctx *ctx, perrk_kernel_stat *stats, int n_stages, int reset);
+
+/* Writes a short text describing the launch configuration in use (and, after
+ * autotuning, the candidate timings). */
 int perrk_get_tuning(perrk_ctx *ctx, char *buf, size_t len);
 
 /* Last error message of ctx ("" if none). */

@@ -1,5 +1,5 @@
 // perrk_host.cpp -- host side of libperrk: descriptor validation, element
-// tables, level-sorted active lists, buffer planning, the launch sequence of
+// tables, per-stage active lists, buffer planning, the launch sequence of
 // one P-ERRK step (optionally captured once into a hipGraph), and the C ABI
 // declared in include/perrk.h.
 
@@ -31,7 +31,11 @@ struct perrk_ctx {
     std::vector<int> bstages;  // stages with b_i != 0
     perrk_options opt{};
     RelaxParams rp{};
-    LaunchCfg cfg{4};
+    LaunchCfg cfg{4};               // default stage launch shape
+    std::vector<LaunchCfg> scfg;    // per stage (autotuned at the first step when opt.tune)
+    bool tuned = false;
+    std::string tune_report;
+    size_t max_lds = 65536;         // LDS bytes a workgroup may use on this device
     std::vector<int32_t> n_active;  // per stage
     std::vector<int64_t> active_off;  // start of each stage's list in d_active
     // streams and events
@@ -39,7 +43,7 @@ struct perrk_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     // device buffers
     ElemInfo *d_elem = nullptr;
-    int32_t *d_active = nullptr;
+    int2 *d_active = nullptr;  // per stage: {element | level << 28, case}
     int64_t *d_case_off = nullptr;
     CaseState *d_cs = nullptr;
     double *d_coef = nullptr;  // [S][2 * PERRK_MAXR]
@@ -64,7 +68,9 @@ struct perrk_ctx {
     int npev = 0;
     int pcls[NEV / 2] = {};
     double pbytes[NEV / 2] = {};
+    int pstage[NEV / 2] = {};
     perrk_kernel_stat stats[PERRK_K_CLASSES] = {};
+    std::vector<perrk_kernel_stat> sstats;  // per stage
     std::vector<double> stage_bytes;  // algorithmic bytes of each stage launch
     double pass_bytes = 0.0, update_bytes = 0.0;
     // graph
@@ -169,7 +175,9 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
         }
         total += ne;
     }
-    if (total > (int64_t)INT32_MAX / 64) return ck.bad("too many elements (%lld)", (long long)total);
+    const int64_t npe = m->dim == 2 ? 16 : 64;
+    if (total * npe > ((int64_t)1 << 29))
+        return ck.bad("too many nodes (%lld elements x %lld > 2^29)", (long long)total, (long long)npe);
     const int S = t->S, R = t->n_levels;
     if (t->order < 2 || t->order > 4) return ck.bad("order must be 2, 3 or 4");
     if (S < 2 || S > PERRK_MAXS) return ck.bad("S must be in 2..%d", PERRK_MAXS);
@@ -272,64 +280,132 @@ hipError_t mark_begin(perrk_ctx *c)
     return hipEventRecord(c->pev[c->npev], c->stream);
 }
 
-hipError_t mark_end(perrk_ctx *c, int cls, double bytes)
+hipError_t mark_end(perrk_ctx *c, int cls, double bytes, int stage = -1)
 {
     if (!c->profiling || c->npev + 2 > perrk_ctx::NEV) return hipSuccess;
     const hipError_t e = hipEventRecord(c->pev[c->npev + 1], c->stream);
     c->pcls[c->npev / 2] = cls;
+    c->pstage[c->npev / 2] = stage;
     c->pbytes[c->npev / 2] = bytes;
     c->npev += 2;
     return e;
 }
 
-// Enqueues one full step on ctx->stream (no host synchronisation).
-int enqueue_step(perrk_ctx *c, double *u)
+// Arguments, kernel variant and kind of stage i.
+void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int &kind)
 {
-    const size_t ks = c->precision == PERRK_MIXED ? 4 : 8;
-    (void)ks;
-    StageArgs a{};
+    a = StageArgs{};
     a.U = u;
     a.elem = c->d_elem;
-    a.active = c->d_active;
     a.cs = c->d_cs;
     a.err = c->d_err;
     a.nelem = c->nelem;
     a.gam = c->gam;
+    a.gm1 = c->gam - 1.0;
+    a.inv_gm1 = 1.0 / (c->gam - 1.0);
     const int S = c->S;
     void *kbuf[2] = {c->d_Ka, c->d_Kb};
-    for (int i = 0; i < S; ++i) {
-        const int kind = i == 0 ? SK_FIRST : (i == S - 1 ? SK_LAST : SK_MID);
-        a.K1 = c->d_K1;
-        a.Kp = i >= 2 ? kbuf[(i - 2) % 2] : c->d_K1;
-        a.Kout = i == 0 ? c->d_K1 : kbuf[(i - 1) % 2];
-        a.d_out = c->d_d;
-        a.active = c->d_active + c->active_off[i];
-        a.n_active = c->n_active[i];
-        a.b1 = c->b[0];
-        a.bsm1 = (S >= 3) ? c->b[S - 2] : 0.0;
-        a.bs = c->b[S - 1];
-        if (S == 2) a.b1 = c->b[0];
-        a.ep_partial = nullptr;
-        for (size_t j = 0; j < c->bstages.size(); ++j)
-            if (c->bstages[j] == i) a.ep_partial = c->d_ep + j * (size_t)c->nelem;
-        // stages entering d and dH are evaluated in double precision in every mode
-        const bool mixed = c->precision == PERRK_MIXED;
-        const int variant = !mixed ? 0 : (c->b[i] != 0.0 ? 2 : 1);
-        a.k64_out = nullptr;
-        a.k64_1 = nullptr;
-        a.k64_sm1 = nullptr;
-        if (mixed && i == 0 && c->b[0] != 0.0 && S > 1) a.k64_out = c->d_k64_1;
-        if (mixed && S >= 3 && i == S - 2 && c->b[S - 2] != 0.0) a.k64_out = c->d_k64_sm1;
-        if (mixed && kind == SK_LAST) {
-            a.k64_1 = c->b[0] != 0.0 ? c->d_k64_1 : nullptr;
-            a.k64_sm1 = (S >= 3 && c->b[S - 2] != 0.0) ? c->d_k64_sm1 : nullptr;
+    kind = i == 0 ? SK_FIRST : (i == S - 1 ? SK_LAST : SK_MID);
+    a.K1 = c->d_K1;
+    a.Kp = i >= 2 ? kbuf[(i - 2) % 2] : c->d_K1;
+    a.Kout = i == 0 ? c->d_K1 : kbuf[(i - 1) % 2];
+    a.d_out = c->d_d;
+    a.active = c->d_active + c->active_off[i];
+    a.n_active = c->n_active[i];
+    a.b1 = c->b[0];
+    a.bsm1 = (S >= 3) ? c->b[S - 2] : 0.0;
+    a.bs = c->b[S - 1];
+    a.ep_partial = nullptr;
+    for (size_t j = 0; j < c->bstages.size(); ++j)
+        if (c->bstages[j] == i) a.ep_partial = c->d_ep + j * (size_t)c->nelem;
+    // stages entering d and dH are evaluated in double precision in every mode
+    const bool mixed = c->precision == PERRK_MIXED;
+    variant = !mixed ? 0 : (c->b[i] != 0.0 ? 2 : 1);
+    if (mixed && i == 0 && c->b[0] != 0.0 && S > 1) a.k64_out = c->d_k64_1;
+    if (mixed && S >= 3 && i == S - 2 && c->b[S - 2] != 0.0) a.k64_out = c->d_k64_sm1;
+    if (mixed && kind == SK_LAST) {
+        a.k64_1 = c->b[0] != 0.0 ? c->d_k64_1 : nullptr;
+        a.k64_sm1 = (S >= 3 && c->b[S - 2] != 0.0) ? c->d_k64_sm1 : nullptr;
+    }
+}
+
+const double *stage_coef(const perrk_ctx *c, int i) { return c->d_coef + (size_t)i * 2 * PERRK_MAXR; }
+
+// Picks the wavefronts per workgroup of every stage launch by timing the
+// candidates on the caller's state, stage by stage in step order (a stage
+// launch only reads U_n and earlier stage registers, so repeating it is
+// harmless; results do not depend on the launch shape).
+int autotune(perrk_ctx *c, double *u)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHECK(c, hipEventCreate(&e0));
+    HIPCHECK(c, hipEventCreate(&e1));
+    std::string rep = "autotuned waves per workgroup (stage: choice [ms per candidate 1/2/4/8]):";
+    int status = PERRK_OK;
+    for (int i = 0; i < c->S && status == PERRK_OK; ++i) {
+        StageArgs a;
+        int variant = 0, kind = 0;
+        stage_setup(c, u, i, a, variant, kind);
+        int best = c->cfg.epb_mult;
+        float best_ms = 1e30f;
+        char buf[160];
+        std::snprintf(buf, sizeof buf, " %d:", i + 1);
+        std::string line = buf;
+        for (int wpb = 1; wpb <= PERRK_MAX_WPB; wpb *= 2) {
+            if (stage_lds_bytes(c->dim, variant, wpb) > c->max_lds) {
+                line += " -";
+                continue;
+            }
+            const LaunchCfg cf{wpb};
+            if (launch_stage(c->dim, variant, c->flux, kind, a, stage_coef(c, i), cf, c->stream) != hipSuccess) {
+                (void)hipGetLastError();
+                line += " x";
+                continue;
+            }
+            float tmin = 1e30f;
+            for (int r = 0; r < 3; ++r) {
+                if (hipEventRecord(e0, c->stream) != hipSuccess ||
+                    launch_stage(c->dim, variant, c->flux, kind, a, stage_coef(c, i), cf, c->stream) != hipSuccess ||
+                    hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    status = fail(c, PERRK_EHIP, "autotuning launch failed: %s", hipGetErrorString(hipGetLastError()));
+                    break;
+                }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                tmin = std::min(tmin, ms);
+            }
+            if (status != PERRK_OK) break;
+            std::snprintf(buf, sizeof buf, " %.4f", tmin);
+            line += buf;
+            if (tmin < best_ms) {
+                best_ms = tmin;
+                best = wpb;
+            }
         }
+        c->scfg[i].epb_mult = best;
+        std::snprintf(buf, sizeof buf, " -> %d;", best);
+        rep += line + buf;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != PERRK_OK) return status;
+    c->tune_report = rep;
+    c->tuned = true;
+    return PERRK_OK;
+}
+
+// Enqueues one full step on ctx->stream (no host synchronisation).
+int enqueue_step(perrk_ctx *c, double *u)
+{
+    for (int i = 0; i < c->S; ++i) {
+        StageArgs a;
+        int variant = 0, kind = 0;
+        stage_setup(c, u, i, a, variant, kind);
         HIPCHECK(c, mark_begin(c));
-        HIPCHECK(c, launch_stage(c->dim, variant, c->flux, kind, a, c->d_coef + (size_t)i * 2 * PERRK_MAXR,
-                                 c->cfg, c->stream));
+        HIPCHECK(c, launch_stage(c->dim, variant, c->flux, kind, a, stage_coef(c, i), c->scfg[i], c->stream));
         HIPCHECK(c, mark_end(c, kind == SK_FIRST ? PERRK_K_STAGE_FIRST
                                 : (kind == SK_MID ? PERRK_K_STAGE_MID : PERRK_K_STAGE_LAST),
-                             c->stage_bytes[i]));
+                             c->stage_bytes[i], i));
     }
     HIPCHECK(c, mark_begin(c));
     HIPCHECK(c, launch_relax_prepare(c->d_cs, c->d_case_off, c->n_cases, c->d_ep, c->nelem, c->rp,
@@ -375,7 +451,7 @@ void perrk_default_options(perrk_options *o)
     o->guess = PERRK_GUESS_PREV;
     o->fast_passes = 6;
     o->use_graph = 1;
-    o->tune = 0;
+    o->tune = 1;
 }
 
 int perrk_validate(const perrk_mesh_desc *mesh, const perrk_partition_desc *part,
@@ -455,18 +531,26 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
         c->case_off.push_back((int64_t)elem.size());
     }
     c->nelem = (int64_t)elem.size();
+    // the neighbour's level travels with its index (element counts are below 2^28,
+    // levels below 16), so a stage reads a neighbour's stage state without first
+    // loading the neighbour's table entry
+    for (auto &ei : elem)
+        for (int k = 0; k < 6; ++k)
+            ei.nbr[k] = (int32_t)((uint32_t)ei.nbr[k] | ((uint32_t)elem[ei.nbr[k]].level << PERRK_NBR_SHIFT));
 
     // active element list of every stage, in natural element order (spatial
     // neighbours are processed together): stage i evaluates the levels with
     // E >= S - i + 1, stage 1 every element
-    std::vector<int32_t> order;
+    std::vector<int2> order;
     c->n_active.resize(c->S);
     c->active_off.resize(c->S + 1);
     for (int i = 0; i < c->S; ++i) {
         c->active_off[i] = (int64_t)order.size();
         for (int64_t e = 0; e < c->nelem; ++e) {
             const int E = c->E[elem[e].level];
-            if (i == 0 || i >= c->S - E + 1) order.push_back((int32_t)e);
+            if (i == 0 || i >= c->S - E + 1)
+                order.push_back(make_int2((int32_t)((uint32_t)e | ((uint32_t)elem[e].level << PERRK_NBR_SHIFT)),
+                                          elem[e].case_id));
         }
         c->n_active[i] = (int32_t)(order.size() - c->active_off[i]);
     }
@@ -494,6 +578,8 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     for (int j = 0; j < rp.nb && j < 3; ++j) rp.bw[j] = c->b[c->bstages[j]];
     c->rp = rp;
     c->cfg.epb_mult = 4;
+    c->scfg.assign(c->S, c->cfg);
+    c->sstats.assign(c->S, perrk_kernel_stat{});
 
     // algorithmic (compulsory) bytes of each launch
     {
@@ -551,12 +637,18 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
         }                                                                                       \
     } while (0)
     c->user_stream = (hipStream_t)stream;
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+            c->max_lds = (size_t)lds;
+    }
     HIPINIT(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIPINIT(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIPINIT(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
     for (auto &e : c->ring_ev) HIPINIT(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPINIT(hipMalloc(&c->d_elem, sizeof(ElemInfo) * c->nelem));
-    HIPINIT(hipMalloc(&c->d_active, sizeof(int32_t) * order.size()));
+    HIPINIT(hipMalloc(&c->d_active, sizeof(int2) * order.size()));
     HIPINIT(hipMalloc(&c->d_case_off, sizeof(int64_t) * (c->n_cases + 1)));
     HIPINIT(hipMalloc(&c->d_cs, sizeof(CaseState) * c->n_cases));
     HIPINIT(hipMalloc(&c->d_coef, sizeof(double) * coef.size()));
@@ -579,7 +671,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipHostMalloc(&c->h_err, sizeof(int32_t), 0));
     HIPINIT(hipHostMalloc(&c->h_H, sizeof(double) * c->n_cases, 0));
     HIPINIT(hipMemcpyAsync(c->d_elem, elem.data(), sizeof(ElemInfo) * c->nelem, hipMemcpyHostToDevice, c->stream));
-    HIPINIT(hipMemcpyAsync(c->d_active, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice,
+    HIPINIT(hipMemcpyAsync(c->d_active, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice,
                            c->stream));
     HIPINIT(hipMemcpyAsync(c->d_case_off, c->case_off.data(), sizeof(int64_t) * (c->n_cases + 1),
                            hipMemcpyHostToDevice, c->stream));
@@ -610,6 +702,10 @@ int perrk_step(perrk_ctx *c, void *u_dev, const double *dt, perrk_step_info *inf
     HIPCHECK(c, hipMemcpyAsync(ddt, hdt, sizeof(double) * c->n_cases, hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipEventRecord(c->ring_ev[slot], c->stream));
     HIPCHECK(c, launch_set_dt(c->d_cs, ddt, c->n_cases, c->stream));
+    if (c->opt.tune && !c->tuned) {
+        const int st = autotune(c, static_cast<double *>(u_dev));
+        if (st != PERRK_OK) return st;
+    }
     if (c->opt.use_graph && !c->profiling) {
         if (!c->gexec || c->graph_u != u_dev) {
             if (c->gexec) {
@@ -658,6 +754,12 @@ int perrk_step(perrk_ctx *c, void *u_dev, const double *dt, perrk_step_info *inf
                 s.ms += ms;
                 s.bytes += bytes;
                 s.launches += 1;
+                if (c->pstage[k] >= 0) {
+                    perrk_kernel_stat &q = c->sstats[c->pstage[k]];
+                    q.ms += ms;
+                    q.bytes += bytes;
+                    q.launches += 1;
+                }
             }
             c->npev = 0;
         }
@@ -722,6 +824,8 @@ int perrk_rhs(perrk_ctx *c, const void *u_dev, void *k_dev)
     a.err = c->d_err;
     a.nelem = c->nelem;
     a.gam = c->gam;
+    a.gm1 = c->gam - 1.0;
+    a.inv_gm1 = 1.0 / (c->gam - 1.0);
     HIPCHECK(c, launch_stage(c->dim, c->precision == PERRK_MIXED ? 1 : 0, c->flux, SK_FIRST, a, c->d_coef,
                              c->cfg, c->stream));
     HIPCHECK(c, hipEventRecord(c->ev_out, c->stream));
@@ -797,12 +901,22 @@ int perrk_get_kernel_stats(perrk_ctx *c, perrk_kernel_stat *stats, int reset)
     return PERRK_OK;
 }
 
+int perrk_get_stage_stats(perrk_ctx *c, perrk_kernel_stat *stats, int n_stages, int reset)
+{
+    if (!c || !stats || n_stages != c->S) return PERRK_EINVAL;
+    std::memcpy(stats, c->sstats.data(), sizeof(perrk_kernel_stat) * c->S);
+    if (reset) c->sstats.assign(c->S, perrk_kernel_stat{});
+    return PERRK_OK;
+}
+
 int perrk_get_tuning(perrk_ctx *c, char *buf, size_t len)
 {
     if (!c || !buf || !len) return PERRK_EINVAL;
-    std::snprintf(buf, len, "dim=%d precision=%s flux=%s waves_per_block=%d fast_passes=%d graph=%d", c->dim,
-                  c->precision ? "mixed" : "fp64", c->flux ? "hll" : "ec", c->cfg.epb_mult, c->opt.fast_passes,
-                  c->opt.use_graph);
+    std::string w;
+    for (const LaunchCfg &x : c->scfg) w += (w.empty() ? "" : ",") + std::to_string(x.epb_mult);
+    std::snprintf(buf, len, "dim=%d precision=%s flux=%s stage_waves_per_workgroup=[%s] fast_passes=%d graph=%d %s",
+                  c->dim, c->precision ? "mixed" : "fp64", c->flux ? "hll" : "ec", w.c_str(), c->opt.fast_passes,
+                  c->opt.use_graph, c->tuned ? c->tune_report.c_str() : "(not tuned)");
     return PERRK_OK;
 }
 

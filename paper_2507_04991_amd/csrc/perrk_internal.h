@@ -7,14 +7,17 @@
 
 #include "perrk.h"
 
-#define PERRK_MAXR 16        // levels
+#define PERRK_MAXR 16        // levels (a level index fits in 4 bits)
+#define PERRK_NBR_MASK 0x0FFFFFFF
+#define PERRK_NBR_SHIFT 28
 #define PERRK_MAXS 64        // stages
 #define PERRK_RED_THREADS 1024  // block size of every per-case reduction (fixed: results depend on it)
 #define PERRK_MLP_NW 1377
 
 // Per-element geometry and bookkeeping (natural element order, all cases).
 struct ElemInfo {
-    int32_t nbr[6];     // periodic neighbours: -x, +x, -y, +y, -z, +z (global element index)
+    int32_t nbr[6];     // periodic neighbours -x, +x, -y, +y, -z, +z: global element index in
+                        // bits 0..27, the neighbour's level in bits 28..31 (same case)
     int32_t level;      // level index r
     int32_t case_id;    // owning case
     double metric[3];   // 2 / h_d
@@ -46,8 +49,10 @@ struct CaseState {
     double H_delta;     // H(U_{n+1}) - H(U_n) at the accepted gamma
     double e[3];        // stage entropy production of the b_i != 0 stages
     double t;           // accumulated relaxed time
-    double ghist[3];    // last three accepted gamma - 1 (learned guess features)
+    double ghist[3];    // last three accepted gamma - 1, most recent first (learned guess features)
     int32_t state, k, iters, passes, flags, bis_count, widen, trivial;
+    int32_t nsteps;     // steps taken (the learned guess needs three earlier gammas)
+    int32_t pad_;
 };
 
 struct RelaxParams {
@@ -67,13 +72,13 @@ struct StageArgs {
     void *Kout;               // K_i (stage storage type); unused for the last stage
     double *d_out;            // last stage: d = b_1 K_1 + b_{S-1} K_{S-1} + b_S K_S
     const ElemInfo *elem;
-    const int32_t *active;    // level-sorted element list; the first n_active are active
+    const int2 *active;       // active elements of the stage: {index | level << 28, case}
     int32_t n_active;
     const CaseState *cs;      // dt per case
     double *ep_partial;       // [nelem] per-element J sum q w.K, or NULL
     int32_t *err;             // bit 1: non-physical, bit 2: non-finite state formed
     int64_t nelem;
-    double gam;
+    double gam, gm1, inv_gm1; // gamma, gamma - 1, 1 / (gamma - 1)
     double b1, bsm1, bs;      // last stage weights
     double *k64_out;          // optional double copy of K_i (b_i != 0 stages in mixed precision)
     const double *k64_1;      // last stage: double copies of K_1 and K_{S-1}, or NULL to read the
@@ -84,8 +89,12 @@ struct StageArgs {
 enum { SK_FIRST = 0, SK_MID = 1, SK_LAST = 2 };
 
 struct LaunchCfg {
-    int epb_mult;   // wavefronts (of 64 lanes) per workgroup
+    int epb_mult;   // wavefronts (of 64 lanes) per workgroup (1, 2, 4 or 8)
 };
+#define PERRK_MAX_WPB 8
+
+// Workgroup LDS bytes of a stage launch with wpb wavefronts per workgroup.
+size_t stage_lds_bytes(int dim, int variant, int wpb);
 
 // Kernel launchers (perrk_kernels.hip).
 // variant: 0 double flux / double storage, 1 float / float, 2 double flux / float storage

@@ -21,7 +21,7 @@
 //   6. if b_i != 0, reduces J q w(U_{n,i}) . K_i over the element's lanes
 //      (fixed butterfly) into one partial per element (EntropyChange_...
 //      rearranged node-wise form).
-// Only the active prefix of the level-sorted element list is launched.
+// Each stage launches over its own list of active elements (natural order).
 //
 // Relaxation (Sec. 3.1): a residual pass reads U_n and d once per node and
 // reduces J q [s(u + gamma dt d) - s(u)] (cancellation-free form),
@@ -52,23 +52,23 @@ struct Geo {
 //   W = diag(1, 5, 5, 1)/6, B = diag(-1, 0, 0, 1).  Diagonal of Dsplit = 0.
 #define PHI 1.61803398874989484820458683437
 #define SQ5 2.23606797749978969640917366873
-__constant__ double c_ds64[16] = {
-    0.0, 5.0 * PHI, -5.0 * (PHI - 1.0), 1.0,
-    -PHI, 0.0, SQ5, -(PHI - 1.0),
-    PHI - 1.0, -SQ5, 0.0, PHI,
-    -1.0, 5.0 * (PHI - 1.0), -5.0 * PHI, 0.0};
-__constant__ float c_ds32[16] = {
-    0.0f, (float)(5.0 * PHI), (float)(-5.0 * (PHI - 1.0)), 1.0f,
-    (float)(-PHI), 0.0f, (float)SQ5, (float)(-(PHI - 1.0)),
-    (float)(PHI - 1.0), (float)(-SQ5), 0.0f, (float)PHI,
-    -1.0f, (float)(5.0 * (PHI - 1.0)), (float)(-5.0 * PHI), 0.0f};
 
+// a_t for t in 0..3, by selection (no indexed memory access)
 template <typename T>
-__device__ __forceinline__ T dsplit(int i, int m);
-template <>
-__device__ __forceinline__ double dsplit<double>(int i, int m) { return c_ds64[i * 4 + m]; }
-template <>
-__device__ __forceinline__ float dsplit<float>(int i, int m) { return c_ds32[i * 4 + m]; }
+__device__ __forceinline__ T sel4(int t, T a0, T a1, T a2, T a3)
+{
+    const T lo = (t & 1) ? a1 : a0, hi = (t & 1) ? a3 : a2;
+    return (t & 2) ? hi : lo;
+}
+
+// Dsplit[t][(t + j) & 3] for j = 1, 2, 3 (t = position of the node on its line).
+template <typename T, int J>
+__device__ __forceinline__ T dsplit_j(int t)
+{
+    if (J == 1) return sel4<T>(t, (T)(5.0 * PHI), (T)SQ5, (T)PHI, (T)-1.0);
+    if (J == 2) return sel4<T>(t, (T)(-5.0 * (PHI - 1.0)), (T)(-(PHI - 1.0)), (T)(PHI - 1.0), (T)(5.0 * (PHI - 1.0)));
+    return sel4<T>(t, (T)1.0, (T)(-PHI), (T)(-SQ5), (T)(-5.0 * PHI));
+}
 
 // 1D LGL weights: 1/6 at the ends, 5/6 inside.
 __device__ __forceinline__ double lglw(int i) { return (i == 0 || i == 3) ? (1.0 / 6.0) : (5.0 / 6.0); }
@@ -98,10 +98,22 @@ __device__ __forceinline__ double node_weight(int node)
 #define C_R7 (-25865068.0 / 1915538625.0)
 #define C_R8 (-5472607916.0 / 488462349375.0)
 
+// 1/x for finite nonzero x: the hardware reciprocal estimate refined by two
+// Newton steps r <- r + r (1 - x r) (error within an ulp, cheaper than the
+// correctly rounded division).
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 __device__ __forceinline__ double lmean(double a, double b)
 {
     const double d = a - b, s = a + b;
-    const double rs = 1.0 / s;
+    const double rs = rcp64(s);
     const double z = d * rs, u = z * z;
     if (u < 1.0e-2) {
         const double P = 1.0 + u * (C_R1 + u * (C_R2 + u * (C_R3 + u * (C_R4 + u * (C_R5 + u * (C_R6 +
@@ -114,7 +126,7 @@ __device__ __forceinline__ double lmean(double a, double b)
 __device__ __forceinline__ double inv_lmean(double a, double b)
 {
     const double d = a - b, s = a + b;
-    const double rs = 1.0 / s;
+    const double rs = rcp64(s);
     const double z = d * rs, u = z * z;
     if (u < 1.0e-2) {
         const double F = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0 + u * (1.0 / 9.0 +
@@ -159,20 +171,20 @@ struct Prim {
     T rho, v[DIM], p, beta;  // beta = rho / p
 };
 
-// Primitive variables of a double-precision state.  Sets bit 1 of bad for
-// rho <= 0 or p <= 0, bit 2 for non-finite input.
+// Primitive variables of a double-precision state (gm1 = gamma - 1).  Sets
+// bit 1 of bad for rho <= 0 or p <= 0, bit 2 for non-finite input.
 template <int DIM>
-__device__ __forceinline__ void make_prim_f32(const double *u, double gam, Prim<float, DIM> &P, int &bad);
+__device__ __forceinline__ void make_prim_f32(const double *u, double gm1, Prim<float, DIM> &P, int &bad);
 
 template <typename T, int DIM>
-__device__ __forceinline__ void make_prim(const double *u, double gam, Prim<T, DIM> &P, int &bad)
+__device__ __forceinline__ void make_prim(const double *u, double gm1, Prim<T, DIM> &P, int &bad)
 {
     if constexpr (sizeof(T) == 4) {
-        make_prim_f32<DIM>(u, gam, P, bad);
+        make_prim_f32<DIM>(u, gm1, P, bad);
         return;
     }
     const double rho = u[0];
-    const double ir = 1.0 / rho;
+    const double ir = rcp64(rho);
     double ke = 0.0;
     double v[DIM];
 #pragma unroll
@@ -180,31 +192,32 @@ __device__ __forceinline__ void make_prim(const double *u, double gam, Prim<T, D
         v[k] = u[1 + k] * ir;
         ke += u[1 + k] * v[k];
     }
-    const double p = (gam - 1.0) * (u[DIM + 1] - 0.5 * ke);
-    bool fin = true;
+    const double p = gm1 * (u[DIM + 1] - 0.5 * ke);
+    double sum = u[0];
 #pragma unroll
-    for (int k = 0; k < DIM + 2; ++k) fin = fin && isfinite(u[k]);
-    if (!fin) bad |= 2;
+    for (int k = 1; k < DIM + 2; ++k) sum += u[k];
+    if (!isfinite(sum)) bad |= 2;  // a sum of finite values can overflow only beyond 1e308
     else if (!(rho > 0.0) || !(p > 0.0)) bad |= 1;
     P.rho = (T)rho;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) P.v[k] = (T)v[k];
     P.p = (T)p;
-    P.beta = (T)(rho / p);
+    P.beta = (T)(rho * rcp64(p));
 }
 
 // Single-precision variant: the state is rounded to single precision first and
 // the primitive variables are formed in single precision (reciprocals by the
-// hardware instruction); admissibility is judged on the double state.
+// hardware instruction).  A state whose components exceed the single-precision
+// range counts as non-finite.
 template <int DIM>
-__device__ __forceinline__ void make_prim_f32(const double *u, double gam, Prim<float, DIM> &P, int &bad)
+__device__ __forceinline__ void make_prim_f32(const double *u, double gm1, Prim<float, DIM> &P, int &bad)
 {
-    bool fin = true;
-#pragma unroll
-    for (int k = 0; k < DIM + 2; ++k) fin = fin && isfinite(u[k]);
     float uf[DIM + 2];
 #pragma unroll
     for (int k = 0; k < DIM + 2; ++k) uf[k] = (float)u[k];
+    float sum = uf[0];
+#pragma unroll
+    for (int k = 1; k < DIM + 2; ++k) sum += uf[k];
     const float rho = uf[0];
     const float ir = __builtin_amdgcn_rcpf(rho);
     float ke = 0.0f;
@@ -213,22 +226,20 @@ __device__ __forceinline__ void make_prim_f32(const double *u, double gam, Prim<
         P.v[k] = uf[1 + k] * ir;
         ke += uf[1 + k] * P.v[k];
     }
-    const float p = (float)(gam - 1.0) * (uf[DIM + 1] - 0.5f * ke);
-    if (!fin) bad |= 2;
+    const float p = (float)gm1 * (uf[DIM + 1] - 0.5f * ke);
+    if (!isfinite(sum)) bad |= 2;
     else if (!(rho > 0.0f) || !(p > 0.0f)) bad |= 1;
     P.rho = rho;
     P.p = p;
     P.beta = rho * __builtin_amdgcn_rcpf(p);
 }
 
-// Velocity component d of a state with a runtime d, as a blend with exact 0/1
-// weights (keeps the components in registers; exact for finite values).
+// Velocity component d of a state with a runtime d, by selection of values.
 template <typename T, int DIM>
 __device__ __forceinline__ T vdir(const Prim<T, DIM> &P, int d)
 {
-    T r = (d == 0 ? (T)1 : (T)0) * P.v[0] + (d == 1 ? (T)1 : (T)0) * P.v[1];
-    if (DIM == 3) r += (d == 2 ? (T)1 : (T)0) * P.v[DIM - 1];
-    return r;
+    if (DIM == 2) return d == 0 ? P.v[0] : P.v[1];
+    return d == 0 ? P.v[0] : (d == 1 ? P.v[1] : P.v[DIM - 1]);
 }
 
 // Ranocha's entropy-conservative, kinetic-energy-preserving two-point flux in
@@ -254,7 +265,8 @@ __device__ __forceinline__ void flux_ec(int d, const Prim<T, DIM> &L, const Prim
 // HLL two-wave flux with Davis wave-speed estimates in direction d; the
 // conserved states are rebuilt from the primitive ones.
 template <typename T, int DIM>
-__device__ __forceinline__ void flux_hll(int d, const Prim<T, DIM> &L, const Prim<T, DIM> &R, T gam, T *f)
+__device__ __forceinline__ void flux_hll(int d, const Prim<T, DIM> &L, const Prim<T, DIM> &R, T gam, T inv_gm1,
+                                         T *f)
 {
     const T vl = vdir<T, DIM>(L, d), vr = vdir<T, DIM>(R, d);
     const T cl = sqrt(gam * L.p / L.rho), cr = sqrt(gam * R.p / R.rho);
@@ -271,8 +283,8 @@ __device__ __forceinline__ void flux_hll(int d, const Prim<T, DIM> &L, const Pri
         kl += uL[1 + k] * L.v[k];
         kr += uR[1 + k] * R.v[k];
     }
-    uL[DIM + 1] = L.p / (gam - (T)1) + (T)0.5 * kl;
-    uR[DIM + 1] = R.p / (gam - (T)1) + (T)0.5 * kr;
+    uL[DIM + 1] = L.p * inv_gm1 + (T)0.5 * kl;
+    uR[DIM + 1] = R.p * inv_gm1 + (T)0.5 * kr;
 #pragma unroll
     for (int k = 0; k < DIM + 1; ++k) {
         fl[k] = uL[k] * vl;
@@ -351,29 +363,73 @@ __device__ __forceinline__ double entropy_diff(const double *u, const double *du
     return -drho * (log(p1) - gam * log(rho1)) - rho * (log1p(dp / p) - gam * log1p(drho / rho));
 }
 
-template <typename T>
-__device__ __forceinline__ T ld(const void *p, size_t i) { return static_cast<const T *>(p)[i]; }
 
-// U_{n,i} at one node of element e: U_n + dt (c1 K_1 + cp K_{i-1}); K_{i-1} is
-// read only when its coefficient is nonzero (it may hold stale data otherwise).
+// Raw data of one node for its stage state: U_n, K_1 and K_{i-1}.  Every load
+// depends only on the element index, so a lane issues all of them at once;
+// K_{i-1} is read even where its coefficient is zero (it may then hold stale
+// values, which the combination discards by selection, never by multiplication).
+template <int V, typename KT>
+struct NodeRaw {
+    double u[V];
+    KT k1[V], kp[V];
+};
+
+// Element of field v of a node array at byte offset o of the field: the field
+// base is uniform (scalar registers) and o a 32-bit lane offset, so the
+// address costs no vector arithmetic.
+// The field base is passed through an empty asm statement with a scalar-register
+// operand: the compiler then keeps one scalar base per field instead of
+// reassociating base + v * field + o into a vector address per load.
+template <typename T>
+__device__ __forceinline__ const T &at(const void *base, int v, size_t field, uint32_t o)
+{
+    const char *b = reinterpret_cast<const char *>(static_cast<const T *>(base) + v * field);
+    asm("" : "+s"(b));
+    return *reinterpret_cast<const T *>(b + o);
+}
+
+template <typename T>
+__device__ __forceinline__ T &at_w(void *base, int v, size_t field, uint32_t o)
+{
+    char *b = reinterpret_cast<char *>(static_cast<T *>(base) + v * field);
+    asm("" : "+s"(b));
+    return *reinterpret_cast<T *>(b + o);
+}
+
+// base[i] with a 32-bit byte offset (tables indexed by element, case or level
+// are far below 4 GiB).
+template <typename T>
+__device__ __forceinline__ const T &elt(const T *base, uint32_t i)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (uint32_t)sizeof(T));
+}
+
 template <int DIM, typename KT, int KIND>
-__device__ __forceinline__ void form_state(const StageArgs &a, const double *coef, int e, int node,
-                                           int level, int case_id, double *u)
+__device__ __forceinline__ void load_raw(const StageArgs &a, int e, int node, NodeRaw<Geo<DIM>::V, KT> &r)
 {
     constexpr int NPE = Geo<DIM>::NPE, V = Geo<DIM>::V;
-    double dt = 0.0, c1 = 0.0, cp = 0.0;
-    if (KIND != SK_FIRST) {
-        dt = a.cs[case_id].dt;
-        c1 = coef[level];
-        cp = coef[PERRK_MAXR + level];
-    }
+    const size_t field = (size_t)a.nelem * NPE;
+    const uint32_t n = (uint32_t)e * NPE + node;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        const size_t idx = ((size_t)v * a.nelem + e) * NPE + node;
-        double x = a.U[idx];
+        r.u[v] = at<double>(a.U, v, field, n * 8u);
         if (KIND != SK_FIRST) {
-            double s = c1 * (double)ld<KT>(a.K1, idx);
-            if (cp != 0.0) s += cp * (double)ld<KT>(a.Kp, idx);
+            r.k1[v] = at<KT>(a.K1, v, field, n * (uint32_t)sizeof(KT));
+            r.kp[v] = at<KT>(a.Kp, v, field, n * (uint32_t)sizeof(KT));
+        }
+    }
+}
+
+// U_{n,i} = U_n + dt (c1 K_1 + cp K_{i-1}) with the node's level coefficients.
+template <int V, typename KT, int KIND>
+__device__ __forceinline__ void combine(const NodeRaw<V, KT> &r, double dt, double c1, double cp, double *u)
+{
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        double x = r.u[v];
+        if (KIND != SK_FIRST) {
+            double s = c1 * (double)r.k1[v];
+            s += (cp != 0.0) ? cp * (double)r.kp[v] : 0.0;
             x = x + dt * s;
         }
         u[v] = x;
@@ -431,17 +487,59 @@ __device__ __forceinline__ int node_pos(int d, int node)
     return d == 0 ? (node & 3) : (d == 1 ? ((node >> 2) & 3) : (node >> 4));
 }
 
-// Pairs of positions on a line: (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
+// Pairs of positions on a line, k = 0..5: (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
 __device__ __forceinline__ void pair_pos(int k, int &a, int &b)
 {
     a = k < 3 ? 0 : (k < 5 ? 1 : 2);
     b = k < 3 ? k + 1 : (k < 5 ? k - 1 : 3);
 }
 
-__device__ __forceinline__ int pair_index(int t, int m)
+// Pair index k of positions (t, (t + j) & 3), j = 1, 2, 3.
+template <int J>
+__device__ __forceinline__ int pair_k(int t)
 {
-    const int a = t < m ? t : m, b = t < m ? m : t;
-    return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+    if (J == 1) return sel4<int>(t, 0, 3, 5, 2);
+    if (J == 2) return sel4<int>(t, 1, 4, 1, 4);
+    return sel4<int>(t, 2, 0, 3, 5);
+}
+
+// Lane -> node pair of round rd over the directions [D0, D0 + ND): element slot
+// es, direction offset dd, line l, pair k.  Bit fields of the lane index:
+//   2D (ND = 2): 4 slots x 2 directions x 4 lines x 2 pairs per round, 3 rounds;
+//   3D, ND = 2:  2 directions x 16 lines x 2 pairs per round, 3 rounds;
+//   3D, ND = 1:  16 lines x 4 pairs, then 16 lines x 2 pairs on lanes 0..31.
+template <int DIM, int ND>
+struct PairRounds {
+    static_assert(DIM == 3 || ND == 2, "2D evaluates both directions in one phase");
+    static constexpr int N = (DIM == 3 && ND == 1) ? 2 : 3;
+};
+
+template <int DIM, int ND>
+__device__ __forceinline__ bool pair_of(int rd, int lane, int &es, int &dd, int &l, int &k)
+{
+    if (DIM == 2) {
+        es = lane >> 4;
+        dd = (lane >> 3) & 1;
+        l = (lane >> 1) & 3;
+        k = 2 * rd + (lane & 1);
+        return true;
+    }
+    es = 0;
+    if (ND == 2) {
+        dd = lane >> 5;
+        l = (lane >> 1) & 15;
+        k = 2 * rd + (lane & 1);
+        return true;
+    }
+    dd = 0;
+    if (rd == 0) {
+        l = lane >> 2;
+        k = lane & 3;
+        return true;
+    }
+    l = (lane >> 1) & 15;
+    k = 4 + (lane & 1);
+    return lane < 32;
 }
 
 template <typename T, int DIM>
@@ -466,23 +564,20 @@ __device__ __forceinline__ void lds_get_prim(const T *slot, int node, Prim<T, DI
     P.beta = slot[(DIM + 2) * NPE + node];
 }
 
-// Two-point volume fluxes of the pairs of directions [d0, d0 + nd), one pair per
+// Two-point volume fluxes of the pairs of directions [D0, D0 + ND), one pair per
 // lane and round, written to vf of the pair's element slot.
 template <int DIM, typename T, int D0, int ND>
 __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_gm1)
 {
-    constexpr int d0 = D0, nd = ND;
     constexpr int EPW = SG<DIM>::EPW, NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V;
     constexpr int SLOT = SG<DIM>::SLOT, NQ = SG<DIM>::NQ, NPE = SG<DIM>::NPE, NFN = SG<DIM>::NFN;
-    const int per_slot = nd * NPD;
-    const int total = EPW * per_slot;
-    for (int g = lane; g < total; g += 64) {
-        const int es = g / per_slot;
-        const int p = g - es * per_slot;
-        const int d = d0 + p / NPD;
-        const int l = (p % NPD) / 6;
+#pragma unroll
+    for (int rd = 0; rd < PairRounds<DIM, ND>::N; ++rd) {
+        int es, dd, l, k;
+        if (!pair_of<DIM, ND>(rd, lane, es, dd, l, k)) continue;
         int ta, tb;
-        pair_pos(p % 6, ta, tb);
+        pair_pos(k, ta, tb);
+        const int d = D0 + dd;
         T *slot = lds + (size_t)(wave * EPW + es) * SLOT;
         Prim<T, DIM> A, B;
         lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, ta), A);
@@ -490,6 +585,7 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
         T f[V];
         flux_ec<T, DIM>(d, A, B, inv_gm1, f);
         T *vf = slot + NQ * NPE + V * NFN;
+        const int p = dd * NPD + l * 6 + k;
 #pragma unroll
         for (int v = 0; v < V; ++v) vf[v * NPP + p] = f[v];
     }
@@ -513,13 +609,14 @@ __device__ __forceinline__ void gather(const T *slot, int node, const ElemInfo &
         T acc[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[v] = 0;
+        const int pb = dd * NPD + l * 6;
+        const int p1 = pb + pair_k<1>(t), p2 = pb + pair_k<2>(t), p3 = pb + pair_k<3>(t);
+        const T w1 = dsplit_j<T, 1>(t), w2 = dsplit_j<T, 2>(t), w3 = dsplit_j<T, 3>(t);
 #pragma unroll
-        for (int j = 1; j < 4; ++j) {
-            const int m = (t + j) & 3;
-            const int pidx = dd * NPD + l * 6 + pair_index(t, m);
-            const T w = dsplit<T>(t, m);
-#pragma unroll
-            for (int v = 0; v < V; ++v) acc[v] += w * vf[v * NPP + pidx];
+        for (int v = 0; v < V; ++v) {
+            acc[v] += w1 * vf[v * NPP + p1];
+            acc[v] += w2 * vf[v * NPP + p2];
+            acc[v] += w3 * vf[v * NPP + p3];
         }
         if (t == 0 || t == 3) {
             const int q = (2 * d + (t == 3 ? 1 : 0)) * NLINE + l;
@@ -532,53 +629,33 @@ __device__ __forceinline__ void gather(const T *slot, int node, const ElemInfo &
     }
 }
 
-// Surface flux of every face node of the wave's elements: the neighbour's
-// stage state at the matching node is formed here (with the neighbour's level
-// coefficients) and f*(u-, u+) is stored lifted: +6 f* on right faces, -6 f* on left.
-template <int DIM, typename T, typename KT, int FLUX, int KIND>
-__device__ __forceinline__ void surface_fluxes(const StageArgs &a, const double *coef, T *lds, int wave,
-                                               int lane, int e, int &bad)
+// Face nodes of a wavefront: EPW * NFN of them (64 in 2D, 96 in 3D), spread over
+// the lanes in FR rounds; face node g = lane + 64 r belongs to element slot
+// g / NFN, which is the lane's own slot (2D: 16 face nodes per quadrilateral;
+// 3D: one element per wavefront).
+template <int DIM>
+struct FaceRounds {
+    static constexpr int N = (SG<DIM>::EPW * SG<DIM>::NFN + 63) / 64;
+};
+
+template <int DIM>
+struct FaceNode {
+    int q, d, side, own;  // face-node slot, direction, side (1 = +), own node on the face
+};
+
+template <int DIM>
+__device__ __forceinline__ bool face_node(int r, int lane, FaceNode<DIM> &F, int &nn)
 {
-    constexpr int EPW = SG<DIM>::EPW, NFN = SG<DIM>::NFN, NLINE = SG<DIM>::NLINE, V = SG<DIM>::V;
-    constexpr int SLOT = SG<DIM>::SLOT, NQ = SG<DIM>::NQ, NPE = SG<DIM>::NPE;
-    const T inv_gm1 = (T)(1.0 / (a.gam - 1.0));
-    for (int g = lane; g < EPW * NFN; g += 64) {
-        const int es = g / NFN;          // equals the lane's own element slot
-        const int q = g - es * NFN;
-        const int f = q / NLINE, l = q - f * NLINE;
-        const int d = f >> 1, side = f & 1;
-        const int own = line_node<DIM>(d, l, side ? 3 : 0);
-        const int nn = line_node<DIM>(d, l, side ? 0 : 3);
-        T *slot = lds + (size_t)(wave * EPW + es) * SLOT;
-        const int nb = a.elem[e].nbr[2 * d + side];
-        const ElemInfo en = a.elem[nb];
-        double un[V];
-        form_state<DIM, KT, KIND>(a, coef, nb, nn, en.level, en.case_id, un);
-        Prim<T, DIM> PN, PO;
-        make_prim<T, DIM>(un, a.gam, PN, bad);
-        lds_get_prim<T, DIM>(slot, own, PO);
-        // minus / plus states of the face, selected field by field (values, not
-        // addresses, so that everything stays in registers)
-        Prim<T, DIM> L, R;
-        L.rho = side ? PO.rho : PN.rho;
-        R.rho = side ? PN.rho : PO.rho;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            L.v[k] = side ? PO.v[k] : PN.v[k];
-            R.v[k] = side ? PN.v[k] : PO.v[k];
-        }
-        L.p = side ? PO.p : PN.p;
-        R.p = side ? PN.p : PO.p;
-        L.beta = side ? PO.beta : PN.beta;
-        R.beta = side ? PN.beta : PO.beta;
-        T fs[V];
-        if (FLUX == PERRK_FLUX_HLL) flux_hll<T, DIM>(d, L, R, (T)a.gam, fs);
-        else flux_ec<T, DIM>(d, L, R, inv_gm1, fs);
-        const T lift = side ? (T)6 : (T)-6;  // +-1/q_boundary, q_boundary = 1/6
-        T *sf = slot + NQ * NPE;
-#pragma unroll
-        for (int v = 0; v < V; ++v) sf[v * NFN + q] = lift * fs[v];
-    }
+    constexpr int EPW = SG<DIM>::EPW, NFN = SG<DIM>::NFN, NLINE = SG<DIM>::NLINE;
+    const int g = lane + 64 * r;
+    const int es = g / NFN;
+    F.q = g - es * NFN;
+    const int f = F.q / NLINE, l = F.q - f * NLINE;
+    F.d = f >> 1;
+    F.side = f & 1;
+    F.own = line_node<DIM>(F.d, l, F.side ? 3 : 0);
+    nn = line_node<DIM>(F.d, l, F.side ? 0 : 3);  // matching node of the neighbour
+    return g < EPW * NFN;
 }
 
 }  // namespace
@@ -586,11 +663,16 @@ __device__ __forceinline__ void surface_fluxes(const StageArgs &a, const double 
 namespace {
 
 // T: flux arithmetic; KT: stage storage.  Lane = node of the element slot
-// lane / NPE of its wavefront.
+// lane / NPE of its wavefront.  Memory access is arranged so that the global
+// loads of a lane form at most three dependent levels, all issued before the
+// first barrier: the active entry (element, level, case); then the element's
+// own U_n / K_1 / K_{i-1}, dt, its level coefficients and the neighbour words of
+// its face nodes; then the neighbours' data at the matching nodes.
 template <int DIM, typename T, typename KT, int FLUX, int KIND>
-__global__ void __launch_bounds__(256) stage_kernel(const StageArgs a, const double *coef)
+__global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageArgs a, const double *coef)
 {
     constexpr int NPE = SG<DIM>::NPE, V = SG<DIM>::V, EPW = SG<DIM>::EPW, SLOT = SG<DIM>::SLOT;
+    constexpr int NQ = SG<DIM>::NQ, NFN = SG<DIM>::NFN, FR = FaceRounds<DIM>::N;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -599,21 +681,91 @@ __global__ void __launch_bounds__(256) stage_kernel(const StageArgs a, const dou
     const int epb = (int)(blockDim.x >> 6) * EPW;
     const int li = xcd_block(blockIdx.x, gridDim.x) * epb + eslot;
     const bool valid = li < a.n_active;
-    const int e = a.active[valid ? li : a.n_active - 1];
-    const ElemInfo ei = a.elem[e];
+    const int2 act = elt(a.active, (uint32_t)(valid ? li : a.n_active - 1));
+    const int e = (int)((uint32_t)act.x & PERRK_NBR_MASK);
+    const int lvl = (int)((uint32_t)act.x >> PERRK_NBR_SHIFT);
     T *slot = lds + (size_t)eslot * SLOT;
-    const T inv_gm1 = (T)(1.0 / (a.gam - 1.0));
+    const T inv_gm1 = (T)a.inv_gm1;
     int bad = 0;
 
+    // ---- loads
+    double dt = 0.0, c1 = 0.0, cp = 0.0;
+    if (KIND != SK_FIRST) {
+        dt = elt(a.cs, (uint32_t)act.y).dt;
+        c1 = elt(coef, (uint32_t)lvl);
+        cp = elt(coef, (uint32_t)(PERRK_MAXR + lvl));
+    }
+    NodeRaw<V, KT> own;
+    load_raw<DIM, KT, KIND>(a, e, node, own);
+    FaceNode<DIM> F[FR];
+    bool fv[FR];
+    NodeRaw<V, KT> nr[FR];
+    double nc1[FR], ncp[FR];
+#pragma unroll
+    for (int r = 0; r < FR; ++r) {
+        int nn;
+        fv[r] = face_node<DIM>(r, lane, F[r], nn);
+        const uint32_t w = (uint32_t)elt(a.elem, (uint32_t)e).nbr[2 * F[r].d + F[r].side];
+        const int nb = (int)(w & PERRK_NBR_MASK);
+        nc1[r] = 0.0;
+        ncp[r] = 0.0;
+        if (KIND != SK_FIRST) {
+            const int lv = (int)(w >> PERRK_NBR_SHIFT);
+            nc1[r] = elt(coef, (uint32_t)lv);
+            ncp[r] = elt(coef, (uint32_t)(PERRK_MAXR + lv));
+        }
+        load_raw<DIM, KT, KIND>(a, nb, nn, nr[r]);
+    }
+
+    // ---- own stage state, published in LDS; neighbour states kept in registers
     double u[V];
-    form_state<DIM, KT, KIND>(a, coef, e, node, ei.level, ei.case_id, u);
+    combine<V, KT, KIND>(own, dt, c1, cp, u);
     {
         Prim<T, DIM> me;
-        make_prim<T, DIM>(u, a.gam, me, bad);
+        make_prim<T, DIM>(u, a.gm1, me, bad);
         lds_put_prim<T, DIM>(slot, node, me);
     }
+    Prim<T, DIM> PN[FR];
+#pragma unroll
+    for (int r = 0; r < FR; ++r) {
+        double un[V];
+        combine<V, KT, KIND>(nr[r], dt, nc1[r], ncp[r], un);  // same case, hence the same dt
+        make_prim<T, DIM>(un, a.gm1, PN[r], bad);
+    }
     __syncthreads();
-    surface_fluxes<DIM, T, KT, FLUX, KIND>(a, coef, lds, wave, lane, e, bad);
+
+    // ---- surface fluxes, lifted: +6 f* on right faces, -6 f* on left (+-1/q_boundary)
+#pragma unroll
+    for (int r = 0; r < FR; ++r) {
+        if (!fv[r]) continue;
+        Prim<T, DIM> PO;
+        lds_get_prim<T, DIM>(slot, F[r].own, PO);
+        const bool sd = F[r].side != 0;
+        // minus / plus states of the face, selected field by field (values, not
+        // addresses, so that everything stays in registers)
+        Prim<T, DIM> L, R;
+        L.rho = sd ? PO.rho : PN[r].rho;
+        R.rho = sd ? PN[r].rho : PO.rho;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            L.v[k] = sd ? PO.v[k] : PN[r].v[k];
+            R.v[k] = sd ? PN[r].v[k] : PO.v[k];
+        }
+        L.p = sd ? PO.p : PN[r].p;
+        R.p = sd ? PN[r].p : PO.p;
+        L.beta = sd ? PO.beta : PN[r].beta;
+        R.beta = sd ? PN[r].beta : PO.beta;
+        T fs[V];
+        if (FLUX == PERRK_FLUX_HLL) flux_hll<T, DIM>(F[r].d, L, R, (T)a.gam, inv_gm1, fs);
+        else flux_ec<T, DIM>(F[r].d, L, R, inv_gm1, fs);
+        const T lift = sd ? (T)6 : (T)-6;
+        T *sf = slot + NQ * NPE;
+#pragma unroll
+        for (int v = 0; v < V; ++v) sf[v * NFN + F[r].q] = lift * fs[v];
+    }
+
+    // ---- volume fluxes and the gather
+    const ElemInfo ei = elt(a.elem, (uint32_t)e);
     T du[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) du[v] = 0;
@@ -633,18 +785,19 @@ __global__ void __launch_bounds__(256) stage_kernel(const StageArgs a, const dou
     for (int v = 0; v < V; ++v) k[v] = -(double)du[v];
 
     if (valid) {
+        const size_t field = (size_t)a.nelem * NPE;
+        const uint32_t n = (uint32_t)e * NPE + node, o8 = n * 8u, ok = n * (uint32_t)sizeof(KT);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const size_t idx = ((size_t)v * a.nelem + e) * NPE + node;
             if (KIND == SK_LAST) {
                 double dv = a.bs * k[v];
                 if (a.bsm1 != 0.0)
-                    dv += a.bsm1 * (a.k64_sm1 ? a.k64_sm1[idx] : (double)ld<KT>(a.Kp, idx));
-                if (a.b1 != 0.0) dv += a.b1 * (a.k64_1 ? a.k64_1[idx] : (double)ld<KT>(a.K1, idx));
-                a.d_out[idx] = dv;
+                    dv += a.bsm1 * (a.k64_sm1 ? at<double>(a.k64_sm1, v, field, o8) : (double)own.kp[v]);
+                if (a.b1 != 0.0) dv += a.b1 * (a.k64_1 ? at<double>(a.k64_1, v, field, o8) : (double)own.k1[v]);
+                at_w<double>(a.d_out, v, field, o8) = dv;
             } else {
-                static_cast<KT *>(a.Kout)[idx] = (KT)k[v];
-                if (a.k64_out) a.k64_out[idx] = k[v];
+                at_w<KT>(a.Kout, v, field, ok) = (KT)k[v];
+                if (a.k64_out) at_w<double>(a.k64_out, v, field, o8) = k[v];
             }
         }
     }
@@ -890,10 +1043,15 @@ __device__ void relax_update(CaseState &C, const double *S, const RelaxParams &r
     }
 }
 
+// One workgroup per case, before the first residual pass: sums the stage
+// entropy production of the case (fixed order), forms dH = dt sum_i b_i e_i,
+// resets the solver state and sets the first evaluation point (the previous
+// gamma, or that plus the learned increment).
 __global__ void __launch_bounds__(PERRK_RED_THREADS)
 relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, int64_t nelem,
                      RelaxParams rp, const float *mlp)
 {
+    __shared__ float sx[8], sh1[32], sh2[32];
     const int c = blockIdx.x;
     const int64_t b = case_off[c], e = case_off[c + 1];
     double ej[3] = {0.0, 0.0, 0.0};
@@ -902,8 +1060,44 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
         case_sum<1>(ep + (size_t)j * nelem, 1, b, e, o);
         ej[j] = o[0];
     }
-    if (threadIdx.x != 0) return;
     CaseState &C = cs[c];
+    // learned guess of the increment gamma_n - gamma_{n-1} (MLP 8-32-32-1, tanh; the
+    // weights are followed by the feature mean[8], scale[8] and the output scale and
+    // shift).  Features, formed in double precision: the last two increments of
+    // gamma, gamma_{n-1} - 1, dt, and the stage entropy-production terms of this step
+    // divided by the sum of their magnitudes (zero-padded to four).
+    const bool learned = rp.guess == 1 && mlp != nullptr && C.nsteps >= 3;
+    const float *W1 = mlp, *b1 = W1 + 256, *W2 = b1 + 32, *b2 = W2 + 1024, *W3 = b2 + 32, *b3 = W3 + 32;
+    const float *mean = b3 + 1, *scale = mean + 8, *oscale = scale + 8;
+    if (learned) {
+        if (threadIdx.x == 0) {
+            double x[8];
+            x[0] = C.ghist[0] - C.ghist[1];
+            x[1] = C.ghist[1] - C.ghist[2];
+            x[2] = C.ghist[0];
+            x[3] = C.dt;
+            double sabs = 0.0;
+            for (int j = 0; j < rp.nb; ++j) sabs += fabs(ej[j]);
+            for (int j = 0; j < 4; ++j) x[4 + j] = (j < rp.nb && sabs > 0.0) ? ej[j] / sabs : 0.0;
+            for (int i = 0; i < 8; ++i) sx[i] = (float)((x[i] - (double)mean[i]) * (double)scale[i]);
+        }
+        __syncthreads();
+        if (threadIdx.x < 32) {
+            const int o = threadIdx.x;
+            float s = b1[o];
+            for (int i = 0; i < 8; ++i) s += W1[o * 8 + i] * sx[i];
+            sh1[o] = tanhf(s);
+        }
+        __syncthreads();
+        if (threadIdx.x < 32) {
+            const int o = threadIdx.x;
+            float s = b2[o];
+            for (int i = 0; i < 32; ++i) s += W2[o * 32 + i] * sh1[i];
+            sh2[o] = tanhf(s);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
     double dH = 0.0;
     for (int j = 0; j < rp.nb; ++j) {
         C.e[j] = ej[j];
@@ -919,34 +1113,11 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
     C.r = 0.0;
     C.rp = 0.0;
     double g0 = C.gamma_prev;
-    if (rp.guess == 1 && mlp != nullptr) {
-        // learned guess of gamma - 1 (MLP 8-32-32-1, tanh), weights then mean[8], scale[8], out scale
-        float x[8];
-        x[0] = (float)C.ghist[0];
-        x[1] = (float)C.ghist[1];
-        x[2] = (float)C.ghist[2];
-        x[3] = (float)C.dt;
-        double sabs = 0.0;
-        for (int j = 0; j < rp.nb; ++j) sabs += fabs(ej[j]);
-        for (int j = 0; j < 4; ++j) x[4 + j] = (j < rp.nb && sabs > 0.0) ? (float)(ej[j] / sabs) : 0.0f;
-        const float *W1 = mlp, *b1 = W1 + 256, *W2 = b1 + 32, *b2 = W2 + 1024, *W3 = b2 + 32, *b3 = W3 + 32;
-        const float *mean = b3 + 1, *scale = mean + 8, *oscale = scale + 8;
-        for (int i = 0; i < 8; ++i) x[i] = (x[i] - mean[i]) * scale[i];
-        float h1[32], h2[32];
-        for (int o = 0; o < 32; ++o) {
-            float s = b1[o];
-            for (int i = 0; i < 8; ++i) s += W1[o * 8 + i] * x[i];
-            h1[o] = tanhf(s);
-        }
-        for (int o = 0; o < 32; ++o) {
-            float s = b2[o];
-            for (int i = 0; i < 32; ++i) s += W2[o * 32 + i] * h1[i];
-            h2[o] = tanhf(s);
-        }
+    if (learned) {
         float y = b3[0];
-        for (int i = 0; i < 32; ++i) y += W3[i] * h2[i];
+        for (int i = 0; i < 32; ++i) y += W3[i] * sh2[i];
         const double pred = (double)y * (double)oscale[0] + (double)oscale[1];
-        if (isfinite(pred) && fabs(pred) < 0.5) g0 = 1.0 + pred;
+        if (isfinite(pred) && fabs(pred) < 0.1 && g0 + pred > 0.0) g0 += pred;
     }
     C.gamma = g0;
     C.gamma_b = g0;
@@ -1065,6 +1236,7 @@ relax_complete_kernel(const double *U, const double *d, const ElemInfo *elem, Ca
         C.ghist[1] = C.ghist[0];
         C.ghist[0] = C.gamma_acc - 1.0;
         C.gamma_prev = C.gamma_acc;
+        C.nsteps += 1;
     }
 }
 
@@ -1183,9 +1355,17 @@ hipError_t launch_stage_d(int variant, int flux, int kind, const StageArgs &a, c
 
 }  // namespace
 
+size_t stage_lds_bytes(int dim, int variant, int wpb)
+{
+    const size_t tb = variant == 1 ? sizeof(float) : sizeof(double);
+    if (dim == 2) return (size_t)wpb * SG<2>::EPW * SG<2>::SLOT * tb;
+    return (size_t)wpb * SG<3>::EPW * SG<3>::SLOT * tb;
+}
+
 hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArgs &a, const double *coef,
                         LaunchCfg cfg, hipStream_t s)
 {
+    if (cfg.epb_mult < 1 || cfg.epb_mult > PERRK_MAX_WPB) return hipErrorInvalidValue;
     if (dim == 2) return launch_stage_d<2>(variant, flux, kind, a, coef, cfg, s);
     return launch_stage_d<3>(variant, flux, kind, a, coef, cfg, s);
 }

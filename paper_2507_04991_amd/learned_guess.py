@@ -1,13 +1,14 @@
 """Learned initial guess for the relaxation solve.
 
-A small network (8 -> 32 -> 32 -> 1, tanh) predicts gamma - 1 of a step from
-the last three accepted gamma - 1 of the same case, the step size and the
-entropy-production terms of the stages with b_i != 0 (normalised by the sum of
-their magnitudes, zero-padded to four).  It is trained on (features,
-converged gamma) pairs logged from the method's own solves, with the
-library's HIP forward / gradient / Adam kernels; the step kernels evaluate it
-before the first residual pass.  Newton and bisection still decide the
-accepted gamma, so the guess only changes how many passes a step needs.
+A small network (8 -> 32 -> 32 -> 1, tanh) predicts the increment
+gamma_n - gamma_{n-1} of a case's relaxation parameter from: the last two
+increments, gamma_{n-1} - 1, the step size and the entropy-production terms of
+this step's stages with b_i != 0 (divided by the sum of their magnitudes,
+zero-padded to four).  It is trained on (features, increment) pairs logged
+from the method's own solves, with the library's HIP forward / gradient / Adam
+kernels; the step evaluates it before the first residual pass once a case has
+taken three steps.  Newton and bisection still decide the accepted gamma, so
+the guess only changes how many passes a step needs.
 
 The feature definition here matches the one evaluated on the device.
 """
@@ -21,12 +22,15 @@ from . import perrk as P
 
 NFEAT = 8
 MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
+DEFAULT_MODEL = os.path.join(MODEL_DIR, "guess_vortex_ensemble_p3.npz")
 
 
 def features(ghist, dt, e, nb):
     """ghist: [3] previous gamma - 1 (most recent first); e: stage entropy production [nb]."""
     x = np.zeros(NFEAT)
-    x[0:3] = ghist
+    x[0] = ghist[0] - ghist[1]
+    x[1] = ghist[1] - ghist[2]
+    x[2] = ghist[0]
     x[3] = dt
     s = float(np.sum(np.abs(e[:nb])))
     if s > 0.0:
@@ -35,23 +39,26 @@ def features(ghist, dt, e, nb):
 
 
 def collect(stepper, u, dt, steps, nb):
-    """Advance `steps` synchronous steps, logging one (features, gamma - 1) pair per case and step.
-    Steps whose solve fell back or was trivial are skipped."""
+    """Advance `steps` synchronous steps, logging one (features, gamma_n - gamma_{n-1})
+    pair per case and step once the case has three earlier gammas.  Steps whose
+    solve fell back or was trivial are skipped.  Returns X, Y, the passes of the
+    logged steps and the previous gamma of each logged pair."""
     n = stepper.n_cases
     dt = np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,))
     hist = np.zeros((n, 3))
-    X, Y, passes = [], [], []
-    for _ in range(steps):
+    X, Y, passes, prev = [], [], [], []
+    for step in range(steps):
         infos = stepper.step(u, dt)
         for c, inf in enumerate(infos):
             g1 = inf["gamma"] - 1.0
-            if inf["flags"] == 0:
+            if inf["flags"] == 0 and step >= 3:
                 X.append(features(hist[c], dt[c], np.asarray(inf["e"]), nb))
-                Y.append(g1)
+                Y.append(g1 - hist[c, 0])
                 passes.append(inf["passes"])
+                prev.append(hist[c, 0])
             hist[c, 1:] = hist[c, :2].copy()
             hist[c, 0] = g1
-    return np.array(X), np.array(Y), np.array(passes)
+    return np.array(X), np.array(Y), np.array(passes), np.array(prev)
 
 
 def normalisation(X, Y):
@@ -136,8 +143,7 @@ def evaluate(problem, model, steps, precision=P.MIXED):
             passes += [i["passes"] for i in infos]
             rmax = max(rmax, max(abs(i["r"]) for i in infos))
             flags |= int(np.bitwise_or.reduce([i["flags"] for i in infos]))
-        out[name] = dict(passes_mean=float(np.mean(passes)), r_max=rmax, flags=flags,
-                         gamma=st.relaxation_state()[0].tolist())
+        out[name] = dict(passes_mean=float(np.mean(passes)), r_max=rmax, flags=flags)
         st.close()
     return out
 
@@ -153,31 +159,38 @@ def main(argv=None):
     from . import problems
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", default=DEFAULT_MODEL)
     ap.add_argument("--train-seed", type=int, default=1000)
     ap.add_argument("--eval-seed", type=int, default=7)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--epochs", type=int, default=3000)
     ap.add_argument("--cases", type=int, default=256)
+    ap.add_argument("--eval-steps", type=int, default=60)
+    ap.add_argument("--save-data", default=None, help="also write the logged pairs (npz)")
     args = ap.parse_args(argv)
     P.lib()
     prob = problems.ensemble(args.train_seed, args.cases)
     d = P.Descriptors(prob["faces"], prob["lev"], prob["tab"], precision=P.MIXED)
     st = P.Stepper(d, P.default_options())
     u = torch.tensor(prob["U0"], device="cuda").contiguous()
-    X, Y, passes = collect(st, u, prob["dt"], args.steps, nb=int(np.count_nonzero(prob["tab"]["b"])))
+    X, Y, passes, prev = collect(st, u, prob["dt"], args.steps, nb=int(np.count_nonzero(prob["tab"]["b"])))
     st.close()
-    print(f"# collected {len(Y)} pairs, gamma-1 in [{Y.min():.3e}, {Y.max():.3e}], passes {passes.mean():.3f}",
+    if args.save_data:
+        np.savez(args.save_data, X=X, Y=Y, passes=passes, prev=prev)
+    print(f"# collected {len(Y)} pairs, increment in [{Y.min():.3e}, {Y.max():.3e}], passes {passes.mean():.3f}",
           flush=True)
     model_w, mean, scale, hist = train(X, Y, epochs=args.epochs, log_every=500)
     print("# loss", hist, flush=True)
     model = (model_w, mean, scale)
     pred = predict(model, X)
     res = dict(pairs=int(len(Y)), train_rmse=float(np.sqrt(np.mean((pred - Y) ** 2))),
-               prev_rmse=float(np.sqrt(np.mean((X[:, 0] - Y) ** 2))), y_std=float(Y.std()), loss=hist)
+               prev_rmse=float(np.sqrt(np.mean(Y ** 2))),
+               linear_extrapolation_rmse=float(np.sqrt(np.mean((X[:, 0] - Y) ** 2))), y_std=float(Y.std()),
+               loss=hist)
     evalp = problems.ensemble(args.eval_seed, args.cases)
-    res["heldout"] = evaluate(evalp, model, 40)
-    save(args.out, model, dict(train_seed=np.array(args.train_seed), steps=np.array(args.steps)))
+    res["heldout"] = evaluate(evalp, model, args.eval_steps)
+    save(args.out, model, dict(train_seed=np.array(args.train_seed), steps=np.array(args.steps),
+                               cases=np.array(args.cases), epochs=np.array(args.epochs)))
     print(json.dumps(res), flush=True)
 
 

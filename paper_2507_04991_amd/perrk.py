@@ -66,7 +66,7 @@ K_CLASSES = ["stage_first", "stage_mid", "stage_last", "residual", "solver", "up
 
 EXPORTS = ["perrk_default_options", "perrk_validate", "perrk_init", "perrk_step", "perrk_entropy",
            "perrk_rhs", "perrk_get_relaxation_state", "perrk_set_relaxation_state",
-           "perrk_set_guess_model", "perrk_set_profiling", "perrk_get_kernel_stats",
+           "perrk_set_guess_model", "perrk_set_profiling", "perrk_get_kernel_stats", "perrk_get_stage_stats",
            "perrk_get_tuning", "perrk_last_error", "perrk_version", "perrk_destroy",
            "perrk_mlp_workspace_bytes", "perrk_mlp_forward", "perrk_mlp_loss_grad", "perrk_mlp_adam"]
 
@@ -107,6 +107,8 @@ def lib():
         L.perrk_set_profiling.restype = ctypes.c_int
         L.perrk_get_kernel_stats.argtypes = [p, ctypes.POINTER(KernelStat), ctypes.c_int]
         L.perrk_get_kernel_stats.restype = ctypes.c_int
+        L.perrk_get_stage_stats.argtypes = [p, ctypes.POINTER(KernelStat), ctypes.c_int, ctypes.c_int]
+        L.perrk_get_stage_stats.restype = ctypes.c_int
         L.perrk_get_tuning.argtypes = [p, ctypes.c_char_p, sz]
         L.perrk_get_tuning.restype = ctypes.c_int
         L.perrk_last_error.argtypes = [p]
@@ -199,6 +201,7 @@ class Stepper:
             raise PerrkError(st, "perrk_init failed (see stderr)")
         self.ctx = ctx
         self.n_cases = desc.n_cases
+        self.n_stages = len(desc.c)
         self._infos = (StepInfo * desc.n_cases)()
 
     def _check(self, st):
@@ -261,9 +264,15 @@ class Stepper:
         self._check(lib().perrk_get_kernel_stats(self.ctx, arr, int(reset)))
         return {name: dict(ms=s.ms, bytes=s.bytes, launches=s.launches) for name, s in zip(K_CLASSES, arr)}
 
+    def stage_stats(self, reset=True):
+        """Per-stage profiling statistics: list of dict(ms, bytes, launches), stage 1 first."""
+        arr = (KernelStat * self.n_stages)()
+        self._check(lib().perrk_get_stage_stats(self.ctx, arr, self.n_stages, int(reset)))
+        return [dict(ms=s.ms, bytes=s.bytes, launches=s.launches) for s in arr]
+
     def tuning(self):
-        buf = ctypes.create_string_buffer(256)
-        lib().perrk_get_tuning(self.ctx, buf, 256)
+        buf = ctypes.create_string_buffer(4096)
+        lib().perrk_get_tuning(self.ctx, buf, 4096)
         return buf.value.decode()
 
     def close(self):

@@ -73,3 +73,44 @@ def test_training_fits_a_smooth_target(P):
     model, mean, scale, hist = L.train(X, Y, epochs=400, lr=3e-3)
     pred = L.predict((model, mean, scale), X)
     assert np.sqrt(np.mean((pred - Y) ** 2)) < 0.05 * np.std(Y)
+
+
+def test_step_uses_learned_increment(P):
+    """With every first evaluation accepted (tol_r huge), the accepted gamma is the
+    first evaluation point: gamma_prev for the first three steps of a case, then
+    gamma_prev plus the network's increment for the features of that step."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from helpers import problem_2d
+    from paper_2507_04991_amd import learned_guess as L
+
+    f, U0, tab, dt, lev = problem_2d(nx=8, ny=6, order=3, E=(4, 6, 8, 12))
+    rng = np.random.default_rng(11)
+    w = (rng.normal(scale=0.4, size=M.NPARAM)).astype(np.float32)
+    mean = rng.normal(scale=0.1, size=8).astype(np.float32)
+    scale = np.abs(rng.normal(size=8)).astype(np.float32) + 0.5
+    scale[:3] = 1.0e5  # increments and gamma - 1 are small
+    full = np.concatenate([w, np.array([1.0e-4, 2.0e-5], dtype=np.float32)])
+    d = P.Descriptors([f], [lev], tab)
+    st = P.Stepper(d, P.default_options(guess=P.GUESS_MLP, tol_r=1.0e30))
+    st.set_guess_model(full, mean, scale)
+    u = dev(U0)
+    nb = int(np.count_nonzero(tab["b"]))
+    hist = np.zeros(3)
+    gamma_prev = 1.0
+    for step in range(6):
+        inf = st.step(u, np.array([dt]))[0]
+        expect = gamma_prev
+        if step >= 3:
+            x = L.features(hist, dt, np.asarray(inf["e"]), nb)
+            xn = ((x - mean.astype(np.float64)) * scale.astype(np.float64)).astype(np.float32)
+            y = M.forward(w.astype(np.float64), xn[None, :].astype(np.float64))[0]
+            expect = gamma_prev + (y * float(full[-2]) + float(full[-1]))
+            assert abs(expect - gamma_prev) > 1e-6  # the guess moved the point
+        assert inf["passes"] == 1
+        assert abs(inf["gamma"] - expect) <= 1e-9, (step, inf["gamma"], expect)
+        hist[1:] = hist[:2].copy()
+        hist[0] = inf["gamma"] - 1.0
+        gamma_prev = inf["gamma"]
+    st.close()
