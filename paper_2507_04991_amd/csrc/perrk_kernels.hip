@@ -205,16 +205,12 @@ __device__ __forceinline__ void make_prim(const double *u, double gm1, Prim<T, D
     P.beta = (T)(rho * rcp64(p));
 }
 
-// Single-precision variant: the state is rounded to single precision first and
-// the primitive variables are formed in single precision (reciprocals by the
+// Single-precision variant from a single-precision state (reciprocals by the
 // hardware instruction).  A state whose components exceed the single-precision
 // range counts as non-finite.
 template <int DIM>
-__device__ __forceinline__ void make_prim_f32(const double *u, double gm1, Prim<float, DIM> &P, int &bad)
+__device__ __forceinline__ void prim_f32(const float *uf, double gm1, Prim<float, DIM> &P, int &bad)
 {
-    float uf[DIM + 2];
-#pragma unroll
-    for (int k = 0; k < DIM + 2; ++k) uf[k] = (float)u[k];
     float sum = uf[0];
 #pragma unroll
     for (int k = 1; k < DIM + 2; ++k) sum += uf[k];
@@ -232,6 +228,16 @@ __device__ __forceinline__ void make_prim_f32(const double *u, double gm1, Prim<
     P.rho = rho;
     P.p = p;
     P.beta = rho * __builtin_amdgcn_rcpf(p);
+}
+
+// From a double-precision state, rounded to single precision first.
+template <int DIM>
+__device__ __forceinline__ void make_prim_f32(const double *u, double gm1, Prim<float, DIM> &P, int &bad)
+{
+    float uf[DIM + 2];
+#pragma unroll
+    for (int k = 0; k < DIM + 2; ++k) uf[k] = (float)u[k];
+    prim_f32<DIM>(uf, gm1, P, bad);
 }
 
 // Velocity component d of a state with a runtime d, by selection of values.
@@ -374,26 +380,38 @@ struct NodeRaw {
     KT k1[V], kp[V];
 };
 
-// Element of field v of a node array at byte offset o of the field: the field
-// base is uniform (scalar registers) and o a 32-bit lane offset, so the
-// address costs no vector arithmetic.
-// The field base is passed through an empty asm statement with a scalar-register
-// operand: the compiler then keeps one scalar base per field instead of
-// reassociating base + v * field + o into a vector address per load.
+// Node arrays are read and written with buffer instructions: one resource per
+// field (base = array + v * field, range = the field's bytes; scalar registers)
+// and one 32-bit byte offset per lane, shared by every field and array of the
+// same element size, so an access costs no vector address arithmetic.  The
+// node count of all cases is limited to 2^29, so a field spans less than 4 GiB.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+constexpr int RSRC_WORD3 = 0x00020000;  // word 3 of a raw gfx9 buffer resource: 32-bit data format
+
 template <typename T>
-__device__ __forceinline__ const T &at(const void *base, int v, size_t field, uint32_t o)
+__device__ __forceinline__ Rsrc field_rsrc(const void *base, int v, size_t field)
 {
-    const char *b = reinterpret_cast<const char *>(static_cast<const T *>(base) + v * field);
-    asm("" : "+s"(b));
-    return *reinterpret_cast<const T *>(b + o);
+    T *p = const_cast<T *>(static_cast<const T *>(base)) + (size_t)v * field;
+    return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)(uint32_t)(field * sizeof(T)), RSRC_WORD3);
 }
 
 template <typename T>
-__device__ __forceinline__ T &at_w(void *base, int v, size_t field, uint32_t o)
+__device__ __forceinline__ T bload(Rsrc r, uint32_t o)
 {
-    char *b = reinterpret_cast<char *>(static_cast<T *>(base) + v * field);
-    asm("" : "+s"(b));
-    return *reinterpret_cast<T *>(b + o);
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)o, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)o, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(T x, Rsrc r, uint32_t o)
+{
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, (int)o, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, (int)o, 0, 0);
 }
 
 // base[i] with a 32-bit byte offset (tables indexed by element, case or level
@@ -412,10 +430,10 @@ __device__ __forceinline__ void load_raw(const StageArgs &a, int e, int node, No
     const uint32_t n = (uint32_t)e * NPE + node;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        r.u[v] = at<double>(a.U, v, field, n * 8u);
+        r.u[v] = bload<double>(field_rsrc<double>(a.U, v, field), n * 8u);
         if (KIND != SK_FIRST) {
-            r.k1[v] = at<KT>(a.K1, v, field, n * (uint32_t)sizeof(KT));
-            r.kp[v] = at<KT>(a.Kp, v, field, n * (uint32_t)sizeof(KT));
+            r.k1[v] = bload<KT>(field_rsrc<KT>(a.K1, v, field), n * (uint32_t)sizeof(KT));
+            r.kp[v] = bload<KT>(field_rsrc<KT>(a.Kp, v, field), n * (uint32_t)sizeof(KT));
         }
     }
 }
@@ -431,6 +449,24 @@ __device__ __forceinline__ void combine(const NodeRaw<V, KT> &r, double dt, doub
             double s = c1 * (double)r.k1[v];
             s += (cp != 0.0) ? cp * (double)r.kp[v] : 0.0;
             x = x + dt * s;
+        }
+        u[v] = x;
+    }
+}
+
+// The same in single precision (stages whose fluxes are single precision): U_n is
+// rounded first, the combination is formed in single precision.
+template <int V, typename KT, int KIND>
+__device__ __forceinline__ void combine_f32(const NodeRaw<V, KT> &r, double dt, double c1, double cp, float *u)
+{
+    const float fdt = (float)dt, fc1 = (float)c1, fcp = (float)cp;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        float x = (float)r.u[v];
+        if (KIND != SK_FIRST) {
+            float s = fc1 * (float)r.k1[v];
+            s += (cp != 0.0) ? fcp * (float)r.kp[v] : 0.0f;
+            x = x + fdt * s;
         }
         u[v] = x;
     }
@@ -717,20 +753,34 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         load_raw<DIM, KT, KIND>(a, nb, nn, nr[r]);
     }
 
-    // ---- own stage state, published in LDS; neighbour states kept in registers
+    // ---- own stage state, published in LDS; neighbour states (same case, hence
+    // the same dt) kept in registers.  Single-precision stages form the states in
+    // single precision, the others in double.
     double u[V];
-    combine<V, KT, KIND>(own, dt, c1, cp, u);
+    Prim<T, DIM> PN[FR];
     {
         Prim<T, DIM> me;
-        make_prim<T, DIM>(u, a.gm1, me, bad);
-        lds_put_prim<T, DIM>(slot, node, me);
-    }
-    Prim<T, DIM> PN[FR];
+        if constexpr (sizeof(T) == 4) {
+            float uf[V];
+            combine_f32<V, KT, KIND>(own, dt, c1, cp, uf);
+            prim_f32<DIM>(uf, a.gm1, me, bad);
 #pragma unroll
-    for (int r = 0; r < FR; ++r) {
-        double un[V];
-        combine<V, KT, KIND>(nr[r], dt, nc1[r], ncp[r], un);  // same case, hence the same dt
-        make_prim<T, DIM>(un, a.gm1, PN[r], bad);
+            for (int r = 0; r < FR; ++r) {
+                float unf[V];
+                combine_f32<V, KT, KIND>(nr[r], dt, nc1[r], ncp[r], unf);
+                prim_f32<DIM>(unf, a.gm1, PN[r], bad);
+            }
+        } else {
+            combine<V, KT, KIND>(own, dt, c1, cp, u);
+            make_prim<T, DIM>(u, a.gm1, me, bad);
+#pragma unroll
+            for (int r = 0; r < FR; ++r) {
+                double un[V];
+                combine<V, KT, KIND>(nr[r], dt, nc1[r], ncp[r], un);
+                make_prim<T, DIM>(un, a.gm1, PN[r], bad);
+            }
+        }
+        lds_put_prim<T, DIM>(slot, node, me);
     }
     __syncthreads();
 
@@ -792,16 +842,20 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
             if (KIND == SK_LAST) {
                 double dv = a.bs * k[v];
                 if (a.bsm1 != 0.0)
-                    dv += a.bsm1 * (a.k64_sm1 ? at<double>(a.k64_sm1, v, field, o8) : (double)own.kp[v]);
-                if (a.b1 != 0.0) dv += a.b1 * (a.k64_1 ? at<double>(a.k64_1, v, field, o8) : (double)own.k1[v]);
-                at_w<double>(a.d_out, v, field, o8) = dv;
+                    dv += a.bsm1 * (a.k64_sm1 ? bload<double>(field_rsrc<double>(a.k64_sm1, v, field), o8)
+                                              : (double)own.kp[v]);
+                if (a.b1 != 0.0)
+                    dv += a.b1 * (a.k64_1 ? bload<double>(field_rsrc<double>(a.k64_1, v, field), o8)
+                                          : (double)own.k1[v]);
+                bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
             } else {
-                at_w<KT>(a.Kout, v, field, ok) = (KT)k[v];
-                if (a.k64_out) at_w<double>(a.k64_out, v, field, o8) = k[v];
+                bstore<KT>((KT)k[v], field_rsrc<KT>(a.Kout, v, field), ok);
+                if (a.k64_out) bstore<double>(k[v], field_rsrc<double>(a.k64_out, v, field), o8);
             }
         }
     }
-    if (a.ep_partial != nullptr) {
+    // stages with b_i != 0 run in double precision (u holds the stage state)
+    if (sizeof(T) == 8 && a.ep_partial != nullptr) {
         // entropy production with K_i as it enters d: double when a double copy is
         // kept (or K is stored in double), else as stored
         double w[V];

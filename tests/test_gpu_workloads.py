@@ -1,0 +1,218 @@
+"""Parity on the benchmark workloads at their full sizes, through the C ABI.
+
+  vortex16   16^2 graded quads, p = 2, E = {3, 6}, 100 steps, FP64: every step
+             against the oracle (passes, flags, gamma) and the state at the end.
+  kh64       64^2 graded quads, HLL surface flux, p = 3, E = {4, 6, 8, 12}: FP64
+             steps against the oracle; mixed precision within the single-precision
+             flux bound, per field.
+  tgv32      32^3 graded hexahedra (10.5 M DOF), p = 4, E = {5, 9, 14}: one step
+             in FP64 against the oracle; in mixed precision the right-hand side and
+             a step without relaxation within the bound, gamma certified.
+  ensemble   256 vortex cases (32 M DOF) in the launch configuration the benchmark
+             times (graph capture, autotuned launch shapes): one step, sampled
+             cases recomputed by the oracle one by one.
+
+The same tolerances as the small parity tests: 1e-12 relative error of the
+whole state in FP64; in mixed precision 32 eps32 (2/h)_max F per stage right-hand
+side (F the largest physical flux magnitude), 4 dt times that after one step.
+"""
+import numpy as np
+import pytest
+
+from tests.helpers import field_errors, flux_scale, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_04991_amd import perrk
+    perrk.lib()
+    return perrk
+
+
+def otab(oracle, tab):
+    return oracle.Tableau(tab["order"], tab["c"], tab["b"], tab["a_sub"], tab["E"])
+
+
+def stepper(P, prob, precision=0, **opt):
+    d = P.Descriptors(prob["faces"], prob["lev"], prob["tab"], surface_flux=prob["flux"], precision=precision)
+    st = P.Stepper(d, P.default_options(**opt))
+    u = torch.tensor(prob["U0"], dtype=torch.float64, device="cuda").contiguous()
+    return st, u
+
+
+def mixed_bound(prob, dim, faces=None, U0=None):
+    from paper_2507_04991_amd import workloads as W
+    f = faces if faces is not None else prob["faces"][0]
+    U = U0 if U0 is not None else prob["U0"]
+    hmin = W.element_widths(f).min()
+    return 32 * np.finfo(np.float32).eps * (2.0 / hmin) * flux_scale(U, dim)
+
+
+def test_vortex16_100_steps_fp64(P, oracle):
+    from paper_2507_04991_amd import problems
+    prob = problems.vortex16()
+    f, lev, dt = prob["faces"][0], prob["lev"][0], float(prob["dt"][0])
+    print("case vortex16, 100 steps", flush=True)
+    st, u = stepper(P, prob)
+    Uref, tref, hist = oracle.run(oracle.Mesh(f), otab(oracle, prob["tab"]), lev, prob["U0"], dt, 100)
+    for n in range(100):
+        info = st.step(u, np.array([dt]))[0]
+        h = hist[n]
+        assert info["flags"] == h["flags"] == 0, n
+        assert info["passes"] == h["passes"], n
+        assert abs(info["gamma"] - h["gamma"]) <= 1e-12, n
+        assert abs(info["r"]) <= 1e-12, n
+    assert rel_err(u.cpu().numpy(), Uref) < 1e-12
+    _, _, t = st.relaxation_state()
+    assert abs(t[0] - tref) <= 1e-12 * tref
+    st.close()
+
+
+def test_kh64_hll(P, oracle):
+    from paper_2507_04991_amd import problems
+    prob = problems.kh64()
+    f, lev, dt = prob["faces"][0], prob["lev"][0], float(prob["dt"][0])
+    print("case kh64 hll", flush=True)
+    m, t = oracle.Mesh(f, surface_flux=1), otab(oracle, prob["tab"])
+    st, u = stepper(P, prob)
+    Uref, g = prob["U0"].copy(), 1.0
+    refs = []
+    for n in range(3):
+        info = st.step(u, np.array([dt]))[0]
+        Uref, iref = oracle.step(m, t, lev, Uref, dt, oracle.relax_options(gamma0=g))
+        g = iref["gamma"]
+        refs.append(Uref)
+        assert info["flags"] == iref["flags"] == 0
+        assert info["passes"] == iref["passes"]
+        assert abs(info["gamma"] - iref["gamma"]) <= 1e-12
+        assert rel_err(u.cpu().numpy(), Uref) < 1e-12, n
+    st.close()
+    # mixed precision, one step, per field
+    stm, um = stepper(P, prob, precision=1)
+    K = stm.rhs(um).cpu().numpy().astype(np.float64)
+    Kref = oracle.rhs(m, prob["U0"])
+    bound = mixed_bound(prob, 2)
+    print("kh64 mixed rhs per-field max abs error", field_errors(K, Kref), "bound", bound, flush=True)
+    assert np.abs(K - Kref).max() <= bound
+    info = stm.step(um, np.array([dt]))[0]
+    assert abs(info["r"]) <= 1e-12 and info["flags"] == 0
+    errU = field_errors(um.cpu().numpy(), refs[0])
+    print("kh64 mixed step per-field max abs error", errU, flush=True)
+    assert max(errU) <= 4 * dt * bound
+    stm.close()
+
+
+def test_tgv32_one_step(P, oracle):
+    from paper_2507_04991_amd import problems
+    prob = problems.tgv32()
+    f, lev, dt = prob["faces"][0], prob["lev"][0], float(prob["dt"][0])
+    print("case tgv32 one step", flush=True)
+    Uref, iref = oracle.step(oracle.Mesh(f), otab(oracle, prob["tab"]), lev, prob["U0"], dt)
+    st, u = stepper(P, prob)
+    info = st.step(u, np.array([dt]))[0]
+    assert info["flags"] == iref["flags"] == 0
+    assert info["passes"] == iref["passes"]
+    assert abs(info["gamma"] - iref["gamma"]) <= 1e-12
+    assert rel_err(u.cpu().numpy(), Uref) < 1e-12
+    st.close()
+    # Mixed precision at Mach 0.1: the single-precision right-hand side stays within
+    # its bound (the absolute pressure ~71 and enthalpy ~250 make the relative
+    # error large), and so does a step without relaxation.  With relaxation the
+    # root of r moves with the single-precision error of the stages (r is a small
+    # difference of entropies), so only its certification is asserted; the shift
+    # of gamma is reported.
+    bound = mixed_bound(prob, 3)
+    stm, um = stepper(P, prob, precision=1)
+    K = stm.rhs(um).cpu().numpy().astype(np.float64)
+    Kref = oracle.rhs(oracle.Mesh(f), prob["U0"])
+    print("tgv32 mixed rhs per-field max abs error", field_errors(K, Kref), "bound", bound, flush=True)
+    assert np.abs(K - Kref).max() <= bound
+    info_m = stm.step(um, np.array([dt]))[0]
+    assert abs(info_m["r"]) <= 1e-12 and info_m["flags"] == 0
+    print("tgv32 gamma mixed", info_m["gamma"], "fp64", info["gamma"], flush=True)
+    stm.close()
+    Unr, _ = oracle.step(oracle.Mesh(f), otab(oracle, prob["tab"]), lev, prob["U0"], dt,
+                         oracle.relax_options(relax=False))
+    stn, un = stepper(P, prob, precision=1, relax=0)
+    stn.step(un, np.array([dt]))
+    errU = field_errors(un.cpu().numpy(), Unr)
+    print("tgv32 mixed step without relaxation per-field max abs error", errU, "bound", 4 * dt * bound, flush=True)
+    assert max(errU) <= 4 * dt * bound
+    stn.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ensemble_full_size_sampled(P, oracle, precision):
+    """The whole 256-case ensemble stepped once as the benchmark launches it;
+    eight cases (every mesh size, first and last case) recomputed by the oracle."""
+    from paper_2507_04991_amd import problems
+    prob = problems.ensemble(0, 256)
+    print(f"case ensemble256 precision={precision}", flush=True)
+    st, u = stepper(P, prob, precision=precision)
+    infos = st.step(u, prob["dt"])
+    assert all(abs(i["r"]) <= 1e-12 and i["flags"] == 0 for i in infos)
+    Ug = u.cpu().numpy()
+    sizes = [c["n"] for c in prob["cases"]]
+    pick = {0, len(sizes) - 1}
+    for n in sorted(set(sizes)):
+        idx = [k for k, s in enumerate(sizes) if s == n]
+        pick.update(idx[:2])
+    offs = np.cumsum([0] + [c["U0"].shape[1] for c in prob["cases"]])
+    t = otab(oracle, prob["tab"])
+    for k in sorted(pick):
+        c = prob["cases"][k]
+        Uref, iref = oracle.step(oracle.Mesh(c["faces"]), t, prob["lev"][k], c["U0"], float(prob["dt"][k]))
+        Uk = Ug[:, offs[k]:offs[k + 1]]
+        if precision == 0:
+            assert rel_err(Uk, Uref) < 1e-12, k
+            assert abs(infos[k]["gamma"] - iref["gamma"]) <= 1e-12, k
+            assert infos[k]["passes"] == iref["passes"], k
+        else:
+            bound = 4 * float(prob["dt"][k]) * mixed_bound(prob, 2, c["faces"], c["U0"])
+            err = np.abs(Uk - Uref).max()
+            assert err <= bound, (k, err, bound)
+    st.close()
+
+
+def test_checkpoint_resume_bitwise(P):
+    """State and relaxation state saved after some steps and restored into a new
+    context continue bitwise identically."""
+    from paper_2507_04991_amd import problems
+    prob = problems.vortex16()
+    dt = prob["dt"]
+    st, u = stepper(P, prob)
+    for _ in range(4):
+        st.step(u, dt)
+    u_saved = u.clone()
+    g, off, t = st.relaxation_state()
+    for _ in range(3):
+        st.step(u, dt)
+    st2, _ = stepper(P, prob)
+    st2.set_relaxation_state(g, off, t)
+    u2 = u_saved.clone()
+    for _ in range(3):
+        st2.step(u2, dt)
+    assert torch.equal(u, u2)
+    assert np.array_equal(st.relaxation_state()[2], st2.relaxation_state()[2])
+    st.close()
+    st2.close()
+
+
+def test_learned_guess_gain_on_held_out_cases(P):
+    """The shipped network (trained on another seed's ensemble) against the
+    previous-gamma guess on held-out cases: both accept only certified roots;
+    the mean number of residual passes per step is reported and must not grow."""
+    from paper_2507_04991_amd import learned_guess as L
+    from paper_2507_04991_amd import problems
+    prob = problems.ensemble(7, 128)
+    out = L.evaluate(prob, L.load(L.DEFAULT_MODEL), 60)
+    print("held-out residual passes per step:", out, flush=True)
+    for v in out.values():
+        assert v["r_max"] <= 1e-12 and v["flags"] == 0
+    assert out["learned"]["passes_mean"] <= out["prev"]["passes_mean"] + 1e-9
