@@ -56,10 +56,17 @@ typedef enum {
 
 enum { PERRK_FLUX_EC = 0, PERRK_FLUX_HLL = 1 };
 /* FP64: every operation in double precision.
- * MIXED: volume and surface fluxes in single precision with single-precision
- * accumulation and single-precision stage storage; stage-state formation,
- * direction d, entropy sums and the gamma solve stay double precision. */
-enum { PERRK_FP64 = 0, PERRK_MIXED = 1 };
+ * MIXED: the stages with b_i = 0 compute volume and surface fluxes in single
+ * precision with single-precision accumulation, form their stage states in
+ * single precision and store K_i in single precision; the stages with
+ * b_i != 0 (those entering d and the entropy change dH) run in double
+ * precision; d, entropy sums and the gamma solve are double precision.
+ * MIXED_ALL: every stage in single precision as above; d and the stage
+ * entropy production are accumulated in double precision from the
+ * single-precision K_i, and the gamma solve is double precision, so gamma is
+ * the certified root of r for those K_i (entropy is then conserved to the
+ * single-precision rounding of the K_i rather than to double rounding). */
+enum { PERRK_FP64 = 0, PERRK_MIXED = 1, PERRK_MIXED_ALL = 2 };
 /* STEP: r anchored to H(U_n) (first equality of the discrete entropy balance);
  * INITIAL: to H(U_0), the entropy of the first state stepped (its offset is
  * part of the relaxation state, see perrk_get_relaxation_state). */
@@ -85,7 +92,7 @@ typedef struct {
                                   the domain is periodic in every direction */
     double gas_gamma;          /* ratio of specific heats (> 1) */
     int32_t surface_flux;      /* PERRK_FLUX_EC or PERRK_FLUX_HLL */
-    int32_t precision;         /* PERRK_FP64 or PERRK_MIXED */
+    int32_t precision;         /* PERRK_FP64, PERRK_MIXED or PERRK_MIXED_ALL */
 } perrk_mesh_desc;
 
 typedef struct {
@@ -135,7 +142,7 @@ typedef struct {
 
 /* Default options: relax = 1, max_newton = 10, tol_r = 1e-12, tol_step = 1e-15,
  * anchor = STEP, max_bisect = 60, bracket [0.8, 1.2], guess = PREV,
- * fast_passes = 6, use_graph = 1, tune = 1. */
+ * fast_passes = 3, use_graph = 1, tune = 1. */
 void perrk_default_options(perrk_options *opts);
 
 /* Validates every descriptor on the host (no GPU call): tableau structure,
@@ -170,7 +177,8 @@ int perrk_entropy(perrk_ctx *ctx, const void *u_dev, double *H);
 
 /* k_dev = F(u_dev) on every element: the semidiscretisation the stages
  * evaluate.  k_dev has the stage storage type: double (FP64) or float
- * (MIXED), same layout as u_dev.  Asynchronous on the context's stream. */
+ * (MIXED, MIXED_ALL: single-precision fluxes), same layout as u_dev.
+ * Asynchronous on the context's stream. */
 int perrk_rhs(perrk_ctx *ctx, const void *u_dev, void *k_dev);
 
 /* Previous accepted gamma per case (the Newton starting value) and the

@@ -154,7 +154,7 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
     if (!(m->gas_gamma > 1.0) || !std::isfinite(m->gas_gamma)) return ck.bad("gas_gamma must be > 1");
     if (m->surface_flux != PERRK_FLUX_EC && m->surface_flux != PERRK_FLUX_HLL)
         return ck.bad("unknown surface flux %d", m->surface_flux);
-    if (m->precision != PERRK_FP64 && m->precision != PERRK_MIXED)
+    if (m->precision != PERRK_FP64 && m->precision != PERRK_MIXED && m->precision != PERRK_MIXED_ALL)
         return ck.bad("unknown precision %d", m->precision);
     int64_t total = 0;
     const double *f = m->face_coords;
@@ -318,9 +318,9 @@ void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int
     a.ep_partial = nullptr;
     for (size_t j = 0; j < c->bstages.size(); ++j)
         if (c->bstages[j] == i) a.ep_partial = c->d_ep + j * (size_t)c->nelem;
-    // stages entering d and dH are evaluated in double precision in every mode
+    // MIXED: stages entering d and dH are evaluated in double precision
     const bool mixed = c->precision == PERRK_MIXED;
-    variant = !mixed ? 0 : (c->b[i] != 0.0 ? 2 : 1);
+    variant = c->precision == PERRK_FP64 ? 0 : (mixed && c->b[i] != 0.0 ? 2 : 1);
     if (mixed && i == 0 && c->b[0] != 0.0 && S > 1) a.k64_out = c->d_k64_1;
     if (mixed && S >= 3 && i == S - 2 && c->b[S - 2] != 0.0) a.k64_out = c->d_k64_sm1;
     if (mixed && kind == SK_LAST) {
@@ -449,7 +449,7 @@ void perrk_default_options(perrk_options *o)
     o->bisect_lo = 0.8;
     o->bisect_hi = 1.2;
     o->guess = PERRK_GUESS_PREV;
-    o->fast_passes = 6;
+    o->fast_passes = 3;
     o->use_graph = 1;
     o->tune = 1;
 }
@@ -584,7 +584,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     // algorithmic (compulsory) bytes of each launch
     {
         const double dofe = (double)c->V * c->npe;  // DOF per element
-        const double kb = c->precision == PERRK_MIXED ? 4.0 : 8.0;
+        const double kb = c->precision == PERRK_FP64 ? 8.0 : 4.0;
         std::vector<int64_t> per_level(c->R, 0);
         for (int64_t e = 0; e < c->nelem; ++e) per_level[elem[e].level]++;
         c->stage_bytes.assign(c->S, 0.0);
@@ -622,7 +622,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
 
     // device state
     const size_t M = (size_t)c->V * c->nelem * c->npe;
-    const size_t ks = c->precision == PERRK_MIXED ? 4 : 8;
+    const size_t ks = c->precision == PERRK_FP64 ? 8 : 4;
     auto bail = [&](int code) {
         free_all(c);
         delete c;
@@ -826,7 +826,7 @@ int perrk_rhs(perrk_ctx *c, const void *u_dev, void *k_dev)
     a.gam = c->gam;
     a.gm1 = c->gam - 1.0;
     a.inv_gm1 = 1.0 / (c->gam - 1.0);
-    HIPCHECK(c, launch_stage(c->dim, c->precision == PERRK_MIXED ? 1 : 0, c->flux, SK_FIRST, a, c->d_coef,
+    HIPCHECK(c, launch_stage(c->dim, c->precision == PERRK_FP64 ? 0 : 1, c->flux, SK_FIRST, a, c->d_coef,
                              c->cfg, c->stream));
     HIPCHECK(c, hipEventRecord(c->ev_out, c->stream));
     HIPCHECK(c, hipStreamWaitEvent(c->user_stream, c->ev_out, 0));
@@ -915,7 +915,8 @@ int perrk_get_tuning(perrk_ctx *c, char *buf, size_t len)
     std::string w;
     for (const LaunchCfg &x : c->scfg) w += (w.empty() ? "" : ",") + std::to_string(x.epb_mult);
     std::snprintf(buf, len, "dim=%d precision=%s flux=%s stage_waves_per_workgroup=[%s] fast_passes=%d graph=%d %s",
-                  c->dim, c->precision ? "mixed" : "fp64", c->flux ? "hll" : "ec", w.c_str(), c->opt.fast_passes,
+                  c->dim, c->precision == PERRK_MIXED ? "mixed" : (c->precision == PERRK_MIXED_ALL ? "mixed_all" : "fp64"),
+                  c->flux ? "hll" : "ec", w.c_str(), c->opt.fast_passes,
                   c->opt.use_graph, c->tuned ? c->tune_report.c_str() : "(not tuned)");
     return PERRK_OK;
 }

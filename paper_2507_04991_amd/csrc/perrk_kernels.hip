@@ -141,10 +141,8 @@ __device__ __forceinline__ float lmean(float a, float b)
     const float d = a - b, s = a + b;
     const float rs = __builtin_amdgcn_rcpf(s);
     const float z = d * rs, u = z * z;
-    if (u < 1.0e-2f) {
-        const float P = 1.0f + u * ((float)C_R1 + u * ((float)C_R2 + u * (float)C_R3));
-        return 0.5f * s * P;
-    }
+    if (u < 1.0e-2f)
+        return s * (0.5f + u * ((float)(0.5 * C_R1) + u * ((float)(0.5 * C_R2) + u * (float)(0.5 * C_R3))));
     return d * __builtin_amdgcn_rcpf(__logf(a * __builtin_amdgcn_rcpf(b)));
 }
 
@@ -153,10 +151,8 @@ __device__ __forceinline__ float inv_lmean(float a, float b)
     const float d = a - b, s = a + b;
     const float rs = __builtin_amdgcn_rcpf(s);
     const float z = d * rs, u = z * z;
-    if (u < 1.0e-2f) {
-        const float F = 1.0f + u * (1.0f / 3.0f + u * (1.0f / 5.0f + u * (1.0f / 7.0f)));
-        return 2.0f * rs * F;
-    }
+    if (u < 1.0e-2f)
+        return rs * (2.0f + u * ((float)(2.0 / 3.0) + u * ((float)(2.0 / 5.0) + u * (float)(2.0 / 7.0))));
     return __logf(a * __builtin_amdgcn_rcpf(b)) * __builtin_amdgcn_rcpf(d);
 }
 
@@ -256,15 +252,19 @@ __device__ __forceinline__ void flux_ec(int d, const Prim<T, DIM> &L, const Prim
 {
     const T rm = lmean(L.rho, R.rho);
     const T ibm = inv_lmean(L.beta, R.beta);
+    T va[DIM];  // arithmetic means of the velocity components
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) va[k] = (T)0.5 * (L.v[k] + R.v[k]);
     const T vl = vdir<T, DIM>(L, d), vr = vdir<T, DIM>(R, d);
-    const T fr = rm * (T)0.5 * (vl + vr);
+    const T vm = DIM == 2 ? (d == 0 ? va[0] : va[1]) : (d == 0 ? va[0] : (d == 1 ? va[1] : va[DIM - 1]));
+    const T fr = rm * vm;
     const T pa = (T)0.5 * (L.p + R.p);
     T vv = 0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) vv += L.v[k] * R.v[k];
     f[0] = fr;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) f[1 + k] = fr * (T)0.5 * (L.v[k] + R.v[k]) + (k == d ? pa : (T)0);
+    for (int k = 0; k < DIM; ++k) f[1 + k] = fr * va[k] + (k == d ? pa : (T)0);
     f[DIM + 1] = fr * ((T)0.5 * vv + inv_gm1 * ibm) + (T)0.5 * (L.p * vr + R.p * vl);
 }
 
@@ -765,6 +765,8 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
             combine_f32<V, KT, KIND>(own, dt, c1, cp, uf);
             prim_f32<DIM>(uf, a.gm1, me, bad);
 #pragma unroll
+            for (int v = 0; v < V; ++v) u[v] = (double)uf[v];  // for the entropy production
+#pragma unroll
             for (int r = 0; r < FR; ++r) {
                 float unf[V];
                 combine_f32<V, KT, KIND>(nr[r], dt, nc1[r], ncp[r], unf);
@@ -854,8 +856,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
             }
         }
     }
-    // stages with b_i != 0 run in double precision (u holds the stage state)
-    if (sizeof(T) == 8 && a.ep_partial != nullptr) {
+    if (a.ep_partial != nullptr) {
         // entropy production with K_i as it enters d: double when a double copy is
         // kept (or K is stored in double), else as stored
         double w[V];

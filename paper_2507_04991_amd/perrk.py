@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libperrk.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENONPHYS, ENONFINITE, WARN_FALLBACK = 0, -1, -2, -3, -4, -5, 1
 FLUX_EC, FLUX_HLL = 0, 1
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_ALL = 0, 1, 2
 ANCHOR_STEP, ANCHOR_INITIAL = 0, 1
 GUESS_PREV, GUESS_MLP = 0, 1
 FLAG_BISECT, FLAG_FALLBACK, FLAG_TRIVIAL = 1, 2, 4
@@ -232,7 +232,7 @@ class Stepper:
 
     def rhs(self, u):
         t = self._torch
-        dtype = t.float32 if self.desc.mesh.precision == MIXED else t.float64
+        dtype = t.float64 if self.desc.mesh.precision == FP64 else t.float32
         k = t.empty_like(u, dtype=dtype)
         self._check(lib().perrk_rhs(self.ctx, self._u(u), ctypes.c_void_p(k.data_ptr())))
         return k
