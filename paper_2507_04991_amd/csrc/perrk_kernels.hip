@@ -84,11 +84,12 @@ __device__ __forceinline__ double node_weight(int node)
 // ---------------------------------------------------------------- log mean
 // L(a, b) = (a - b) / (log a - log b).  With s = a + b, z = (a - b)/s, u = z^2:
 // log(a/b) = 2 z (1 + u/3 + u^2/5 + ...) = 2 z F(u), so L = (s/2) / F(u) and
-// 1/L = (2/s) F(u).  For u < 1e-2 both are evaluated by series (1/F(u) =
-// 1 - u/3 - 4u^2/45 - 44u^3/945 - 428u^4/14175 - ..., coefficients of the
-// reciprocal power series; truncated after u^8 in double, u^3 in single
-// precision, below the rounding unit) with a single reciprocal; otherwise
-// from log1p((a-b)/b) (hardware logarithm of the ratio in single precision).
+// 1/L = (2/s) F(u).  Near a = b both are evaluated by series with a single
+// reciprocal (1/F(u) = 1 - u/3 - 4u^2/45 - 44u^3/945 - 428u^4/14175 - ...,
+// coefficients of the reciprocal power series): in double precision for
+// u < 2.5e-3, truncated after u^6; in single precision for u < 1e-2, truncated
+// after u^3 (the omitted terms are below the rounding unit).  Otherwise from
+// log1p((a-b)/b) (the hardware logarithm of the ratio in single precision).
 #define C_R1 (-1.0 / 3.0)
 #define C_R2 (-4.0 / 45.0)
 #define C_R3 (-44.0 / 945.0)
@@ -97,6 +98,14 @@ __device__ __forceinline__ double node_weight(int node)
 #define C_R6 (-10719068.0 / 638512875.0)
 #define C_R7 (-25865068.0 / 1915538625.0)
 #define C_R8 (-5472607916.0 / 488462349375.0)
+
+// 1/x as every kernel computes it: the hardware reciprocal in single precision,
+// the refined one below in double (the same expression wherever a value must
+// agree bit for bit, e.g. rho / p on both sides of a face).
+template <typename T>
+__device__ __forceinline__ T recip(T x);
+template <>
+__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // 1/x for finite nonzero x: the hardware reciprocal estimate refined by two
 // Newton steps r <- r + r (1 - x r) (error within an ulp, cheaper than the
@@ -110,14 +119,16 @@ __device__ __forceinline__ double rcp64(double x)
     return fma(r, e, r);
 }
 
+template <>
+__device__ __forceinline__ double recip<double>(double x) { return rcp64(x); }
+
 __device__ __forceinline__ double lmean(double a, double b)
 {
     const double d = a - b, s = a + b;
     const double rs = rcp64(s);
     const double z = d * rs, u = z * z;
-    if (u < 1.0e-2) {
-        const double P = 1.0 + u * (C_R1 + u * (C_R2 + u * (C_R3 + u * (C_R4 + u * (C_R5 + u * (C_R6 +
-                         u * (C_R7 + u * C_R8)))))));
+    if (u < 2.5e-3) {
+        const double P = 1.0 + u * (C_R1 + u * (C_R2 + u * (C_R3 + u * (C_R4 + u * (C_R5 + u * C_R6)))));
         return 0.5 * s * P;
     }
     return d / log1p(d / b);
@@ -128,9 +139,9 @@ __device__ __forceinline__ double inv_lmean(double a, double b)
     const double d = a - b, s = a + b;
     const double rs = rcp64(s);
     const double z = d * rs, u = z * z;
-    if (u < 1.0e-2) {
+    if (u < 2.5e-3) {
         const double F = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0 + u * (1.0 / 9.0 +
-                         u * (1.0 / 11.0 + u * (1.0 / 13.0 + u * (1.0 / 15.0 + u * (1.0 / 17.0))))))));
+                         u * (1.0 / 11.0 + u * (1.0 / 13.0))))));
         return 2.0 * rs * F;
     }
     return log1p(d / b) / d;
@@ -156,10 +167,7 @@ __device__ __forceinline__ float inv_lmean(float a, float b)
     return __logf(a * __builtin_amdgcn_rcpf(b)) * __builtin_amdgcn_rcpf(d);
 }
 
-template <typename T>
-__device__ __forceinline__ T recip(T x) { return (T)1 / x; }
-template <>
-__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 
 // ---------------------------------------------------------------- node data
 template <typename T, int DIM>
@@ -198,7 +206,7 @@ __device__ __forceinline__ void make_prim(const double *u, double gm1, Prim<T, D
 #pragma unroll
     for (int k = 0; k < DIM; ++k) P.v[k] = (T)v[k];
     P.p = (T)p;
-    P.beta = (T)(rho * rcp64(p));
+    P.beta = (T)(rho * recip<double>(p));
 }
 
 // Single-precision variant from a single-precision state (reciprocals by the
@@ -223,7 +231,7 @@ __device__ __forceinline__ void prim_f32(const float *uf, double gm1, Prim<float
     else if (!(rho > 0.0f) || !(p > 0.0f)) bad |= 1;
     P.rho = rho;
     P.p = p;
-    P.beta = rho * __builtin_amdgcn_rcpf(p);
+    P.beta = rho * recip<float>(p);
 }
 
 // From a double-precision state, rounded to single precision first.
@@ -482,8 +490,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 }
 
 // ---------------------------------------------------------------- stage kernel
-// LDS per element slot (flux precision T), structure of arrays:
-//   prim[NQ][NPE]   own stage state: rho, v_0..v_{DIM-1}, p, rho/p
+// LDS per element slot (flux precision T):
+//   prim[NPE][NQ]   own stage state per node: rho, v_0..v_{DIM-1}, p
 //   sf[V][NFN]      lifted surface flux of each face node (+-6 f*), NFN = 2 DIM NPE/4
 //   vf[V][NPP]      two-point fluxes of the pairs of the current phase (up to two directions)
 template <int DIM>
@@ -493,7 +501,7 @@ struct SG {
     static constexpr int NFN = 2 * DIM * NLINE;  // face nodes
     static constexpr int NPD = 6 * NLINE;        // node pairs per direction
     static constexpr int NPP = 2 * NPD;          // pairs held per phase
-    static constexpr int NQ = DIM + 3;
+    static constexpr int NQ = DIM + 2;
     static constexpr int SLOT = NQ * NPE + V * NFN + V * NPP;  // LDS words per element slot
 };
 
@@ -578,26 +586,30 @@ __device__ __forceinline__ bool pair_of(int rd, int lane, int &es, int &dd, int 
     return lane < 32;
 }
 
+// Primitive variables of a node in LDS: rho, v_0..v_{DIM-1}, p, contiguous per
+// node (one or two wide LDS reads); rho/p is formed on reading with the same
+// expression make_prim uses.
 template <typename T, int DIM>
 __device__ __forceinline__ void lds_put_prim(T *slot, int node, const Prim<T, DIM> &P)
 {
-    constexpr int NPE = SG<DIM>::NPE;
-    slot[node] = P.rho;
+    constexpr int NQ = SG<DIM>::NQ;
+    T *q = slot + node * NQ;
+    q[0] = P.rho;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) slot[(1 + k) * NPE + node] = P.v[k];
-    slot[(DIM + 1) * NPE + node] = P.p;
-    slot[(DIM + 2) * NPE + node] = P.beta;
+    for (int k = 0; k < DIM; ++k) q[1 + k] = P.v[k];
+    q[DIM + 1] = P.p;
 }
 
 template <typename T, int DIM>
 __device__ __forceinline__ void lds_get_prim(const T *slot, int node, Prim<T, DIM> &P)
 {
-    constexpr int NPE = SG<DIM>::NPE;
-    P.rho = slot[node];
+    constexpr int NQ = SG<DIM>::NQ;
+    const T *q = slot + node * NQ;
+    P.rho = q[0];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) P.v[k] = slot[(1 + k) * NPE + node];
-    P.p = slot[(DIM + 1) * NPE + node];
-    P.beta = slot[(DIM + 2) * NPE + node];
+    for (int k = 0; k < DIM; ++k) P.v[k] = q[1 + k];
+    P.p = q[DIM + 1];
+    P.beta = P.rho * recip<T>(P.p);
 }
 
 // Two-point volume fluxes of the pairs of directions [D0, D0 + ND), one pair per
@@ -733,6 +745,18 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     }
     NodeRaw<V, KT> own;
     load_raw<DIM, KT, KIND>(a, e, node, own);
+    // last stage: the double-precision copies of K_1 / K_{S-1} that enter d are
+    // loaded here too, so that their latency overlaps the flux work
+    double k64sm1[V], k64_1[V];  // (double-precision stages only; mixed precision keeps these copies)
+    if constexpr (KIND == SK_LAST && sizeof(T) == 8) {
+        const size_t field = (size_t)a.nelem * NPE;
+        const uint32_t o8 = ((uint32_t)e * NPE + node) * 8u;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            k64sm1[v] = a.k64_sm1 ? bload<double>(field_rsrc<double>(a.k64_sm1, v, field), o8) : 0.0;
+            k64_1[v] = a.k64_1 ? bload<double>(field_rsrc<double>(a.k64_1, v, field), o8) : 0.0;
+        }
+    }
     FaceNode<DIM> F[FR];
     bool fv[FR];
     NodeRaw<V, KT> nr[FR];
@@ -843,12 +867,13 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         for (int v = 0; v < V; ++v) {
             if (KIND == SK_LAST) {
                 double dv = a.bs * k[v];
-                if (a.bsm1 != 0.0)
-                    dv += a.bsm1 * (a.k64_sm1 ? bload<double>(field_rsrc<double>(a.k64_sm1, v, field), o8)
-                                              : (double)own.kp[v]);
-                if (a.b1 != 0.0)
-                    dv += a.b1 * (a.k64_1 ? bload<double>(field_rsrc<double>(a.k64_1, v, field), o8)
-                                          : (double)own.k1[v]);
+                double ksm1 = (double)own.kp[v], k1 = (double)own.k1[v];
+                if constexpr (sizeof(T) == 8) {
+                    if (a.k64_sm1) ksm1 = k64sm1[v];
+                    if (a.k64_1) k1 = k64_1[v];
+                }
+                if (a.bsm1 != 0.0) dv += a.bsm1 * ksm1;
+                if (a.b1 != 0.0) dv += a.b1 * k1;
                 bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
             } else {
                 bstore<KT>((KT)k[v], field_rsrc<KT>(a.Kout, v, field), ok);
