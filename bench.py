@@ -323,6 +323,27 @@ def main():
     # right-hand-side evaluations per step, counted in DOF: sum_r E^(r) M^(r)
     E = np.asarray(wl["tab"]["E"])
     n_rhs = float(sum(E[np.asarray(lv)].sum() for lv in wl["lev"])) * (M / wl["U0"].shape[1])
+    if not args.no_compare:
+        # the paper's comparison: the same mesh, dt and steps with every element on the
+        # largest-E level (the single-level method P-ERRK_{p;S_max}); tau / tau* and
+        # N_RHS / N_RHS* with * = multirate
+        R = len(E)
+        wl1 = dict(wl, lev=[np.full_like(np.asarray(lv), R - 1) for lv in wl["lev"]])
+        head = plan[0]
+        one = run_variant(P, torch, wl1, head[1], args.steps, args.warmup,
+                          guess=P.GUESS_MLP if head[2] else P.GUESS_PREV, model=model if head[2] else None)
+        n_rhs1 = float(E[-1]) * M
+        cmp = dict(variant=head_name, single_level_ms_per_step=one["seconds"] / args.steps * 1e3,
+                   multirate_ms_per_step=mixed["seconds"] / args.steps * 1e3,
+                   tau_ratio=one["seconds"] / mixed["seconds"], n_rhs_ratio=n_rhs1 / n_rhs,
+                   single_level_newton_passes_per_step=one["passes_mean"], single_level_max_abs_r=one["r_max"])
+        if wl["kind"] == "ensemble":
+            e1 = ensemble_l2_errors(wl, one["u"].cpu().numpy(), one["t"])
+            em = ensemble_l2_errors(wl, mixed["u"].cpu().numpy(), mixed["t"])
+            cmp.update(l2_error_mean_single_level=float(e1.mean()), l2_error_mean_multirate=float(em.mean()))
+        print(f"# single level: {cmp['single_level_ms_per_step']:.3f} ms/step, tau/tau* {cmp['tau_ratio']:.3f}, "
+              f"N_RHS/N_RHS* {cmp['n_rhs_ratio']:.3f}", file=sys.stderr, flush=True)
+        extra["multirate_vs_single_level"] = cmp
     extra.update(rhs_dof_evals_per_step=n_rhs, rhs_dof_evals_per_s=n_rhs * args.steps / mixed["seconds"],
                  newton_passes_per_step=mixed["passes_mean"], max_abs_r=mixed["r_max"])
     line.update(extra)

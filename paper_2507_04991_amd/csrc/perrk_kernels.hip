@@ -480,6 +480,18 @@ __device__ __forceinline__ void combine_f32(const NodeRaw<V, KT> &r, double dt, 
     }
 }
 
+// Synchronisation of the stage kernel's LDS phases.  Each wavefront reads and
+// writes only its own element slots, and the LDS operations of one wavefront
+// are performed in issue order, so no workgroup barrier is needed: the
+// wavefront-scope fences and the wave barrier only keep the compiler from
+// moving LDS accesses across the phase boundary.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Workgroups are handed to the 8 XCDs of the device round-robin; renumber them
 // so that each XCD works on one contiguous range of logical blocks (neighbouring
 // elements then share that XCD's L2).
@@ -713,9 +725,10 @@ namespace {
 // T: flux arithmetic; KT: stage storage.  Lane = node of the element slot
 // lane / NPE of its wavefront.  Memory access is arranged so that the global
 // loads of a lane form at most three dependent levels, all issued before the
-// first barrier: the active entry (element, level, case); then the element's
-// own U_n / K_1 / K_{i-1}, dt, its level coefficients and the neighbour words of
-// its face nodes; then the neighbours' data at the matching nodes.
+// first LDS phase boundary: the active entry (element, level, case); then the
+// element's own U_n / K_1 / K_{i-1}, dt, its level coefficients and the
+// neighbour words of its face nodes; then the neighbours' data at the matching
+// nodes.  A wavefront never waits for the other wavefronts of its workgroup.
 template <int DIM, typename T, typename KT, int FLUX, int KIND>
 __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageArgs a, const double *coef)
 {
@@ -808,7 +821,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         }
         lds_put_prim<T, DIM>(slot, node, me);
     }
-    __syncthreads();
+    wave_lds_sync();
 
     // ---- surface fluxes, lifted: +6 f* on right faces, -6 f* on left (+-1/q_boundary)
 #pragma unroll
@@ -846,12 +859,12 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
 #pragma unroll
     for (int v = 0; v < V; ++v) du[v] = 0;
     volume_pairs<DIM, T, 0, 2>(lds, wave, lane, inv_gm1);
-    __syncthreads();
+    wave_lds_sync();
     gather<DIM, T, 0, 2>(slot, node, ei, du);
     if constexpr (DIM == 3) {
-        __syncthreads();
+        wave_lds_sync();
         volume_pairs<DIM, T, 2, 1>(lds, wave, lane, inv_gm1);
-        __syncthreads();
+        wave_lds_sync();
         gather<DIM, T, 2, 1>(slot, node, ei, du);
     }
 

@@ -47,6 +47,8 @@ def pick_levels(kind, lev, R, n, seed):
         return np.random.default_rng(seed + 17).integers(0, R, size=n).astype(np.int32)
     if kind == "roundrobin":
         return (np.arange(n) % R).astype(np.int32)
+    if kind == "single":  # every element on the largest-E level: the single-level method
+        return np.full(n, R - 1, dtype=np.int32)
     raise ValueError(kind)
 
 
