@@ -344,6 +344,32 @@ def main():
         print(f"# single level: {cmp['single_level_ms_per_step']:.3f} ms/step, tau/tau* {cmp['tau_ratio']:.3f}, "
               f"N_RHS/N_RHS* {cmp['n_rhs_ratio']:.3f}", file=sys.stderr, flush=True)
         extra["multirate_vs_single_level"] = cmp
+        # relaxed classic RK4 (R-RK_{4;4}) at its own stable step, compared per unit of
+        # simulated time: tau / tau* = (ms per step / dt) ratio, with * = multirate
+        from paper_2507_04991_amd import tableau as T
+        from paper_2507_04991_amd import workloads as W
+        rk4 = T.classic_rk4()
+        dim = len(wl["faces"][0])
+        dts4, levs4, off = [], [], 0
+        for k, faces in enumerate(wl["faces"]):
+            ne = np.asarray(wl["lev"][k]).shape[0]
+            dt4, lv4 = T.assign_levels(rk4, W.element_widths(faces).min(axis=1),
+                                       W.max_wave_speed(wl["U0"][:, off:off + ne], dim))
+            dts4.append(dt4)
+            levs4.append(lv4)
+            off += ne
+        wl4 = dict(wl, tab=rk4, lev=levs4, dt=np.array(dts4))
+        r4 = run_variant(P, torch, wl4, head[1], args.steps, args.warmup)
+        ratio_dt = float(np.mean(np.asarray(wl["dt"]) / np.array(dts4)))
+        ms4 = r4["seconds"] / args.steps * 1e3
+        ms_m = mixed["seconds"] / args.steps * 1e3
+        rk = dict(precision_mode=head_name.replace("+learned", ""), rk4_ms_per_step=ms4,
+                  dt_ratio_multirate_over_rk4=ratio_dt, tau_ratio=ms4 * ratio_dt / ms_m,
+                  n_rhs_ratio=4.0 * M * ratio_dt / n_rhs, rk4_newton_passes_per_step=r4["passes_mean"],
+                  rk4_max_abs_r=r4["r_max"])
+        print(f"# relaxed RK4: {ms4:.3f} ms/step at dt x {1 / ratio_dt:.3f}, tau/tau* {rk['tau_ratio']:.3f}, "
+              f"N_RHS/N_RHS* {rk['n_rhs_ratio']:.3f}", file=sys.stderr, flush=True)
+        extra["multirate_vs_relaxed_rk4"] = rk
     extra.update(rhs_dof_evals_per_step=n_rhs, rhs_dof_evals_per_s=n_rhs * args.steps / mixed["seconds"],
                  newton_passes_per_step=mixed["passes_mean"], max_abs_r=mixed["r_max"])
     line.update(extra)

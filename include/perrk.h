@@ -106,7 +106,9 @@ typedef struct {
     int32_t n_levels;          /* 1..16 */
     const int32_t *E;          /* [n_levels] stage evaluations, 2..S */
     const double *c;           /* [S] abscissae shared by all levels */
-    const double *b;           /* [S] weights shared by all levels; nonzero only at i = 1, S-1, S */
+    const double *b;           /* [S] weights shared by all levels, >= 0; at most 8 nonzero, and every
+                                  level must evaluate each stage i > 1 with b_i != 0 (the archetypes
+                                  have b_i != 0 only at i = 1, S-1, S; classic RK4 has four) */
     const double *a_sub;       /* [n_levels][S]: a^(r)_{i,i-1}; a^(r)_{i,1} = c_i - a^(r)_{i,i-1}.
                                   Must vanish for stages a level skips and for its first
                                   evaluated stage after K_1. */
@@ -134,7 +136,7 @@ typedef struct {
     double r;          /* relaxation residual at the accepted gamma */
     double dH;         /* dt sum_i b_i <W(U_{n,i}), K_i> */
     double H_delta;    /* H(U_{n+1}) - H(U_n) as integrated by the residual */
-    double e[3];       /* <W(U_{n,i}), K_i> of the stages with b_i != 0, in stage order */
+    double e[8];       /* <W(U_{n,i}), K_i> of the stages with b_i != 0, in stage order (at most 8) */
     double t;          /* accumulated relaxed time sum gamma dt since init */
     int32_t passes;    /* residual evaluations (full-mesh reductions) of the solve */
     int32_t flags;     /* PERRK_FLAG_* */

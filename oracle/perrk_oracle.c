@@ -744,6 +744,10 @@ int or_step(const or_mesh *m, const or_tableau *t, const int *level, const or_re
 {
     int st = or_validate(m, t, level);
     if (st) return st;
+    /* this form keeps K_1, K_{S-1} and K_S for d: other nonzero weights need the
+       dense form (or_step_dense) */
+    for (int i = 1; i < t->S - 2; ++i)
+        if (t->b[i] != 0.0) return OR_EINVAL;
     st = or_check_state(m, U);
     if (st) return st;
     int S = t->S, ne = or_nelem(m), npe = or_npe(m->dim), V = m->dim + 2;

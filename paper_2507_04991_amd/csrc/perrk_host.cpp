@@ -192,8 +192,11 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
     for (int i = 0; i < S; ++i) {
         if (!std::isfinite(t->c[i]) || !std::isfinite(t->b[i])) return ck.bad("non-finite c or b");
         if (t->b[i] < 0.0) return ck.bad("b_%d < 0", i + 1);
-        if (t->b[i] != 0.0 && !(i == 0 || i >= S - 2))
-            return ck.bad("b_%d != 0: only b_1, b_{S-1}, b_S may be nonzero", i + 1);
+    }
+    {
+        int nb = 0;
+        for (int i = 0; i < S; ++i) nb += t->b[i] != 0.0;
+        if (nb > PERRK_MAXB) return ck.bad("%d weights b_i != 0: at most %d", nb, PERRK_MAXB);
     }
     for (int r = 0; r < R; ++r) {
         const int E = t->E[r];
@@ -206,8 +209,10 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
                 return ck.bad("level %d: stage %d is skipped or first evaluated, a_{i,i-1} must be 0", r,
                               i + 1);
         }
-        if (S >= 3 && t->b[S - 2] != 0.0 && E < 3)
-            return ck.bad("b_{S-1} != 0 needs every level to evaluate stage S-1 (E >= 3)");
+        for (int i = 1; i < S; ++i)
+            if (t->b[i] != 0.0 && i < S - E + 1)
+                return ck.bad("b_%d != 0 needs every level to evaluate stage %d (level %d has E = %d)", i + 1,
+                              i + 1, r, E);
     }
     // order conditions of the partitioned method for every level combination
     std::vector<double> one(S, 1.0), cv(t->c, t->c + S), c2(S), c3(S);
@@ -315,6 +320,18 @@ void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int
     a.b1 = c->b[0];
     a.bsm1 = (S >= 3) ? c->b[S - 2] : 0.0;
     a.bs = c->b[S - 1];
+    // stages with b_i != 0 other than 1, S-1, S add b_i K_i to d as they finish
+    // (the first of them writes d); the last stage then adds its terms to d
+    bool any_acc = false;
+    for (int j = 1; j < S - 2; ++j) {
+        if (c->b[j] == 0.0) continue;
+        if (j == i) {
+            a.b_acc = c->b[j];
+            a.acc_mode = any_acc ? 2 : 1;
+        }
+        any_acc = true;
+    }
+    if (i == S - 1) a.d_has = any_acc ? 1 : 0;
     a.ep_partial = nullptr;
     for (size_t j = 0; j < c->bstages.size(); ++j)
         if (c->bstages[j] == i) a.ep_partial = c->d_ep + j * (size_t)c->nelem;
@@ -575,7 +592,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     rp.relax = o.relax;
     rp.guess = o.guess;
     rp.nb = (int)c->bstages.size();
-    for (int j = 0; j < rp.nb && j < 3; ++j) rp.bw[j] = c->b[c->bstages[j]];
+    for (int j = 0; j < rp.nb && j < PERRK_MAXB; ++j) rp.bw[j] = c->b[c->bstages[j]];
     c->rp = rp;
     c->cfg.epb_mult = 4;
     c->scfg.assign(c->S, c->cfg);
@@ -588,6 +605,9 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
         std::vector<int64_t> per_level(c->R, 0);
         for (int64_t e = 0; e < c->nelem; ++e) per_level[elem[e].level]++;
         c->stage_bytes.assign(c->S, 0.0);
+        int first_acc = -1;  // first stage with b_i != 0 other than 1, S-1, S
+        for (int j = 1; j < c->S - 2 && first_acc < 0; ++j)
+            if (c->b[j] != 0.0) first_acc = j;
         for (int i = 0; i < c->S; ++i) {
             double bytes = 0.0;
             for (int r = 0; r < c->R; ++r) {
@@ -605,11 +625,13 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
                     if (cp != 0.0) be += kb;                          // K_{i-1}
                     if (last) {
                         be += 8.0;                                    // write d
+                        if (first_acc >= 0) be += 8.0;                // read the accumulated d
                         if (c->S >= 3 && c->b[c->S - 2] != 0.0) be += mixed ? 8.0 : (cp != 0.0 ? 0.0 : kb);
                         if (c->b[0] != 0.0 && mixed) be += 8.0;       // double K_1 for d
                     } else {
                         be += kb;                                     // write K_i
                         if (mixed && i == c->S - 2 && c->b[i] != 0.0) be += 8.0;  // its double copy
+                        if (i < c->S - 2 && c->b[i] != 0.0) be += first_acc == i ? 8.0 : 16.0;  // d
                     }
                 }
                 bytes += be * dofe * per_level[r];
@@ -660,7 +682,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
         if (c->b[0] != 0.0) HIPINIT(hipMalloc(&c->d_k64_1, sizeof(double) * M));
         if (c->S >= 3 && c->b[c->S - 2] != 0.0) HIPINIT(hipMalloc(&c->d_k64_sm1, sizeof(double) * M));
     }
-    HIPINIT(hipMalloc(&c->d_ep, sizeof(double) * 3 * c->nelem));
+    HIPINIT(hipMalloc(&c->d_ep, sizeof(double) * std::max<size_t>(1, c->bstages.size()) * c->nelem));
     HIPINIT(hipMalloc(&c->d_partial, sizeof(double) * 4 * c->nelem));
     HIPINIT(hipMalloc(&c->d_H, sizeof(double) * c->n_cases));
     HIPINIT(hipMalloc(&c->d_dt, sizeof(double) * c->n_cases * perrk_ctx::NRING));
@@ -778,7 +800,7 @@ int perrk_step(perrk_ctx *c, void *u_dev, const double *dt, perrk_step_info *inf
         I.r = C.r;
         I.dH = C.dH;
         I.H_delta = C.H_delta;
-        for (int j = 0; j < 3; ++j) I.e[j] = C.e[j];
+        for (int j = 0; j < PERRK_MAXB; ++j) I.e[j] = C.e[j];
         I.t = C.t;
         I.passes = C.passes;
         I.flags = C.flags;

@@ -11,6 +11,7 @@
 #define PERRK_NBR_MASK 0x0FFFFFFF
 #define PERRK_NBR_SHIFT 28
 #define PERRK_MAXS 64        // stages
+#define PERRK_MAXB 8         // stages with b_i != 0 (entropy-production slots)
 #define PERRK_RED_THREADS 1024  // block size of every per-case reduction (fixed: results depend on it)
 #define PERRK_MLP_NW 1377
 
@@ -47,7 +48,7 @@ struct CaseState {
     double lo, hi;      // bisection bracket
     double offset;      // H(U_n) - H(U_0) (initial anchoring)
     double H_delta;     // H(U_{n+1}) - H(U_n) at the accepted gamma
-    double e[3];        // stage entropy production of the b_i != 0 stages
+    double e[PERRK_MAXB];  // stage entropy production of the b_i != 0 stages
     double t;           // accumulated relaxed time
     double ghist[3];    // last three accepted gamma - 1, most recent first (learned guess features)
     int32_t state, k, iters, passes, flags, bis_count, widen, trivial;
@@ -60,7 +61,7 @@ struct RelaxParams {
     int32_t max_newton, max_bisect, anchor, relax;
     int32_t guess;
     int32_t nb;          // number of b != 0 stages (entropy-production slots)
-    double bw[3];        // their weights
+    double bw[PERRK_MAXB];  // their weights
 };
 
 // Arguments of one stage launch.  The per-level coefficients of the stage live
@@ -80,6 +81,9 @@ struct StageArgs {
     int64_t nelem;
     double gam, gm1, inv_gm1; // gamma, gamma - 1, 1 / (gamma - 1)
     double b1, bsm1, bs;      // last stage weights
+    double b_acc;             // stages with b_i != 0 other than 1, S-1, S: b_i (K_i enters d here)
+    int32_t acc_mode;         //   1: d = b_i K_i, 2: d += b_i K_i, 0: no contribution
+    int32_t d_has;            // last stage: d already holds the contributions of such stages
     double *k64_out;          // optional double copy of K_i (b_i != 0 stages in mixed precision)
     const double *k64_1;      // last stage: double copies of K_1 and K_{S-1}, or NULL to read the
     const double *k64_sm1;    //   stage storage

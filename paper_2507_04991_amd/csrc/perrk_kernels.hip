@@ -760,6 +760,13 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     load_raw<DIM, KT, KIND>(a, e, node, own);
     // last stage: the double-precision copies of K_1 / K_{S-1} that enter d are
     // loaded here too, so that their latency overlaps the flux work
+    double dacc[V];  // last stage: the contributions to d accumulated by earlier stages
+    if constexpr (KIND == SK_LAST) {
+        const size_t field = (size_t)a.nelem * NPE;
+        const uint32_t o8 = ((uint32_t)e * NPE + node) * 8u;
+#pragma unroll
+        for (int v = 0; v < V; ++v) dacc[v] = a.d_has ? bload<double>(field_rsrc<double>(a.d_out, v, field), o8) : 0.0;
+    }
     double k64sm1[V], k64_1[V];  // (double-precision stages only; mixed precision keeps these copies)
     if constexpr (KIND == SK_LAST && sizeof(T) == 8) {
         const size_t field = (size_t)a.nelem * NPE;
@@ -887,10 +894,16 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
                 }
                 if (a.bsm1 != 0.0) dv += a.bsm1 * ksm1;
                 if (a.b1 != 0.0) dv += a.b1 * k1;
+                if (a.d_has) dv += dacc[v];
                 bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
             } else {
                 bstore<KT>((KT)k[v], field_rsrc<KT>(a.Kout, v, field), ok);
                 if (a.k64_out) bstore<double>(k[v], field_rsrc<double>(a.k64_out, v, field), o8);
+                if (a.acc_mode) {
+                    double dv = a.b_acc * k[v];
+                    if (a.acc_mode == 2) dv += bload<double>(field_rsrc<double>(a.d_out, v, field), o8);
+                    bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
+                }
             }
         }
     }
@@ -1147,7 +1160,7 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
     __shared__ float sx[8], sh1[32], sh2[32];
     const int c = blockIdx.x;
     const int64_t b = case_off[c], e = case_off[c + 1];
-    double ej[3] = {0.0, 0.0, 0.0};
+    double ej[PERRK_MAXB] = {};
     for (int j = 0; j < rp.nb; ++j) {
         double o[1];
         case_sum<1>(ep + (size_t)j * nelem, 1, b, e, o);

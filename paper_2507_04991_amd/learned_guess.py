@@ -3,8 +3,8 @@
 A small network (8 -> 32 -> 32 -> 1, tanh) predicts the increment
 gamma_n - gamma_{n-1} of a case's relaxation parameter from: the last two
 increments, gamma_{n-1} - 1, the step size and the entropy-production terms of
-this step's stages with b_i != 0 (divided by the sum of their magnitudes,
-zero-padded to four).  It is trained on (features, increment) pairs logged
+this step's first four stages with b_i != 0 (divided by the sum of the
+magnitudes of all of them, zero-padded to four).  It is trained on (features, increment) pairs logged
 from the method's own solves, with the library's HIP forward / gradient / Adam
 kernels; the step evaluates it before the first residual pass once a case has
 taken three steps.  Newton and bisection still decide the accepted gamma, so
@@ -33,8 +33,9 @@ def features(ghist, dt, e, nb):
     x[2] = ghist[0]
     x[3] = dt
     s = float(np.sum(np.abs(e[:nb])))
+    m = min(nb, 4)
     if s > 0.0:
-        x[4:4 + nb] = np.asarray(e[:nb]) / s
+        x[4:4 + m] = np.asarray(e[:m]) / s
     return x
 
 

@@ -54,7 +54,7 @@ class Options(ctypes.Structure):
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("r", ctypes.c_double), ("dH", ctypes.c_double),
-                ("H_delta", ctypes.c_double), ("e", ctypes.c_double * 3), ("t", ctypes.c_double),
+                ("H_delta", ctypes.c_double), ("e", ctypes.c_double * 8), ("t", ctypes.c_double),
                 ("passes", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 

@@ -393,6 +393,19 @@ def _stable_step_of(P, spectrum=None, tol=STAB_TOL) -> float:
     return lo
 
 
+def classic_rk4():
+    """The classic fourth-order Runge-Kutta method (the paper's relaxed comparison
+    method R-RK_{4;4}) in the library's tableau form: one level with E = S = 4,
+    c = (0, 1/2, 1/2, 1), b = (1/6, 1/3, 1/3, 1/6), a_{2,1} = 1/2, a_{3,2} = 1/2,
+    a_{4,3} = 1 (every row couples to a single earlier stage, so a_{i,1} =
+    c_i - a_{i,i-1} with a_sub = (0, 0, 1/2, 1)); h_stab from its stability
+    polynomial 1 + z + z^2/2 + z^3/6 + z^4/24 on the model spectrum."""
+    P = np.array(_fixed_coeffs(4))
+    return dict(order=4, S=4, E=[4], c=np.array([0.0, 0.5, 0.5, 1.0]),
+                b=np.array([1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0]),
+                a_sub=np.array([[0.0, 0.0, 0.5, 1.0]]), h_stab=np.array([_stable_step_of(P)]))
+
+
 _CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tableaux.json")
 
 

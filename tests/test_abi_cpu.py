@@ -43,13 +43,16 @@ def test_validate_accepts_good_descriptors():
     for order, E in [(3, [4, 6, 8, 12]), (4, [5, 9, 14])]:
         d = desc(tab=T.get_tableau(order, E))
         assert d.validate()[0] == P.OK
+    # classic RK4: four nonzero weights, one level evaluating every stage
+    st, msg = desc(tab=T.classic_rk4()).validate()
+    assert st == P.OK, msg
 
 
 @pytest.mark.parametrize("mutate,expect", [
     (lambda t: t["b"].__setitem__(-1, 0.9), "order 1"),
     (lambda t: t["c"].__setitem__(-1, 0.51), "order 2"),
     (lambda t: t["a_sub"].__setitem__((0, 2), 0.1), "skipped or first evaluated"),
-    (lambda t: t["b"].__setitem__(2, 0.1), "only b_1"),
+    (lambda t: t["b"].__setitem__(2, 0.1), "needs every level to evaluate stage 3"),
     (lambda t: t["E"].__setitem__(0, 7), "outside"),
 ])
 def test_validate_rejects_bad_tableaux(mutate, expect):

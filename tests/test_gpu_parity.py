@@ -77,6 +77,37 @@ def test_steps_match_oracle_2d(P, oracle, order, E, levels):
         assert rel_err(u.cpu().numpy(), Uref) < 1e-12, n
 
 
+@pytest.mark.parametrize("precision", [0, 2])
+def test_classic_rk4_matches_dense_oracle(P, oracle, precision):
+    """Relaxed classic RK4 (b_i != 0 in all four stages: d and dH accumulate stage
+    by stage) against the oracle's literal dense step: FP64 to 1e-12; single
+    precision in every stage within the mixed bound."""
+    from paper_2507_04991_amd import tableau as T
+    from paper_2507_04991_amd import workloads as W
+    from tests.helpers import stable_dt
+    f, U0, _, _, _ = problem_2d()
+    tab = T.classic_rk4()
+    lev = np.zeros(U0.shape[1], dtype=np.int32)
+    dt = stable_dt(tab, f, U0, lev)
+    st, u = make(P, f, U0, tab, lev, precision=precision)
+    m, t = omesh(oracle, f), otab(oracle, tab)
+    Uref, g = U0.copy(), 1.0
+    bound = 32 * np.finfo(np.float32).eps * (2.0 / W.element_widths(f).min()) * flux_scale(U0, 2)
+    for n in range(3):
+        info = st.step(u, dt)[0]
+        Uref, iref = oracle.step(m, t, lev, Uref, dt, oracle.relax_options(gamma0=g), dense=True)
+        g = iref["gamma"]
+        assert iref["status"] == 0 and info["flags"] == iref["flags"] == 0
+        assert abs(info["r"]) <= 1e-12
+        if precision == 0:
+            assert info["passes"] == iref["passes"]
+            assert abs(info["gamma"] - iref["gamma"]) <= 1e-12
+            assert abs(info["dH"] - iref["dH"]) <= 1e-13 * max(1.0, abs(iref["dH"]))
+            assert rel_err(u.cpu().numpy(), Uref) < 1e-12, n
+        else:
+            assert np.abs(u.cpu().numpy() - Uref).max() <= (n + 1) * 4 * dt * bound, n
+
+
 @pytest.mark.parametrize("flux", [0, 1])
 def test_steps_match_oracle_3d(P, oracle, flux):
     f, U0, tab, dt, lev = problem_3d()

@@ -356,6 +356,34 @@ def test_single_level_reduces_to_textbook_methods(oracle):
     assert np.abs(U1 - ref).max() < 1e-14
 
 
+def test_classic_rk4_in_dense_form(oracle):
+    """Classic RK4 (b with four nonzero weights) through the literal dense step
+    equals U + dt (k1 + 2 k2 + 2 k3 + k4) / 6 composed from the right-hand side;
+    the low-storage step, which keeps only K_1, K_{S-1} and K_S, refuses it."""
+    f = mesh2(6, 6)
+    m = oracle.Mesh(f)
+    U0 = W.vortex_state(W.node_coords(f))
+    dt = 0.02
+    lev = np.zeros(m.nelem, dtype=np.int32)
+    F = lambda U: oracle.rhs(m, U)
+    t = T.classic_rk4()
+    tab = oracle.Tableau(4, t["c"], t["b"], t["a_sub"], t["E"])
+    U1, info = oracle.step(m, tab, lev, U0, dt, oracle.relax_options(relax=False), dense=True)
+    assert info["status"] == 0
+    k1 = F(U0)
+    k2 = F(U0 + 0.5 * dt * k1)
+    k3 = F(U0 + 0.5 * dt * k2)
+    k4 = F(U0 + dt * k3)
+    ref = U0 + dt * (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0
+    assert np.abs(U1 - ref).max() < 1e-14
+    # with relaxation: the root certified, dH from the four stage terms
+    U2, info = oracle.step(m, tab, lev, U0, dt, dense=True)
+    assert info["status"] == 0 and info["flags"] == 0 and abs(info["r"]) <= 1e-12
+    assert abs(info["gamma"] - 1.0) < 1e-3
+    _, i3 = oracle.step(m, tab, lev, U0, dt)
+    assert i3["status"] == oracle.EINVAL
+
+
 def test_shu_vortex_initial_entropy_is_zero(oracle):
     """p = rho^gamma everywhere, so s = -rho log(p / rho^gamma) = 0 pointwise."""
     f = mesh2(16, 16)
