@@ -72,7 +72,7 @@ def lib():
         _lib.or_entropy.argtypes = [i, p, d]
         _lib.or_entropy_diff.restype = d
         _lib.or_entropy_diff.argtypes = [i, p, p, d]
-        for fn in ("or_flux_ec", "or_flux_hll"):
+        for fn in ("or_flux_ec", "or_flux_hll", "or_flux_llf", "or_flux_hlle", "or_flux_hllc"):
             getattr(_lib, fn).argtypes = [i, i, p, p, d, p]
         _lib.or_flux_phys.argtypes = [i, i, p, d, p]
         _lib.or_entropy_vars.argtypes = [i, p, d, p]
@@ -128,6 +128,24 @@ def flux_ec(dim, direction, uL, uR, gam=1.4):
 def flux_hll(dim, direction, uL, uR, gam=1.4):
     uL, uR, f = _f64(uL), _f64(uR), np.zeros(dim + 2)
     lib().or_flux_hll(dim, direction, _ptr(uL), _ptr(uR), gam, _ptr(f))
+    return f
+
+
+def flux_llf(dim, direction, uL, uR, gam=1.4):
+    uL, uR, f = _f64(uL), _f64(uR), np.zeros(dim + 2)
+    lib().or_flux_llf(dim, direction, _ptr(uL), _ptr(uR), gam, _ptr(f))
+    return f
+
+
+def flux_hlle(dim, direction, uL, uR, gam=1.4):
+    uL, uR, f = _f64(uL), _f64(uR), np.zeros(dim + 2)
+    lib().or_flux_hlle(dim, direction, _ptr(uL), _ptr(uR), gam, _ptr(f))
+    return f
+
+
+def flux_hllc(dim, direction, uL, uR, gam=1.4):
+    uL, uR, f = _f64(uL), _f64(uR), np.zeros(dim + 2)
+    lib().or_flux_hllc(dim, direction, _ptr(uL), _ptr(uR), gam, _ptr(f))
     return f
 
 

@@ -43,7 +43,8 @@ typedef struct {
     int n[3];             /* elements per direction; n[2] = 1 in 2D */
     const double *faces;  /* face coordinates, direction 0 then 1 (then 2): n[d]+1 each */
     double gam;           /* ratio of specific heats */
-    int surface_flux;     /* 0: Ranocha EC flux, 1: HLL with Davis wave speeds */
+    int surface_flux;     /* 0: Ranocha EC flux, 1: HLL (Davis speeds), 2: local Lax-Friedrichs,
+                             3: HLLE (Einfeldt speeds), 4: HLLC (Davis speeds) */
 } or_mesh;
 
 typedef struct {
@@ -208,6 +209,110 @@ void or_flux_hll(int dim, int dir, const double *uL, const double *uR, double ga
     } else {
         for (int k = 0; k < V; ++k)
             f[k] = (lmax * fl[k] - lmin * fr[k] + lmin * lmax * (uR[k] - uL[k])) / (lmax - lmin);
+    }
+}
+
+/* Local Lax-Friedrichs (Rusanov) flux
+ *   f = (f(u_L) + f(u_R)) / 2 - lambda (u_R - u_L) / 2,
+ *   lambda = max(|vn_L| + c_L, |vn_R| + c_R). */
+void or_flux_llf(int dim, int dir, const double *uL, const double *uR, double gam, double *f)
+{
+    double rl, rr, vl[3], vr[3], pl, pr;
+    or_prim(dim, uL, gam, &rl, vl, &pl);
+    or_prim(dim, uR, gam, &rr, vr, &pr);
+    double cl = sqrt(gam * pl / rl), cr = sqrt(gam * pr / rr);
+    double lam = fmax(fabs(vl[dir]) + cl, fabs(vr[dir]) + cr);
+    double fl[5], fr[5];
+    or_flux_phys(dim, dir, uL, gam, fl);
+    or_flux_phys(dim, dir, uR, gam, fr);
+    for (int k = 0; k < dim + 2; ++k) f[k] = 0.5 * (fl[k] + fr[k]) - 0.5 * lam * (uR[k] - uL[k]);
+}
+
+/* HLL flux with Einfeldt's wave speeds (HLLE): Roe averages with weights
+ * sqrt(rho) give vn~ and c~^2 = (gamma-1) (H~ - |v~|^2 / 2), H = (E + p) / rho;
+ *   lmin = min(vn_L - c_L, vn~ - c~),  lmax = max(vn_R + c_R, vn~ + c~),
+ * then the two-wave formula (upwind when all speeds have one sign). */
+void or_flux_hlle(int dim, int dir, const double *uL, const double *uR, double gam, double *f)
+{
+    double rl, rr, vl[3], vr[3], pl, pr;
+    or_prim(dim, uL, gam, &rl, vl, &pl);
+    or_prim(dim, uR, gam, &rr, vr, &pr);
+    double cl = sqrt(gam * pl / rl), cr = sqrt(gam * pr / rr);
+    double sl = sqrt(rl), sr = sqrt(rr);
+    double hl = (uL[dim + 1] + pl) / rl, hr = (uR[dim + 1] + pr) / rr;
+    double vt[3], v2 = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        vt[d] = (sl * vl[d] + sr * vr[d]) / (sl + sr);
+        v2 += vt[d] * vt[d];
+    }
+    double ht = (sl * hl + sr * hr) / (sl + sr);
+    double ct = sqrt((gam - 1.0) * (ht - 0.5 * v2));
+    double lmin = fmin(vl[dir] - cl, vt[dir] - ct);
+    double lmax = fmax(vr[dir] + cr, vt[dir] + ct);
+    double fl[5], fr[5];
+    or_flux_phys(dim, dir, uL, gam, fl);
+    or_flux_phys(dim, dir, uR, gam, fr);
+    int V = dim + 2;
+    if (lmin >= 0.0) {
+        for (int k = 0; k < V; ++k) f[k] = fl[k];
+    } else if (lmax <= 0.0) {
+        for (int k = 0; k < V; ++k) f[k] = fr[k];
+    } else {
+        for (int k = 0; k < V; ++k)
+            f[k] = (lmax * fl[k] - lmin * fr[k] + lmin * lmax * (uR[k] - uL[k])) / (lmax - lmin);
+    }
+}
+
+/* HLLC flux (three waves; Toro's formulation) with the Davis wave speeds of
+ * or_flux_hll.  Contact speed
+ *   s* = (p_R - p_L + rho_L vn_L (sL - vn_L) - rho_R vn_R (sR - vn_R))
+ *        / (rho_L (sL - vn_L) - rho_R (sR - vn_R)),
+ * star state of side K: rho_K (sK - vn_K) / (sK - s*) times
+ *   (1, v_K with its normal component replaced by s*,
+ *    E_K / rho_K + (s* - vn_K) (s* + p_K / (rho_K (sK - vn_K)))),
+ * flux f_K + sK (u*_K - u_K) on the side of the contact that holds x = 0. */
+void or_flux_hllc(int dim, int dir, const double *uL, const double *uR, double gam, double *f)
+{
+    double rl, rr, vl[3], vr[3], pl, pr;
+    or_prim(dim, uL, gam, &rl, vl, &pl);
+    or_prim(dim, uR, gam, &rr, vr, &pr);
+    double cl = sqrt(gam * pl / rl), cr = sqrt(gam * pr / rr);
+    double sL = fmin(vl[dir] - cl, vr[dir] - cr);
+    double sR = fmax(vl[dir] + cl, vr[dir] + cr);
+    double fl[5], fr[5];
+    or_flux_phys(dim, dir, uL, gam, fl);
+    or_flux_phys(dim, dir, uR, gam, fr);
+    int V = dim + 2;
+    if (sL >= 0.0) {
+        for (int k = 0; k < V; ++k) f[k] = fl[k];
+        return;
+    }
+    if (sR <= 0.0) {
+        for (int k = 0; k < V; ++k) f[k] = fr[k];
+        return;
+    }
+    double ml = rl * (sL - vl[dir]), mr = rr * (sR - vr[dir]);
+    double ss = (pr - pl + ml * vl[dir] - mr * vr[dir]) / (ml - mr);
+    const int left = ss >= 0.0;
+    const double *u = left ? uL : uR, *fk = left ? fl : fr, *vk = left ? vl : vr;
+    double rk = left ? rl : rr, pk = left ? pl : pr, sk = left ? sL : sR, mk = left ? ml : mr;
+    double fac = mk / (sk - ss);
+    double us[5];
+    us[0] = fac;
+    for (int d = 0; d < dim; ++d) us[1 + d] = fac * (d == dir ? ss : vk[d]);
+    us[dim + 1] = fac * (u[dim + 1] / rk + (ss - vk[dir]) * (ss + pk / mk));
+    for (int k = 0; k < V; ++k) f[k] = fk[k] + sk * (us[k] - u[k]);
+}
+
+/* The surface flux selected for the mesh. */
+static void or_surface_flux(const or_mesh *m, int dir, const double *uL, const double *uR, double *f)
+{
+    switch (m->surface_flux) {
+    case 1: or_flux_hll(m->dim, dir, uL, uR, m->gam, f); break;
+    case 2: or_flux_llf(m->dim, dir, uL, uR, m->gam, f); break;
+    case 3: or_flux_hlle(m->dim, dir, uL, uR, m->gam, f); break;
+    case 4: or_flux_hllc(m->dim, dir, uL, uR, m->gam, f); break;
+    default: or_flux_ec(m->dim, dir, uL, uR, m->gam, f);
     }
 }
 
@@ -397,12 +502,10 @@ int or_rhs(const or_mesh *m, const double *U, const unsigned char *active, doubl
                     double un[5], f[5];
                     or_get(m, U, or_elem_index(m, jx), or_node_index(jl), un);
                     if (right) {
-                        if (m->surface_flux == 1) or_flux_hll(dim, d, u, un, m->gam, f);
-                        else or_flux_ec(dim, d, u, un, m->gam, f);
+                        or_surface_flux(m, d, u, un, f);
                         for (int v = 0; v < V; ++v) acc[v] += f[v] / q[3];
                     } else {
-                        if (m->surface_flux == 1) or_flux_hll(dim, d, un, u, m->gam, f);
-                        else or_flux_ec(dim, d, un, u, m->gam, f);
+                        or_surface_flux(m, d, un, u, f);
                         for (int v = 0; v < V; ++v) acc[v] -= f[v] / q[0];
                     }
                 }

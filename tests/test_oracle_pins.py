@@ -116,6 +116,139 @@ def test_hll_flux_properties(oracle, dim):
     assert np.allclose(oracle.flux_hll(2, 0, vn, un), oracle.flux_phys(2, 0, un))
 
 
+def cons(rho, v, p):
+    v = np.asarray(v, dtype=np.float64)
+    return np.concatenate([[rho], rho * v, [p / (G - 1) + 0.5 * rho * v @ v]])
+
+
+def mirror(u, d):
+    """The state seen with the normal direction d reversed."""
+    m = np.array(u, dtype=np.float64)
+    m[1 + d] = -m[1 + d]
+    return m
+
+
+@pytest.mark.parametrize("name", ["llf", "hlle", "hllc"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_dissipative_flux_consistency_symmetry_entropy(oracle, name, dim):
+    """Consistency, reflection symmetry and the entropy inequality
+    (w_R - w_L) . f <= psi_R - psi_L on random state pairs with large jumps."""
+    fn = getattr(oracle, "flux_" + name)
+    rng = np.random.default_rng(11 + dim)
+    for _ in range(300):
+        uL, uR = rand_state(rng, dim, 0.1, 4.0), rand_state(rng, dim, 0.1, 4.0)
+        for d in range(dim):
+            assert np.allclose(fn(dim, d, uL, uL), oracle.flux_phys(dim, d, uL), rtol=1e-14, atol=1e-14)
+            f = fn(dim, d, uL, uR)
+            fm = fn(dim, d, mirror(uR, d), mirror(uL, d))
+            assert np.allclose(fm, -mirror(f, d), rtol=1e-13, atol=1e-13)
+            wL, wR = oracle.entropy_vars(dim, uL), oracle.entropy_vars(dim, uR)
+            prod = (wR - wL) @ f - (G - 1) * (uR[1 + d] - uL[1 + d])
+            assert prod <= 1e-13 * (np.abs(wR - wL) @ np.abs(f) + 1)
+    if name != "llf":
+        # supersonic to the right: the upwind (left) physical flux
+        u, v = cons(1.0, [3.0, 0.2, 0.1][:dim], 1.0), cons(1.2, [3.1, -0.1, 0.0][:dim], 1.1)
+        assert np.allclose(fn(dim, 0, u, v), oracle.flux_phys(dim, 0, u), rtol=1e-14, atol=1e-14)
+
+
+def test_llf_flux_on_a_contact(oracle):
+    """Across a contact (equal p and v) the central part is exact and the
+    dissipation is -(|v_n| + max(c_L, c_R)) (u_R - u_L) / 2."""
+    for vn in (0.0, 0.4, -0.7):
+        uL, uR = cons(1.0, [vn, 0.3], 1.0), cons(0.25, [vn, 0.3], 1.0)
+        cmax = math.sqrt(G * 1.0 / 0.25)
+        fc = 0.5 * (oracle.flux_phys(2, 0, uL) + oracle.flux_phys(2, 0, uR))
+        assert np.allclose(oracle.flux_llf(2, 0, uL, uR), fc - 0.5 * (abs(vn) + cmax) * (uR - uL),
+                           rtol=1e-14, atol=1e-14)
+
+
+def shock_pair(rho_r, v_r, p_r, ratio, vt):
+    """States on both sides of a right-facing shock (pre-shock state on the right,
+    pressure ratio p_L / p_R = ratio > 1) from the Rankine-Hugoniot relations for
+    a polytropic gas, and the shock speed."""
+    mu = (G - 1) / (G + 1)
+    c_r = math.sqrt(G * p_r / rho_r)
+    s = v_r + c_r * math.sqrt((G + 1) / (2 * G) * ratio + (G - 1) / (2 * G))
+    rho_l = rho_r * (ratio + mu) / (mu * ratio + 1)
+    v_l = s + rho_r * (v_r - s) / rho_l
+    return cons(rho_l, [v_l, vt], ratio * p_r), cons(rho_r, [v_r, vt], p_r), s
+
+
+@pytest.mark.parametrize("v_r,ratio", [(-0.3, 3.0), (-1.0, 1.5), (-1.6, 5.0), (0.2, 10.0)])
+def test_hlle_resolves_an_isolated_shock(oracle, v_r, ratio):
+    """Roe's average makes the shock speed an exact wave speed, so the HLLE flux
+    across an isolated shock is Godunov's: f(u_L) if it moves right, f(u_R) if
+    left.  The Davis speeds of plain HLL do not have this property."""
+    uL, uR, s = shock_pair(1.0, v_r, 1.0, ratio, 0.25)
+    fL, fR = oracle.flux_phys(2, 0, uL), oracle.flux_phys(2, 0, uR)
+    assert np.allclose(fR - fL, s * (uR - uL), rtol=1e-13, atol=1e-13)  # the pair is a shock
+    exact = fL if s > 0 else fR
+    assert np.allclose(oracle.flux_hlle(2, 0, uL, uR), exact, rtol=1e-13, atol=1e-13)
+    assert np.abs(oracle.flux_hll(2, 0, uL, uR) - exact).max() > 1e-3
+    # the same shock seen with the normal reversed (a left-facing shock)
+    fm = oracle.flux_hlle(2, 0, mirror(uR, 0), mirror(uL, 0))
+    assert np.allclose(fm, -mirror(exact, 0), rtol=1e-13, atol=1e-13)
+
+
+def test_hllc_resolves_contact_and_shear(oracle):
+    """A contact with a tangential velocity jump (equal p and v_n) is an exact
+    solution of the HLLC fan; plain HLL smears it."""
+    for vn in (0.5, -0.4, 0.0):
+        uL, uR = cons(1.0, [vn, 0.7, -0.2], 1.3), cons(0.2, [vn, -0.4, 0.6], 1.3)
+        exact = oracle.flux_phys(3, 0, uL if vn > 0 else uR)
+        assert np.allclose(oracle.flux_hllc(3, 0, uL, uR), exact, rtol=1e-14, atol=1e-14)
+        assert np.abs(oracle.flux_hll(3, 0, uL, uR) - exact).max() > 1e-2
+
+
+def galilean(u, d, w):
+    """Conserved state seen from a frame moving with velocity w e_d."""
+    g = np.array(u, dtype=np.float64)
+    g[1 + d] = u[1 + d] - u[0] * w
+    g[-1] = u[-1] - w * u[1 + d] + 0.5 * u[0] * w * w
+    return g
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_hllc_star_states_satisfy_the_jump_conditions(oracle, dim):
+    """The two star states are read off the HLLC flux in frames moving just
+    inside the outer waves (the flux there is f*_K = f_K + s_K (u*_K - u_K), the
+    jump condition across the outer wave).  They must move with one normal
+    velocity s*, keep each side's tangential velocity, have the flux of a contact,
+    f*_K = s* u*_K + p* (0, e_d, s*) with one p* for both sides, and conserve the
+    Riemann fan: (s* - s_L) u*_L + (s_R - s*) u*_R = s_R u_R - s_L u_L - (f_R - f_L)."""
+    rng = np.random.default_rng(5)
+    d = dim - 1
+    for _ in range(200):
+        uL, uR = rand_state(rng, dim, 0.5, 1.5), rand_state(rng, dim, 0.5, 1.5)
+        rl, vl, pl = prim(uL, dim)
+        rr, vr, pr = prim(uR, dim)
+        cl, cr = math.sqrt(G * pl / rl), math.sqrt(G * pr / rr)
+        sL, sR = min(vl[d] - cl, vr[d] - cr), max(vl[d] + cl, vr[d] + cr)  # Davis estimates
+        star = []
+        for side, w in ((0, sL + 0.02 * (sR - sL)), (1, sR - 0.02 * (sR - sL))):
+            a, b = galilean(uL, d, w), galilean(uR, d, w)
+            f = oracle.flux_hllc(dim, d, a, b)
+            k = (a, b)[side]
+            us = k + (f - oracle.flux_phys(dim, d, k)) / ((sL, sR)[side] - w)
+            star.append(galilean(us, d, -w))
+        (r1, v1, _), (r2, v2, _) = prim(star[0], dim), prim(star[1], dim)
+        ss = v1[d]
+        assert abs(v2[d] - ss) < 1e-12
+        for k in range(dim):
+            if k != d:
+                assert abs(v1[k] - vl[k]) < 1e-12 and abs(v2[k] - vr[k]) < 1e-12
+        fs = [oracle.flux_phys(dim, d, u) + sk * (us - u) for u, sk, us in ((uL, sL, star[0]), (uR, sR, star[1]))]
+        pstar = fs[0][1 + d] - ss * star[0][1 + d]
+        for us, fk in zip(star, fs):
+            contact = ss * us
+            contact[1 + d] += pstar
+            contact[-1] += pstar * ss
+            assert np.allclose(fk, contact, rtol=1e-12, atol=1e-12)
+        fan = (ss - sL) * star[0] + (sR - ss) * star[1]
+        rhs = sR * uR - sL * uL - (oracle.flux_phys(dim, d, uR) - oracle.flux_phys(dim, d, uL))
+        assert np.allclose(fan, rhs, rtol=1e-12, atol=1e-12)
+
+
 # ---------------------------------------------------------------- entropy
 @pytest.mark.parametrize("dim", [2, 3])
 def test_entropy_variables_are_gradient(oracle, dim):
@@ -178,7 +311,7 @@ def mesh2(nx=8, ny=6, graded=True, flux=0):
     return f
 
 
-@pytest.mark.parametrize("dim,flux", [(2, 0), (2, 1), (3, 0), (3, 1)])
+@pytest.mark.parametrize("dim,flux", [(2, 0), (2, 1), (2, 2), (2, 3), (2, 4), (3, 0), (3, 1), (3, 4)])
 def test_rhs_free_stream_conservation_entropy(oracle, dim, flux):
     if dim == 2:
         f = mesh2()
@@ -195,7 +328,7 @@ def test_rhs_free_stream_conservation_entropy(oracle, dim, flux):
     ep = oracle.entropy_production(m, U, K)
     if flux == 0:
         assert abs(ep) < 1e-14 * scale
-    # discontinuous data: EC stays zero, HLL dissipates
+    # discontinuous data: EC stays zero, the dissipative fluxes produce entropy decay
     rng = np.random.default_rng(3)
     ne = co[0].shape[0]
     pc = [rng.uniform(0.5, 1.5, (ne, 1)) * np.ones_like(co[0]) for _ in range(dim + 2)]
