@@ -17,7 +17,9 @@
  *     non-relaxed step gamma = 1, as fallbacks.
  *   - Sec. 2.1 / 4.1: DGSEM on Legendre-Gauss-Lobatto nodes with
  *     entropy-conservative flux differencing (Ranocha's EC/KEP two-point flux)
- *     in the volume, and the same flux or HLL (Davis wave speeds) at faces.
+ *     in the volume; at faces the same flux or a dissipative one (Sec. 1 and
+ *     the applications of Sec. 4-5): HLL with Davis wave speeds, local
+ *     Lax-Friedrichs (Rusanov), HLLE (Einfeldt speeds), HLLC (Toro).
  *   - Sec. 2.3: entropy s(u) = -rho log(p / rho^gamma), H its quadrature.
  *
  * Data layout of every state array (caller's and library's): structure of
@@ -54,7 +56,19 @@ typedef enum {
     PERRK_WARN_FALLBACK = 1 /* some case took the non-relaxed step gamma = 1 (see flags) */
 } perrk_status;
 
-enum { PERRK_FLUX_EC = 0, PERRK_FLUX_HLL = 1 };
+/* Surface fluxes.  EC: Ranocha's entropy-conservative flux.  HLL: two waves,
+ * speeds min/max(v_n -+ c) of both sides (Davis).  LLF: central flux minus
+ * lambda (u_R - u_L) / 2, lambda = max(|v_n| + c) of both sides.  HLLE: HLL
+ * with the Davis speeds widened by the Roe-averaged v_n -+ c (Einfeldt).
+ * HLLC: three waves with the Davis outer speeds and Toro's contact speed and
+ * star states.  All but EC dissipate entropy. */
+enum { PERRK_FLUX_EC = 0, PERRK_FLUX_HLL = 1, PERRK_FLUX_LLF = 2, PERRK_FLUX_HLLE = 3, PERRK_FLUX_HLLC = 4 };
+/* Volume term.  FLUX_DIFFERENCING: split form with Ranocha's EC two-point flux
+ * (Sec. 4.1; entropy conservative with the EC surface flux).  WEAK: the
+ * standard weak-form volume integral (the linear-invariant test of Sec. 4.2),
+ * evaluated as the split form with the central two-point flux, which the SBP
+ * property of the LGL derivative matrix makes identical to it. */
+enum { PERRK_VOLUME_FLUX_DIFFERENCING = 0, PERRK_VOLUME_WEAK = 1 };
 /* FP64: every operation in double precision.
  * MIXED: the stages with b_i = 0 compute volume and surface fluxes in single
  * precision with single-precision accumulation, form their stage states in
@@ -91,8 +105,9 @@ typedef struct {
     const double *face_coords; /* per case, per direction: n+1 increasing face positions, concatenated;
                                   the domain is periodic in every direction */
     double gas_gamma;          /* ratio of specific heats (> 1) */
-    int32_t surface_flux;      /* PERRK_FLUX_EC or PERRK_FLUX_HLL */
+    int32_t surface_flux;      /* PERRK_FLUX_EC .. PERRK_FLUX_HLLC */
     int32_t precision;         /* PERRK_FP64, PERRK_MIXED or PERRK_MIXED_ALL */
+    int32_t volume_integral;   /* PERRK_VOLUME_FLUX_DIFFERENCING or PERRK_VOLUME_WEAK */
 } perrk_mesh_desc;
 
 typedef struct {

@@ -35,7 +35,7 @@ def build(force: bool = False) -> str:
 class _Mesh(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3),
                 ("faces", ctypes.POINTER(ctypes.c_double)), ("gam", ctypes.c_double),
-                ("surface_flux", ctypes.c_int)]
+                ("surface_flux", ctypes.c_int), ("volume_integral", ctypes.c_int)]
 
 
 class _Tableau(ctypes.Structure):
@@ -178,18 +178,20 @@ def entropy_diff(dim, u, du, gam=1.4) -> float:
 class Mesh:
     """Periodic Cartesian mesh: ``faces`` is a list of per-direction face coordinates."""
 
-    def __init__(self, faces, gam: float = 1.4, surface_flux: int = 0):
+    def __init__(self, faces, gam: float = 1.4, surface_flux: int = 0, volume_integral: int = 0):
         self.dim = len(faces)
         self.faces_list = [_f64(f) for f in faces]
         self.n = [len(f) - 1 for f in self.faces_list] + ([1] if self.dim == 2 else [])
         self.faces = _f64(np.concatenate(self.faces_list))
         self.gam = gam
         self.surface_flux = surface_flux
+        self.volume_integral = volume_integral
         self.nelem = int(np.prod(self.n[: self.dim]))
         self.npe = 4 ** self.dim
         self.V = self.dim + 2
         self._s = _Mesh(self.dim, (ctypes.c_int * 3)(*self.n),
-                        self.faces.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), gam, surface_flux)
+                        self.faces.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), gam, surface_flux,
+                        volume_integral)
 
     @property
     def shape(self):

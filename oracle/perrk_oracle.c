@@ -13,7 +13,10 @@
  *     entropy-conservative flux differencing in the volume, entropy-conservative
  *     or entropy-stable surface fluxes (the paper cites these; their formulas are
  *     restated here from the published mathematics: Ranocha's EC/KEP flux, the
- *     HLL two-wave solver with Davis speeds).
+ *     HLL two-wave solver with Davis speeds, and the dissipative fluxes of the
+ *     validation and application runs of Sec. 4.2, 4.3 and 5: local
+ *     Lax-Friedrichs, HLLE, HLLC); the standard weak-form volume integral of
+ *     the linear-invariant test of Sec. 4.2 as an alternative volume term.
  *   - Sec. 2.2: partitioned RK in Butcher form (PartitionedRKSystem), the
  *     archetype tableaux of Appendix A, the active-stage rule and the cheap
  *     update of inactive partitions.
@@ -45,6 +48,7 @@ typedef struct {
     double gam;           /* ratio of specific heats */
     int surface_flux;     /* 0: Ranocha EC flux, 1: HLL (Davis speeds), 2: local Lax-Friedrichs,
                              3: HLLE (Einfeldt speeds), 4: HLLC (Davis speeds) */
+    int volume_integral;  /* 0: flux differencing with the EC flux, 1: standard weak form */
 } or_mesh;
 
 typedef struct {
@@ -482,15 +486,22 @@ int or_rhs(const or_mesh *m, const double *U, const unsigned char *active, doubl
             for (int d = 0; d < dim; ++d) {
                 double scale = 2.0 / or_width(m, e, d);
                 double acc[5] = { 0, 0, 0, 0, 0 };
-                /* volume: flux differencing along the line */
                 for (int mm = 0; mm < 4; ++mm) {
-                    if (mm == il[d]) continue;
                     int jl[3] = { il[0], il[1], il[2] };
                     jl[d] = mm;
                     double um[5], f[5];
                     or_get(m, U, e, or_node_index(jl), um);
-                    or_flux_ec(dim, d, u, um, m->gam, f);
-                    for (int v = 0; v < V; ++v) acc[v] += Ds[il[d] * 4 + mm] * f[v];
+                    if (m->volume_integral == 1) {
+                        /* weak form: the integral of l_i' f is, by LGL quadrature,
+                           sum_m q_m D[m][i] f(u_m); divided by q_i (the mass matrix)
+                           and with the sign of K = -(...) */
+                        or_flux_phys(dim, d, um, m->gam, f);
+                        for (int v = 0; v < V; ++v) acc[v] -= q[mm] * D[mm * 4 + il[d]] / q[il[d]] * f[v];
+                    } else if (mm != il[d]) {
+                        /* flux differencing along the line (Dsplit has a zero diagonal) */
+                        or_flux_ec(dim, d, u, um, m->gam, f);
+                        for (int v = 0; v < V; ++v) acc[v] += Ds[il[d] * 4 + mm] * f[v];
+                    }
                 }
                 /* surface: right face (i_d = 3) and left face (i_d = 0) */
                 if (il[d] == 3 || il[d] == 0) {

@@ -20,7 +20,7 @@
 struct perrk_ctx {
     std::string err;
     // problem
-    int dim = 2, V = 4, npe = 16, n_cases = 1, precision = 0, flux = 0;
+    int dim = 2, V = 4, npe = 16, n_cases = 1, precision = 0, flux = 0, volume = 0;
     double gam = 1.4;
     int64_t nelem = 0;
     std::vector<int64_t> case_off;
@@ -152,8 +152,10 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
     if (m->n_cases < 1) return ck.bad("n_cases must be >= 1");
     if (!m->n_elem_dir || !m->face_coords) return ck.bad("null mesh arrays");
     if (!(m->gas_gamma > 1.0) || !std::isfinite(m->gas_gamma)) return ck.bad("gas_gamma must be > 1");
-    if (m->surface_flux != PERRK_FLUX_EC && m->surface_flux != PERRK_FLUX_HLL)
+    if (m->surface_flux < PERRK_FLUX_EC || m->surface_flux > PERRK_FLUX_HLLC)
         return ck.bad("unknown surface flux %d", m->surface_flux);
+    if (m->volume_integral != PERRK_VOLUME_FLUX_DIFFERENCING && m->volume_integral != PERRK_VOLUME_WEAK)
+        return ck.bad("unknown volume integral %d", m->volume_integral);
     if (m->precision != PERRK_FP64 && m->precision != PERRK_MIXED && m->precision != PERRK_MIXED_ALL)
         return ck.bad("unknown precision %d", m->precision);
     int64_t total = 0;
@@ -308,6 +310,8 @@ void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int
     a.gam = c->gam;
     a.gm1 = c->gam - 1.0;
     a.inv_gm1 = 1.0 / (c->gam - 1.0);
+    a.flux = c->flux;
+    a.volume = c->volume;
     const int S = c->S;
     void *kbuf[2] = {c->d_Ka, c->d_Kb};
     kind = i == 0 ? SK_FIRST : (i == S - 1 ? SK_LAST : SK_MID);
@@ -500,6 +504,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     c->n_cases = m->n_cases;
     c->precision = m->precision;
     c->flux = m->surface_flux;
+    c->volume = m->volume_integral;
     c->gam = m->gas_gamma;
     c->order = t->order;
     c->S = t->S;
@@ -848,6 +853,8 @@ int perrk_rhs(perrk_ctx *c, const void *u_dev, void *k_dev)
     a.gam = c->gam;
     a.gm1 = c->gam - 1.0;
     a.inv_gm1 = 1.0 / (c->gam - 1.0);
+    a.flux = c->flux;
+    a.volume = c->volume;
     HIPCHECK(c, launch_stage(c->dim, c->precision == PERRK_FP64 ? 0 : 1, c->flux, SK_FIRST, a, c->d_coef,
                              c->cfg, c->stream));
     HIPCHECK(c, hipEventRecord(c->ev_out, c->stream));
@@ -933,12 +940,14 @@ int perrk_get_stage_stats(perrk_ctx *c, perrk_kernel_stat *stats, int n_stages, 
 
 int perrk_get_tuning(perrk_ctx *c, char *buf, size_t len)
 {
+    static const char *const flux_names[] = {"ec", "hll", "llf", "hlle", "hllc"};
     if (!c || !buf || !len) return PERRK_EINVAL;
     std::string w;
     for (const LaunchCfg &x : c->scfg) w += (w.empty() ? "" : ",") + std::to_string(x.epb_mult);
-    std::snprintf(buf, len, "dim=%d precision=%s flux=%s stage_waves_per_workgroup=[%s] fast_passes=%d graph=%d %s",
+    std::snprintf(buf, len,
+                  "dim=%d precision=%s flux=%s volume=%s stage_waves_per_workgroup=[%s] fast_passes=%d graph=%d %s",
                   c->dim, c->precision == PERRK_MIXED ? "mixed" : (c->precision == PERRK_MIXED_ALL ? "mixed_all" : "fp64"),
-                  c->flux ? "hll" : "ec", w.c_str(), c->opt.fast_passes,
+                  flux_names[c->flux], c->volume ? "weak" : "flux_differencing", w.c_str(), c->opt.fast_passes,
                   c->opt.use_graph, c->tuned ? c->tune_report.c_str() : "(not tuned)");
     return PERRK_OK;
 }

@@ -80,6 +80,8 @@ struct StageArgs {
     int32_t *err;             // bit 1: non-physical, bit 2: non-finite state formed
     int64_t nelem;
     double gam, gm1, inv_gm1; // gamma, gamma - 1, 1 / (gamma - 1)
+    int32_t flux;             // surface flux (PERRK_FLUX_*)
+    int32_t volume;           // volume term (PERRK_VOLUME_*)
     double b1, bsm1, bs;      // last stage weights
     double b_acc;             // stages with b_i != 0 other than 1, S-1, S: b_i (K_i enters d here)
     int32_t acc_mode;         //   1: d = b_i K_i, 2: d += b_i K_i, 0: no contribution
@@ -101,7 +103,9 @@ struct LaunchCfg {
 size_t stage_lds_bytes(int dim, int variant, int wpb);
 
 // Kernel launchers (perrk_kernels.hip).
-// variant: 0 double flux / double storage, 1 float / float, 2 double flux / float storage
+// variant: 0 double flux / double storage, 1 float / float, 2 double flux / float storage;
+// flux = 0 with a.volume = 0 runs the EC-only kernel, anything else the kernel with
+// run-time selected surface flux and volume term
 hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArgs &a, const double *coef,
                         LaunchCfg cfg, hipStream_t s);
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases,

@@ -276,16 +276,23 @@ __device__ __forceinline__ void flux_ec(int d, const Prim<T, DIM> &L, const Prim
     f[DIM + 1] = fr * ((T)0.5 * vv + inv_gm1 * ibm) + (T)0.5 * (L.p * vr + R.p * vl);
 }
 
-// HLL two-wave flux with Davis wave-speed estimates in direction d; the
-// conserved states are rebuilt from the primitive ones.
+// Dissipative surface fluxes in direction d, selected at run time (the value is
+// uniform over the launch):
+//   PERRK_FLUX_HLL   two-wave HLL with Davis speeds min/max(v_n -+ c)
+//   PERRK_FLUX_LLF   local Lax-Friedrichs: HLL with speeds -+max(|v_n| + c)
+//   PERRK_FLUX_HLLE  HLL with Einfeldt speeds: the Davis outer speeds widened by
+//                    the Roe-averaged (sqrt(rho)-weighted) v_n -+ c
+//   PERRK_FLUX_HLLC  three waves (Toro): Davis outer speeds, contact speed s*,
+//                    star state of the side of the contact that holds x = 0
+// The conserved states are rebuilt from the primitive ones.
 template <typename T, int DIM>
-__device__ __forceinline__ void flux_hll(int d, const Prim<T, DIM> &L, const Prim<T, DIM> &R, T gam, T inv_gm1,
-                                         T *f)
+__device__ __forceinline__ void flux_diss(int kind, int d, const Prim<T, DIM> &L, const Prim<T, DIM> &R, T gam,
+                                          T inv_gm1, T *f)
 {
     const T vl = vdir<T, DIM>(L, d), vr = vdir<T, DIM>(R, d);
     const T cl = sqrt(gam * L.p / L.rho), cr = sqrt(gam * R.p / R.rho);
-    const T lmin = fmin(vl - cl, vr - cr);
-    const T lmax = fmax(vl + cl, vr + cr);
+    T lmin = fmin(vl - cl, vr - cr);
+    T lmax = fmax(vl + cl, vr + cr);
     T uL[DIM + 2], uR[DIM + 2], fl[DIM + 2], fr[DIM + 2];
     T kl = 0, kr = 0;
     uL[0] = L.rho;
@@ -313,12 +320,45 @@ __device__ __forceinline__ void flux_hll(int d, const Prim<T, DIM> &L, const Pri
     }
     fl[DIM + 1] = (uL[DIM + 1] + L.p) * vl;
     fr[DIM + 1] = (uR[DIM + 1] + R.p) * vr;
+    if (kind == PERRK_FLUX_LLF) {
+        lmax = fmax(fabs(vl) + cl, fabs(vr) + cr);
+        lmin = -lmax;
+    } else if (kind == PERRK_FLUX_HLLE) {
+        const T sl = sqrt(L.rho), sr = sqrt(R.rho);
+        const T iw = (T)1 / (sl + sr);
+        T v2 = 0, vn = 0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const T vt = (sl * L.v[k] + sr * R.v[k]) * iw;
+            v2 += vt * vt;
+            vn = k == d ? vt : vn;
+        }
+        const T ht = (sl * (uL[DIM + 1] + L.p) / L.rho + sr * (uR[DIM + 1] + R.p) / R.rho) * iw;
+        const T ct = sqrt((gam - (T)1) * (ht - (T)0.5 * v2));
+        lmin = fmin(vl - cl, vn - ct);
+        lmax = fmax(vr + cr, vn + ct);
+    }
     if (lmin >= (T)0) {
 #pragma unroll
         for (int k = 0; k < DIM + 2; ++k) f[k] = fl[k];
     } else if (lmax <= (T)0) {
 #pragma unroll
         for (int k = 0; k < DIM + 2; ++k) f[k] = fr[k];
+    } else if (kind == PERRK_FLUX_HLLC) {
+        const T ml = L.rho * (lmin - vl), mr = R.rho * (lmax - vr);
+        const T ss = (R.p - L.p + ml * vl - mr * vr) / (ml - mr);
+        const bool left = ss >= (T)0;
+        const T sk = left ? lmin : lmax, mk = left ? ml : mr, vk = left ? vl : vr;
+        const T rk = left ? L.rho : R.rho, pk = left ? L.p : R.p;
+        const T fac = mk / (sk - ss);
+        T us[DIM + 2];
+        us[0] = fac;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) us[1 + k] = fac * (k == d ? ss : (left ? L.v[k] : R.v[k]));
+        const T ek = left ? uL[DIM + 1] : uR[DIM + 1];
+        us[DIM + 1] = fac * (ek / rk + (ss - vk) * (ss + pk / mk));
+#pragma unroll
+        for (int k = 0; k < DIM + 2; ++k) f[k] = (left ? fl[k] : fr[k]) + sk * (us[k] - (left ? uL[k] : uR[k]));
     } else {
         const T inv = (T)1 / (lmax - lmin);
 #pragma unroll
@@ -624,9 +664,32 @@ __device__ __forceinline__ void lds_get_prim(const T *slot, int node, Prim<T, DI
     P.beta = P.rho * recip<T>(P.p);
 }
 
+// Central two-point flux (f(u_A) + f(u_B)) / 2 in direction d.  In the split
+// form sum_m Dsplit[t][m] f#(t, m) it gives D f - B f / q (the rows of D sum to
+// zero), which with the lifted surface flux is the strong form and, by the SBP
+// property q D + D^T q = B, exactly the standard weak form.
+template <typename T, int DIM>
+__device__ __forceinline__ void flux_central(int d, const Prim<T, DIM> &A, const Prim<T, DIM> &B, T inv_gm1, T *f)
+{
+    const T va = vdir<T, DIM>(A, d), vb = vdir<T, DIM>(B, d);
+    T ka = 0, kb = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        ka += A.v[k] * A.v[k];
+        kb += B.v[k] * B.v[k];
+    }
+    const T ma = A.rho * va, mb = B.rho * vb;
+    f[0] = (T)0.5 * (ma + mb);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) f[1 + k] = (T)0.5 * (ma * A.v[k] + mb * B.v[k] + (k == d ? A.p + B.p : (T)0));
+    const T ea = A.p * inv_gm1 + (T)0.5 * A.rho * ka, eb = B.p * inv_gm1 + (T)0.5 * B.rho * kb;
+    f[DIM + 1] = (T)0.5 * ((ea + A.p) * va + (eb + B.p) * vb);
+}
+
 // Two-point volume fluxes of the pairs of directions [D0, D0 + ND), one pair per
-// lane and round, written to vf of the pair's element slot.
-template <int DIM, typename T, int D0, int ND>
+// lane and round, written to vf of the pair's element slot: the EC flux, or the
+// central flux for the weak form.
+template <int DIM, typename T, int D0, int ND, bool WEAK>
 __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_gm1)
 {
     constexpr int EPW = SG<DIM>::EPW, NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V;
@@ -643,7 +706,8 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
         lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, ta), A);
         lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, tb), B);
         T f[V];
-        flux_ec<T, DIM>(d, A, B, inv_gm1, f);
+        if (WEAK) flux_central<T, DIM>(d, A, B, inv_gm1, f);
+        else flux_ec<T, DIM>(d, A, B, inv_gm1, f);
         T *vf = slot + NQ * NPE + V * NFN;
         const int p = dd * NPD + l * 6 + k;
 #pragma unroll
@@ -852,7 +916,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         L.beta = sd ? PO.beta : PN[r].beta;
         R.beta = sd ? PN[r].beta : PO.beta;
         T fs[V];
-        if (FLUX == PERRK_FLUX_HLL) flux_hll<T, DIM>(F[r].d, L, R, (T)a.gam, inv_gm1, fs);
+        if (FLUX && a.flux != PERRK_FLUX_EC) flux_diss<T, DIM>(a.flux, F[r].d, L, R, (T)a.gam, inv_gm1, fs);
         else flux_ec<T, DIM>(F[r].d, L, R, inv_gm1, fs);
         const T lift = sd ? (T)6 : (T)-6;
         T *sf = slot + NQ * NPE;
@@ -865,12 +929,15 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     T du[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) du[v] = 0;
-    volume_pairs<DIM, T, 0, 2>(lds, wave, lane, inv_gm1);
+    const bool weak = FLUX && a.volume;  // uniform over the launch
+    if (weak) volume_pairs<DIM, T, 0, 2, true>(lds, wave, lane, inv_gm1);
+    else volume_pairs<DIM, T, 0, 2, false>(lds, wave, lane, inv_gm1);
     wave_lds_sync();
     gather<DIM, T, 0, 2>(slot, node, ei, du);
     if constexpr (DIM == 3) {
         wave_lds_sync();
-        volume_pairs<DIM, T, 2, 1>(lds, wave, lane, inv_gm1);
+        if (weak) volume_pairs<DIM, T, 2, 1, true>(lds, wave, lane, inv_gm1);
+        else volume_pairs<DIM, T, 2, 1, false>(lds, wave, lane, inv_gm1);
         wave_lds_sync();
         gather<DIM, T, 2, 1>(slot, node, ei, du);
     }
@@ -1455,7 +1522,7 @@ template <int DIM>
 hipError_t launch_stage_d(int variant, int flux, int kind, const StageArgs &a, const double *coef,
                           LaunchCfg cfg, hipStream_t s)
 {
-    if (flux) return launch_stage_v<DIM, 1>(variant, kind, a, coef, cfg, s);
+    if (flux || a.volume) return launch_stage_v<DIM, 1>(variant, kind, a, coef, cfg, s);
     return launch_stage_v<DIM, 0>(variant, kind, a, coef, cfg, s);
 }
 

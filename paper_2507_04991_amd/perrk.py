@@ -15,7 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libperrk.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENONPHYS, ENONFINITE, WARN_FALLBACK = 0, -1, -2, -3, -4, -5, 1
-FLUX_EC, FLUX_HLL = 0, 1
+FLUX_EC, FLUX_HLL, FLUX_LLF, FLUX_HLLE, FLUX_HLLC = 0, 1, 2, 3, 4
+VOLUME_FLUX_DIFFERENCING, VOLUME_WEAK = 0, 1
 FP64, MIXED, MIXED_ALL = 0, 1, 2
 ANCHOR_STEP, ANCHOR_INITIAL = 0, 1
 GUESS_PREV, GUESS_MLP = 0, 1
@@ -32,7 +33,8 @@ class MeshDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_cases", ctypes.c_int32),
                 ("n_elem_dir", ctypes.POINTER(ctypes.c_int32)),
                 ("face_coords", ctypes.POINTER(ctypes.c_double)), ("gas_gamma", ctypes.c_double),
-                ("surface_flux", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("surface_flux", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("volume_integral", ctypes.c_int32)]
 
 
 class PartitionDesc(ctypes.Structure):
@@ -150,7 +152,7 @@ class Descriptors:
     """Host-side descriptors (keeps the numpy buffers alive)."""
 
     def __init__(self, faces_per_case, levels, tableau, gas_gamma=1.4, surface_flux=FLUX_EC,
-                 precision=FP64):
+                 precision=FP64, volume_integral=VOLUME_FLUX_DIFFERENCING):
         self.dim = len(faces_per_case[0])
         self.n_cases = len(faces_per_case)
         n = []
@@ -167,7 +169,7 @@ class Descriptors:
         self.b = np.ascontiguousarray(tableau["b"], dtype=np.float64)
         self.a_sub = np.ascontiguousarray(tableau["a_sub"], dtype=np.float64)
         self.mesh = MeshDesc(self.dim, self.n_cases, _ip(self.n), _dp(self.faces), gas_gamma, surface_flux,
-                             precision)
+                             precision, volume_integral)
         self.part = PartitionDesc(len(self.E), _ip(self.levels))
         self.tab = TableauDesc(int(tableau["order"]), len(self.c), len(self.E), _ip(self.E), _dp(self.c),
                                _dp(self.b), _dp(self.a_sub))

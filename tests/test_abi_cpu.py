@@ -73,6 +73,13 @@ def test_validate_rejects_bad_mesh_and_levels():
     assert d.validate()[0] == P.EINVAL
     d = desc(surface_flux=7)
     assert d.validate()[0] == P.EINVAL
+    d = desc(surface_flux=-1)
+    assert d.validate()[0] == P.EINVAL
+    for flux in range(5):
+        for volume in (0, 1):
+            assert desc(surface_flux=flux, volume_integral=volume).validate()[0] == P.OK
+    st, msg = desc(volume_integral=2).validate()
+    assert st == P.EINVAL and "volume" in msg, msg
     d = desc()
     assert d.validate(P.default_options(fast_passes=0))[0] == P.EINVAL
     assert d.validate(P.default_options(bisect_lo=1.1))[0] == P.EINVAL

@@ -311,15 +311,16 @@ def mesh2(nx=8, ny=6, graded=True, flux=0):
     return f
 
 
-@pytest.mark.parametrize("dim,flux", [(2, 0), (2, 1), (2, 2), (2, 3), (2, 4), (3, 0), (3, 1), (3, 4)])
-def test_rhs_free_stream_conservation_entropy(oracle, dim, flux):
+@pytest.mark.parametrize("dim,flux,volume", [(2, 0, 0), (2, 1, 0), (2, 2, 0), (2, 3, 0), (2, 4, 0), (3, 0, 0),
+                                             (3, 1, 0), (3, 4, 0), (2, 4, 1), (3, 3, 1)])
+def test_rhs_free_stream_conservation_entropy(oracle, dim, flux, volume):
     if dim == 2:
         f = mesh2()
         U = W.vortex_state(W.node_coords(f))
     else:
         f = [W.graded_faces(4, 0, 2 * np.pi)] * 3
         U = W.taylor_green_state(W.node_coords(f), mach=0.3, phase=(0.1, 0.4, 0.9))
-    m = oracle.Mesh(f, surface_flux=flux)
+    m = oracle.Mesh(f, surface_flux=flux, volume_integral=volume)
     co = W.node_coords(f)
     assert np.abs(oracle.rhs(m, W.free_stream_state(co))).max() < 1e-13
     K = oracle.rhs(m, U)
@@ -328,7 +329,9 @@ def test_rhs_free_stream_conservation_entropy(oracle, dim, flux):
     ep = oracle.entropy_production(m, U, K)
     if flux == 0:
         assert abs(ep) < 1e-14 * scale
-    # discontinuous data: EC stays zero, the dissipative fluxes produce entropy decay
+    # element-wise constant data: EC stays zero, the dissipative fluxes produce
+    # entropy decay (with either volume term, whose contribution then vanishes in
+    # the entropy balance)
     rng = np.random.default_rng(3)
     ne = co[0].shape[0]
     pc = [rng.uniform(0.5, 1.5, (ne, 1)) * np.ones_like(co[0]) for _ in range(dim + 2)]
@@ -342,14 +345,15 @@ def test_rhs_free_stream_conservation_entropy(oracle, dim, flux):
         assert epb < -1e-6 * sb
 
 
-def test_rhs_consistent_with_pde(oracle):
+@pytest.mark.parametrize("flux,volume", [(0, 0), (2, 0), (4, 1), (3, 1)])
+def test_rhs_consistent_with_pde(oracle, flux, volume):
     """At t = 0 the vortex only advects: dU/dt = -(v_inf . grad) U.  The DGSEM
     residual against the analytic time derivative must converge under refinement."""
     errs = []
     for n in (16, 32, 64):
         f = [W.uniform_faces(n, 0, 10)] * 2
         co = W.node_coords(f)
-        m = oracle.Mesh(f)
+        m = oracle.Mesh(f, surface_flux=flux, volume_integral=volume)
         K = oracle.rhs(m, W.vortex_state(co))
         h = 1e-5
         dUdt = (W.vortex_state(co, t=h) - W.vortex_state(co, t=-h)) / (2 * h)
@@ -358,6 +362,32 @@ def test_rhs_consistent_with_pde(oracle):
         errs.append(max(np.abs(K[v] - dUdt[v])[inner].max() for v in range(4)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert rates.min() > 2.5, (errs, rates)
+
+
+@pytest.mark.parametrize("flux", [0, 1, 2, 3, 4])
+def test_weak_form_exact_for_piecewise_linear_flux(oracle, flux):
+    """rho and p continuous and piecewise linear in x (kinks at the faces of a
+    graded mesh), v constant: every flux component is continuous and linear in
+    each element, LGL quadrature integrates the weak form exactly, and the
+    residual is -df_x/dx, the slope of f_x over each element, at every node."""
+    rng = np.random.default_rng(4)
+    fx, fy = W.graded_faces(8, 0, 10), W.graded_faces(6, 0, 10)
+    rho_f = rng.uniform(0.6, 1.6, len(fx))
+    rho_f[-1] = rho_f[0]
+    p_f = rng.uniform(0.6, 1.6, len(fx))
+    p_f[-1] = p_f[0]
+    vel = (0.4, -0.3)
+    co = W.node_coords([fx, fy])
+    rho, p = np.interp(co[0], fx, rho_f), np.interp(co[0], fx, p_f)
+    U = W.conserved(rho, [np.full_like(rho, v) for v in vel], p)
+    m = oracle.Mesh([fx, fy], surface_flux=flux, volume_integral=1)
+    K = oracle.rhs(m, U)
+    face_flux = [oracle.flux_phys(2, 0, cons(r, vel, pp)) for r, pp in zip(rho_f, p_f)]
+    nx = len(fx) - 1
+    for e in range(K.shape[1]):
+        ix = e % nx
+        slope = (face_flux[ix + 1] - face_flux[ix]) / (fx[ix + 1] - fx[ix])
+        assert np.allclose(K[:, e, :], -slope[:, None], rtol=1e-12, atol=1e-12), e
 
 
 # ---------------------------------------------------------------- tableaux
