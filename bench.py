@@ -10,6 +10,9 @@ edge with one wave speed per case, and a per-case step size; all cases advance t
 every case's active elements, the step captured in a hipGraph).
 --workload tgv: 3D Taylor-Green vortex, Mach 0.1, 32^3 graded hexahedra,
 fourth-order P-ERRK with E = {5, 9, 14}.
+--surface-flux / --volume: the same workload with a dissipative surface flux
+(HLL, LLF, HLLE, HLLC) and/or the standard weak-form volume term (Sec. 4.2, 4.3
+and 5 use these), which runs the stage kernel's dissipative instantiation.
 
 Variants on identical inputs (same mesh, dt, steps and initial state):
   mixed(+learned)      single-precision fluxes, flux accumulation, stage states and
@@ -44,6 +47,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "P-ERRK DOF-updates/s on 1 GPU; mixed/learned vs FP64 plain at equal L2 error"
 HBM_PEAK_GBS = 8000.0
+FLUX_NAMES = ["ec", "hll", "llf", "hlle", "hllc"]  # PERRK_FLUX_* order
+VOLUME_NAMES = ["flux_differencing", "weak"]  # PERRK_VOLUME_* order
 Q1 = np.array([1.0, 5.0, 5.0, 1.0]) / 6.0
 
 
@@ -67,7 +72,8 @@ def workload_tgv(n=32, seed=0):
 
 
 def run_variant(P, torch, wl, precision, steps, warmup, profile=False, guess=0, model=None):
-    d = P.Descriptors(wl["faces"], wl["lev"], wl["tab"], surface_flux=wl.get("flux", 0), precision=precision)
+    d = P.Descriptors(wl["faces"], wl["lev"], wl["tab"], surface_flux=wl.get("flux", 0), precision=precision,
+                      volume_integral=wl.get("volume", 0))
     st = P.Stepper(d, P.default_options(guess=guess))
     if model is not None:
         st.set_guess_model(*model)
@@ -181,7 +187,7 @@ def cpu_baseline(wl, target_dof=12.0e6):
         ne = wl["lev"][k].shape[0]
         U = wl["U0"][:, off:off + ne]
         off += ne
-        m = O.Mesh(faces)
+        m = O.Mesh(faces, surface_flux=wl.get("flux", 0), volume_integral=wl.get("volume", 0))
         t0 = time.perf_counter()
         O.step(m, t, wl["lev"][k], U, float(wl["dt"][k]))
         sec += time.perf_counter() - t0
@@ -200,6 +206,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["ensemble", "tgv"], default="ensemble")
+    ap.add_argument("--surface-flux", choices=FLUX_NAMES, default=None,
+                    help="surface flux instead of the workload's own (EC)")
+    ap.add_argument("--volume", choices=VOLUME_NAMES, default="flux_differencing",
+                    help="volume term: EC flux differencing or the standard weak form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="time the mixed variant only")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -232,6 +242,11 @@ def main():
                           "GBps_read_plus_write": 2 * n * 8 / sec / 1e9}), flush=True)
         return
     wl = workload_ensemble() if args.workload == "ensemble" else workload_tgv()
+    if args.surface_flux is not None or args.volume != "flux_differencing":
+        fl = FLUX_NAMES.index(args.surface_flux) if args.surface_flux is not None else wl.get("flux", 0)
+        wl["flux"], wl["volume"] = fl, VOLUME_NAMES.index(args.volume)
+        wl["name"] += f"_{FLUX_NAMES[fl]}_{args.volume}"
+        wl["desc"] += f"; surface flux {FLUX_NAMES[fl]}, volume term {args.volume} (instead of EC)"
     M = wl["U0"].size
     print(f"# workload {wl['name']}: {M} DOF, {len(wl['faces'])} case(s)", file=sys.stderr, flush=True)
 

@@ -43,7 +43,7 @@ struct perrk_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     // device buffers
     ElemInfo *d_elem = nullptr;
-    int2 *d_active = nullptr;  // per stage: {element | level << 28, case}
+    ActiveEntry *d_active = nullptr;  // per stage: active elements with their neighbour words
     int64_t *d_case_off = nullptr;
     CaseState *d_cs = nullptr;
     double *d_coef = nullptr;  // [S][2 * PERRK_MAXR]
@@ -563,16 +563,20 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     // active element list of every stage, in natural element order (spatial
     // neighbours are processed together): stage i evaluates the levels with
     // E >= S - i + 1, stage 1 every element
-    std::vector<int2> order;
+    std::vector<ActiveEntry> order;
     c->n_active.resize(c->S);
     c->active_off.resize(c->S + 1);
     for (int i = 0; i < c->S; ++i) {
         c->active_off[i] = (int64_t)order.size();
         for (int64_t e = 0; e < c->nelem; ++e) {
             const int E = c->E[elem[e].level];
-            if (i == 0 || i >= c->S - E + 1)
-                order.push_back(make_int2((int32_t)((uint32_t)e | ((uint32_t)elem[e].level << PERRK_NBR_SHIFT)),
-                                          elem[e].case_id));
+            if (i == 0 || i >= c->S - E + 1) {
+                ActiveEntry en{};
+                en.elem_level = (int32_t)((uint32_t)e | ((uint32_t)elem[e].level << PERRK_NBR_SHIFT));
+                en.case_id = elem[e].case_id;
+                for (int k = 0; k < 6; ++k) en.nbr[k] = elem[e].nbr[k];
+                order.push_back(en);
+            }
         }
         c->n_active[i] = (int32_t)(order.size() - c->active_off[i]);
     }
@@ -675,7 +679,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
     for (auto &e : c->ring_ev) HIPINIT(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPINIT(hipMalloc(&c->d_elem, sizeof(ElemInfo) * c->nelem));
-    HIPINIT(hipMalloc(&c->d_active, sizeof(int2) * order.size()));
+    HIPINIT(hipMalloc(&c->d_active, sizeof(ActiveEntry) * order.size()));
     HIPINIT(hipMalloc(&c->d_case_off, sizeof(int64_t) * (c->n_cases + 1)));
     HIPINIT(hipMalloc(&c->d_cs, sizeof(CaseState) * c->n_cases));
     HIPINIT(hipMalloc(&c->d_coef, sizeof(double) * coef.size()));
@@ -698,7 +702,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipHostMalloc(&c->h_err, sizeof(int32_t), 0));
     HIPINIT(hipHostMalloc(&c->h_H, sizeof(double) * c->n_cases, 0));
     HIPINIT(hipMemcpyAsync(c->d_elem, elem.data(), sizeof(ElemInfo) * c->nelem, hipMemcpyHostToDevice, c->stream));
-    HIPINIT(hipMemcpyAsync(c->d_active, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice,
+    HIPINIT(hipMemcpyAsync(c->d_active, order.data(), sizeof(ActiveEntry) * order.size(), hipMemcpyHostToDevice,
                            c->stream));
     HIPINIT(hipMemcpyAsync(c->d_case_off, c->case_off.data(), sizeof(int64_t) * (c->n_cases + 1),
                            hipMemcpyHostToDevice, c->stream));

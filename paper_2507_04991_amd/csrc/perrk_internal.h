@@ -25,6 +25,16 @@ struct ElemInfo {
     double jac;         // prod_d h_d / 2
 };
 
+// Entry of a stage's active-element list: the element with its level, its case,
+// and its neighbour words (as in ElemInfo::nbr), so that one load of 32 bytes
+// gives a lane everything the addresses and coefficients of its own and its
+// neighbours' nodes depend on.
+struct __attribute__((aligned(32))) ActiveEntry {
+    int32_t elem_level;  // element index | level << PERRK_NBR_SHIFT
+    int32_t case_id;
+    int32_t nbr[6];
+};
+
 // Relaxation solver states.
 enum {
     RS_NEWTON = 0,
@@ -73,7 +83,7 @@ struct StageArgs {
     void *Kout;               // K_i (stage storage type); unused for the last stage
     double *d_out;            // last stage: d = b_1 K_1 + b_{S-1} K_{S-1} + b_S K_S
     const ElemInfo *elem;
-    const int2 *active;       // active elements of the stage: {index | level << 28, case}
+    const ActiveEntry *active; // active elements of the stage
     int32_t n_active;
     const CaseState *cs;      // dt per case
     double *ep_partial;       // [nelem] per-element J sum q w.K, or NULL

@@ -554,7 +554,18 @@ struct SG {
     static constexpr int NPD = 6 * NLINE;        // node pairs per direction
     static constexpr int NPP = 2 * NPD;          // pairs held per phase
     static constexpr int NQ = DIM + 2;
-    static constexpr int SLOT = NQ * NPE + V * NFN + V * NPP;  // LDS words per element slot
+};
+
+// Element slot in LDS, in words of T: primitives [node][NQ], then (single
+// precision only) rho/p per node, the lifted surface fluxes sf[V][NFN] and the
+// pair fluxes vf[V][NPP].  Double-precision slots recompute rho/p where they read
+// a node (a smaller slot keeps more waves resident); single-precision slots store
+// it once per node, which saves a quarter-rate reciprocal per read.
+template <int DIM, typename T>
+struct SL {
+    static constexpr bool BETA = sizeof(T) == 4;
+    static constexpr int PRIM = SG<DIM>::NQ * SG<DIM>::NPE + (BETA ? SG<DIM>::NPE : 0);
+    static constexpr int SLOT = PRIM + SG<DIM>::V * (SG<DIM>::NFN + SG<DIM>::NPP);  // LDS words per slot
 };
 
 // Node of line l (the other coordinates) at position t along direction d.
@@ -639,29 +650,32 @@ __device__ __forceinline__ bool pair_of(int rd, int lane, int &es, int &dd, int 
 }
 
 // Primitive variables of a node in LDS: rho, v_0..v_{DIM-1}, p, contiguous per
-// node (one or two wide LDS reads); rho/p is formed on reading with the same
-// expression make_prim uses.
+// node (one or two wide LDS reads); rho/p stored beside them in single
+// precision, formed on reading in double precision with the same expression
+// make_prim uses (so that both sides of a face see the same bits).
 template <typename T, int DIM>
 __device__ __forceinline__ void lds_put_prim(T *slot, int node, const Prim<T, DIM> &P)
 {
-    constexpr int NQ = SG<DIM>::NQ;
+    constexpr int NQ = SG<DIM>::NQ, NPE = SG<DIM>::NPE;
     T *q = slot + node * NQ;
     q[0] = P.rho;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) q[1 + k] = P.v[k];
     q[DIM + 1] = P.p;
+    if constexpr (SL<DIM, T>::BETA) slot[NQ * NPE + node] = P.beta;
 }
 
 template <typename T, int DIM>
 __device__ __forceinline__ void lds_get_prim(const T *slot, int node, Prim<T, DIM> &P)
 {
-    constexpr int NQ = SG<DIM>::NQ;
+    constexpr int NQ = SG<DIM>::NQ, NPE = SG<DIM>::NPE;
     const T *q = slot + node * NQ;
     P.rho = q[0];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) P.v[k] = q[1 + k];
     P.p = q[DIM + 1];
-    P.beta = P.rho * recip<T>(P.p);
+    if constexpr (SL<DIM, T>::BETA) P.beta = slot[NQ * NPE + node];
+    else P.beta = P.rho * recip<T>(P.p);
 }
 
 // Central two-point flux (f(u_A) + f(u_B)) / 2 in direction d.  In the split
@@ -693,7 +707,7 @@ template <int DIM, typename T, int D0, int ND, bool WEAK>
 __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_gm1)
 {
     constexpr int EPW = SG<DIM>::EPW, NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V;
-    constexpr int SLOT = SG<DIM>::SLOT, NQ = SG<DIM>::NQ, NPE = SG<DIM>::NPE, NFN = SG<DIM>::NFN;
+    constexpr int SLOT = SL<DIM, T>::SLOT, PRIM = SL<DIM, T>::PRIM, NFN = SG<DIM>::NFN;
 #pragma unroll
     for (int rd = 0; rd < PairRounds<DIM, ND>::N; ++rd) {
         int es, dd, l, k;
@@ -708,7 +722,7 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
         T f[V];
         if (WEAK) flux_central<T, DIM>(d, A, B, inv_gm1, f);
         else flux_ec<T, DIM>(d, A, B, inv_gm1, f);
-        T *vf = slot + NQ * NPE + V * NFN;
+        T *vf = slot + PRIM + V * NFN;
         const int p = dd * NPD + l * 6 + k;
 #pragma unroll
         for (int v = 0; v < V; ++v) vf[v * NPP + p] = f[v];
@@ -721,9 +735,9 @@ template <int DIM, typename T, int D0, int ND>
 __device__ __forceinline__ void gather(const T *slot, int node, const ElemInfo &ei, T *du)
 {
     constexpr int d0 = D0, nd = ND;
-    constexpr int NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V, NQ = SG<DIM>::NQ;
-    constexpr int NPE = SG<DIM>::NPE, NFN = SG<DIM>::NFN, NLINE = SG<DIM>::NLINE;
-    const T *sf = slot + NQ * NPE;
+    constexpr int NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V, PRIM = SL<DIM, T>::PRIM;
+    constexpr int NFN = SG<DIM>::NFN, NLINE = SG<DIM>::NLINE;
+    const T *sf = slot + PRIM;
     const T *vf = sf + V * NFN;
 #pragma unroll
     for (int dd = 0; dd < nd; ++dd) {
@@ -796,8 +810,8 @@ namespace {
 template <int DIM, typename T, typename KT, int FLUX, int KIND>
 __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageArgs a, const double *coef)
 {
-    constexpr int NPE = SG<DIM>::NPE, V = SG<DIM>::V, EPW = SG<DIM>::EPW, SLOT = SG<DIM>::SLOT;
-    constexpr int NQ = SG<DIM>::NQ, NFN = SG<DIM>::NFN, FR = FaceRounds<DIM>::N;
+    constexpr int NPE = SG<DIM>::NPE, V = SG<DIM>::V, EPW = SG<DIM>::EPW, SLOT = SL<DIM, T>::SLOT;
+    constexpr int PRIM = SL<DIM, T>::PRIM, NFN = SG<DIM>::NFN, FR = FaceRounds<DIM>::N;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -806,7 +820,11 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     const int epb = (int)(blockDim.x >> 6) * EPW;
     const int li = xcd_block(blockIdx.x, gridDim.x) * epb + eslot;
     const bool valid = li < a.n_active;
-    const int2 act = elt(a.active, (uint32_t)(valid ? li : a.n_active - 1));
+    // the active entry in two 16-byte loads: {element | level, case, nbr 0, nbr 1},
+    // {nbr 2 .. nbr 5}
+    const int4 *ap = reinterpret_cast<const int4 *>(a.active);
+    const uint32_t ai = (uint32_t)(valid ? li : a.n_active - 1);
+    const int4 act = elt(ap, 2u * ai), act2 = elt(ap, 2u * ai + 1u);
     const int e = (int)((uint32_t)act.x & PERRK_NBR_MASK);
     const int lvl = (int)((uint32_t)act.x >> PERRK_NBR_SHIFT);
     T *slot = lds + (size_t)eslot * SLOT;
@@ -849,7 +867,9 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     for (int r = 0; r < FR; ++r) {
         int nn;
         fv[r] = face_node<DIM>(r, lane, F[r], nn);
-        const uint32_t w = (uint32_t)elt(a.elem, (uint32_t)e).nbr[2 * F[r].d + F[r].side];
+        const int f = 2 * F[r].d + F[r].side;
+        const uint32_t w = (uint32_t)(f < 2 ? (f == 0 ? act.z : act.w)
+                                            : sel4<int>(f - 2, act2.x, act2.y, act2.z, act2.w));
         const int nb = (int)(w & PERRK_NBR_MASK);
         nc1[r] = 0.0;
         ncp[r] = 0.0;
@@ -919,7 +939,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         if (FLUX && a.flux != PERRK_FLUX_EC) flux_diss<T, DIM>(a.flux, F[r].d, L, R, (T)a.gam, inv_gm1, fs);
         else flux_ec<T, DIM>(F[r].d, L, R, inv_gm1, fs);
         const T lift = sd ? (T)6 : (T)-6;
-        T *sf = slot + NQ * NPE;
+        T *sf = slot + PRIM;
 #pragma unroll
         for (int v = 0; v < V; ++v) sf[v * NFN + F[r].q] = lift * fs[v];
     }
@@ -1489,7 +1509,7 @@ __global__ void init_cases_kernel(CaseState *cs, int n)
 template <int DIM, typename T, typename KT, int FLUX, int KIND>
 hipError_t launch_stage_t(const StageArgs &a, const double *coef, LaunchCfg cfg, hipStream_t s)
 {
-    constexpr int EPW = SG<DIM>::EPW, SLOT = SG<DIM>::SLOT;
+    constexpr int EPW = SG<DIM>::EPW, SLOT = SL<DIM, T>::SLOT;
     const int wpb = cfg.epb_mult;
     const int epb = wpb * EPW;
     if (a.n_active <= 0) return hipSuccess;
@@ -1530,9 +1550,12 @@ hipError_t launch_stage_d(int variant, int flux, int kind, const StageArgs &a, c
 
 size_t stage_lds_bytes(int dim, int variant, int wpb)
 {
-    const size_t tb = variant == 1 ? sizeof(float) : sizeof(double);
-    if (dim == 2) return (size_t)wpb * SG<2>::EPW * SG<2>::SLOT * tb;
-    return (size_t)wpb * SG<3>::EPW * SG<3>::SLOT * tb;
+    if (variant == 1) {
+        if (dim == 2) return (size_t)wpb * SG<2>::EPW * SL<2, float>::SLOT * sizeof(float);
+        return (size_t)wpb * SG<3>::EPW * SL<3, float>::SLOT * sizeof(float);
+    }
+    if (dim == 2) return (size_t)wpb * SG<2>::EPW * SL<2, double>::SLOT * sizeof(double);
+    return (size_t)wpb * SG<3>::EPW * SL<3, double>::SLOT * sizeof(double);
 }
 
 hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArgs &a, const double *coef,
