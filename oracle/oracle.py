@@ -35,7 +35,8 @@ def build(force: bool = False) -> str:
 class _Mesh(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3),
                 ("faces", ctypes.POINTER(ctypes.c_double)), ("gam", ctypes.c_double),
-                ("surface_flux", ctypes.c_int), ("volume_integral", ctypes.c_int)]
+                ("surface_flux", ctypes.c_int), ("volume_integral", ctypes.c_int),
+                ("physics", ctypes.c_int), ("c_h", ctypes.c_double)]
 
 
 class _Tableau(ctypes.Structure):
@@ -75,6 +76,15 @@ def lib():
         for fn in ("or_flux_ec", "or_flux_hll", "or_flux_llf", "or_flux_hlle", "or_flux_hllc"):
             getattr(_lib, fn).argtypes = [i, i, p, p, d, p]
         _lib.or_flux_phys.argtypes = [i, i, p, d, p]
+        _lib.or_mhd_flux_phys.argtypes = [i, p, d, d, p]
+        for fn in ("or_mhd_flux_ec", "or_mhd_flux_llf", "or_mhd_flux_central"):
+            getattr(_lib, fn).argtypes = [i, p, p, d, d, p]
+        _lib.or_mhd_nonconservative.argtypes = [i, p, d, p, p]
+        _lib.or_mhd_entropy.restype = d
+        _lib.or_mhd_entropy.argtypes = [p, d]
+        _lib.or_mhd_entropy_vars.argtypes = [p, d, p]
+        _lib.or_mhd_entropy_diff.restype = d
+        _lib.or_mhd_entropy_diff.argtypes = [p, p, d]
         _lib.or_entropy_vars.argtypes = [i, p, d, p]
         _lib.or_lgl.argtypes = [p, p, p, p]
         _lib.or_rhs.restype = i
@@ -155,6 +165,50 @@ def flux_phys(dim, direction, u, gam=1.4):
     return f
 
 
+def mhd_flux_phys(direction, u, gam=1.4, c_h=0.0):
+    u, f = _f64(u), np.zeros(9)
+    lib().or_mhd_flux_phys(direction, _ptr(u), gam, c_h, _ptr(f))
+    return f
+
+
+def _mhd2(fn, direction, uL, uR, gam, c_h):
+    uL, uR, f = _f64(uL), _f64(uR), np.zeros(9)
+    getattr(lib(), fn)(direction, _ptr(uL), _ptr(uR), gam, c_h, _ptr(f))
+    return f
+
+
+def mhd_flux_ec(direction, uL, uR, gam=1.4, c_h=0.0):
+    return _mhd2("or_mhd_flux_ec", direction, uL, uR, gam, c_h)
+
+
+def mhd_flux_llf(direction, uL, uR, gam=1.4, c_h=0.0):
+    return _mhd2("or_mhd_flux_llf", direction, uL, uR, gam, c_h)
+
+
+def mhd_flux_central(direction, uL, uR, gam=1.4, c_h=0.0):
+    return _mhd2("or_mhd_flux_central", direction, uL, uR, gam, c_h)
+
+
+def mhd_nonconservative(direction, u, gam=1.4):
+    u, phi, phin = _f64(u), np.zeros(9), np.zeros(9)
+    lib().or_mhd_nonconservative(direction, _ptr(u), gam, _ptr(phi), _ptr(phin))
+    return phi, phin
+
+
+def mhd_entropy(u, gam=1.4) -> float:
+    return lib().or_mhd_entropy(_ptr(_f64(u)), gam)
+
+
+def mhd_entropy_vars(u, gam=1.4):
+    u, w = _f64(u), np.zeros(9)
+    lib().or_mhd_entropy_vars(_ptr(u), gam, _ptr(w))
+    return w
+
+
+def mhd_entropy_diff(u, du, gam=1.4) -> float:
+    return lib().or_mhd_entropy_diff(_ptr(_f64(u)), _ptr(_f64(du)), gam)
+
+
 def entropy(dim, u, gam=1.4) -> float:
     u = _f64(u)
     return lib().or_entropy(dim, _ptr(u), gam)
@@ -178,7 +232,8 @@ def entropy_diff(dim, u, du, gam=1.4) -> float:
 class Mesh:
     """Periodic Cartesian mesh: ``faces`` is a list of per-direction face coordinates."""
 
-    def __init__(self, faces, gam: float = 1.4, surface_flux: int = 0, volume_integral: int = 0):
+    def __init__(self, faces, gam: float = 1.4, surface_flux: int = 0, volume_integral: int = 0,
+                 physics: int = 0, c_h: float = 0.0):
         self.dim = len(faces)
         self.faces_list = [_f64(f) for f in faces]
         self.n = [len(f) - 1 for f in self.faces_list] + ([1] if self.dim == 2 else [])
@@ -186,12 +241,14 @@ class Mesh:
         self.gam = gam
         self.surface_flux = surface_flux
         self.volume_integral = volume_integral
+        self.physics = physics
+        self.c_h = c_h
         self.nelem = int(np.prod(self.n[: self.dim]))
         self.npe = 4 ** self.dim
-        self.V = self.dim + 2
+        self.V = 9 if physics == 1 else self.dim + 2
         self._s = _Mesh(self.dim, (ctypes.c_int * 3)(*self.n),
                         self.faces.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), gam, surface_flux,
-                        volume_integral)
+                        volume_integral, physics, c_h)
 
     @property
     def shape(self):

@@ -21,6 +21,9 @@
  *     archetype tableaux of Appendix A, the active-stage rule and the cheap
  *     update of inactive partitions.
  *   - Sec. 2.3: entropy s(u) = -rho log(p / rho^gamma) (EntropyMathematical).
+ *   - Sec. 4.1.1 and 4.3.3: ideal GLM-MHD as a second system (nine variables,
+ *     the same entropy with the MHD pressure, an EC two-point flux, the Powell
+ *     and GLM non-conservative terms, LLF and central surface fluxes).
  *   - Sec. 2.4 / 3: relaxed update U_{n+1} = U_n + gamma dt d, entropy change
  *     Delta H from the stage entropy production (EntropyChangeDefinition,
  *     its rearranged node-wise form), relaxation residual r(gamma) and its
@@ -37,6 +40,7 @@
 #define OR_N 4            /* LGL nodes per direction */
 #define OR_MAXS 64        /* maximum number of stages */
 #define OR_MAXR 32        /* maximum number of levels */
+#define OR_MAXV 9         /* maximum number of conserved variables per node */
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2, OR_ENONPHYS = -4, OR_ENONFINITE = -5 };
 enum { OR_FLAG_BISECT = 1, OR_FLAG_FALLBACK = 2, OR_FLAG_TRIVIAL = 4 };
@@ -49,6 +53,8 @@ typedef struct {
     int surface_flux;     /* 0: Ranocha EC flux, 1: HLL (Davis speeds), 2: local Lax-Friedrichs,
                              3: HLLE (Einfeldt speeds), 4: HLLC (Davis speeds) */
     int volume_integral;  /* 0: flux differencing with the EC flux, 1: standard weak form */
+    int physics;          /* 0: compressible Euler (V = dim + 2), 1: ideal GLM-MHD (V = 9) */
+    double c_h;           /* GLM-MHD: divergence-cleaning speed */
 } or_mesh;
 
 typedef struct {
@@ -367,6 +373,227 @@ double or_entropy_diff(int dim, const double *u, const double *du, double gam)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Ideal GLM-MHD (the second system of Sec. 4.1.1 and 4.3.3)                 */
+/* ------------------------------------------------------------------------ */
+/* u = (rho, rho v_1..3, E, B_1..3, psi), V = 9, in one or two space
+ * dimensions (all three vector components kept: the "1.5D" form).
+ *   p = (gamma-1) (E - rho |v|^2/2 - |B|^2/2 - psi^2/2)
+ * Physical flux in direction n (GLM extension with cleaning speed c_h):
+ *   f_rho = rho v_n
+ *   f_m   = rho v v_n + (p + |B|^2/2) e_n - B B_n
+ *   f_E   = v_n (rho |v|^2/2 + gamma p/(gamma-1) + |B|^2) - B_n (v.B) + c_h psi B_n
+ *           (the psi^2/2 part of E is carried by the non-conservative term)
+ *   f_B   = v_n B - B_n v + c_h psi e_n
+ *   f_psi = c_h B_n
+ * Non-conservative part (Powell term with the GLM transport of psi): the
+ * system is u_t + sum_n [ d_n f_n + Phi(u) d_n B_n + Phi_n(u) d_n psi ] = 0 with
+ *   Phi   = (0, B, v.B, v, 0)            (the Powell source, times div B)
+ *   Phi_n = (0, 0, 0, 0, v_n psi, 0, 0, 0, v_n).                              */
+static int or_mhd_prim(const double *u, double gam, double *rho, double *v, double *p, double *B, double *psi)
+{
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(u[k])) return OR_ENONFINITE;
+    *rho = u[0];
+    if (!(*rho > 0.0)) return OR_ENONPHYS;
+    double kin = 0.0, mag = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        v[d] = u[1 + d] / u[0];
+        kin += 0.5 * u[1 + d] * v[d];
+        B[d] = u[5 + d];
+        mag += 0.5 * B[d] * B[d];
+    }
+    *psi = u[8];
+    *p = (gam - 1.0) * (u[4] - kin - mag - 0.5 * u[8] * u[8]);
+    if (!(*p > 0.0)) return OR_ENONPHYS;
+    return OR_OK;
+}
+
+void or_mhd_flux_phys(int dir, const double *u, double gam, double c_h, double *f)
+{
+    double rho, v[3], p, B[3], psi;
+    or_mhd_prim(u, gam, &rho, v, &p, B, &psi);
+    double vn = v[dir], Bn = B[dir], vB = v[0] * B[0] + v[1] * B[1] + v[2] * B[2];
+    double ptot = p + 0.5 * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    f[0] = rho * vn;
+    for (int d = 0; d < 3; ++d) f[1 + d] = u[1 + d] * vn - B[d] * Bn + (d == dir ? ptot : 0.0);
+    f[4] = vn * (u[4] - 0.5 * psi * psi + ptot) - Bn * vB + c_h * psi * Bn;
+    for (int d = 0; d < 3; ++d) f[5 + d] = vn * B[d] - v[d] * Bn + (d == dir ? c_h * psi : 0.0);
+    f[8] = c_h * Bn;
+}
+
+/* Entropy-conservative two-point flux for ideal GLM-MHD with the Powell term
+ * (the Derigs et al. form of the Chandrashekar-type flux; the paper cites an
+ * EC MHD flux without printing it).  With beta = rho / (2p), arithmetic means
+ * {.}, logarithmic means {.}_log and p~ = {rho} / (2 {beta}):
+ *   f_rho = {rho}_log {v_n}
+ *   f_m   = f_rho {v} - (B_n,L B_R + B_n,R B_L)/2 + (p~ + (B_L.B_R)/2) e_n
+ *   f_B   = {v_n B - B_n v} + c_h {psi} e_n
+ *   f_psi = c_h {B_n}
+ *   f_E   = f_rho ( 1/(2 (gamma-1) {beta}_log) - {|v|^2}/2 ) + f_m.{v} + f_B.{B}
+ *           + f_psi {psi} - {v_n |B|^2}/2 + {B_n} {v.B} - c_h {psi B_n}         */
+void or_mhd_flux_ec(int dir, const double *uL, const double *uR, double gam, double c_h, double *f)
+{
+    double rl, rr, vl[3], vr[3], pl, pr, Bl[3], Br[3], sl, sr;
+    or_mhd_prim(uL, gam, &rl, vl, &pl, Bl, &sl);
+    or_mhd_prim(uR, gam, &rr, vr, &pr, Br, &sr);
+    double bl = 0.5 * rl / pl, br = 0.5 * rr / pr;
+    double rho_log = or_logmean(rl, rr), beta_log = or_logmean(bl, br);
+    double ptil = 0.5 * (rl + rr) / (bl + br);  /* {rho} / (2 {beta}) */
+    double va[3], Ba[3], BB = 0.0, v2a = 0.0, vBl = 0.0, vBr = 0.0, B2l = 0.0, B2r = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        va[d] = 0.5 * (vl[d] + vr[d]);
+        Ba[d] = 0.5 * (Bl[d] + Br[d]);
+        BB += Bl[d] * Br[d];
+        v2a += 0.5 * (vl[d] * vl[d] + vr[d] * vr[d]);
+        vBl += vl[d] * Bl[d];
+        vBr += vr[d] * Br[d];
+        B2l += Bl[d] * Bl[d];
+        B2r += Br[d] * Br[d];
+    }
+    double psa = 0.5 * (sl + sr);
+    double f0 = rho_log * va[dir];
+    f[0] = f0;
+    for (int d = 0; d < 3; ++d)
+        f[1 + d] = f0 * va[d] - 0.5 * (Bl[dir] * Br[d] + Br[dir] * Bl[d]) + (d == dir ? ptil + 0.5 * BB : 0.0);
+    for (int d = 0; d < 3; ++d)
+        f[5 + d] = 0.5 * (vl[dir] * Bl[d] - vl[d] * Bl[dir] + vr[dir] * Br[d] - vr[d] * Br[dir])
+                   + (d == dir ? c_h * psa : 0.0);
+    f[8] = c_h * Ba[dir];
+    double fe = f0 * (0.5 / ((gam - 1.0) * beta_log) - 0.5 * v2a);
+    for (int d = 0; d < 3; ++d) fe += f[1 + d] * va[d] + f[5 + d] * Ba[d];
+    fe += f[8] * psa;
+    fe += -0.25 * (vl[dir] * B2l + vr[dir] * B2r) + Ba[dir] * 0.5 * (vBl + vBr)
+          - c_h * 0.5 * (sl * Bl[dir] + sr * Br[dir]);
+    f[4] = fe;
+}
+
+/* Fast magnetosonic speed in direction n:
+ *   c_f^2 = (a^2 + |B|^2/rho + sqrt((a^2 + |B|^2/rho)^2 - 4 a^2 B_n^2/rho)) / 2,
+ * a^2 = gamma p / rho. */
+static double or_mhd_cfast(int dir, const double *u, double gam)
+{
+    double rho, v[3], p, B[3], psi;
+    or_mhd_prim(u, gam, &rho, v, &p, B, &psi);
+    double a2 = gam * p / rho, b2 = (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]) / rho;
+    double bn2 = B[dir] * B[dir] / rho;
+    return sqrt(0.5 * (a2 + b2 + sqrt((a2 + b2) * (a2 + b2) - 4.0 * a2 * bn2)));
+}
+
+/* Local Lax-Friedrichs flux (f_L + f_R)/2 - lambda (u_R - u_L)/2,
+ * lambda = max(|v_n| + c_f) over both sides. */
+void or_mhd_flux_llf(int dir, const double *uL, const double *uR, double gam, double c_h, double *f)
+{
+    double fl[9], fr[9];
+    or_mhd_flux_phys(dir, uL, gam, c_h, fl);
+    or_mhd_flux_phys(dir, uR, gam, c_h, fr);
+    double lam = fmax(fabs(uL[1 + dir] / uL[0]) + or_mhd_cfast(dir, uL, gam),
+                      fabs(uR[1 + dir] / uR[0]) + or_mhd_cfast(dir, uR, gam));
+    for (int k = 0; k < 9; ++k) f[k] = 0.5 * (fl[k] + fr[k]) - 0.5 * lam * (uR[k] - uL[k]);
+}
+
+/* Central flux (f_L + f_R)/2. */
+void or_mhd_flux_central(int dir, const double *uL, const double *uR, double gam, double c_h, double *f)
+{
+    double fl[9], fr[9];
+    or_mhd_flux_phys(dir, uL, gam, c_h, fl);
+    or_mhd_flux_phys(dir, uR, gam, c_h, fr);
+    for (int k = 0; k < 9; ++k) f[k] = 0.5 * (fl[k] + fr[k]);
+}
+
+/* Phi(u) and Phi_n(u) of the non-conservative part (see above). */
+void or_mhd_nonconservative(int dir, const double *u, double gam, double *phi, double *phin)
+{
+    double rho, v[3], p, B[3], psi;
+    or_mhd_prim(u, gam, &rho, v, &p, B, &psi);
+    for (int k = 0; k < 9; ++k) phi[k] = phin[k] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        phi[1 + d] = B[d];
+        phi[5 + d] = v[d];
+    }
+    phi[4] = v[0] * B[0] + v[1] * B[1] + v[2] * B[2];
+    phin[4] = v[dir] * psi;
+    phin[8] = v[dir];
+}
+
+/* Entropy s = -rho log(p / rho^gamma) with the MHD pressure (the same
+ * mathematical entropy as for the Euler equations, Sec. 4.1.1). */
+double or_mhd_entropy(const double *u, double gam)
+{
+    double rho, v[3], p, B[3], psi;
+    or_mhd_prim(u, gam, &rho, v, &p, B, &psi);
+    return -rho * (log(p) - gam * log(rho));
+}
+
+/* w = ds/du:
+ *   w_rho = gamma - log(p rho^-gamma) - (gamma-1) rho |v|^2 / (2p)
+ *   w_m = (gamma-1) rho v / p,  w_E = -(gamma-1) rho / p,
+ *   w_B = (gamma-1) rho B / p,  w_psi = (gamma-1) rho psi / p.               */
+void or_mhd_entropy_vars(const double *u, double gam, double *w)
+{
+    double rho, v[3], p, B[3], psi;
+    or_mhd_prim(u, gam, &rho, v, &p, B, &psi);
+    double rp = rho / p, v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    w[0] = gam - (log(p) - gam * log(rho)) - 0.5 * (gam - 1.0) * rp * v2;
+    for (int d = 0; d < 3; ++d) {
+        w[1 + d] = (gam - 1.0) * rp * v[d];
+        w[5 + d] = (gam - 1.0) * rp * B[d];
+    }
+    w[4] = -(gam - 1.0) * rp;
+    w[8] = (gam - 1.0) * rp * psi;
+}
+
+/* s(u + du) - s(u) without cancellation, as or_entropy_diff with
+ *   dp = (gamma-1) [ dE - (m.dm + |dm|^2/2) / rho' + drho |m|^2 / (2 rho rho')
+ *                    - (B.dB + |dB|^2/2) - (psi dpsi + dpsi^2/2) ]. */
+double or_mhd_entropy_diff(const double *u, const double *du, double gam)
+{
+    double rho, v[3], p, B[3], psi;
+    or_mhd_prim(u, gam, &rho, v, &p, B, &psi);
+    double drho = du[0], rho1 = rho + drho;
+    double mdm = 0.0, dm2 = 0.0, m2 = 0.0, BdB = 0.0, dB2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        mdm += u[1 + d] * du[1 + d];
+        dm2 += du[1 + d] * du[1 + d];
+        m2 += u[1 + d] * u[1 + d];
+        BdB += B[d] * du[5 + d];
+        dB2 += du[5 + d] * du[5 + d];
+    }
+    double dp = (gam - 1.0) * (du[4] - (mdm + 0.5 * dm2) / rho1 + drho * m2 / (2.0 * rho * rho1)
+                               - (BdB + 0.5 * dB2) - (psi * du[8] + 0.5 * du[8] * du[8]));
+    double p1 = p + dp;
+    return -drho * (log(p1) - gam * log(rho1)) - rho * (log1p(dp / p) - gam * log1p(drho / rho));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Physics dispatch                                                          */
+/* ------------------------------------------------------------------------ */
+
+static int or_nvar(const or_mesh *m) { return m->physics == 1 ? 9 : m->dim + 2; }
+
+static int or_node_ok(const or_mesh *m, const double *u)
+{
+    double rho, v[3], p, B[3], psi;
+    if (m->physics == 1) return or_mhd_prim(u, m->gam, &rho, v, &p, B, &psi);
+    return or_prim(m->dim, u, m->gam, &rho, v, &p);
+}
+
+static double or_node_entropy(const or_mesh *m, const double *u)
+{
+    return m->physics == 1 ? or_mhd_entropy(u, m->gam) : or_entropy(m->dim, u, m->gam);
+}
+
+static void or_node_entropy_vars(const or_mesh *m, const double *u, double *w)
+{
+    if (m->physics == 1) or_mhd_entropy_vars(u, m->gam, w);
+    else or_entropy_vars(m->dim, u, m->gam, w);
+}
+
+static double or_node_entropy_diff(const or_mesh *m, const double *u, const double *du)
+{
+    return m->physics == 1 ? or_mhd_entropy_diff(u, du, m->gam) : or_entropy_diff(m->dim, u, du, m->gam);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Mesh helpers                                                              */
 /* ------------------------------------------------------------------------ */
 
@@ -419,14 +646,14 @@ static int or_node_index(const int *il) { return il[0] + 4 * (il[1] + 4 * il[2])
 
 static void or_get(const or_mesh *m, const double *U, int e, int l, double *u)
 {
-    int ne = or_nelem(m), npe = or_npe(m->dim);
-    for (int v = 0; v < m->dim + 2; ++v) u[v] = U[((size_t)v * ne + e) * npe + l];
+    int ne = or_nelem(m), npe = or_npe(m->dim), V = or_nvar(m);
+    for (int v = 0; v < V; ++v) u[v] = U[((size_t)v * ne + e) * npe + l];
 }
 
 static void or_put(const or_mesh *m, double *U, int e, int l, const double *u)
 {
-    int ne = or_nelem(m), npe = or_npe(m->dim);
-    for (int v = 0; v < m->dim + 2; ++v) U[((size_t)v * ne + e) * npe + l] = u[v];
+    int ne = or_nelem(m), npe = or_npe(m->dim), V = or_nvar(m);
+    for (int v = 0; v < V; ++v) U[((size_t)v * ne + e) * npe + l] = u[v];
 }
 
 /* Quadrature weight of node l (tensor product of the 1D LGL weights). */
@@ -447,9 +674,9 @@ int or_check_state(const or_mesh *m, const double *U)
     int ne = or_nelem(m), npe = or_npe(m->dim);
     for (int e = 0; e < ne; ++e)
         for (int l = 0; l < npe; ++l) {
-            double u[5], rho, v[3], p;
+            double u[OR_MAXV];
             or_get(m, U, e, l, u);
-            int st = or_prim(m->dim, u, m->gam, &rho, v, &p);
+            int st = or_node_ok(m, u);
             if (st) return st;
         }
     return OR_OK;
@@ -467,8 +694,11 @@ int or_check_state(const or_mesh *m, const double *U)
  * the traces of the periodic neighbour across the right / left face, f# is
  * the EC volume flux and f* the selected surface flux.  active == NULL means
  * all elements.  Inactive elements' K entries are left untouched. */
+static int or_mhd_rhs(const or_mesh *m, const double *U, const unsigned char *active, double *K);
+
 int or_rhs(const or_mesh *m, const double *U, const unsigned char *active, double *K)
 {
+    if (m->physics == 1) return or_mhd_rhs(m, U, active, K);
     double xi[4], q[4], D[16], Ds[16];
     or_lgl(xi, q, D, Ds);
     int dim = m->dim, V = dim + 2, npe = or_npe(dim), ne = or_nelem(m);
@@ -530,6 +760,92 @@ int or_rhs(const or_mesh *m, const double *U, const unsigned char *active, doubl
     return OR_OK;
 }
 
+/* GLM-MHD right-hand side (2D meshes; the third vector components are carried
+ * along).  Per node and direction d, with the volume term (EC flux
+ * differencing, or the standard weak form, by volume_integral), the surface
+ * flux f* (EC, LLF or central by surface_flux) and the non-conservative part in
+ * strong form with the interface averages of B_d and psi (the Powell term's
+ * standard DGSEM discretisation):
+ *   dU/dt = - sum_d (2/h_d) [ sum_{m != i} Dsplit[i][m] f#(u, u_m)   (or the weak form)
+ *             + (1/q_i) (delta_i3 f*(u, u+) - delta_i0 f*(u-, u))
+ *             + Phi(u) ( sum_m D[i][m] B_d,m + (1/q_i) (delta_i3 ({B_d}+ - B_d) - delta_i0 ({B_d}- - B_d)) )
+ *             + Phi_d(u) ( the same with psi ) ]                             */
+static void or_mhd_surface_flux(const or_mesh *m, int dir, const double *uL, const double *uR, double *f)
+{
+    if (m->surface_flux == 2) or_mhd_flux_llf(dir, uL, uR, m->gam, m->c_h, f);
+    else if (m->surface_flux == 5) or_mhd_flux_central(dir, uL, uR, m->gam, m->c_h, f);
+    else or_mhd_flux_ec(dir, uL, uR, m->gam, m->c_h, f);
+}
+
+static int or_mhd_rhs(const or_mesh *m, const double *U, const unsigned char *active, double *K)
+{
+    double xi[4], q[4], D[16], Ds[16];
+    or_lgl(xi, q, D, Ds);
+    int dim = m->dim, npe = or_npe(dim), ne = or_nelem(m);
+    int st = or_check_state(m, U);
+    if (st) return st;
+    for (int e = 0; e < ne; ++e) {
+        if (active && !active[e]) continue;
+        int ix[3];
+        or_elem_ijk(m, e, ix);
+        for (int l = 0; l < npe; ++l) {
+            int il[3];
+            or_node_ijk(l, il);
+            double u[9], du[9] = { 0 };
+            or_get(m, U, e, l, u);
+            for (int d = 0; d < dim; ++d) {
+                double scale = 2.0 / or_width(m, e, d);
+                double acc[9] = { 0 }, dB = 0.0, dpsi = 0.0;
+                int t = il[d];
+                for (int mm = 0; mm < 4; ++mm) {
+                    int jl[3] = { il[0], il[1], il[2] };
+                    jl[d] = mm;
+                    double um[9], f[9];
+                    or_get(m, U, e, or_node_index(jl), um);
+                    dB += D[t * 4 + mm] * um[5 + d];
+                    dpsi += D[t * 4 + mm] * um[8];
+                    if (m->volume_integral == 1) {
+                        /* weak form, as for the Euler equations */
+                        or_mhd_flux_phys(d, um, m->gam, m->c_h, f);
+                        for (int v = 0; v < 9; ++v) acc[v] -= q[mm] * D[mm * 4 + t] / q[t] * f[v];
+                    } else if (mm != t) {
+                        or_mhd_flux_ec(d, u, um, m->gam, m->c_h, f);
+                        for (int v = 0; v < 9; ++v) acc[v] += Ds[t * 4 + mm] * f[v];
+                    }
+                }
+                if (t == 3 || t == 0) {
+                    int right = (t == 3);
+                    int jx[3] = { ix[0], ix[1], ix[2] };
+                    jx[d] = right ? (ix[d] + 1) % m->n[d] : (ix[d] + m->n[d] - 1) % m->n[d];
+                    int jl[3] = { il[0], il[1], il[2] };
+                    jl[d] = right ? 0 : 3;
+                    double un[9], f[9];
+                    or_get(m, U, or_elem_index(m, jx), or_node_index(jl), un);
+                    double Bavg = 0.5 * (u[5 + d] + un[5 + d]), savg = 0.5 * (u[8] + un[8]);
+                    if (right) {
+                        or_mhd_surface_flux(m, d, u, un, f);
+                        for (int v = 0; v < 9; ++v) acc[v] += f[v] / q[3];
+                        dB += (Bavg - u[5 + d]) / q[3];
+                        dpsi += (savg - u[8]) / q[3];
+                    } else {
+                        or_mhd_surface_flux(m, d, un, u, f);
+                        for (int v = 0; v < 9; ++v) acc[v] -= f[v] / q[0];
+                        dB -= (Bavg - u[5 + d]) / q[0];
+                        dpsi -= (savg - u[8]) / q[0];
+                    }
+                }
+                double phi[9], phin[9];
+                or_mhd_nonconservative(d, u, m->gam, phi, phin);
+                for (int v = 0; v < 9; ++v) du[v] += scale * (acc[v] + phi[v] * dB + phin[v] * dpsi);
+            }
+            double k[9];
+            for (int v = 0; v < 9; ++v) k[v] = -du[v];
+            or_put(m, K, e, l, k);
+        }
+    }
+    return OR_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Integrals                                                                 */
 /* ------------------------------------------------------------------------ */
@@ -542,9 +858,9 @@ double or_total_entropy(const or_mesh *m, const double *U)
     for (int e = 0; e < ne; ++e) {
         double J = or_jac(m, e), He = 0.0;
         for (int l = 0; l < npe; ++l) {
-            double u[5];
+            double u[OR_MAXV];
             or_get(m, U, e, l, u);
-            He += or_qnode(m->dim, l) * or_entropy(m->dim, u, m->gam);
+            He += or_qnode(m->dim, l) * or_node_entropy(m, u);
         }
         H += J * He;
     }
@@ -554,7 +870,7 @@ double or_total_entropy(const or_mesh *m, const double *U)
 /* Discrete integrals of the conserved variables, out[v] = sum_e J_e sum_l q_l u_v. */
 void or_total_conserved(const or_mesh *m, const double *U, double *out)
 {
-    int npe = or_npe(m->dim), ne = or_nelem(m), V = m->dim + 2;
+    int npe = or_npe(m->dim), ne = or_nelem(m), V = or_nvar(m);
     for (int v = 0; v < V; ++v) out[v] = 0.0;
     for (int e = 0; e < ne; ++e) {
         double J = or_jac(m, e);
@@ -570,15 +886,15 @@ void or_total_conserved(const or_mesh *m, const double *U, double *out)
  * (EntropyChange_EntropyVariables_ReArranged without the dt b_i factor). */
 double or_entropy_production(const or_mesh *m, const double *U, const double *K)
 {
-    int npe = or_npe(m->dim), ne = or_nelem(m), V = m->dim + 2;
+    int npe = or_npe(m->dim), ne = or_nelem(m), V = or_nvar(m);
     double s = 0.0;
     for (int e = 0; e < ne; ++e) {
         double J = or_jac(m, e), se = 0.0;
         for (int l = 0; l < npe; ++l) {
-            double u[5], k[5], w[5];
+            double u[OR_MAXV], k[OR_MAXV], w[OR_MAXV];
             or_get(m, U, e, l, u);
             or_get(m, K, e, l, k);
-            or_entropy_vars(m->dim, u, m->gam, w);
+            or_node_entropy_vars(m, u, w);
             double dot = 0.0;
             for (int v = 0; v < V; ++v) dot += w[v] * k[v];
             se += or_qnode(m->dim, l) * dot;
@@ -598,23 +914,23 @@ double or_entropy_production(const or_mesh *m, const double *U, const double *K)
 void or_relax_eval(const or_mesh *m, const double *Un, const double *d, double dt, double gamma,
                    double dH, double offset, double *r, double *rp)
 {
-    int npe = or_npe(m->dim), ne = or_nelem(m), V = m->dim + 2;
+    int npe = or_npe(m->dim), ne = or_nelem(m), V = or_nvar(m);
     double sr = 0.0, srp = 0.0;
     for (int e = 0; e < ne; ++e) {
         double J = or_jac(m, e), er = 0.0, erp = 0.0;
         for (int l = 0; l < npe; ++l) {
-            double u[5], dd[5], du[5], u1[5], w[5];
+            double u[OR_MAXV], dd[OR_MAXV], du[OR_MAXV], u1[OR_MAXV], w[OR_MAXV];
             or_get(m, Un, e, l, u);
             or_get(m, d, e, l, dd);
             for (int v = 0; v < V; ++v) {
                 du[v] = gamma * dt * dd[v];
                 u1[v] = u[v] + du[v];
             }
-            or_entropy_vars(m->dim, u1, m->gam, w);
+            or_node_entropy_vars(m, u1, w);
             double dot = 0.0;
             for (int v = 0; v < V; ++v) dot += w[v] * dt * dd[v];
             double ql = or_qnode(m->dim, l);
-            er += ql * or_entropy_diff(m->dim, u, du, m->gam);
+            er += ql * or_node_entropy_diff(m, u, du);
             erp += ql * dot;
         }
         sr += J * er;
@@ -627,14 +943,14 @@ void or_relax_eval(const or_mesh *m, const double *Un, const double *d, double d
 /* True when the candidate state U_n + gamma dt d is admissible at every node. */
 static int or_candidate_ok(const or_mesh *m, const double *Un, const double *d, double dt, double gamma)
 {
-    int npe = or_npe(m->dim), ne = or_nelem(m), V = m->dim + 2;
+    int npe = or_npe(m->dim), ne = or_nelem(m), V = or_nvar(m);
     for (int e = 0; e < ne; ++e)
         for (int l = 0; l < npe; ++l) {
-            double u[5], dd[5], rho, v[3], p;
+            double u[OR_MAXV], dd[OR_MAXV];
             or_get(m, Un, e, l, u);
             or_get(m, d, e, l, dd);
             for (int k = 0; k < V; ++k) u[k] += gamma * dt * dd[k];
-            if (or_prim(m->dim, u, m->gam, &rho, v, &p)) return 0;
+            if (or_node_ok(m, u)) return 0;
         }
     return 1;
 }
@@ -651,7 +967,7 @@ void or_relax_solve(const or_mesh *m, const double *Un, const double *d, double 
     int passes = 0, iters = 0;
     info->flags = 0;
     /* trivial direction: any gamma is a root */
-    int npe = or_npe(m->dim), ne = or_nelem(m), V = m->dim + 2, nonzero = 0;
+    int npe = or_npe(m->dim), ne = or_nelem(m), V = or_nvar(m), nonzero = 0;
     for (size_t k = 0; k < (size_t)V * ne * npe; ++k)
         if (d[k] != 0.0) { nonzero = 1; break; }
     if (!nonzero) {
@@ -757,6 +1073,7 @@ int or_stage_active(const or_tableau *t, int r, int i)
 static int or_validate(const or_mesh *m, const or_tableau *t, const int *level)
 {
     if (!(m->dim == 2 || m->dim == 3)) return OR_EINVAL;
+    if (m->physics == 1 && m->dim != 2) return OR_EINVAL;
     if (t->S < 2 || t->S > OR_MAXS || t->R < 1 || t->R > OR_MAXR) return OR_EINVAL;
     for (int r = 0; r < t->R; ++r) {
         if (t->E[r] < 2 || t->E[r] > t->S) return OR_EINVAL;
@@ -778,7 +1095,7 @@ static int or_validate(const or_mesh *m, const or_tableau *t, const int *level)
 static int or_finish_step(const or_mesh *m, const or_tableau *t, const or_relax *opt, double *U,
                           const double *d, double dt, double dH, or_info *info)
 {
-    size_t M = (size_t)(m->dim + 2) * or_nelem(m) * or_npe(m->dim);
+    size_t M = (size_t)or_nvar(m) * or_nelem(m) * or_npe(m->dim);
     info->dH = dH;
     info->H_old = or_total_entropy(m, U);
     if (opt->relax) {
@@ -808,7 +1125,7 @@ int or_step_dense(const or_mesh *m, const or_tableau *t, const int *level, const
     if (st) return st;
     st = or_check_state(m, U);
     if (st) return st;
-    int S = t->S, ne = or_nelem(m), npe = or_npe(m->dim), V = m->dim + 2;
+    int S = t->S, ne = or_nelem(m), npe = or_npe(m->dim), V = or_nvar(m);
     size_t M = (size_t)V * ne * npe;
     double *Kall = (double *)calloc(M * S, sizeof(double));
     double *Ui = (double *)malloc(M * sizeof(double));
@@ -864,7 +1181,7 @@ int or_step(const or_mesh *m, const or_tableau *t, const int *level, const or_re
         if (t->b[i] != 0.0) return OR_EINVAL;
     st = or_check_state(m, U);
     if (st) return st;
-    int S = t->S, ne = or_nelem(m), npe = or_npe(m->dim), V = m->dim + 2;
+    int S = t->S, ne = or_nelem(m), npe = or_npe(m->dim), V = or_nvar(m);
     size_t M = (size_t)V * ne * npe;
     double *K1 = (double *)calloc(M, sizeof(double));
     double *Kp = (double *)calloc(M, sizeof(double));

@@ -139,6 +139,59 @@ def weak_blast_x_state(coords, gam=GAMMA):
     return conserved(rho, vel, p, gam)
 
 
+# ---------------------------------------------------------------- ideal GLM-MHD
+# u = (rho, rho v_1..3, E, B_1..3, psi), E = p/(gamma-1) + rho |v|^2/2 + |B|^2/2 + psi^2/2
+
+def mhd_conserved(rho, vel3, p, B3, psi, gam=GAMMA) -> np.ndarray:
+    kin = 0.5 * rho * sum(v * v for v in vel3)
+    mag = 0.5 * sum(b * b for b in B3)
+    E = p / (gam - 1.0) + kin + mag + 0.5 * psi * psi
+    return np.stack([rho] + [rho * v for v in vel3] + [E] + list(B3) + [psi]).astype(np.float64)
+
+
+def mhd_weak_blast_state(coords, gam=GAMMA):
+    """1.5D MHD weak blast (Sec. 4.1.1): the Euler weak-blast data in x with
+    v_y = v_z = 0, B = (1, 1, 1), psi = 0; no variation in y."""
+    x = coords[0]
+    inner = np.abs(x) <= 0.5
+    rho = np.where(inner, 1.1691, 1.0)
+    vx = np.where(inner, 0.1882 * np.sign(x), 0.0)
+    p = np.where(inner, 1.245, 1.0)
+    z, one = np.zeros_like(x), np.ones_like(x)
+    return mhd_conserved(rho, [vx, z, z], p, [one, one, one], z, gam)
+
+
+def mhd_alfven_state(coords, t=0.0, gam=5.0 / 3.0, amp=0.1):
+    """Circularly polarised Alfven wave on [0, sqrt 2]^2 (Sec. 4.3.3 set-up):
+    along x_par = (x + y)/sqrt 2 with B_par = 1, rho = 1, p = 0.1, v_par = 0,
+    v_perp = amp sin(theta), v_z = amp cos(theta), B_perp = v_perp, B_z = v_z,
+    theta = 2 pi (x_par + t) (period 1 in t), psi = 0; e_perp = (-1, 1)/sqrt 2."""
+    x, y = coords
+    s2 = math.sqrt(2.0)
+    th = 2.0 * math.pi * ((x + y) / s2 + t)
+    vperp, vz = amp * np.sin(th), amp * np.cos(th)
+    vx, vy = -vperp / s2, vperp / s2
+    Bx, By = 1.0 / s2 - vperp / s2, 1.0 / s2 + vperp / s2
+    one = np.ones_like(x)
+    return mhd_conserved(one, [vx, vy, vz], 0.1 * one, [Bx, By, vz], 0.0 * one, gam)
+
+
+def mhd_max_wave_speed(U, dim, gam=GAMMA) -> np.ndarray:
+    """Per-element max over nodes and directions of |v_d| + c_f,d (fast
+    magnetosonic speed), for level assignment."""
+    rho = U[0]
+    v = [U[1 + k] / rho for k in range(3)]
+    B = [U[5 + k] for k in range(3)]
+    p = (gam - 1.0) * (U[4] - 0.5 * rho * sum(w * w for w in v) - 0.5 * sum(b * b for b in B) - 0.5 * U[8] ** 2)
+    a2 = gam * p / rho
+    b2 = sum(b * b for b in B) / rho
+    s = []
+    for d in range(dim):
+        cf = np.sqrt(0.5 * (a2 + b2 + np.sqrt((a2 + b2) ** 2 - 4.0 * a2 * B[d] ** 2 / rho)))
+        s.append(np.abs(v[d]) + cf)
+    return np.max(np.stack(s), axis=0).max(axis=1)
+
+
 def free_stream_state(coords, rho=1.3, vel=None, p=0.9, gam=GAMMA):
     dim = len(coords)
     vel = vel if vel is not None else [0.3, -0.2, 0.1][:dim]

@@ -1,0 +1,178 @@
+"""Pins of the oracle's ideal GLM-MHD system (Sec. 4.1.1 and 4.3.3) against what
+the mathematics fixes: reduction to the Euler flux, consistency and symmetry of
+the two-point fluxes, entropy variables and the stable entropy difference
+against high-precision arithmetic, entropy conservation of the EC
+semidiscretisation with the Powell term on data with div B != 0 and psi != 0,
+free-stream preservation, and convergence of the residual to the time
+derivative of the exact Alfven wave."""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+
+from paper_2507_04991_amd import workloads as W
+
+G = 1.4
+
+
+def rand_mhd(rng, lo=0.4, hi=2.0):
+    rho, p = rng.uniform(lo, hi), rng.uniform(lo, hi)
+    v, B = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+    psi = rng.uniform(-0.3, 0.3)
+    return np.concatenate([[rho], rho * v, [p / (G - 1) + 0.5 * rho * v @ v + 0.5 * B @ B + 0.5 * psi ** 2], B,
+                           [psi]])
+
+
+def test_flux_reduces_to_euler_without_field(oracle):
+    """B = 0, psi = 0: the MHD physical flux is the 3D Euler flux (an independent
+    implementation in the oracle)."""
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        u = rand_mhd(rng)
+        u[5:] = 0.0
+        u[4] = u[4]  # E unchanged: p now includes the former magnetic energy
+        ue = np.concatenate([u[:4], [u[4]]])
+        for d in range(3):
+            fm = oracle.mhd_flux_phys(d, u, G, c_h=0.7)
+            fe = oracle.flux_phys(3, d, ue, G)
+            assert np.allclose(fm[:5], fe, rtol=1e-14, atol=1e-14)
+            assert np.allclose(fm[5:], 0.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("name", ["ec", "llf", "central"])
+def test_two_point_fluxes_consistent(oracle, name):
+    fn = getattr(oracle, "mhd_flux_" + name)
+    rng = np.random.default_rng(2)
+    for _ in range(100):
+        u = rand_mhd(rng)
+        for d in range(3):
+            assert np.allclose(fn(d, u, u, G, 0.8), oracle.mhd_flux_phys(d, u, G, 0.8), rtol=1e-13, atol=1e-13)
+    for _ in range(100):
+        uL, uR = rand_mhd(rng), rand_mhd(rng)
+        for d in range(3):
+            if name != "llf":
+                assert np.allclose(fn(d, uL, uR, G, 0.8), fn(d, uR, uL, G, 0.8), rtol=1e-14, atol=1e-14)
+
+
+def test_entropy_vars_and_difference_against_mpmath(oracle):
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(3)
+
+    def S(u):
+        u = [mpmath.mpf(x) for x in u]
+        rho = u[0]
+        kin = sum(u[1 + k] ** 2 for k in range(3)) / (2 * rho)
+        mag = sum(u[5 + k] ** 2 for k in range(3)) / 2
+        p = (mpmath.mpf(G) - 1) * (u[4] - kin - mag - u[8] ** 2 / 2)
+        return -rho * (mpmath.log(p) - mpmath.mpf(G) * mpmath.log(rho))
+
+    for _ in range(10):
+        u = rand_mhd(rng)
+        w = oracle.mhd_entropy_vars(u, G)
+        for k in range(9):
+            g = mpmath.diff(lambda x: S([x if j == k else u[j] for j in range(9)]), mpmath.mpf(u[k]))
+            assert abs(w[k] - float(g)) < 1e-13 * (1 + abs(float(g))), k
+        du = rng.uniform(-1, 1, 9) * 1e-7 * np.abs(u).max()
+        exact = float(S([mpmath.mpf(a) + mpmath.mpf(b) for a, b in zip(u, du)]) - S(u))
+        got = oracle.mhd_entropy_diff(u, du, G)
+        assert abs(got - exact) < 1e-14 * abs(exact) + 1e-30
+        assert abs(oracle.mhd_entropy(u, G) - float(S(u))) < 1e-14 * abs(float(S(u))) + 1e-15
+
+
+def smooth_mhd_state(coords, seed):
+    """Smooth periodic data on [0, 1]^2 with div B != 0 and psi != 0."""
+    x, y = coords
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, 12)
+    s = lambda k, a: a * np.sin(2 * np.pi * (x + 2 * y) + ph[k]) + 0.5 * a * np.cos(2 * np.pi * (2 * x - y) + ph[k + 6])
+    rho = 1.0 + s(0, 0.2)
+    v = [s(1, 0.3), s(2, 0.3), s(3, 0.2)]
+    p = 1.0 + s(4, 0.2)
+    B = [0.8 + s(5, 0.3), -0.5 + s(1, 0.2), 0.3 + s(2, 0.2)]
+    psi = s(3, 0.1)
+    return W.mhd_conserved(rho, v, p, B, psi, G)
+
+
+def mhd_mesh(oracle, n=(6, 5), surface=0, volume=0, c_h=0.9, graded=True):
+    f = [W.graded_faces(n[0], 0, 1) if graded else W.uniform_faces(n[0], 0, 1),
+         W.graded_faces(n[1] + (n[1] % 2), 0, 1) if graded else W.uniform_faces(n[1], 0, 1)]
+    return f, oracle.Mesh(f, gam=G, surface_flux=surface, volume_integral=volume, physics=1, c_h=c_h)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ec_semidiscretisation_conserves_entropy(oracle, seed):
+    """EC volume and surface flux with the Powell term: sum J q w . K = 0 to
+    rounding, on data with div B != 0 and psi != 0 (so the non-conservative
+    terms and the GLM coupling all contribute)."""
+    f, m = mhd_mesh(oracle)
+    U = smooth_mhd_state(W.node_coords(f), seed)
+    K = oracle.rhs(m, U)
+    ep = oracle.entropy_production(m, U, K)
+    scale = np.abs(K).max()
+    assert abs(ep) < 1e-13 * scale, (ep, scale)
+    # the non-conservative terms matter: dropping the GLM coupling (c_h = 0)
+    # changes K, and element-wise constant data with an LLF surface flux
+    # dissipates
+    _, m0 = mhd_mesh(oracle, c_h=0.0)
+    assert np.abs(oracle.rhs(m0, U) - K).max() > 1e-3 * scale
+    _, ml = mhd_mesh(oracle, surface=2)
+    co = W.node_coords(f)
+    ne = co[0].shape[0]
+    rng = np.random.default_rng(seed + 5)
+    pc = [rng.uniform(0.6, 1.4, (ne, 1)) * np.ones_like(co[0]) for _ in range(9)]
+    Ub = W.mhd_conserved(pc[0], [0.3 * (pc[k] - 1) for k in (1, 2, 3)], pc[4], [pc[5] - 0.5, pc[6] - 1, pc[7]],
+                         0.2 * (pc[8] - 1), G)
+    Kb = oracle.rhs(ml, Ub)
+    assert oracle.entropy_production(ml, Ub, Kb) < -1e-6 * np.abs(Kb).max()
+
+
+def test_free_stream_and_mass_conservation(oracle):
+    for surface, volume in [(0, 0), (2, 1), (5, 1)]:
+        f, m = mhd_mesh(oracle, surface=surface, volume=volume)
+        co = W.node_coords(f)
+        one = np.ones_like(co[0])
+        U = W.mhd_conserved(1.2 * one, [0.3 * one, -0.2 * one, 0.1 * one], 0.9 * one, [0.7 * one, -0.4 * one, 0.5 * one],
+                            0.1 * one, G)
+        assert np.abs(oracle.rhs(m, U)).max() < 1e-13
+        U = smooth_mhd_state(co, 3)
+        K = oracle.rhs(m, U)
+        tot = oracle.total_conserved(m, K)
+        assert abs(tot[0]) < 1e-14 * np.abs(K).max()  # mass (no non-conservative part)
+
+
+def test_one_and_a_half_d_conserves_everything(oracle):
+    """y-invariant data with constant B_x (the 1.5D blast): the non-conservative
+    terms vanish and every variable is conserved; with EC fluxes entropy too."""
+    fx = np.concatenate([np.linspace(-2, -1, 9)[:-1], np.linspace(-1, -0.5, 9)[:-1], np.linspace(-0.5, 0.5, 33)[:-1],
+                         np.linspace(0.5, 1, 9)[:-1], np.linspace(1, 2, 9)])
+    f = [fx, W.uniform_faces(2, 0, 0.25)]
+    m = oracle.Mesh(f, gam=G, surface_flux=0, physics=1, c_h=1.0)
+    U = W.mhd_weak_blast_state(W.node_coords(f))
+    K = oracle.rhs(m, U)
+    tot = oracle.total_conserved(m, K)
+    assert np.abs(tot).max() < 1e-13 * np.abs(K).max()
+    assert abs(oracle.entropy_production(m, U, K)) < 1e-13 * np.abs(K).max()
+    # y-invariance is kept
+    Kr = K.reshape(9, 2, 64, 4, 4)
+    assert np.abs(Kr[:, 0] - Kr[:, 1]).max() < 1e-13 * np.abs(K).max()
+    assert np.abs(Kr - Kr[:, :, :, :1, :]).max() < 1e-12 * np.abs(K).max()
+
+
+@pytest.mark.parametrize("surface,volume", [(2, 1), (0, 0), (2, 0), (5, 1)])
+def test_alfven_residual_converges_to_exact_time_derivative(oracle, surface, volume):
+    """The residual at t = 0 against the analytic time derivative of the exact
+    Alfven wave must converge under refinement (also pins the wave's data: the
+    other sign of B_perp or of t gives an O(1) residual)."""
+    gam = 5.0 / 3.0
+    errs = []
+    for n in (4, 8, 16):
+        f = [W.uniform_faces(n, 0, math.sqrt(2))] * 2
+        co = W.node_coords(f)
+        m = oracle.Mesh(f, gam=gam, surface_flux=surface, volume_integral=volume, physics=1, c_h=1.0)
+        K = oracle.rhs(m, W.mhd_alfven_state(co, 0.0, gam))
+        h = 1e-5
+        dUdt = (W.mhd_alfven_state(co, h, gam) - W.mhd_alfven_state(co, -h, gam)) / (2 * h)
+        errs.append(np.abs(K - dUdt).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates.min() > 2.5, (errs, rates)
