@@ -10,6 +10,9 @@ edge with one wave speed per case, and a per-case step size; all cases advance t
 every case's active elements, the step captured in a hipGraph).
 --workload tgv: 3D Taylor-Green vortex, Mach 0.1, 32^3 graded hexahedra,
 fourth-order P-ERRK with E = {5, 9, 14}.
+--workload alfven: 2D ideal GLM-MHD Alfven wave, 256^2 uniform cells, weak form
+with LLF surface flux and the Powell / GLM terms, p = 3 with E = {10..14} at
+random (the GLM-MHD path is double precision only; no comparisons).
 --surface-flux / --volume: the same workload with a dissipative surface flux
 (HLL, LLF, HLLE, HLLC) and/or the standard weak-form volume term (Sec. 4.2, 4.3
 and 5 use these), which runs the stage kernel's dissipative instantiation.
@@ -71,9 +74,20 @@ def workload_tgv(n=32, seed=0):
     return wl
 
 
+def workload_alfven(n=256, seed=0):
+    from paper_2507_04991_amd import problems
+
+    wl = problems.alfven(seed, n)
+    wl["desc"] = (f"2D ideal GLM-MHD Alfven wave (gamma 5/3, c_h 1) on [0, sqrt 2]^2, {n}^2 uniform quads, "
+                  f"DGSEM k=3, weak-form volume term, LLF surface flux, Powell and GLM terms, P-ERRK p=3 "
+                  f"E={{10..14}} assigned to the cells at random")
+    return wl
+
+
 def run_variant(P, torch, wl, precision, steps, warmup, profile=False, guess=0, model=None):
     d = P.Descriptors(wl["faces"], wl["lev"], wl["tab"], surface_flux=wl.get("flux", 0), precision=precision,
-                      volume_integral=wl.get("volume", 0))
+                      volume_integral=wl.get("volume", 0), gas_gamma=wl.get("gam", 1.4),
+                      system=wl.get("system", 0), glm_ch=wl.get("glm_ch", 0.0))
     st = P.Stepper(d, P.default_options(guess=guess))
     if model is not None:
         st.set_guess_model(*model)
@@ -150,7 +164,7 @@ def stage_groups(wl, stage_stats, precision):
         kind = "first" if i == 0 else ("last" if i == S - 1 else "mid")
         ft = "double" if precision == 0 or (precision == 1 and b[i] != 0.0) else "float"
         st = "double" if precision == 0 else "float"
-        name = f"stage_kernel<{dim}, {ft}, {st}, {kind}>"
+        name = f"stage_kernel<{dim}, {ft}, {st}, {kind}>" if wl.get("system", 0) != 1 else f"mhd_stage_kernel<{kind}>"
         g = out.setdefault(name, dict(ms=0.0, bytes=0.0, launches=0))
         g["ms"] += s["ms"]
         g["bytes"] += s["bytes"]
@@ -187,7 +201,8 @@ def cpu_baseline(wl, target_dof=12.0e6):
         ne = wl["lev"][k].shape[0]
         U = wl["U0"][:, off:off + ne]
         off += ne
-        m = O.Mesh(faces, surface_flux=wl.get("flux", 0), volume_integral=wl.get("volume", 0))
+        m = O.Mesh(faces, gam=wl.get("gam", 1.4), surface_flux=wl.get("flux", 0),
+                   volume_integral=wl.get("volume", 0), physics=wl.get("system", 0), c_h=wl.get("glm_ch", 0.0))
         t0 = time.perf_counter()
         O.step(m, t, wl["lev"][k], U, float(wl["dt"][k]))
         sec += time.perf_counter() - t0
@@ -205,7 +220,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["ensemble", "tgv"], default="ensemble")
+    ap.add_argument("--workload", choices=["ensemble", "tgv", "alfven"], default="ensemble")
     ap.add_argument("--surface-flux", choices=FLUX_NAMES, default=None,
                     help="surface flux instead of the workload's own (EC)")
     ap.add_argument("--volume", choices=VOLUME_NAMES, default="flux_differencing",
@@ -241,7 +256,8 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "seconds_per_copy": sec,
                           "GBps_read_plus_write": 2 * n * 8 / sec / 1e9}), flush=True)
         return
-    wl = workload_ensemble() if args.workload == "ensemble" else workload_tgv()
+    wl = {"ensemble": workload_ensemble, "tgv": workload_tgv, "alfven": workload_alfven}[args.workload]()
+    mhd = wl.get("system", 0) == 1
     if args.surface_flux is not None or args.volume != "flux_differencing":
         fl = FLUX_NAMES.index(args.surface_flux) if args.surface_flux is not None else wl.get("flux", 0)
         wl["flux"], wl["volume"] = fl, VOLUME_NAMES.index(args.volume)
@@ -257,6 +273,8 @@ def main():
             ("mixed_all", P.MIXED_ALL, False), ("fp64", P.FP64, False)]
     if not learned:
         plan = [(n, p, g) for n, p, g in plan if not g]
+    if mhd:  # the GLM-MHD path is double precision only
+        plan = [("fp64", P.FP64, False)]
     if args.no_compare:
         plan = plan[:1]
     head_name = plan[0][0]
@@ -325,7 +343,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32/f64",
+        "dtype": "f64" if head_name == "fp64" else "f32/f64",
         "data": "synthetic",
         "config": {"workload": wl["name"], "description": wl["desc"], "dof": int(M),
                    "elements": int(wl["U0"].shape[1]), "cases": len(wl["faces"]), "variant": head_name,
@@ -338,7 +356,7 @@ def main():
     # right-hand-side evaluations per step, counted in DOF: sum_r E^(r) M^(r)
     E = np.asarray(wl["tab"]["E"])
     n_rhs = float(sum(E[np.asarray(lv)].sum() for lv in wl["lev"])) * (M / wl["U0"].shape[1])
-    if not args.no_compare:
+    if not args.no_compare and not mhd:
         # the paper's comparison: the same mesh, dt and steps with every element on the
         # largest-E level (the single-level method P-ERRK_{p;S_max}); tau / tau* and
         # N_RHS / N_RHS* with * = multirate

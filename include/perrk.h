@@ -24,7 +24,8 @@
  *
  * Data layout of every state array (caller's and library's): structure of
  * arrays [v][elem][node], node fastest; v = rho, rho v_1..rho v_dim, rho e
- * (V = dim + 2 fields); node = i + 4 j (+ 16 k) with i along x; elements of a
+ * (V = dim + 2 fields; GLM-MHD: the nine fields listed at PERRK_SYSTEM_GLM_MHD);
+ * node = i + 4 j (+ 16 k) with i along x; elements of a
  * case numbered ix + nx (iy + ny iz), cases concatenated.  Every pointer
  * named *_dev is device memory; everything else is host memory.
  *
@@ -62,13 +63,27 @@ typedef enum {
  * with the Davis speeds widened by the Roe-averaged v_n -+ c (Einfeldt).
  * HLLC: three waves with the Davis outer speeds and Toro's contact speed and
  * star states.  All but EC dissipate entropy. */
-enum { PERRK_FLUX_EC = 0, PERRK_FLUX_HLL = 1, PERRK_FLUX_LLF = 2, PERRK_FLUX_HLLE = 3, PERRK_FLUX_HLLC = 4 };
+enum { PERRK_FLUX_EC = 0, PERRK_FLUX_HLL = 1, PERRK_FLUX_LLF = 2, PERRK_FLUX_HLLE = 3, PERRK_FLUX_HLLC = 4,
+       PERRK_FLUX_CENTRAL = 5 /* (f_L + f_R)/2: GLM-MHD only */ };
 /* Volume term.  FLUX_DIFFERENCING: split form with Ranocha's EC two-point flux
  * (Sec. 4.1; entropy conservative with the EC surface flux).  WEAK: the
  * standard weak-form volume integral (the linear-invariant test of Sec. 4.2),
  * evaluated as the split form with the central two-point flux, which the SBP
  * property of the LGL derivative matrix makes identical to it. */
 enum { PERRK_VOLUME_FLUX_DIFFERENCING = 0, PERRK_VOLUME_WEAK = 1 };
+/* System of conservation laws.  EULER: compressible Euler, V = dim + 2 fields
+ * (rho, rho v_1..rho v_dim, rho e).  GLM_MHD: ideal MHD with generalised
+ * Lagrange multiplier divergence cleaning (the second system of Sec. 4.1.1 and
+ * 4.3.3), 2D meshes only, V = 9 fields (rho, rho v_1..3, E, B_1..3, psi; all
+ * three vector components are carried, so a mesh with no variation in y gives
+ * the "1.5D" problems), PERRK_FP64 only.  Its system adds the Powell term
+ * Phi(u) div B, Phi = (0, B, v.B, v, 0), and the GLM transport
+ * v_d psi (0, 0, 0, 0, psi, 0, 0, 0, 1) d_d psi to the flux divergence; the
+ * cleaning speed c_h is glm_ch.  Surface fluxes: EC, LLF (fast magnetosonic
+ * speeds) or CENTRAL; volume term: EC flux differencing or WEAK.  The entropy
+ * is the same s = -rho log(p rho^-gamma) with the MHD pressure
+ * p = (gamma-1)(E - rho |v|^2/2 - |B|^2/2 - psi^2/2). */
+enum { PERRK_SYSTEM_EULER = 0, PERRK_SYSTEM_GLM_MHD = 1 };
 /* FP64: every operation in double precision.
  * MIXED: the stages with b_i = 0 compute volume and surface fluxes in single
  * precision with single-precision accumulation, form their stage states in
@@ -108,6 +123,8 @@ typedef struct {
     int32_t surface_flux;      /* PERRK_FLUX_EC .. PERRK_FLUX_HLLC */
     int32_t precision;         /* PERRK_FP64, PERRK_MIXED or PERRK_MIXED_ALL */
     int32_t volume_integral;   /* PERRK_VOLUME_FLUX_DIFFERENCING or PERRK_VOLUME_WEAK */
+    int32_t system;            /* PERRK_SYSTEM_EULER or PERRK_SYSTEM_GLM_MHD */
+    double glm_ch;             /* GLM-MHD divergence-cleaning speed (>= 0); ignored for Euler */
 } perrk_mesh_desc;
 
 typedef struct {

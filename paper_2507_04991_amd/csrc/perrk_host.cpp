@@ -20,7 +20,8 @@
 struct perrk_ctx {
     std::string err;
     // problem
-    int dim = 2, V = 4, npe = 16, n_cases = 1, precision = 0, flux = 0, volume = 0;
+    int dim = 2, V = 4, npe = 16, n_cases = 1, precision = 0, flux = 0, volume = 0, sys = 0;
+    double c_h = 0.0;
     double gam = 1.4;
     int64_t nelem = 0;
     std::vector<int64_t> case_off;
@@ -152,8 +153,18 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
     if (m->n_cases < 1) return ck.bad("n_cases must be >= 1");
     if (!m->n_elem_dir || !m->face_coords) return ck.bad("null mesh arrays");
     if (!(m->gas_gamma > 1.0) || !std::isfinite(m->gas_gamma)) return ck.bad("gas_gamma must be > 1");
-    if (m->surface_flux < PERRK_FLUX_EC || m->surface_flux > PERRK_FLUX_HLLC)
+    if (m->system != PERRK_SYSTEM_EULER && m->system != PERRK_SYSTEM_GLM_MHD)
+        return ck.bad("unknown system %d", m->system);
+    if (m->system == PERRK_SYSTEM_GLM_MHD) {
+        if (m->dim != 2) return ck.bad("GLM-MHD needs dim = 2");
+        if (m->precision != PERRK_FP64) return ck.bad("GLM-MHD runs in PERRK_FP64 only");
+        if (m->surface_flux != PERRK_FLUX_EC && m->surface_flux != PERRK_FLUX_LLF &&
+            m->surface_flux != PERRK_FLUX_CENTRAL)
+            return ck.bad("GLM-MHD surface flux must be EC, LLF or CENTRAL (got %d)", m->surface_flux);
+        if (!(m->glm_ch >= 0.0) || !std::isfinite(m->glm_ch)) return ck.bad("glm_ch must be finite and >= 0");
+    } else if (m->surface_flux < PERRK_FLUX_EC || m->surface_flux > PERRK_FLUX_HLLC) {
         return ck.bad("unknown surface flux %d", m->surface_flux);
+    }
     if (m->volume_integral != PERRK_VOLUME_FLUX_DIFFERENCING && m->volume_integral != PERRK_VOLUME_WEAK)
         return ck.bad("unknown volume integral %d", m->volume_integral);
     if (m->precision != PERRK_FP64 && m->precision != PERRK_MIXED && m->precision != PERRK_MIXED_ALL)
@@ -312,6 +323,8 @@ void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int
     a.inv_gm1 = 1.0 / (c->gam - 1.0);
     a.flux = c->flux;
     a.volume = c->volume;
+    a.sys = c->sys;
+    a.c_h = c->c_h;
     const int S = c->S;
     void *kbuf[2] = {c->d_Ka, c->d_Kb};
     kind = i == 0 ? SK_FIRST : (i == S - 1 ? SK_LAST : SK_MID);
@@ -373,7 +386,7 @@ int autotune(perrk_ctx *c, double *u)
         std::snprintf(buf, sizeof buf, " %d:", i + 1);
         std::string line = buf;
         for (int wpb = 1; wpb <= PERRK_MAX_WPB; wpb *= 2) {
-            if (stage_lds_bytes(c->dim, variant, wpb) > c->max_lds) {
+            if (stage_lds_bytes(c->dim, variant, wpb, c->sys) > c->max_lds) {
                 line += " -";
                 continue;
             }
@@ -435,7 +448,7 @@ int enqueue_step(perrk_ctx *c, double *u)
     if (c->rp.relax) {
         for (int p = 0; p < c->opt.fast_passes; ++p) {
             HIPCHECK(c, mark_begin(c));
-            HIPCHECK(c, launch_relax_pass(c->dim, u, c->d_d, c->d_elem, c->d_cs, c->d_partial, c->nelem, c->gam,
+            HIPCHECK(c, launch_relax_pass(c->dim, c->sys, u, c->d_d, c->d_elem, c->d_cs, c->d_partial, c->nelem, c->gam,
                                           c->stream));
             HIPCHECK(c, mark_end(c, PERRK_K_RESIDUAL, c->pass_bytes));
             HIPCHECK(c, mark_begin(c));
@@ -444,11 +457,11 @@ int enqueue_step(perrk_ctx *c, double *u)
         }
     }
     HIPCHECK(c, mark_begin(c));
-    HIPCHECK(c, launch_relax_complete(c->dim, u, c->d_d, c->d_elem, c->d_cs, c->d_case_off, c->n_cases,
+    HIPCHECK(c, launch_relax_complete(c->dim, c->sys, u, c->d_d, c->d_elem, c->d_cs, c->d_case_off, c->n_cases,
                                       c->d_partial, c->nelem, c->gam, c->rp, c->stream));
     HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
     HIPCHECK(c, mark_begin(c));
-    HIPCHECK(c, launch_final_update(c->dim, u, c->d_d, c->d_elem, c->d_cs, c->d_err, c->nelem, c->stream));
+    HIPCHECK(c, launch_final_update(c->dim, c->sys, u, c->d_d, c->d_elem, c->d_cs, c->d_err, c->nelem, c->stream));
     HIPCHECK(c, mark_end(c, PERRK_K_UPDATE, c->update_bytes));
     return PERRK_OK;
 }
@@ -499,7 +512,9 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     if (!c) return PERRK_ENOMEM;
     c->opt = o;
     c->dim = m->dim;
-    c->V = m->dim + 2;
+    c->sys = m->system;
+    c->c_h = m->system == PERRK_SYSTEM_GLM_MHD ? m->glm_ch : 0.0;
+    c->V = m->system == PERRK_SYSTEM_GLM_MHD ? 9 : m->dim + 2;
     c->npe = m->dim == 2 ? 16 : 64;
     c->n_cases = m->n_cases;
     c->precision = m->precision;
@@ -603,7 +618,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     rp.nb = (int)c->bstages.size();
     for (int j = 0; j < rp.nb && j < PERRK_MAXB; ++j) rp.bw[j] = c->b[c->bstages[j]];
     c->rp = rp;
-    c->cfg.epb_mult = 4;
+    c->cfg.epb_mult = c->sys == PERRK_SYSTEM_GLM_MHD ? 1 : 4;  // GLM-MHD: 27 KB of LDS per wavefront
     c->scfg.assign(c->S, c->cfg);
     c->sstats.assign(c->S, perrk_kernel_stat{});
 
@@ -830,7 +845,7 @@ int perrk_entropy(perrk_ctx *c, const void *u_dev, double *H)
     if (!c || !u_dev || !H) return fail(c, PERRK_EINVAL, "null argument");
     HIPCHECK(c, hipEventRecord(c->ev_in, c->user_stream));
     HIPCHECK(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
-    HIPCHECK(c, launch_entropy(c->dim, static_cast<const double *>(u_dev), c->d_elem, c->d_partial, c->d_H,
+    HIPCHECK(c, launch_entropy(c->dim, c->sys, static_cast<const double *>(u_dev), c->d_elem, c->d_partial, c->d_H,
                                c->d_case_off, c->n_cases, c->nelem, c->gam, c->d_err, c->stream));
     HIPCHECK(c, hipMemcpyAsync(c->h_H, c->d_H, sizeof(double) * c->n_cases, hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
@@ -859,6 +874,8 @@ int perrk_rhs(perrk_ctx *c, const void *u_dev, void *k_dev)
     a.inv_gm1 = 1.0 / (c->gam - 1.0);
     a.flux = c->flux;
     a.volume = c->volume;
+    a.sys = c->sys;
+    a.c_h = c->c_h;
     HIPCHECK(c, launch_stage(c->dim, c->precision == PERRK_FP64 ? 0 : 1, c->flux, SK_FIRST, a, c->d_coef,
                              c->cfg, c->stream));
     HIPCHECK(c, hipEventRecord(c->ev_out, c->stream));
@@ -944,13 +961,14 @@ int perrk_get_stage_stats(perrk_ctx *c, perrk_kernel_stat *stats, int n_stages, 
 
 int perrk_get_tuning(perrk_ctx *c, char *buf, size_t len)
 {
-    static const char *const flux_names[] = {"ec", "hll", "llf", "hlle", "hllc"};
+    static const char *const flux_names[] = {"ec", "hll", "llf", "hlle", "hllc", "central"};
     if (!c || !buf || !len) return PERRK_EINVAL;
     std::string w;
     for (const LaunchCfg &x : c->scfg) w += (w.empty() ? "" : ",") + std::to_string(x.epb_mult);
     std::snprintf(buf, len,
-                  "dim=%d precision=%s flux=%s volume=%s stage_waves_per_workgroup=[%s] fast_passes=%d graph=%d %s",
-                  c->dim, c->precision == PERRK_MIXED ? "mixed" : (c->precision == PERRK_MIXED_ALL ? "mixed_all" : "fp64"),
+                  "system=%s dim=%d precision=%s flux=%s volume=%s stage_waves_per_workgroup=[%s] fast_passes=%d "
+                  "graph=%d %s",
+                  c->sys == PERRK_SYSTEM_GLM_MHD ? "glm_mhd" : "euler", c->dim, c->precision == PERRK_MIXED ? "mixed" : (c->precision == PERRK_MIXED_ALL ? "mixed_all" : "fp64"),
                   flux_names[c->flux], c->volume ? "weak" : "flux_differencing", w.c_str(), c->opt.fast_passes,
                   c->opt.use_graph, c->tuned ? c->tune_report.c_str() : "(not tuned)");
     return PERRK_OK;

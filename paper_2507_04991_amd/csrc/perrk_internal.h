@@ -92,6 +92,8 @@ struct StageArgs {
     double gam, gm1, inv_gm1; // gamma, gamma - 1, 1 / (gamma - 1)
     int32_t flux;             // surface flux (PERRK_FLUX_*)
     int32_t volume;           // volume term (PERRK_VOLUME_*)
+    int32_t sys;              // PERRK_SYSTEM_*
+    double c_h;               // GLM-MHD divergence-cleaning speed
     double b1, bsm1, bs;      // last stage weights
     double b_acc;             // stages with b_i != 0 other than 1, S-1, S: b_i (K_i enters d here)
     int32_t acc_mode;         //   1: d = b_i K_i, 2: d += b_i K_i, 0: no contribution
@@ -110,30 +112,31 @@ struct LaunchCfg {
 #define PERRK_MAX_WPB 8
 
 // Workgroup LDS bytes of a stage launch with wpb wavefronts per workgroup.
-size_t stage_lds_bytes(int dim, int variant, int wpb);
+size_t stage_lds_bytes(int dim, int variant, int wpb, int sys);
 
 // Kernel launchers (perrk_kernels.hip).
 // variant: 0 double flux / double storage, 1 float / float, 2 double flux / float storage;
 // flux = 0 with a.volume = 0 runs the EC-only kernel, anything else the kernel with
-// run-time selected surface flux and volume term
+// run-time selected surface flux and volume term; a.sys = 1 runs the GLM-MHD
+// kernel (2D, variant 0 only).  sys: PERRK_SYSTEM_*.
 hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArgs &a, const double *coef,
                         LaunchCfg cfg, hipStream_t s);
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases,
                                 const double *ep_partial, int64_t nelem, RelaxParams rp,
                                 const float *mlp, hipStream_t s);
-hipError_t launch_relax_pass(int dim, const double *U, const double *d, const ElemInfo *elem,
+hipError_t launch_relax_pass(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                              const CaseState *cs, double *partial, int64_t nelem, double gam,
                              hipStream_t s);
 hipError_t launch_relax_finalize(CaseState *cs, const int64_t *case_off, int n_cases,
                                  const double *partial, RelaxParams rp, hipStream_t s);
-hipError_t launch_relax_complete(int dim, const double *U, const double *d, const ElemInfo *elem,
+hipError_t launch_relax_complete(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                                  CaseState *cs, const int64_t *case_off, int n_cases,
                                  double *partial, int64_t nelem, double gam, RelaxParams rp,
                                  hipStream_t s);
-hipError_t launch_final_update(int dim, double *U, const double *d, const ElemInfo *elem,
+hipError_t launch_final_update(int dim, int sys, double *U, const double *d, const ElemInfo *elem,
                                const CaseState *cs, const int32_t *err, int64_t nelem,
                                hipStream_t s);
-hipError_t launch_entropy(int dim, const double *U, const ElemInfo *elem, double *partial,
+hipError_t launch_entropy(int dim, int sys, const double *U, const ElemInfo *elem, double *partial,
                           double *H_out, const int64_t *case_off, int n_cases, int64_t nelem,
                           double gam, int32_t *err, hipStream_t s);
 hipError_t launch_init_cases(CaseState *cs, int n_cases, hipStream_t s);

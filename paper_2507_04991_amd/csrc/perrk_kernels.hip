@@ -1013,6 +1013,467 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     if (bad && valid) atomicOr(a.err, bad);
 }
 
+// ---------------------------------------------------------------- ideal GLM-MHD
+// Nine conserved variables per node, u = (rho, rho v_1..3, E, B_1..3, psi), on
+// 2D meshes (all three vector components carried), double precision.  The
+// system is u_t + sum_d [d_d f_d + Phi(u) d_d B_d + Phi_d(u) d_d psi] = 0 with
+//   p = (gamma-1) (E - rho |v|^2/2 - |B|^2/2 - psi^2/2),
+//   f_rho = rho v_d, f_m = rho v v_d + (p + |B|^2/2) e_d - B B_d,
+//   f_E = v_d (rho |v|^2/2 + gamma p/(gamma-1) + |B|^2) - B_d (v.B) + c_h psi B_d,
+//   f_B = v_d B - B_d v + c_h psi e_d, f_psi = c_h B_d,
+//   Phi = (0, B, v.B, v, 0) (Powell), Phi_d = (0, 0, 0, 0, v_d psi, 0, 0, 0, v_d) (GLM).
+// Volume term: flux differencing with an EC two-point flux, or the central flux
+// (the weak form).  Surface flux: EC, local Lax-Friedrichs or central.  The
+// non-conservative terms: Phi(u_i) times the split-form sum of the pair means
+// {B_d} plus the lifted face means, which is the strong-form derivative of B_d
+// with the face mean as interface value (and the same for psi).
+constexpr int MHD_V = 9;
+constexpr int MHD_NC = 11;  // flux components + the means of B_d and psi
+constexpr int MHD_NQ = 9;   // primitives per node in LDS: rho, v_1..3, p, B_1..3, psi
+constexpr int MHD_SLOT = MHD_NQ * 16 + MHD_NC * (SG<2>::NFN + SG<2>::NPP);  // LDS doubles per element
+
+struct PrimM {
+    double rho, v[3], p, B[3], psi;
+};
+
+__device__ __forceinline__ void make_prim_mhd(const double *u, double gm1, PrimM &P, int &bad)
+{
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < MHD_V; ++k) sum += u[k];
+    const double rho = u[0];
+    const double ir = rcp64(rho);
+    double kin = 0.0, mag = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        P.v[k] = u[1 + k] * ir;
+        kin += u[1 + k] * P.v[k];
+        P.B[k] = u[5 + k];
+        mag += u[5 + k] * u[5 + k];
+    }
+    P.psi = u[8];
+    const double p = gm1 * (u[4] - 0.5 * kin - 0.5 * mag - 0.5 * u[8] * u[8]);
+    if (!isfinite(sum)) bad |= 2;
+    else if (!(rho > 0.0) || !(p > 0.0)) bad |= 1;
+    P.rho = rho;
+    P.p = p;
+}
+
+__device__ __forceinline__ void mhd_put(double *slot, int node, const PrimM &P)
+{
+    double *q = slot + node * MHD_NQ;
+    q[0] = P.rho;
+    q[1] = P.v[0];
+    q[2] = P.v[1];
+    q[3] = P.v[2];
+    q[4] = P.p;
+    q[5] = P.B[0];
+    q[6] = P.B[1];
+    q[7] = P.B[2];
+    q[8] = P.psi;
+}
+
+__device__ __forceinline__ void mhd_get(const double *slot, int node, PrimM &P)
+{
+    const double *q = slot + node * MHD_NQ;
+    P.rho = q[0];
+    P.v[0] = q[1];
+    P.v[1] = q[2];
+    P.v[2] = q[3];
+    P.p = q[4];
+    P.B[0] = q[5];
+    P.B[1] = q[6];
+    P.B[2] = q[7];
+    P.psi = q[8];
+}
+
+__device__ __forceinline__ double sel2(int d, double a, double b) { return d == 0 ? a : b; }
+
+// Physical flux in direction d (0 or 1) from primitive variables.
+__device__ __forceinline__ void mhd_flux_phys(int d, const PrimM &P, double gam, double inv_gm1, double c_h, double *f)
+{
+    const double vn = sel2(d, P.v[0], P.v[1]), Bn = sel2(d, P.B[0], P.B[1]);
+    const double vB = P.v[0] * P.B[0] + P.v[1] * P.B[1] + P.v[2] * P.B[2];
+    const double B2 = P.B[0] * P.B[0] + P.B[1] * P.B[1] + P.B[2] * P.B[2];
+    const double v2 = P.v[0] * P.v[0] + P.v[1] * P.v[1] + P.v[2] * P.v[2];
+    const double ptot = P.p + 0.5 * B2;
+    const double mn = P.rho * vn;
+    f[0] = mn;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[1 + k] = mn * P.v[k] - P.B[k] * Bn + (k == d ? ptot : 0.0);
+    f[4] = vn * (0.5 * P.rho * v2 + gam * inv_gm1 * P.p + B2) - Bn * vB + c_h * P.psi * Bn;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[5 + k] = vn * P.B[k] - P.v[k] * Bn + (k == d ? c_h * P.psi : 0.0);
+    f[8] = c_h * Bn;
+}
+
+// Entropy-conservative two-point flux (with beta = rho / (2p), arithmetic means
+// {.}, logarithmic means {.}_log, p~ = {rho} / (2 {beta})):
+//   f_rho = {rho}_log {v_d}
+//   f_m   = f_rho {v} - (B_d,A B_B + B_d,B B_A)/2 + (p~ + B_A.B_B/2) e_d
+//   f_B   = {v_d B - B_d v} + c_h {psi} e_d,  f_psi = c_h {B_d}
+//   f_E   = f_rho (1/(2 (gamma-1) {beta}_log) - {|v|^2}/2) + f_m.{v} + f_B.{B}
+//           + f_psi {psi} - {v_d |B|^2}/2 + {B_d} {v.B} - c_h {psi B_d}
+__device__ __forceinline__ void mhd_flux_ec(int d, const PrimM &A, const PrimM &B, double inv_gm1, double c_h,
+                                            double *f)
+{
+    const double ba = 0.5 * A.rho * rcp64(A.p), bb = 0.5 * B.rho * rcp64(B.p);
+    const double rho_ln = lmean(A.rho, B.rho);
+    const double ibeta_ln = inv_lmean(ba, bb);
+    const double ptil = (A.rho + B.rho) * rcp64(2.0 * (ba + bb));
+    double va[3], Ba[3], BB = 0.0, v2a = 0.0, vBa = 0.0, vBb = 0.0, B2a = 0.0, B2b = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        va[k] = 0.5 * (A.v[k] + B.v[k]);
+        Ba[k] = 0.5 * (A.B[k] + B.B[k]);
+        BB += A.B[k] * B.B[k];
+        v2a += 0.5 * (A.v[k] * A.v[k] + B.v[k] * B.v[k]);
+        vBa += A.v[k] * A.B[k];
+        vBb += B.v[k] * B.B[k];
+        B2a += A.B[k] * A.B[k];
+        B2b += B.B[k] * B.B[k];
+    }
+    const double Bna = sel2(d, A.B[0], A.B[1]), Bnb = sel2(d, B.B[0], B.B[1]);
+    const double vna = sel2(d, A.v[0], A.v[1]), vnb = sel2(d, B.v[0], B.v[1]);
+    const double psa = 0.5 * (A.psi + B.psi);
+    const double f0 = rho_ln * 0.5 * (vna + vnb);
+    f[0] = f0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[1 + k] = f0 * va[k] - 0.5 * (Bna * B.B[k] + Bnb * A.B[k]) + (k == d ? ptil + 0.5 * BB : 0.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        f[5 + k] = 0.5 * (vna * A.B[k] - A.v[k] * Bna + vnb * B.B[k] - B.v[k] * Bnb) + (k == d ? c_h * psa : 0.0);
+    f[8] = c_h * 0.5 * (Bna + Bnb);
+    double fe = f0 * (0.5 * inv_gm1 * ibeta_ln - 0.5 * v2a);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) fe += f[1 + k] * va[k] + f[5 + k] * Ba[k];
+    fe += f[8] * psa - 0.25 * (vna * B2a + vnb * B2b) + 0.5 * (Bna + Bnb) * 0.5 * (vBa + vBb)
+          - c_h * 0.5 * (A.psi * Bna + B.psi * Bnb);
+    f[4] = fe;
+}
+
+// Fast magnetosonic speed in direction d.
+__device__ __forceinline__ double mhd_cfast(int d, const PrimM &P, double gam)
+{
+    const double ir = rcp64(P.rho);
+    const double a2 = gam * P.p * ir;
+    const double b2 = (P.B[0] * P.B[0] + P.B[1] * P.B[1] + P.B[2] * P.B[2]) * ir;
+    const double Bn = sel2(d, P.B[0], P.B[1]);
+    return sqrt(0.5 * (a2 + b2 + sqrt((a2 + b2) * (a2 + b2) - 4.0 * a2 * Bn * Bn * ir)));
+}
+
+__device__ __forceinline__ void mhd_cons(const PrimM &P, double inv_gm1, double *u)
+{
+    u[0] = P.rho;
+    double kin = 0.0, mag = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        u[1 + k] = P.rho * P.v[k];
+        kin += P.v[k] * P.v[k];
+        u[5 + k] = P.B[k];
+        mag += P.B[k] * P.B[k];
+    }
+    u[4] = P.p * inv_gm1 + 0.5 * P.rho * kin + 0.5 * mag + 0.5 * P.psi * P.psi;
+    u[8] = P.psi;
+}
+
+// Surface flux: EC, local Lax-Friedrichs (max |v_d| + c_f of both sides) or central.
+__device__ __forceinline__ void mhd_flux_surface(int kind, int d, const PrimM &L, const PrimM &R, double gam,
+                                                 double inv_gm1, double c_h, double *f)
+{
+    if (kind == PERRK_FLUX_EC) {
+        mhd_flux_ec(d, L, R, inv_gm1, c_h, f);
+        return;
+    }
+    double fl[MHD_V], fr[MHD_V];
+    mhd_flux_phys(d, L, gam, inv_gm1, c_h, fl);
+    mhd_flux_phys(d, R, gam, inv_gm1, c_h, fr);
+#pragma unroll
+    for (int k = 0; k < MHD_V; ++k) f[k] = 0.5 * (fl[k] + fr[k]);
+    if (kind == PERRK_FLUX_LLF) {
+        const double lam = fmax(fabs(sel2(d, L.v[0], L.v[1])) + mhd_cfast(d, L, gam),
+                                fabs(sel2(d, R.v[0], R.v[1])) + mhd_cfast(d, R, gam));
+        double ul[MHD_V], ur[MHD_V];
+        mhd_cons(L, inv_gm1, ul);
+        mhd_cons(R, inv_gm1, ur);
+#pragma unroll
+        for (int k = 0; k < MHD_V; ++k) f[k] -= 0.5 * lam * (ur[k] - ul[k]);
+    }
+}
+
+// Entropy variables of s = -rho log(p rho^-gamma) with the MHD pressure.
+__device__ __forceinline__ void mhd_entropy_vars(const double *u, double gam, double *w)
+{
+    const double rho = u[0], ir = 1.0 / rho;
+    double m2 = 0.0, B2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        m2 += u[1 + k] * u[1 + k];
+        B2 += u[5 + k] * u[5 + k];
+    }
+    const double p = (gam - 1.0) * (u[4] - 0.5 * m2 * ir - 0.5 * B2 - 0.5 * u[8] * u[8]);
+    const double g1rp = (gam - 1.0) * rho / p;
+    w[0] = gam - (log(p) - gam * log(rho)) - 0.5 * g1rp * m2 * ir * ir;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        w[1 + k] = g1rp * u[1 + k] * ir;
+        w[5 + k] = g1rp * u[5 + k];
+    }
+    w[4] = -g1rp;
+    w[8] = g1rp * u[8];
+}
+
+__device__ __forceinline__ double mhd_entropy_density(const double *u, double gam)
+{
+    double m2 = 0.0, B2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        m2 += u[1 + k] * u[1 + k];
+        B2 += u[5 + k] * u[5 + k];
+    }
+    const double rho = u[0];
+    const double p = (gam - 1.0) * (u[4] - 0.5 * m2 / rho - 0.5 * B2 - 0.5 * u[8] * u[8]);
+    return -rho * (log(p) - gam * log(rho));
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(64 * PERRK_MAX_WPB) mhd_stage_kernel(const StageArgs a, const double *coef)
+{
+    constexpr int NPE = 16, V = MHD_V, NC = MHD_NC, EPW = 4, SLOT = MHD_SLOT;
+    constexpr int NFN = SG<2>::NFN, NPP = SG<2>::NPP, NPD = SG<2>::NPD, NLINE = SG<2>::NLINE;
+    constexpr int FR = FaceRounds<2>::N;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *lds = reinterpret_cast<double *>(smem_raw);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int eslot = wave * EPW + lane / NPE;
+    const int node = lane % NPE;
+    const int epb = (int)(blockDim.x >> 6) * EPW;
+    const int li = xcd_block(blockIdx.x, gridDim.x) * epb + eslot;
+    const bool valid = li < a.n_active;
+    const int4 *ap = reinterpret_cast<const int4 *>(a.active);
+    const uint32_t ai = (uint32_t)(valid ? li : a.n_active - 1);
+    const int4 act = elt(ap, 2u * ai), act2 = elt(ap, 2u * ai + 1u);
+    const int e = (int)((uint32_t)act.x & PERRK_NBR_MASK);
+    const int lvl = (int)((uint32_t)act.x >> PERRK_NBR_SHIFT);
+    double *slot = lds + (size_t)eslot * SLOT;
+    const double gam = a.gam, gm1 = a.gm1, inv_gm1 = a.inv_gm1, c_h = a.c_h;
+    int bad = 0;
+
+    // ---- loads (as in the Euler kernel: own node, the neighbours' face nodes)
+    double dt = 0.0, c1 = 0.0, cp = 0.0;
+    if (KIND != SK_FIRST) {
+        dt = elt(a.cs, (uint32_t)act.y).dt;
+        c1 = elt(coef, (uint32_t)lvl);
+        cp = elt(coef, (uint32_t)(PERRK_MAXR + lvl));
+    }
+    const size_t field = (size_t)a.nelem * NPE;
+    NodeRaw<V, double> own;
+    {
+        const uint32_t o8 = ((uint32_t)e * NPE + node) * 8u;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            own.u[v] = bload<double>(field_rsrc<double>(a.U, v, field), o8);
+            if (KIND != SK_FIRST) {
+                own.k1[v] = bload<double>(field_rsrc<double>(a.K1, v, field), o8);
+                own.kp[v] = bload<double>(field_rsrc<double>(a.Kp, v, field), o8);
+            }
+        }
+    }
+    double dacc[V];
+    if constexpr (KIND == SK_LAST) {
+        const uint32_t o8 = ((uint32_t)e * NPE + node) * 8u;
+#pragma unroll
+        for (int v = 0; v < V; ++v) dacc[v] = a.d_has ? bload<double>(field_rsrc<double>(a.d_out, v, field), o8) : 0.0;
+    }
+    FaceNode<2> F[FR];
+    bool fv[FR];
+    NodeRaw<V, double> nr[FR];
+    double nc1[FR], ncp[FR];
+#pragma unroll
+    for (int r = 0; r < FR; ++r) {
+        int nn;
+        fv[r] = face_node<2>(r, lane, F[r], nn);
+        const int f = 2 * F[r].d + F[r].side;
+        const uint32_t w = (uint32_t)(f < 2 ? (f == 0 ? act.z : act.w) : (f == 2 ? act2.x : act2.y));
+        const int nb = (int)(w & PERRK_NBR_MASK);
+        nc1[r] = 0.0;
+        ncp[r] = 0.0;
+        if (KIND != SK_FIRST) {
+            const int lv = (int)(w >> PERRK_NBR_SHIFT);
+            nc1[r] = elt(coef, (uint32_t)lv);
+            ncp[r] = elt(coef, (uint32_t)(PERRK_MAXR + lv));
+        }
+        const uint32_t o8 = ((uint32_t)nb * NPE + nn) * 8u;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            nr[r].u[v] = bload<double>(field_rsrc<double>(a.U, v, field), o8);
+            if (KIND != SK_FIRST) {
+                nr[r].k1[v] = bload<double>(field_rsrc<double>(a.K1, v, field), o8);
+                nr[r].kp[v] = bload<double>(field_rsrc<double>(a.Kp, v, field), o8);
+            }
+        }
+    }
+
+    // ---- stage states
+    double u[V];
+    PrimM me, PN[FR];
+    combine<V, double, KIND>(own, dt, c1, cp, u);
+    make_prim_mhd(u, gm1, me, bad);
+#pragma unroll
+    for (int r = 0; r < FR; ++r) {
+        double un[V];
+        combine<V, double, KIND>(nr[r], dt, nc1[r], ncp[r], un);
+        make_prim_mhd(un, gm1, PN[r], bad);
+    }
+    mhd_put(slot, node, me);
+    wave_lds_sync();
+
+    // ---- surface fluxes and face means of B_d and psi, lifted by +-6
+#pragma unroll
+    for (int r = 0; r < FR; ++r) {
+        if (!fv[r]) continue;
+        PrimM PO;
+        mhd_get(slot, F[r].own, PO);
+        const bool sd = F[r].side != 0;
+        // minus / plus states selected value by value (registers, not addresses)
+        PrimM L, R;
+        L.rho = sd ? PO.rho : PN[r].rho;
+        R.rho = sd ? PN[r].rho : PO.rho;
+        L.p = sd ? PO.p : PN[r].p;
+        R.p = sd ? PN[r].p : PO.p;
+        L.psi = sd ? PO.psi : PN[r].psi;
+        R.psi = sd ? PN[r].psi : PO.psi;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            L.v[k] = sd ? PO.v[k] : PN[r].v[k];
+            R.v[k] = sd ? PN[r].v[k] : PO.v[k];
+            L.B[k] = sd ? PO.B[k] : PN[r].B[k];
+            R.B[k] = sd ? PN[r].B[k] : PO.B[k];
+        }
+        double fs[V];
+        mhd_flux_surface(a.flux, F[r].d, L, R, gam, inv_gm1, c_h, fs);
+        const double lift = sd ? 6.0 : -6.0;
+        double *sf = slot + MHD_NQ * NPE;
+#pragma unroll
+        for (int v = 0; v < V; ++v) sf[v * NFN + F[r].q] = lift * fs[v];
+        sf[9 * NFN + F[r].q] = lift * 0.5 * (sel2(F[r].d, L.B[0], L.B[1]) + sel2(F[r].d, R.B[0], R.B[1]));
+        sf[10 * NFN + F[r].q] = lift * 0.5 * (L.psi + R.psi);
+    }
+
+    // ---- volume pairs: the two-point flux and the pair means of B_d and psi
+#pragma unroll
+    for (int rd = 0; rd < PairRounds<2, 2>::N; ++rd) {
+        int es, dd, l, k;
+        pair_of<2, 2>(rd, lane, es, dd, l, k);
+        int ta, tb;
+        pair_pos(k, ta, tb);
+        double *ps = lds + (size_t)(wave * EPW + es) * SLOT;
+        PrimM A, B;
+        mhd_get(ps, line_node<2>(dd, l, ta), A);
+        mhd_get(ps, line_node<2>(dd, l, tb), B);
+        double f[V];
+        if (a.volume) {
+            double fa[V], fb[V];
+            mhd_flux_phys(dd, A, gam, inv_gm1, c_h, fa);
+            mhd_flux_phys(dd, B, gam, inv_gm1, c_h, fb);
+#pragma unroll
+            for (int v = 0; v < V; ++v) f[v] = 0.5 * (fa[v] + fb[v]);
+        } else {
+            mhd_flux_ec(dd, A, B, inv_gm1, c_h, f);
+        }
+        double *vf = ps + MHD_NQ * NPE + NC * NFN;
+        const int p = dd * NPD + l * 6 + k;
+#pragma unroll
+        for (int v = 0; v < V; ++v) vf[v * NPP + p] = f[v];
+        vf[9 * NPP + p] = 0.5 * (sel2(dd, A.B[0], A.B[1]) + sel2(dd, B.B[0], B.B[1]));
+        vf[10 * NPP + p] = 0.5 * (A.psi + B.psi);
+    }
+    wave_lds_sync();
+
+    // ---- gather: (2/h_d) [sum_m Dsplit f# + lifted face flux
+    //                        + Phi (sum_m Dsplit {B_d} + lifted face mean) + Phi_d (... psi)]
+    const ElemInfo ei = elt(a.elem, (uint32_t)e);
+    double du[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) du[v] = 0.0;
+    {
+        const double *sf = slot + MHD_NQ * NPE;
+        const double *vf = sf + NC * NFN;
+        const double vB = me.v[0] * me.B[0] + me.v[1] * me.B[1] + me.v[2] * me.B[2];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const int t = node_pos(d, node);
+            const int l = node_line<2>(d, node);
+            double acc[NC];
+#pragma unroll
+            for (int v = 0; v < NC; ++v) acc[v] = 0.0;
+            const int pb = d * NPD + l * 6;
+            const int p1 = pb + pair_k<1>(t), p2 = pb + pair_k<2>(t), p3 = pb + pair_k<3>(t);
+            const double w1 = dsplit_j<double, 1>(t), w2 = dsplit_j<double, 2>(t), w3 = dsplit_j<double, 3>(t);
+#pragma unroll
+            for (int v = 0; v < NC; ++v) {
+                acc[v] += w1 * vf[v * NPP + p1];
+                acc[v] += w2 * vf[v * NPP + p2];
+                acc[v] += w3 * vf[v * NPP + p3];
+            }
+            if (t == 0 || t == 3) {
+                const int q = (2 * d + (t == 3 ? 1 : 0)) * NLINE + l;
+#pragma unroll
+                for (int v = 0; v < NC; ++v) acc[v] += sf[v * NFN + q];
+            }
+            // non-conservative terms of the node's own state
+            const double vn = sel2(d, me.v[0], me.v[1]);
+            acc[1] += me.B[0] * acc[9];
+            acc[2] += me.B[1] * acc[9];
+            acc[3] += me.B[2] * acc[9];
+            acc[4] += vB * acc[9] + vn * me.psi * acc[10];
+            acc[5] += me.v[0] * acc[9];
+            acc[6] += me.v[1] * acc[9];
+            acc[7] += me.v[2] * acc[9];
+            acc[8] += vn * acc[10];
+            const double h = d == 0 ? ei.metric[0] : ei.metric[1];
+#pragma unroll
+            for (int v = 0; v < V; ++v) du[v] += h * acc[v];
+        }
+    }
+
+    double k[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) k[v] = -du[v];
+    if (valid) {
+        const uint32_t o8 = ((uint32_t)e * NPE + node) * 8u;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            if (KIND == SK_LAST) {
+                double dv = a.bs * k[v];
+                if (a.bsm1 != 0.0) dv += a.bsm1 * own.kp[v];
+                if (a.b1 != 0.0) dv += a.b1 * own.k1[v];
+                if (a.d_has) dv += dacc[v];
+                bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
+            } else {
+                bstore<double>(k[v], field_rsrc<double>(a.Kout, v, field), o8);
+                if (a.acc_mode) {
+                    double dv = a.b_acc * k[v];
+                    if (a.acc_mode == 2) dv += bload<double>(field_rsrc<double>(a.d_out, v, field), o8);
+                    bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
+                }
+            }
+        }
+    }
+    if (a.ep_partial != nullptr) {
+        double w[V];
+        mhd_entropy_vars(u, gam, w);
+        double dot = 0.0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) dot += w[v] * k[v];
+        double sm = node_weight<2>(node) * dot;
+#pragma unroll
+        for (int off = NPE / 2; off >= 1; off >>= 1) sm += __shfl_xor(sm, off);
+        if (valid && node == 0) a.ep_partial[e] = ei.jac * sm;
+    }
+    if (bad && valid) atomicOr(a.err, bad);
+}
+
 // ---------------------------------------------------------------- reductions
 // Sum of NC per-element partials over [b, e) by PERRK_RED_THREADS threads in a
 // fixed order (strided sequential sums, then a fixed tree).  Result in out on
@@ -1095,14 +1556,66 @@ __device__ __forceinline__ void relax_node(const double *u, const double *dv, do
     wd = dt * dot;
 }
 
+// The same for ideal GLM-MHD (nine variables): the pressure change gains
+//   -(gamma-1) [(B.dB + |dB|^2/2) + (psi dpsi + dpsi^2/2)],
+// and w' gains the components (gamma-1) rho' B' / p' and (gamma-1) rho' psi' / p'.
+__device__ __forceinline__ void relax_node_mhd(const double *u, const double *dv, double g, double dt, double gam,
+                                               double &ds, double &wd)
+{
+    const double rho = u[0];
+    double du[MHD_V];
+#pragma unroll
+    for (int v = 0; v < MHD_V; ++v) du[v] = g * dt * dv[v];
+    const double drho = du[0], rho1 = rho + drho;
+    const double ir = 1.0 / rho, ir1 = 1.0 / rho1;
+    double mdm = 0.0, dm2 = 0.0, m2 = 0.0, B2 = 0.0, BdB = 0.0, dB2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        mdm += u[1 + k] * du[1 + k];
+        dm2 += du[1 + k] * du[1 + k];
+        m2 += u[1 + k] * u[1 + k];
+        B2 += u[5 + k] * u[5 + k];
+        BdB += u[5 + k] * du[5 + k];
+        dB2 += du[5 + k] * du[5 + k];
+    }
+    const double g1 = gam - 1.0;
+    const double p = g1 * (u[4] - 0.5 * m2 * ir - 0.5 * B2 - 0.5 * u[8] * u[8]);
+    const double dp = g1 * (du[4] - (mdm + 0.5 * dm2) * ir1 + 0.5 * drho * m2 * ir * ir1 - (BdB + 0.5 * dB2)
+                            - (u[8] * du[8] + 0.5 * du[8] * du[8]));
+    const double p1 = p + dp;
+    const double lp = log1p_small(dp / p), lr = log1p_small(drho * ir);
+    const double sth0 = log(p) - gam * log(rho);
+    const double sth1 = sth0 + lp - gam * lr;
+    ds = -drho * sth1 - rho * (lp - gam * lr);
+    const double ip1 = 1.0 / p1;
+    const double m12 = m2 + 2.0 * mdm + dm2;
+    const double g1rp = g1 * rho1 * ip1;
+    double dot = (gam - sth1 - 0.5 * g1 * m12 * ir1 * ip1) * dv[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        dot += g1 * (u[1 + k] + du[1 + k]) * ip1 * dv[1 + k];
+        dot += g1rp * (u[5 + k] + du[5 + k]) * dv[5 + k];
+    }
+    dot += -g1rp * dv[4];
+    dot += g1rp * (u[8] + du[8]) * dv[8];
+    wd = dt * dot;
+}
+
+// Nodes, fields and elements per wavefront of a system (SYS 0: Euler, 1: GLM-MHD in 2D).
+template <int DIM, int SYS>
+struct Sys {
+    static constexpr int NPE = Geo<DIM>::NPE, EPW = Geo<DIM>::EPW;
+    static constexpr int V = SYS == 1 ? MHD_V : Geo<DIM>::V;
+};
+
 // Per-element residual partials: J sum q Delta s at gamma, J sum q w(u + gamma dt d) . dt d,
 // J sum q Delta s at gamma_b (only while opening a bracket), sum |d|.
-template <int DIM>
+template <int DIM, int SYS>
 __device__ __forceinline__ void relax_element(const double *U, const double *dd, const ElemInfo *elem,
                                               const CaseState *cs, double *partial, int64_t nelem,
                                               double gam, int64_t e, int node, bool valid)
 {
-    constexpr int NPE = Geo<DIM>::NPE, V = Geo<DIM>::V;
+    constexpr int NPE = Sys<DIM, SYS>::NPE, V = Sys<DIM, SYS>::V;
     const ElemInfo ei = elem[e];
     const CaseState &C = cs[ei.case_id];
     const int st = C.state;
@@ -1122,11 +1635,13 @@ __device__ __forceinline__ void relax_element(const double *U, const double *dd,
         }
         const double q = node_weight<DIM>(node);
         double ds, wd;
-        relax_node<DIM>(u, dv, g, dt, gam, ds, wd);
+        if constexpr (SYS == 1) relax_node_mhd(u, dv, g, dt, gam, ds, wd);
+        else relax_node<DIM>(u, dv, g, dt, gam, ds, wd);
         sr = q * ds;
         srp = q * wd;
         if (!eval1 && st == RS_BIS_INIT) {
-            relax_node<DIM>(u, dv, C.gamma_b, dt, gam, ds, wd);
+            if constexpr (SYS == 1) relax_node_mhd(u, dv, C.gamma_b, dt, gam, ds, wd);
+            else relax_node<DIM>(u, dv, C.gamma_b, dt, gam, ds, wd);
             srb = q * ds;
         }
     }
@@ -1325,7 +1840,7 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
     C.gamma_acc = 1.0;
 }
 
-template <int DIM>
+template <int DIM, int SYS>
 __global__ void __launch_bounds__(256)
 relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const CaseState *cs,
                   double *partial, int64_t nelem, double gam)
@@ -1351,7 +1866,7 @@ relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t e0 = ((int64_t)blk * (blockDim.x >> 6) + wave) * EPW + lane / NPE;
     const bool valid = e0 < nelem;
-    relax_element<DIM>(U, d, elem, cs, partial, nelem, gam, valid ? e0 : nelem - 1, lane % NPE, valid);
+    relax_element<DIM, SYS>(U, d, elem, cs, partial, nelem, gam, valid ? e0 : nelem - 1, lane % NPE, valid);
 }
 
 __global__ void __launch_bounds__(PERRK_RED_THREADS)
@@ -1369,7 +1884,7 @@ relax_finalize_kernel(CaseState *cs, const int64_t *case_off, const double *part
 // (rarely needed: Newton usually converges within the launched passes), then
 // the per-step bookkeeping.  Every evaluation uses the same per-element code and
 // the same fixed-order sum as the launched passes.
-template <int DIM>
+template <int DIM, int SYS>
 __global__ void __launch_bounds__(PERRK_RED_THREADS)
 relax_complete_kernel(const double *U, const double *d, const ElemInfo *elem, CaseState *cs,
                       const int64_t *case_off, double *partial, int64_t nelem, double gam,
@@ -1395,8 +1910,8 @@ relax_complete_kernel(const double *U, const double *d, const ElemInfo *elem, Ca
         for (int64_t g = b + (int64_t)wave * EPW; g < e; g += (int64_t)NW * EPW) {
             const int64_t el = g + lane / NPE;
             const bool valid = el < e;
-            relax_element<DIM>(U, d, elem, cs, partial, nelem, gam, valid ? el : e - 1, lane % NPE,
-                               valid);
+            relax_element<DIM, SYS>(U, d, elem, cs, partial, nelem, gam, valid ? el : e - 1, lane % NPE,
+                                    valid);
         }
         __syncthreads();
         double S[4];
@@ -1434,12 +1949,12 @@ relax_complete_kernel(const double *U, const double *d, const ElemInfo *elem, Ca
 }
 
 // U <- U + gamma dt d, two doubles per thread; skipped entirely after an error.
-template <int DIM>
+template <int DIM, int SYS>
 __global__ void __launch_bounds__(256)
 final_update_kernel(double *U, const double *d, const ElemInfo *elem, const CaseState *cs,
                     const int32_t *err, int64_t nelem)
 {
-    constexpr int NPE = Geo<DIM>::NPE, V = Geo<DIM>::V;
+    constexpr int NPE = Sys<DIM, SYS>::NPE, V = Sys<DIM, SYS>::V;
     if (*err != 0) return;
     const int64_t n2 = (int64_t)V * nelem * NPE / 2;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
@@ -1456,12 +1971,12 @@ final_update_kernel(double *U, const double *d, const ElemInfo *elem, const Case
     }
 }
 
-template <int DIM>
+template <int DIM, int SYS>
 __global__ void __launch_bounds__(256)
 entropy_elem_kernel(const double *U, const ElemInfo *elem, double *partial, int64_t nelem, double gam,
                     int32_t *err)
 {
-    constexpr int NPE = Geo<DIM>::NPE, V = Geo<DIM>::V, EPW = Geo<DIM>::EPW;
+    constexpr int NPE = Sys<DIM, SYS>::NPE, V = Sys<DIM, SYS>::V, EPW = Sys<DIM, SYS>::EPW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t e0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * EPW + lane / NPE;
     const bool valid = e0 < nelem;
@@ -1470,7 +1985,7 @@ entropy_elem_kernel(const double *U, const ElemInfo *elem, double *partial, int6
     double u[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) u[v] = U[((size_t)v * nelem + e) * NPE + node];
-    double s = node_weight<DIM>(node) * entropy_density<DIM>(u, gam);
+    double s = node_weight<DIM>(node) * (SYS == 1 ? mhd_entropy_density(u, gam) : entropy_density<DIM>(u, gam));
 #pragma unroll
     for (int off = NPE / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
     if (valid && node == 0) partial[e] = elem[e].jac * s;
@@ -1546,10 +2061,23 @@ hipError_t launch_stage_d(int variant, int flux, int kind, const StageArgs &a, c
     return launch_stage_v<DIM, 0>(variant, kind, a, coef, cfg, s);
 }
 
+template <int KIND>
+hipError_t launch_mhd_stage_t(const StageArgs &a, const double *coef, LaunchCfg cfg, hipStream_t s)
+{
+    const int wpb = cfg.epb_mult;
+    const int epb = wpb * 4;
+    if (a.n_active <= 0) return hipSuccess;
+    const int blocks = (a.n_active + epb - 1) / epb;
+    const size_t lds = (size_t)epb * MHD_SLOT * sizeof(double);
+    hipLaunchKernelGGL((mhd_stage_kernel<KIND>), dim3(blocks), dim3(64 * wpb), lds, s, a, coef);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-size_t stage_lds_bytes(int dim, int variant, int wpb)
+size_t stage_lds_bytes(int dim, int variant, int wpb, int sys)
 {
+    if (sys == 1) return (size_t)wpb * 4 * MHD_SLOT * sizeof(double);
     if (variant == 1) {
         if (dim == 2) return (size_t)wpb * SG<2>::EPW * SL<2, float>::SLOT * sizeof(float);
         return (size_t)wpb * SG<3>::EPW * SL<3, float>::SLOT * sizeof(float);
@@ -1562,6 +2090,12 @@ hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArg
                         LaunchCfg cfg, hipStream_t s)
 {
     if (cfg.epb_mult < 1 || cfg.epb_mult > PERRK_MAX_WPB) return hipErrorInvalidValue;
+    if (a.sys == 1) {  // ideal GLM-MHD: 2D, double precision
+        if (dim != 2 || variant != 0) return hipErrorInvalidValue;
+        if (kind == SK_FIRST) return launch_mhd_stage_t<SK_FIRST>(a, coef, cfg, s);
+        if (kind == SK_MID) return launch_mhd_stage_t<SK_MID>(a, coef, cfg, s);
+        return launch_mhd_stage_t<SK_LAST>(a, coef, cfg, s);
+    }
     if (dim == 2) return launch_stage_d<2>(variant, flux, kind, a, coef, cfg, s);
     return launch_stage_d<3>(variant, flux, kind, a, coef, cfg, s);
 }
@@ -1574,18 +2108,21 @@ hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_ca
     return hipGetLastError();
 }
 
-hipError_t launch_relax_pass(int dim, const double *U, const double *d, const ElemInfo *elem,
+hipError_t launch_relax_pass(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                              const CaseState *cs, double *partial, int64_t nelem, double gam,
                              hipStream_t s)
 {
     const int epw = dim == 2 ? 4 : 1;
     const int64_t waves = (nelem + epw - 1) / epw;
     const int64_t blocks = (waves + 3) / 4;
-    if (dim == 2)
-        hipLaunchKernelGGL(relax_pass_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
+    if (sys == 1)
+        hipLaunchKernelGGL((relax_pass_kernel<2, 1>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
+                           partial, nelem, gam);
+    else if (dim == 2)
+        hipLaunchKernelGGL((relax_pass_kernel<2, 0>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
                            partial, nelem, gam);
     else
-        hipLaunchKernelGGL(relax_pass_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
+        hipLaunchKernelGGL((relax_pass_kernel<3, 0>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
                            partial, nelem, gam);
     return hipGetLastError();
 }
@@ -1598,46 +2135,55 @@ hipError_t launch_relax_finalize(CaseState *cs, const int64_t *case_off, int n_c
     return hipGetLastError();
 }
 
-hipError_t launch_relax_complete(int dim, const double *U, const double *d, const ElemInfo *elem,
+hipError_t launch_relax_complete(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                                  CaseState *cs, const int64_t *case_off, int n_cases, double *partial,
                                  int64_t nelem, double gam, RelaxParams rp, hipStream_t s)
 {
-    if (dim == 2)
-        hipLaunchKernelGGL(relax_complete_kernel<2>, dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, U, d,
+    if (sys == 1)
+        hipLaunchKernelGGL((relax_complete_kernel<2, 1>), dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, U, d,
+                           elem, cs, case_off, partial, nelem, gam, rp);
+    else if (dim == 2)
+        hipLaunchKernelGGL((relax_complete_kernel<2, 0>), dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, U, d,
                            elem, cs, case_off, partial, nelem, gam, rp);
     else
-        hipLaunchKernelGGL(relax_complete_kernel<3>, dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, U, d,
+        hipLaunchKernelGGL((relax_complete_kernel<3, 0>), dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, U, d,
                            elem, cs, case_off, partial, nelem, gam, rp);
     return hipGetLastError();
 }
 
-hipError_t launch_final_update(int dim, double *U, const double *d, const ElemInfo *elem,
+hipError_t launch_final_update(int dim, int sys, double *U, const double *d, const ElemInfo *elem,
                                const CaseState *cs, const int32_t *err, int64_t nelem, hipStream_t s)
 {
     const int npe = dim == 2 ? 16 : 64;
-    const int64_t n2 = (int64_t)(dim + 2) * nelem * npe / 2;
+    const int64_t n2 = (int64_t)(sys == 1 ? MHD_V : dim + 2) * nelem * npe / 2;
     int64_t blocks = (n2 + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    if (dim == 2)
-        hipLaunchKernelGGL(final_update_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
+    if (sys == 1)
+        hipLaunchKernelGGL((final_update_kernel<2, 1>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
+                           err, nelem);
+    else if (dim == 2)
+        hipLaunchKernelGGL((final_update_kernel<2, 0>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
                            err, nelem);
     else
-        hipLaunchKernelGGL(final_update_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
+        hipLaunchKernelGGL((final_update_kernel<3, 0>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
                            err, nelem);
     return hipGetLastError();
 }
 
-hipError_t launch_entropy(int dim, const double *U, const ElemInfo *elem, double *partial, double *H_out,
+hipError_t launch_entropy(int dim, int sys, const double *U, const ElemInfo *elem, double *partial, double *H_out,
                           const int64_t *case_off, int n_cases, int64_t nelem, double gam, int32_t *err,
                           hipStream_t s)
 {
     const int epw = dim == 2 ? 4 : 1;
     const int64_t blocks = ((nelem + epw - 1) / epw + 3) / 4;
-    if (dim == 2)
-        hipLaunchKernelGGL(entropy_elem_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, U, elem, partial,
+    if (sys == 1)
+        hipLaunchKernelGGL((entropy_elem_kernel<2, 1>), dim3((unsigned)blocks), dim3(256), 0, s, U, elem, partial,
+                           nelem, gam, err);
+    else if (dim == 2)
+        hipLaunchKernelGGL((entropy_elem_kernel<2, 0>), dim3((unsigned)blocks), dim3(256), 0, s, U, elem, partial,
                            nelem, gam, err);
     else
-        hipLaunchKernelGGL(entropy_elem_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, s, U, elem, partial,
+        hipLaunchKernelGGL((entropy_elem_kernel<3, 0>), dim3((unsigned)blocks), dim3(256), 0, s, U, elem, partial,
                            nelem, gam, err);
     hipLaunchKernelGGL(case_sum_kernel, dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, partial, case_off,
                        H_out);

@@ -15,8 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libperrk.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENONPHYS, ENONFINITE, WARN_FALLBACK = 0, -1, -2, -3, -4, -5, 1
-FLUX_EC, FLUX_HLL, FLUX_LLF, FLUX_HLLE, FLUX_HLLC = 0, 1, 2, 3, 4
+FLUX_EC, FLUX_HLL, FLUX_LLF, FLUX_HLLE, FLUX_HLLC, FLUX_CENTRAL = 0, 1, 2, 3, 4, 5
 VOLUME_FLUX_DIFFERENCING, VOLUME_WEAK = 0, 1
+SYSTEM_EULER, SYSTEM_GLM_MHD = 0, 1
 FP64, MIXED, MIXED_ALL = 0, 1, 2
 ANCHOR_STEP, ANCHOR_INITIAL = 0, 1
 GUESS_PREV, GUESS_MLP = 0, 1
@@ -34,7 +35,7 @@ class MeshDesc(ctypes.Structure):
                 ("n_elem_dir", ctypes.POINTER(ctypes.c_int32)),
                 ("face_coords", ctypes.POINTER(ctypes.c_double)), ("gas_gamma", ctypes.c_double),
                 ("surface_flux", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("volume_integral", ctypes.c_int32)]
+                ("volume_integral", ctypes.c_int32), ("system", ctypes.c_int32), ("glm_ch", ctypes.c_double)]
 
 
 class PartitionDesc(ctypes.Structure):
@@ -152,7 +153,7 @@ class Descriptors:
     """Host-side descriptors (keeps the numpy buffers alive)."""
 
     def __init__(self, faces_per_case, levels, tableau, gas_gamma=1.4, surface_flux=FLUX_EC,
-                 precision=FP64, volume_integral=VOLUME_FLUX_DIFFERENCING):
+                 precision=FP64, volume_integral=VOLUME_FLUX_DIFFERENCING, system=SYSTEM_EULER, glm_ch=0.0):
         self.dim = len(faces_per_case[0])
         self.n_cases = len(faces_per_case)
         n = []
@@ -169,13 +170,13 @@ class Descriptors:
         self.b = np.ascontiguousarray(tableau["b"], dtype=np.float64)
         self.a_sub = np.ascontiguousarray(tableau["a_sub"], dtype=np.float64)
         self.mesh = MeshDesc(self.dim, self.n_cases, _ip(self.n), _dp(self.faces), gas_gamma, surface_flux,
-                             precision, volume_integral)
+                             precision, volume_integral, system, glm_ch)
         self.part = PartitionDesc(len(self.E), _ip(self.levels))
         self.tab = TableauDesc(int(tableau["order"]), len(self.c), len(self.E), _ip(self.E), _dp(self.c),
                                _dp(self.b), _dp(self.a_sub))
         self.nelem = int(sum(np.prod(self.n[3 * i:3 * i + self.dim]) for i in range(self.n_cases)))
         self.npe = 4 ** self.dim
-        self.V = self.dim + 2
+        self.V = 9 if system == SYSTEM_GLM_MHD else self.dim + 2
 
     def validate(self, opts: Options | None = None):
         msg = ctypes.create_string_buffer(512)

@@ -9,9 +9,16 @@
   ensemble   256 isentropic vortices (strength U[1, 6], centre U[3, 7]^2) on graded
              16^2..64^2 meshes, p = 3 with E = {4, 6, 8, 12}, per-case step and levels.
 
+  mhd_blast  1.5D ideal GLM-MHD weak blast (Sec. 4.1.1): [-2, 2] x [0, 1/4] with 64 x 2
+             cells of widths 1/8, 1/16, 1/32 (finest in [-1/2, 1/2]), B = (1, 1, 1),
+             EC volume and surface flux, p = 3 with E = {4, 7, 13}, c_h = 1.
+  alfven     2D ideal GLM-MHD Alfven wave (Sec. 4.3.3) on [0, sqrt 2]^2, n^2 uniform
+             cells, gamma = 5/3, weak-form volume term, LLF surface flux, p = 3 with
+             E = {10, ..., 14} assigned to the cells at random, c_h = 1.
+
 Levels by the shortest edge with one speed per case, step at 0.5 of the optimised
-stable step of the largest level.  Every mesh is graded geometrically (ratio 4,
-finest at the centre).
+stable step of the largest level (random assignments: of every assigned level).
+Every Euler mesh is graded geometrically (ratio 4, finest at the centre).
 """
 from __future__ import annotations
 
@@ -65,3 +72,27 @@ def ensemble(seed=0, n_cases=256):
     U0 = np.ascontiguousarray(np.concatenate([c["U0"] for c in cases], axis=1))
     return dict(kind="ensemble", name=f"vortex_ensemble{n_cases}_p3_E4-6-8-12", faces=[c["faces"] for c in cases],
                 U0=U0, tab=tab, dt=np.array(dts), lev=levs, cases=cases, flux=0)
+
+
+def mhd_blast(seed=0):
+    fx = np.concatenate([np.linspace(-2.0, -1.0, 9)[:-1], np.linspace(-1.0, -0.5, 9)[:-1],
+                         np.linspace(-0.5, 0.5, 33)[:-1], np.linspace(0.5, 1.0, 9)[:-1], np.linspace(1.0, 2.0, 9)])
+    f = [fx, W.uniform_faces(2, 0.0, 0.25)]
+    U0 = W.mhd_weak_blast_state(W.node_coords(f))
+    tab = T.get_tableau(3, [4, 7, 13])
+    dt, lev = T.assign_levels(tab, W.element_widths(f).min(axis=1), W.mhd_max_wave_speed(U0, 2))
+    return dict(kind="mhd_blast", name="mhd_blast1p5d_p3_E4-7-13", faces=[f], U0=U0, tab=tab, dt=np.array([dt]),
+                lev=[lev], flux=0, volume=0, system=1, glm_ch=1.0, gam=W.GAMMA)
+
+
+def alfven(seed=0, n=16):
+    gam = 5.0 / 3.0
+    f = [W.uniform_faces(n, 0.0, float(np.sqrt(2.0)))] * 2
+    U0 = W.mhd_alfven_state(W.node_coords(f), 0.0, gam)
+    tab = T.get_tableau(3, list(range(10, 15)))
+    lev = np.random.default_rng(seed + 17).integers(0, len(tab["E"]), size=n * n).astype(np.int32)
+    speed = float(W.mhd_max_wave_speed(U0, 2, gam).max())
+    h = W.element_widths(f).min(axis=1)
+    dt = 0.5 * float(np.min(np.asarray(tab["h_stab"])[lev] * h / speed))
+    return dict(kind="alfven", name=f"alfven{n}_p3_E10-14_random", faces=[f], U0=U0, tab=tab, dt=np.array([dt]),
+                lev=[lev], flux=2, volume=1, system=1, glm_ch=1.0, gam=gam)

@@ -80,6 +80,20 @@ def test_validate_rejects_bad_mesh_and_levels():
             assert desc(surface_flux=flux, volume_integral=volume).validate()[0] == P.OK
     st, msg = desc(volume_integral=2).validate()
     assert st == P.EINVAL and "volume" in msg, msg
+    assert desc(surface_flux=P.FLUX_CENTRAL).validate()[0] == P.EINVAL  # central: GLM-MHD only
+
+
+def test_validate_glm_mhd_descriptors():
+    ok = dict(system=P.SYSTEM_GLM_MHD, glm_ch=1.0)
+    for flux in (P.FLUX_EC, P.FLUX_LLF, P.FLUX_CENTRAL):
+        for volume in (0, 1):
+            assert desc(surface_flux=flux, volume_integral=volume, **ok).validate()[0] == P.OK
+    for bad, word in [(dict(surface_flux=P.FLUX_HLL), "surface flux"), (dict(precision=P.MIXED), "FP64"),
+                      (dict(glm_ch=-1.0), "glm_ch"), (dict(glm_ch=float("nan")), "glm_ch")]:
+        st, msg = desc(**dict(ok, **bad)).validate()
+        assert st == P.EINVAL and word in msg, msg
+    st, msg = desc(system=7).validate()
+    assert st == P.EINVAL and "system" in msg, msg
     d = desc()
     assert d.validate(P.default_options(fast_passes=0))[0] == P.EINVAL
     assert d.validate(P.default_options(bisect_lo=1.1))[0] == P.EINVAL
