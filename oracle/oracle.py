@@ -36,7 +36,9 @@ class _Mesh(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3),
                 ("faces", ctypes.POINTER(ctypes.c_double)), ("gam", ctypes.c_double),
                 ("surface_flux", ctypes.c_int), ("volume_integral", ctypes.c_int),
-                ("physics", ctypes.c_int), ("c_h", ctypes.c_double)]
+                ("physics", ctypes.c_int), ("c_h", ctypes.c_double), ("viscous", ctypes.c_int),
+                ("mu", ctypes.c_double), ("prandtl", ctypes.c_double), ("bc_x", ctypes.c_int),
+                ("time", ctypes.c_double)]
 
 
 class _Tableau(ctypes.Structure):
@@ -49,7 +51,7 @@ class _Relax(ctypes.Structure):
     _fields_ = [("relax", ctypes.c_int), ("max_newton", ctypes.c_int), ("tol_r", ctypes.c_double),
                 ("tol_step", ctypes.c_double), ("anchor", ctypes.c_int), ("H0", ctypes.c_double),
                 ("bis_lo", ctypes.c_double), ("bis_hi", ctypes.c_double),
-                ("max_bisect", ctypes.c_int), ("gamma0", ctypes.c_double)]
+                ("max_bisect", ctypes.c_int), ("gamma0", ctypes.c_double), ("t0", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -85,6 +87,8 @@ def lib():
         _lib.or_mhd_entropy_vars.argtypes = [p, d, p]
         _lib.or_mhd_entropy_diff.restype = d
         _lib.or_mhd_entropy_diff.argtypes = [p, p, d]
+        _lib.or_viscous_shock_prim.argtypes = [d, d, d, d, p, p, p]
+        _lib.or_ns_viscous_flux.argtypes = [i, d, d, p, d, d, p]
         _lib.or_entropy_vars.argtypes = [i, p, d, p]
         _lib.or_lgl.argtypes = [p, p, p, p]
         _lib.or_rhs.restype = i
@@ -195,6 +199,18 @@ def mhd_nonconservative(direction, u, gam=1.4):
     return phi, phin
 
 
+def viscous_shock_prim(x, t, gam=5.0 / 3.0, mu=0.15):
+    r, u, p = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().or_viscous_shock_prim(float(x), float(t), gam, mu, ctypes.byref(r), ctypes.byref(u), ctypes.byref(p))
+    return r.value, u.value, p.value
+
+
+def ns_viscous_flux(direction, vx, vy, grad, mu, kappa):
+    g, f = _f64(grad).reshape(8), np.zeros(4)
+    lib().or_ns_viscous_flux(direction, float(vx), float(vy), _ptr(g), mu, kappa, _ptr(f))
+    return f
+
+
 def mhd_entropy(u, gam=1.4) -> float:
     return lib().or_mhd_entropy(_ptr(_f64(u)), gam)
 
@@ -233,7 +249,8 @@ class Mesh:
     """Periodic Cartesian mesh: ``faces`` is a list of per-direction face coordinates."""
 
     def __init__(self, faces, gam: float = 1.4, surface_flux: int = 0, volume_integral: int = 0,
-                 physics: int = 0, c_h: float = 0.0):
+                 physics: int = 0, c_h: float = 0.0, viscous: int = 0, mu: float = 0.0, prandtl: float = 0.75,
+                 bc_x: int = 0, time: float = 0.0):
         self.dim = len(faces)
         self.faces_list = [_f64(f) for f in faces]
         self.n = [len(f) - 1 for f in self.faces_list] + ([1] if self.dim == 2 else [])
@@ -243,12 +260,13 @@ class Mesh:
         self.volume_integral = volume_integral
         self.physics = physics
         self.c_h = c_h
+        self.viscous, self.mu, self.prandtl, self.bc_x = viscous, mu, prandtl, bc_x
         self.nelem = int(np.prod(self.n[: self.dim]))
         self.npe = 4 ** self.dim
         self.V = 9 if physics == 1 else self.dim + 2
         self._s = _Mesh(self.dim, (ctypes.c_int * 3)(*self.n),
                         self.faces.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), gam, surface_flux,
-                        volume_integral, physics, c_h)
+                        volume_integral, physics, c_h, viscous, mu, prandtl, bc_x, time)
 
     @property
     def shape(self):
@@ -321,9 +339,9 @@ def relax_eval(mesh: Mesh, Un, d, dt, gamma, dH, offset=0.0):
 
 
 def relax_options(relax=True, max_newton=10, tol_r=1e-12, tol_step=1e-15, anchor=0, H0=0.0,
-                  bis_lo=0.8, bis_hi=1.2, max_bisect=60, gamma0=1.0) -> _Relax:
+                  bis_lo=0.8, bis_hi=1.2, max_bisect=60, gamma0=1.0, t0=0.0) -> _Relax:
     return _Relax(int(relax), max_newton, tol_r, tol_step, anchor, H0, bis_lo, bis_hi, max_bisect,
-                  gamma0)
+                  gamma0, t0)
 
 
 def step(mesh: Mesh, tab: Tableau, level, U, dt, opts: _Relax | None = None, dense=False):
@@ -348,7 +366,7 @@ def run(mesh: Mesh, tab: Tableau, level, U0, dt, nsteps, relax=True, anchor=0, d
     H0 = total_entropy(mesh, U)
     g, t, hist = 1.0, 0.0, []
     for _ in range(nsteps):
-        opts = relax_options(relax=relax, anchor=anchor, H0=H0, gamma0=g, **kw)
+        opts = relax_options(relax=relax, anchor=anchor, H0=H0, gamma0=g, t0=t, **kw)
         U, info = step(mesh, tab, level, U, dt, opts, dense=dense)
         if info["status"] != OK:
             raise ValueError(f"oracle step status {info['status']}")

@@ -55,6 +55,10 @@ typedef struct {
     int volume_integral;  /* 0: flux differencing with the EC flux, 1: standard weak form */
     int physics;          /* 0: compressible Euler (V = dim + 2), 1: ideal GLM-MHD (V = 9) */
     double c_h;           /* GLM-MHD: divergence-cleaning speed */
+    int viscous;          /* Euler only: 1 adds the Navier-Stokes-Fourier terms (BR1), 2D */
+    double mu, prandtl;   /* dynamic viscosity, Prandtl number (kappa = gamma mu / ((gamma-1) Pr)) */
+    int bc_x;             /* 0: periodic in x; 1: the viscous-shock boundaries at both x ends */
+    double time;          /* time of the state the boundary values are taken at (set per stage) */
 } or_mesh;
 
 typedef struct {
@@ -77,6 +81,7 @@ typedef struct {
     double bis_lo, bis_hi;
     int max_bisect;
     double gamma0;        /* initial guess of the Newton iteration */
+    double t0;            /* time of U_n (for time-dependent boundary values) */
 } or_relax;
 
 typedef struct {
@@ -683,6 +688,53 @@ int or_check_state(const or_mesh *m, const double *U)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Viscous shock (Sec. 4.3.2): exact solution and boundary states            */
+/* ------------------------------------------------------------------------ */
+
+/* Becker's viscous shock of the Navier-Stokes-Fourier equations at Pr = 3/4 in
+ * Margolin's explicit form (Ma = 2 / sqrt(3 - gamma)), rho_0 = 1, shock speed
+ * v = 1, viscosity mu, moving with the shock (x_0 = x - v t):
+ *   c_0 = v / Ma, p_0 = c_0^2 rho_0 / gamma,
+ *   l = 2 gamma (4/3 mu) / ((gamma+1) rho_0 v),
+ *   chi = 2 exp(x_0 / (2 l)), w = 1 + (1 - sqrt(1 + 2 chi^2)) / (2 chi^2),
+ *   rho = rho_0 / w, u = v (1 - w), p = p_0 / w (1 + (gamma-1)/2 Ma^2 (1 - w^2)).
+ * The length scale is the one for which this profile solves the equations with
+ * the Stokes stress (longitudinal viscosity 4/3 mu) and Pr = 3/4: the momentum
+ * balance across the profile is -(4/3) mu w' = (gamma+1)/(2 gamma) (w-1)(w-1/2)/w,
+ * and w above satisfies w' = -(w-1)(w-1/2)/(l w). */
+void or_viscous_shock_prim(double x, double t, double gam, double mu, double *rho, double *u, double *p)
+{
+    const double rho0 = 1.0, v = 1.0;
+    double Ma = 2.0 / sqrt(3.0 - gam);
+    double c0 = v / Ma, p0 = c0 * c0 * rho0 / gam;
+    double l = 2.0 * gam * (4.0 / 3.0 * mu) / ((gam + 1.0) * rho0 * v);
+    double chi = 2.0 * exp((x - v * t) / (2.0 * l));
+    double w = 1.0 + (1.0 - sqrt(1.0 + 2.0 * chi * chi)) / (2.0 * chi * chi);
+    *rho = rho0 / w;
+    *u = v * (1.0 - w);
+    *p = p0 / w * (1.0 + 0.5 * (gam - 1.0) * Ma * Ma * (1.0 - w * w));
+}
+
+/* Conserved 2D state of the viscous shock (v_y = 0) at (x, m->time). */
+static void or_viscous_shock_state(const or_mesh *m, double x, double *u)
+{
+    double rho, vx, p;
+    or_viscous_shock_prim(x, m->time, m->gam, m->mu, &rho, &vx, &p);
+    u[0] = rho;
+    u[1] = rho * vx;
+    u[2] = 0.0;
+    u[3] = p / (m->gam - 1.0) + 0.5 * rho * vx * vx;
+}
+
+/* 1 when the face of element coordinates ix in direction d (right or left)
+ * is a domain boundary of the viscous-shock set-up. */
+static int or_x_boundary(const or_mesh *m, const int *ix, int d, int right)
+{
+    if (m->bc_x != 1 || d != 0) return 0;
+    return right ? (ix[0] == m->n[0] - 1) : (ix[0] == 0);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Semidiscretisation F(U) on a set of elements                             */
 /* ------------------------------------------------------------------------ */
 
@@ -695,10 +747,20 @@ int or_check_state(const or_mesh *m, const double *U)
  * the EC volume flux and f* the selected surface flux.  active == NULL means
  * all elements.  Inactive elements' K entries are left untouched. */
 static int or_mhd_rhs(const or_mesh *m, const double *U, const unsigned char *active, double *K);
+static int or_ns_add_viscous(const or_mesh *m, const double *U, const unsigned char *active, double *K);
+static int or_rhs_euler(const or_mesh *m, const double *U, const unsigned char *active, double *K);
 
 int or_rhs(const or_mesh *m, const double *U, const unsigned char *active, double *K)
 {
     if (m->physics == 1) return or_mhd_rhs(m, U, active, K);
+    int status = or_rhs_euler(m, U, active, K);
+    if (status == OR_OK && m->viscous) status = or_ns_add_viscous(m, U, active, K);
+    return status;
+}
+
+/* The Euler part (inviscid flux divergence). */
+static int or_rhs_euler(const or_mesh *m, const double *U, const unsigned char *active, double *K)
+{
     double xi[4], q[4], D[16], Ds[16];
     or_lgl(xi, q, D, Ds);
     int dim = m->dim, V = dim + 2, npe = or_npe(dim), ne = or_nelem(m);
@@ -741,7 +803,13 @@ int or_rhs(const or_mesh *m, const double *U, const unsigned char *active, doubl
                     int jl[3] = { il[0], il[1], il[2] };
                     jl[d] = right ? 0 : 3;
                     double un[5], f[5];
-                    or_get(m, U, or_elem_index(m, jx), or_node_index(jl), un);
+                    if (or_x_boundary(m, ix, d, right)) {
+                        /* viscous shock: inflow of the exact state on the left, outflow on the right */
+                        if (right) for (int v = 0; v < V; ++v) un[v] = u[v];
+                        else or_viscous_shock_state(m, or_faces(m, 0)[0], un);
+                    } else {
+                        or_get(m, U, or_elem_index(m, jx), or_node_index(jl), un);
+                    }
                     if (right) {
                         or_surface_flux(m, d, u, un, f);
                         for (int v = 0; v < V; ++v) acc[v] += f[v] / q[3];
@@ -843,6 +911,170 @@ static int or_mhd_rhs(const or_mesh *m, const double *U, const unsigned char *ac
             or_put(m, K, e, l, k);
         }
     }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Navier-Stokes-Fourier terms (BR1), 2D                                     */
+/* ------------------------------------------------------------------------ */
+/* Viscous flux in direction d from the velocity and the gradients g[dir][q] of
+ * the primitive variables q = (rho, v_x, v_y, T), T = p / rho (gas constant 1),
+ * Stokes hypothesis, heat conductivity kappa = gamma mu / ((gamma-1) Pr):
+ *   tau_xx = mu (4/3 dv_x/dx - 2/3 dv_y/dy), tau_yy = mu (4/3 dv_y/dy - 2/3 dv_x/dx),
+ *   tau_xy = mu (dv_x/dy + dv_y/dx),
+ *   f_v,x = (0, tau_xx, tau_xy, v_x tau_xx + v_y tau_xy + kappa dT/dx), likewise in y. */
+void or_ns_viscous_flux(int d, double vx, double vy, const double *g, double mu, double kappa, double *f)
+{
+    const double *gx = g, *gy = g + 4;
+    double div = gx[1] + gy[2];
+    double txx = mu * (2.0 * gx[1] - 2.0 / 3.0 * div);
+    double tyy = mu * (2.0 * gy[2] - 2.0 / 3.0 * div);
+    double txy = mu * (gy[1] + gx[2]);
+    f[0] = 0.0;
+    if (d == 0) {
+        f[1] = txx;
+        f[2] = txy;
+        f[3] = vx * txx + vy * txy + kappa * gx[3];
+    } else {
+        f[1] = txy;
+        f[2] = tyy;
+        f[3] = vx * txy + vy * tyy + kappa * gy[3];
+    }
+}
+
+static void or_ns_prim4(const double *u, double gam, double *q)
+{
+    double rho, v[3], p;
+    or_prim(2, u, gam, &rho, v, &p);
+    q[0] = rho;
+    q[1] = v[0];
+    q[2] = v[1];
+    q[3] = p / rho;
+}
+
+/* Wall values of q at a boundary face of the viscous shock: the exact velocity
+ * and temperature (moving isothermal no-slip wall), the density of the trace. */
+static void or_ns_wall(const or_mesh *m, int right, const double *qown, double *qw)
+{
+    double x = right ? or_faces(m, 0)[m->n[0]] : or_faces(m, 0)[0];
+    double rho, vx, p;
+    or_viscous_shock_prim(x, m->time, m->gam, m->mu, &rho, &vx, &p);
+    qw[0] = qown[0];
+    qw[1] = vx;
+    qw[2] = 0.0;
+    qw[3] = p / rho;
+}
+
+/* BR1: (1) gradients of q per node in strong form with the face mean of q as
+ * interface value (the wall values at a domain boundary),
+ *   g_d = (2/h_d) [ sum_m D[i][m] q_m + (1/q_i) (delta_i3 (q*_+ - q) - delta_i0 (q*_- - q)) ];
+ * (2) the divergence of the viscous flux in the same form with the face mean of
+ * the two sides' viscous fluxes (at a domain boundary: the flux of the wall
+ * velocity with the trace's gradient), added to K (u_t = ... + div f_v). */
+static int or_ns_add_viscous(const or_mesh *m, const double *U, const unsigned char *active, double *K)
+{
+    double xi[4], q[4], D[16], Ds[16];
+    or_lgl(xi, q, D, Ds);
+    int npe = or_npe(2), ne = or_nelem(m);
+    double kappa = m->gam * m->mu / ((m->gam - 1.0) * m->prandtl);
+    double *G = (double *)malloc(sizeof(double) * (size_t)ne * npe * 8);
+    if (!G) return OR_ENOMEM;
+    for (int e = 0; e < ne; ++e) {
+        int ix[3];
+        or_elem_ijk(m, e, ix);
+        for (int l = 0; l < npe; ++l) {
+            int il[3];
+            or_node_ijk(l, il);
+            double u[4], qo[4];
+            or_get(m, U, e, l, u);
+            or_ns_prim4(u, m->gam, qo);
+            for (int d = 0; d < 2; ++d) {
+                double acc[4] = { 0, 0, 0, 0 };
+                int t = il[d];
+                for (int mm = 0; mm < 4; ++mm) {
+                    int jl[3] = { il[0], il[1], il[2] };
+                    jl[d] = mm;
+                    double um[4], qm[4];
+                    or_get(m, U, e, or_node_index(jl), um);
+                    or_ns_prim4(um, m->gam, qm);
+                    for (int k = 0; k < 4; ++k) acc[k] += D[t * 4 + mm] * qm[k];
+                }
+                if (t == 0 || t == 3) {
+                    int right = (t == 3);
+                    double qs[4];
+                    if (or_x_boundary(m, ix, d, right)) {
+                        or_ns_wall(m, right, qo, qs);
+                    } else {
+                        int jx[3] = { ix[0], ix[1], ix[2] };
+                        jx[d] = right ? (ix[d] + 1) % m->n[d] : (ix[d] + m->n[d] - 1) % m->n[d];
+                        int jl[3] = { il[0], il[1], il[2] };
+                        jl[d] = right ? 0 : 3;
+                        double un[4], qn[4];
+                        or_get(m, U, or_elem_index(m, jx), or_node_index(jl), un);
+                        or_ns_prim4(un, m->gam, qn);
+                        for (int k = 0; k < 4; ++k) qs[k] = 0.5 * (qo[k] + qn[k]);
+                    }
+                    for (int k = 0; k < 4; ++k) acc[k] += (right ? 1.0 : -1.0) * (qs[k] - qo[k]) / q[t];
+                }
+                double sc = 2.0 / or_width(m, e, d);
+                for (int k = 0; k < 4; ++k) G[(((size_t)e * npe + l) * 2 + d) * 4 + k] = sc * acc[k];
+            }
+        }
+    }
+    for (int e = 0; e < ne; ++e) {
+        if (active && !active[e]) continue;
+        int ix[3];
+        or_elem_ijk(m, e, ix);
+        for (int l = 0; l < npe; ++l) {
+            int il[3];
+            or_node_ijk(l, il);
+            double u[4], qo[4], k[4];
+            or_get(m, U, e, l, u);
+            or_ns_prim4(u, m->gam, qo);
+            or_get(m, K, e, l, k);
+            const double *go = G + ((size_t)e * npe + l) * 8;
+            for (int d = 0; d < 2; ++d) {
+                double acc[4] = { 0, 0, 0, 0 }, fo[4];
+                int t = il[d];
+                or_ns_viscous_flux(d, qo[1], qo[2], go, m->mu, kappa, fo);
+                for (int mm = 0; mm < 4; ++mm) {
+                    int jl[3] = { il[0], il[1], il[2] };
+                    jl[d] = mm;
+                    int lm = or_node_index(jl);
+                    double um[4], qm[4], fm[4];
+                    or_get(m, U, e, lm, um);
+                    or_ns_prim4(um, m->gam, qm);
+                    or_ns_viscous_flux(d, qm[1], qm[2], G + ((size_t)e * npe + lm) * 8, m->mu, kappa, fm);
+                    for (int c = 0; c < 4; ++c) acc[c] += D[t * 4 + mm] * fm[c];
+                }
+                if (t == 0 || t == 3) {
+                    int right = (t == 3);
+                    double fs[4];
+                    if (or_x_boundary(m, ix, d, right)) {
+                        double qw[4];
+                        or_ns_wall(m, right, qo, qw);
+                        or_ns_viscous_flux(d, qw[1], qw[2], go, m->mu, kappa, fs);
+                    } else {
+                        int jx[3] = { ix[0], ix[1], ix[2] };
+                        jx[d] = right ? (ix[d] + 1) % m->n[d] : (ix[d] + m->n[d] - 1) % m->n[d];
+                        int jl[3] = { il[0], il[1], il[2] };
+                        jl[d] = right ? 0 : 3;
+                        int en = or_elem_index(m, jx), ln = or_node_index(jl);
+                        double un[4], qn[4], fn[4];
+                        or_get(m, U, en, ln, un);
+                        or_ns_prim4(un, m->gam, qn);
+                        or_ns_viscous_flux(d, qn[1], qn[2], G + ((size_t)en * npe + ln) * 8, m->mu, kappa, fn);
+                        for (int c = 0; c < 4; ++c) fs[c] = 0.5 * (fo[c] + fn[c]);
+                    }
+                    for (int c = 0; c < 4; ++c) acc[c] += (right ? 1.0 : -1.0) * (fs[c] - fo[c]) / q[t];
+                }
+                double sc = 2.0 / or_width(m, e, d);
+                for (int c = 0; c < 4; ++c) k[c] += sc * acc[c];
+            }
+            or_put(m, K, e, l, k);
+        }
+    }
+    free(G);
     return OR_OK;
 }
 
@@ -1074,6 +1306,7 @@ static int or_validate(const or_mesh *m, const or_tableau *t, const int *level)
 {
     if (!(m->dim == 2 || m->dim == 3)) return OR_EINVAL;
     if (m->physics == 1 && m->dim != 2) return OR_EINVAL;
+    if (m->viscous && (m->dim != 2 || m->physics != 0 || !(m->prandtl > 0.0) || !(m->mu >= 0.0))) return OR_EINVAL;
     if (t->S < 2 || t->S > OR_MAXS || t->R < 1 || t->R > OR_MAXR) return OR_EINVAL;
     for (int r = 0; r < t->R; ++r) {
         if (t->E[r] < 2 || t->E[r] > t->S) return OR_EINVAL;
@@ -1148,7 +1381,9 @@ int or_step_dense(const or_mesh *m, const or_tableau *t, const int *level, const
                     Ui[idx] = U[idx] + dt * s;
                 }
             }
-        st = or_rhs(m, Ui, NULL, Kall + (size_t)i * M);
+        or_mesh ms = *m;
+        ms.time = opt->t0 + t->c[i] * dt;  /* boundary values at the stage time */
+        st = or_rhs(&ms, Ui, NULL, Kall + (size_t)i * M);
         if (st) break;
         if (t->b[i] != 0.0) info->e[i] = or_entropy_production(m, Ui, Kall + (size_t)i * M);
     }
@@ -1211,7 +1446,9 @@ int or_step(const or_mesh *m, const or_tableau *t, const int *level, const or_re
                     Ui[idx] = U[idx] + dt * s;
                 }
         }
-        st = or_rhs(m, Ui, act, Kout);
+        or_mesh ms = *m;
+        ms.time = opt->t0 + t->c[i] * dt;  /* boundary values at the stage time */
+        st = or_rhs(&ms, Ui, act, Kout);
         if (st) break;
         if (t->b[i] != 0.0) info->e[i] = or_entropy_production(m, Ui, Kout);
         if (i == S - 2) memcpy(Ksm1, Kout, M * sizeof(double));

@@ -139,6 +139,36 @@ def weak_blast_x_state(coords, gam=GAMMA):
     return conserved(rho, vel, p, gam)
 
 
+# ---------------------------------------------------------------- viscous shock
+def viscous_shock_faces(n: int) -> np.ndarray:
+    """[-2, 2] with n cells (n a multiple of 6): cells of width 8/(3n)... more
+    precisely n/6 cells in each of [-2, -1] and [1, 2] and 2n/3 cells (half the
+    width) in [-1, 1] (the Sec. 4.3.2 refinement by two in the centre)."""
+    assert n % 6 == 0
+    k = n // 6
+    return np.concatenate([np.linspace(-2.0, -1.0, k + 1)[:-1], np.linspace(-1.0, 1.0, 4 * k + 1)[:-1],
+                           np.linspace(1.0, 2.0, k + 1)])
+
+
+def viscous_shock_state(coords, t=0.0, gam=5.0 / 3.0, mu=0.15):
+    """Becker's viscous shock (Sec. 4.3.2, Margolin's explicit profile at
+    Ma = 2/sqrt(3 - gamma)): rho_0 = 1, shock speed 1, moving in +x; no
+    variation in y.  rho = 1/w, v_x = 1 - w, p = p_0/w (1 + (gamma-1)/2 Ma^2 (1 - w^2))
+    with w = 1 + (1 - sqrt(1 + 2 chi^2))/(2 chi^2), chi = 2 exp((x - t)/(2 l)),
+    p_0 = 1/(gamma Ma^2) and the length scale l = 2 gamma (4/3 mu)/(gamma + 1) of the
+    Navier-Stokes-Fourier equations with Stokes stress and Pr = 3/4."""
+    x = coords[0]
+    Ma = 2.0 / math.sqrt(3.0 - gam)
+    p0 = 1.0 / (gam * Ma * Ma)
+    ln = 2.0 * gam * (4.0 / 3.0 * mu) / (gam + 1.0)
+    chi = 2.0 * np.exp((x - t) / (2.0 * ln))
+    w = 1.0 + (1.0 - np.sqrt(1.0 + 2.0 * chi * chi)) / (2.0 * chi * chi)
+    rho = 1.0 / w
+    vx = 1.0 - w
+    p = p0 / w * (1.0 + 0.5 * (gam - 1.0) * Ma * Ma * (1.0 - w * w))
+    return conserved(rho, [vx, np.zeros_like(x)], p, gam)
+
+
 # ---------------------------------------------------------------- ideal GLM-MHD
 # u = (rho, rho v_1..3, E, B_1..3, psi), E = p/(gamma-1) + rho |v|^2/2 + |B|^2/2 + psi^2/2
 
