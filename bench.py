@@ -13,6 +13,8 @@ fourth-order P-ERRK with E = {5, 9, 14}.
 --workload alfven: 2D ideal GLM-MHD Alfven wave, 256^2 uniform cells, weak form
 with LLF surface flux and the Powell / GLM terms, p = 3 with E = {10..14} at
 random (the GLM-MHD path is double precision only; no comparisons).
+--viscous MU: the 2D Euler workload with Navier-Stokes-Fourier terms (BR1,
+Pr = 0.72, double precision only; no comparisons).
 --surface-flux / --volume: the same workload with a dissipative surface flux
 (HLL, LLF, HLLE, HLLC) and/or the standard weak-form volume term (Sec. 4.2, 4.3
 and 5 use these), which runs the stage kernel's dissipative instantiation.
@@ -87,7 +89,8 @@ def workload_alfven(n=256, seed=0):
 def run_variant(P, torch, wl, precision, steps, warmup, profile=False, guess=0, model=None):
     d = P.Descriptors(wl["faces"], wl["lev"], wl["tab"], surface_flux=wl.get("flux", 0), precision=precision,
                       volume_integral=wl.get("volume", 0), gas_gamma=wl.get("gam", 1.4),
-                      system=wl.get("system", 0), glm_ch=wl.get("glm_ch", 0.0))
+                      system=wl.get("system", 0), glm_ch=wl.get("glm_ch", 0.0), viscous=wl.get("viscous", 0),
+                      mu=wl.get("mu", 0.0), prandtl=wl.get("prandtl", 0.75), bc_x=wl.get("bc_x", 0))
     st = P.Stepper(d, P.default_options(guess=guess))
     if model is not None:
         st.set_guess_model(*model)
@@ -164,7 +167,11 @@ def stage_groups(wl, stage_stats, precision):
         kind = "first" if i == 0 else ("last" if i == S - 1 else "mid")
         ft = "double" if precision == 0 or (precision == 1 and b[i] != 0.0) else "float"
         st = "double" if precision == 0 else "float"
-        name = f"stage_kernel<{dim}, {ft}, {st}, {kind}>" if wl.get("system", 0) != 1 else f"mhd_stage_kernel<{kind}>"
+        name = f"stage_kernel<{dim}, {ft}, {st}, {kind}>"
+        if wl.get("system", 0) == 1:
+            name = f"mhd_stage_kernel<{kind}>"
+        elif wl.get("viscous", 0):
+            name = f"ns_grad_kernel+ns_stage_kernel<{kind}>"
         g = out.setdefault(name, dict(ms=0.0, bytes=0.0, launches=0))
         g["ms"] += s["ms"]
         g["bytes"] += s["bytes"]
@@ -202,7 +209,8 @@ def cpu_baseline(wl, target_dof=12.0e6):
         U = wl["U0"][:, off:off + ne]
         off += ne
         m = O.Mesh(faces, gam=wl.get("gam", 1.4), surface_flux=wl.get("flux", 0),
-                   volume_integral=wl.get("volume", 0), physics=wl.get("system", 0), c_h=wl.get("glm_ch", 0.0))
+                   volume_integral=wl.get("volume", 0), physics=wl.get("system", 0), c_h=wl.get("glm_ch", 0.0),
+                   viscous=wl.get("viscous", 0), mu=wl.get("mu", 0.0), prandtl=wl.get("prandtl", 0.75))
         t0 = time.perf_counter()
         O.step(m, t, wl["lev"][k], U, float(wl["dt"][k]))
         sec += time.perf_counter() - t0
@@ -225,6 +233,9 @@ def main():
                     help="surface flux instead of the workload's own (EC)")
     ap.add_argument("--volume", choices=VOLUME_NAMES, default="flux_differencing",
                     help="volume term: EC flux differencing or the standard weak form")
+    ap.add_argument("--viscous", type=float, default=None, metavar="MU",
+                    help="add the Navier-Stokes-Fourier terms (BR1, Pr 0.72) with viscosity MU (2D Euler workloads; "
+                         "double precision)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="time the mixed variant only")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -258,6 +269,13 @@ def main():
         return
     wl = {"ensemble": workload_ensemble, "tgv": workload_tgv, "alfven": workload_alfven}[args.workload]()
     mhd = wl.get("system", 0) == 1
+    if args.viscous is not None:
+        if mhd or len(wl["faces"][0]) != 2:
+            sys.exit("--viscous applies to the 2D Euler workloads")
+        wl.update(viscous=1, mu=args.viscous, prandtl=0.72)
+        wl["name"] += f"_ns_mu{args.viscous:g}"
+        wl["desc"] += f"; Navier-Stokes-Fourier terms by BR1, mu = {args.viscous:g}, Pr = 0.72"
+    fp64_only = mhd or args.viscous is not None
     if args.surface_flux is not None or args.volume != "flux_differencing":
         fl = FLUX_NAMES.index(args.surface_flux) if args.surface_flux is not None else wl.get("flux", 0)
         wl["flux"], wl["volume"] = fl, VOLUME_NAMES.index(args.volume)
@@ -273,7 +291,7 @@ def main():
             ("mixed_all", P.MIXED_ALL, False), ("fp64", P.FP64, False)]
     if not learned:
         plan = [(n, p, g) for n, p, g in plan if not g]
-    if mhd:  # the GLM-MHD path is double precision only
+    if fp64_only:  # the GLM-MHD and viscous paths are double precision only
         plan = [("fp64", P.FP64, False)]
     if args.no_compare:
         plan = plan[:1]
@@ -356,7 +374,7 @@ def main():
     # right-hand-side evaluations per step, counted in DOF: sum_r E^(r) M^(r)
     E = np.asarray(wl["tab"]["E"])
     n_rhs = float(sum(E[np.asarray(lv)].sum() for lv in wl["lev"])) * (M / wl["U0"].shape[1])
-    if not args.no_compare and not mhd:
+    if not args.no_compare and not fp64_only:
         # the paper's comparison: the same mesh, dt and steps with every element on the
         # largest-E level (the single-level method P-ERRK_{p;S_max}); tau / tau* and
         # N_RHS / N_RHS* with * = multirate

@@ -125,6 +125,18 @@ typedef struct {
     int32_t volume_integral;   /* PERRK_VOLUME_FLUX_DIFFERENCING or PERRK_VOLUME_WEAK */
     int32_t system;            /* PERRK_SYSTEM_EULER or PERRK_SYSTEM_GLM_MHD */
     double glm_ch;             /* GLM-MHD divergence-cleaning speed (>= 0); ignored for Euler */
+    int32_t viscous;           /* 1: add the Navier-Stokes-Fourier terms (Sec. 4.3.2): Stokes stress
+                                  with viscosity mu, heat flux -kappa grad T, T = p / rho,
+                                  kappa = gamma mu / ((gamma-1) prandtl), discretised by BR1
+                                  (gradients of rho, v, T and the viscous flux with face means);
+                                  Euler system, dim = 2 and PERRK_FP64 only */
+    double mu, prandtl;        /* viscosity (>= 0) and Prandtl number (> 0) when viscous */
+    int32_t bc_x;              /* 0: periodic; 1: the viscous-shock set-up of Sec. 4.3.2 (one case,
+                                  viscous): at the left x end the exact shock state flows in, the
+                                  right x end is a free outflow, and both are moving isothermal
+                                  walls for the viscous terms (exact velocity and temperature of
+                                  the shock with rho_0 = 1, speed 1, Ma = 2/sqrt(3-gamma), Pr 3/4,
+                                  at the stage time t_n + c_i dt); y stays periodic */
 } perrk_mesh_desc;
 
 typedef struct {

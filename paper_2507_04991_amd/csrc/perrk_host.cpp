@@ -22,6 +22,9 @@ struct perrk_ctx {
     // problem
     int dim = 2, V = 4, npe = 16, n_cases = 1, precision = 0, flux = 0, volume = 0, sys = 0;
     double c_h = 0.0;
+    int viscous = 0, bc_x = 0;        // Navier-Stokes-Fourier terms; viscous-shock x boundaries
+    double mu = 0.0, prandtl = 0.75, x_lo = 0.0, x_hi = 0.0;
+    double *d_grad = nullptr;         // [8][nelem][node] BR1 gradients of the current stage
     double gam = 1.4;
     int64_t nelem = 0;
     std::vector<int64_t> case_off;
@@ -155,6 +158,16 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
     if (!(m->gas_gamma > 1.0) || !std::isfinite(m->gas_gamma)) return ck.bad("gas_gamma must be > 1");
     if (m->system != PERRK_SYSTEM_EULER && m->system != PERRK_SYSTEM_GLM_MHD)
         return ck.bad("unknown system %d", m->system);
+    if (m->viscous != 0 && m->viscous != 1) return ck.bad("viscous must be 0 or 1");
+    if (m->viscous) {
+        if (m->dim != 2 || m->system != PERRK_SYSTEM_EULER || m->precision != PERRK_FP64)
+            return ck.bad("viscous terms need dim = 2, the Euler system and PERRK_FP64");
+        if (!(m->mu >= 0.0) || !std::isfinite(m->mu) || !(m->prandtl > 0.0) || !std::isfinite(m->prandtl))
+            return ck.bad("viscous terms need mu >= 0 and prandtl > 0");
+    }
+    if (m->bc_x != 0 && m->bc_x != 1) return ck.bad("bc_x must be 0 or 1");
+    if (m->bc_x == 1 && (!m->viscous || m->n_cases != 1))
+        return ck.bad("the viscous-shock boundaries need the viscous terms and one case");
     if (m->system == PERRK_SYSTEM_GLM_MHD) {
         if (m->dim != 2) return ck.bad("GLM-MHD needs dim = 2");
         if (m->precision != PERRK_FP64) return ck.bad("GLM-MHD runs in PERRK_FP64 only");
@@ -276,7 +289,7 @@ void free_all(perrk_ctx *c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     void *dev[] = {c->d_elem, c->d_active, c->d_case_off, c->d_cs, c->d_coef, c->d_K1, c->d_Ka,
                    c->d_Kb, c->d_d, c->d_ep, c->d_partial, c->d_H, c->d_dt, c->d_err, c->d_mlp,
-                   c->d_k64_1, c->d_k64_sm1};
+                   c->d_k64_1, c->d_k64_sm1, c->d_grad};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     void *host[] = {c->h_dt, c->h_cs, c->h_err, c->h_H};
@@ -325,6 +338,15 @@ void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int
     a.volume = c->volume;
     a.sys = c->sys;
     a.c_h = c->c_h;
+    a.viscous = c->viscous;
+    a.mu = c->mu;
+    a.prandtl = c->prandtl;
+    a.grad = c->d_grad;
+    a.active_all = c->d_active;  // the first stage's list holds every element
+    a.n_all = (int32_t)c->nelem;
+    a.c_stage = c->c[i];
+    a.x_lo = c->x_lo;
+    a.x_hi = c->x_hi;
     const int S = c->S;
     void *kbuf[2] = {c->d_Ka, c->d_Kb};
     kind = i == 0 ? SK_FIRST : (i == S - 1 ? SK_LAST : SK_MID);
@@ -386,7 +408,7 @@ int autotune(perrk_ctx *c, double *u)
         std::snprintf(buf, sizeof buf, " %d:", i + 1);
         std::string line = buf;
         for (int wpb = 1; wpb <= PERRK_MAX_WPB; wpb *= 2) {
-            if (stage_lds_bytes(c->dim, variant, wpb, c->sys) > c->max_lds) {
+            if (stage_lds_bytes(c->dim, variant, wpb, c->viscous ? 2 : c->sys) > c->max_lds) {
                 line += " -";
                 continue;
             }
@@ -513,6 +535,14 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     c->opt = o;
     c->dim = m->dim;
     c->sys = m->system;
+    c->viscous = m->viscous;
+    c->mu = m->viscous ? m->mu : 0.0;
+    c->prandtl = m->viscous ? m->prandtl : 0.75;
+    c->bc_x = m->bc_x;
+    if (m->bc_x) {
+        c->x_lo = m->face_coords[0];
+        c->x_hi = m->face_coords[m->n_elem_dir[0]];
+    }
     c->c_h = m->system == PERRK_SYSTEM_GLM_MHD ? m->glm_ch : 0.0;
     c->V = m->system == PERRK_SYSTEM_GLM_MHD ? 9 : m->dim + 2;
     c->npe = m->dim == 2 ? 16 : 64;
@@ -590,6 +620,13 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
                 en.elem_level = (int32_t)((uint32_t)e | ((uint32_t)elem[e].level << PERRK_NBR_SHIFT));
                 en.case_id = elem[e].case_id;
                 for (int k = 0; k < 6; ++k) en.nbr[k] = elem[e].nbr[k];
+                if (c->dim == 2) {
+                    // 2D meshes have no z neighbours: that word holds the boundary flags of the
+                    // viscous-shock set-up (bit 0: left x face, bit 1: right x face)
+                    const int ix = (int)(e % m->n_elem_dir[0]);
+                    en.nbr[4] = c->bc_x ? ((ix == 0 ? 1 : 0) | (ix == m->n_elem_dir[0] - 1 ? 2 : 0)) : 0;
+                    en.nbr[5] = 0;
+                }
                 order.push_back(en);
             }
         }
@@ -618,7 +655,8 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     rp.nb = (int)c->bstages.size();
     for (int j = 0; j < rp.nb && j < PERRK_MAXB; ++j) rp.bw[j] = c->b[c->bstages[j]];
     c->rp = rp;
-    c->cfg.epb_mult = c->sys == PERRK_SYSTEM_GLM_MHD ? 1 : 4;  // GLM-MHD: 27 KB of LDS per wavefront
+    // GLM-MHD: 27 KB of LDS per wavefront; Navier-Stokes: 19 KB
+    c->cfg.epb_mult = c->sys == PERRK_SYSTEM_GLM_MHD ? 1 : (c->viscous ? 2 : 4);
     c->scfg.assign(c->S, c->cfg);
     c->sstats.assign(c->S, perrk_kernel_stat{});
 
@@ -702,6 +740,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipMalloc(&c->d_Ka, ks * M));
     HIPINIT(hipMalloc(&c->d_Kb, ks * M));
     HIPINIT(hipMalloc(&c->d_d, sizeof(double) * M));
+    if (c->viscous) HIPINIT(hipMalloc(&c->d_grad, sizeof(double) * 8 * (size_t)c->nelem * c->npe));
     if (c->precision == PERRK_MIXED) {
         if (c->b[0] != 0.0) HIPINIT(hipMalloc(&c->d_k64_1, sizeof(double) * M));
         if (c->S >= 3 && c->b[c->S - 2] != 0.0) HIPINIT(hipMalloc(&c->d_k64_sm1, sizeof(double) * M));
@@ -876,6 +915,15 @@ int perrk_rhs(perrk_ctx *c, const void *u_dev, void *k_dev)
     a.volume = c->volume;
     a.sys = c->sys;
     a.c_h = c->c_h;
+    a.viscous = c->viscous;
+    a.mu = c->mu;
+    a.prandtl = c->prandtl;
+    a.grad = c->d_grad;
+    a.active_all = c->d_active;
+    a.n_all = (int32_t)c->nelem;
+    a.c_stage = 0.0;
+    a.x_lo = c->x_lo;
+    a.x_hi = c->x_hi;
     HIPCHECK(c, launch_stage(c->dim, c->precision == PERRK_FP64 ? 0 : 1, c->flux, SK_FIRST, a, c->d_coef,
                              c->cfg, c->stream));
     HIPCHECK(c, hipEventRecord(c->ev_out, c->stream));

@@ -94,6 +94,13 @@ struct StageArgs {
     int32_t volume;           // volume term (PERRK_VOLUME_*)
     int32_t sys;              // PERRK_SYSTEM_*
     double c_h;               // GLM-MHD divergence-cleaning speed
+    int32_t viscous;          // 1: Navier-Stokes-Fourier terms (BR1), 2D double precision
+    double mu, prandtl;       //   viscosity and Prandtl number
+    double *grad;             //   [8][nelem][node] gradients of (rho, v_x, v_y, T) (d then q)
+    const ActiveEntry *active_all;  // every element (the gradient pass)
+    int32_t n_all;
+    double c_stage;           //   c_i of the stage (boundary values at t_n + c_i dt)
+    double x_lo, x_hi;        //   x ends of the viscous-shock mesh (its boundaries)
     double b1, bsm1, bs;      // last stage weights
     double b_acc;             // stages with b_i != 0 other than 1, S-1, S: b_i (K_i enters d here)
     int32_t acc_mode;         //   1: d = b_i K_i, 2: d += b_i K_i, 0: no contribution
@@ -111,14 +118,16 @@ struct LaunchCfg {
 };
 #define PERRK_MAX_WPB 8
 
-// Workgroup LDS bytes of a stage launch with wpb wavefronts per workgroup.
+// Workgroup LDS bytes of a stage launch with wpb wavefronts per workgroup
+// (sys: PERRK_SYSTEM_*, or 2 for the Navier-Stokes stage kernel).
 size_t stage_lds_bytes(int dim, int variant, int wpb, int sys);
 
 // Kernel launchers (perrk_kernels.hip).
 // variant: 0 double flux / double storage, 1 float / float, 2 double flux / float storage;
 // flux = 0 with a.volume = 0 runs the EC-only kernel, anything else the kernel with
 // run-time selected surface flux and volume term; a.sys = 1 runs the GLM-MHD
-// kernel (2D, variant 0 only).  sys: PERRK_SYSTEM_*.
+// kernel (2D, variant 0 only); a.viscous = 1 runs the BR1 gradient pass and the
+// Navier-Stokes stage kernel (2D, variant 0 only).  sys: PERRK_SYSTEM_*.
 hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArgs &a, const double *coef,
                         LaunchCfg cfg, hipStream_t s);
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases,

@@ -1474,6 +1474,433 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) mhd_stage_kernel(const Sta
     if (bad && valid) atomicOr(a.err, bad);
 }
 
+// ---------------------------------------------------------------- Navier-Stokes-Fourier (BR1), 2D
+// Viscous terms added to the Euler equations in double precision: gradients of
+// q = (rho, v_x, v_y, T), T = p / rho, by the strong-form derivative with face
+// means (BR1), then the divergence of the viscous flux (Stokes stress, heat
+// conductivity kappa = gamma mu / ((gamma-1) Pr)) in the same form.  The
+// full-derivative row of a node at position t is Dsplit/2 off the diagonal and
+// D_tt = -3, 0, 0, 3 on it.  The viscous-shock set-up (one case) replaces the
+// two x ends of the mesh by boundaries: exact inflow / free outflow for the
+// inviscid flux and moving isothermal walls (exact velocity and temperature)
+// for the viscous terms, at the stage time t_n + c_i dt.
+constexpr int NS_NQ = 4;  // q per node
+constexpr int NS_SLOT = NS_NQ * 16 + 8 * 16 + 4 * (SG<2>::NFN + SG<2>::NPP) + 6 * 16 + 3 * SG<2>::NFN;
+// slot layout (doubles): prims [node][4] (rho, v_x, v_y, p) | gradients g[8][node] |
+// inviscid sf[4][NFN], vf[4][NPP] | viscous node fluxes fvn[6][node] (dir, m_x, m_y, E) |
+// lifted viscous face terms sfv[3][NFN]
+constexpr int NS_OFF_G = NS_NQ * 16, NS_OFF_SF = NS_OFF_G + 8 * 16, NS_OFF_VF = NS_OFF_SF + 4 * SG<2>::NFN,
+              NS_OFF_FVN = NS_OFF_VF + 4 * SG<2>::NPP, NS_OFF_SFV = NS_OFF_FVN + 6 * 16;
+constexpr int NS_GRAD_SLOT = NS_NQ * 16 + NS_NQ * SG<2>::NFN;  // gradient kernel: q [node][4] | lifted sq[4][NFN]
+
+// Exact viscous shock (rho_0 = 1, shock speed 1, Ma = 2/sqrt(3 - gamma),
+// l = 2 gamma (4/3 mu)/(gamma + 1)): primitive rho, v_x, p at (x, t).
+__device__ __forceinline__ void viscous_shock(double x, double t, double gam, double mu, double &rho, double &vx,
+                                              double &p)
+{
+    const double Ma2 = 4.0 / (3.0 - gam);
+    const double p0 = 1.0 / (gam * Ma2);
+    const double l = 2.0 * gam * (4.0 / 3.0 * mu) / (gam + 1.0);
+    const double chi = 2.0 * exp((x - t) / (2.0 * l));
+    const double w = 1.0 + (1.0 - sqrt(1.0 + 2.0 * chi * chi)) / (2.0 * chi * chi);
+    rho = 1.0 / w;
+    vx = 1.0 - w;
+    p = p0 / w * (1.0 + 0.5 * (gam - 1.0) * Ma2 * (1.0 - w * w));
+}
+
+// Viscous flux in direction d (components m_x, m_y, E; the mass component is 0)
+// from the velocity and the gradients g[dir * 4 + k] of q.
+__device__ __forceinline__ void ns_vflux(int d, double vx, double vy, const double *g, double mu, double kappa,
+                                         double *f)
+{
+    const double div = g[1] + g[4 + 2];
+    const double txx = mu * (2.0 * g[1] - 2.0 / 3.0 * div);
+    const double tyy = mu * (2.0 * g[4 + 2] - 2.0 / 3.0 * div);
+    const double txy = mu * (g[4 + 1] + g[2]);
+    const double tn0 = d == 0 ? txx : txy, tn1 = d == 0 ? txy : tyy;
+    f[0] = tn0;
+    f[1] = tn1;
+    f[2] = vx * tn0 + vy * tn1 + kappa * (d == 0 ? g[3] : g[4 + 3]);
+}
+
+__device__ __forceinline__ double dfull_diag(int t) { return t == 0 ? -3.0 : (t == 3 ? 3.0 : 0.0); }
+
+// Shared load phase of the two Navier-Stokes kernels: the active entry, the
+// stage coefficients, the own node's raw data and the neighbour's at the lane's
+// face node (the neighbour words and the boundary flags come with the entry).
+struct NsLoad {
+    int e, lvl, cs;
+    uint32_t bcf;  // bit 0: left x face is a boundary, bit 1: right x face
+    double dt, c1, cp;
+    NodeRaw<4, double> own, nr;
+    double nc1, ncp;
+    FaceNode<2> F;
+    bool fv;
+    int nb, nn;
+};
+
+template <int KIND>
+__device__ __forceinline__ void ns_load(const StageArgs &a, const double *coef, uint32_t ai, int lane, int node,
+                                        NsLoad &L)
+{
+    constexpr int NPE = 16;
+    const int4 *ap = reinterpret_cast<const int4 *>(a.active);
+    const int4 act = elt(ap, 2u * ai), act2 = elt(ap, 2u * ai + 1u);
+    L.e = (int)((uint32_t)act.x & PERRK_NBR_MASK);
+    L.lvl = (int)((uint32_t)act.x >> PERRK_NBR_SHIFT);
+    L.cs = act.y;
+    L.bcf = (uint32_t)act2.z;
+    L.dt = L.c1 = L.cp = 0.0;
+    if (KIND != SK_FIRST) {
+        L.dt = elt(a.cs, (uint32_t)L.cs).dt;
+        L.c1 = elt(coef, (uint32_t)L.lvl);
+        L.cp = elt(coef, (uint32_t)(PERRK_MAXR + L.lvl));
+    }
+    const size_t field = (size_t)a.nelem * NPE;
+    const uint32_t o8 = ((uint32_t)L.e * NPE + node) * 8u;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        L.own.u[v] = bload<double>(field_rsrc<double>(a.U, v, field), o8);
+        if (KIND != SK_FIRST) {
+            L.own.k1[v] = bload<double>(field_rsrc<double>(a.K1, v, field), o8);
+            L.own.kp[v] = bload<double>(field_rsrc<double>(a.Kp, v, field), o8);
+        }
+    }
+    L.fv = face_node<2>(0, lane, L.F, L.nn);
+    const int f = 2 * L.F.d + L.F.side;
+    const uint32_t w = (uint32_t)(f < 2 ? (f == 0 ? act.z : act.w) : (f == 2 ? act2.x : act2.y));
+    L.nb = (int)(w & PERRK_NBR_MASK);
+    L.nc1 = L.ncp = 0.0;
+    if (KIND != SK_FIRST) {
+        const int lv = (int)(w >> PERRK_NBR_SHIFT);
+        L.nc1 = elt(coef, (uint32_t)lv);
+        L.ncp = elt(coef, (uint32_t)(PERRK_MAXR + lv));
+    }
+    const uint32_t n8 = ((uint32_t)L.nb * NPE + L.nn) * 8u;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        L.nr.u[v] = bload<double>(field_rsrc<double>(a.U, v, field), n8);
+        if (KIND != SK_FIRST) {
+            L.nr.k1[v] = bload<double>(field_rsrc<double>(a.K1, v, field), n8);
+            L.nr.kp[v] = bload<double>(field_rsrc<double>(a.Kp, v, field), n8);
+        }
+    }
+}
+
+// True when the lane's face is an x boundary of the viscous-shock mesh.
+__device__ __forceinline__ bool ns_boundary(const NsLoad &L)
+{
+    return L.F.d == 0 && (L.bcf & (L.F.side ? 2u : 1u)) != 0u;
+}
+
+// Gradient pass of one stage (every element): g = (2/h_d) [D q + lifted (q* - q)].
+template <int KIND>
+__global__ void __launch_bounds__(64 * PERRK_MAX_WPB) ns_grad_kernel(const StageArgs a, const double *coef)
+{
+    constexpr int NPE = 16, EPW = 4, NFN = SG<2>::NFN, NLINE = SG<2>::NLINE, SLOT = NS_GRAD_SLOT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *lds = reinterpret_cast<double *>(smem_raw);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int eslot = wave * EPW + lane / NPE;
+    const int node = lane % NPE;
+    const int epb = (int)(blockDim.x >> 6) * EPW;
+    const int li = xcd_block(blockIdx.x, gridDim.x) * epb + eslot;
+    const bool valid = li < a.n_active;
+    double *slot = lds + (size_t)eslot * SLOT;
+    NsLoad L;
+    ns_load<KIND>(a, coef, (uint32_t)(valid ? li : a.n_active - 1), lane, node, L);
+    int bad = 0;
+    double u[4], un[4];
+    combine<4, double, KIND>(L.own, L.dt, L.c1, L.cp, u);
+    combine<4, double, KIND>(L.nr, L.dt, L.nc1, L.ncp, un);
+    Prim<double, 2> me, pn;
+    make_prim<double, 2>(u, a.gm1, me, bad);
+    make_prim<double, 2>(un, a.gm1, pn, bad);
+    double *q = slot + node * 4;
+    q[0] = me.rho;
+    q[1] = me.v[0];
+    q[2] = me.v[1];
+    q[3] = me.p * rcp64(me.rho);
+    wave_lds_sync();
+    if (L.fv) {
+        const double *qo = slot + L.F.own * 4;
+        double qs[4];
+        if (ns_boundary(L)) {
+            // moving isothermal wall: exact velocity and temperature, the trace's density
+            const double tt = elt(a.cs, (uint32_t)L.cs).t + a.c_stage * L.dt;
+            double r, vx, p;
+            viscous_shock(L.F.side ? a.x_hi : a.x_lo, tt, a.gam, a.mu, r, vx, p);
+            qs[0] = qo[0];
+            qs[1] = vx;
+            qs[2] = 0.0;
+            qs[3] = p / r;
+        } else {
+            qs[0] = 0.5 * (qo[0] + pn.rho);
+            qs[1] = 0.5 * (qo[1] + pn.v[0]);
+            qs[2] = 0.5 * (qo[2] + pn.v[1]);
+            qs[3] = 0.5 * (qo[3] + pn.p * rcp64(pn.rho));
+        }
+        const double lift = L.F.side ? 6.0 : -6.0;
+        double *sq = slot + 4 * NPE;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sq[k * NFN + L.F.q] = lift * (qs[k] - qo[k]);
+    }
+    wave_lds_sync();
+    if (!valid) return;
+    const ElemInfo ei = elt(a.elem, (uint32_t)L.e);
+    const size_t field = (size_t)a.nelem * NPE;
+    const uint32_t o8 = ((uint32_t)L.e * NPE + node) * 8u;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const int t = node_pos(d, node), l = node_line<2>(d, node);
+        const double *q1 = slot + line_node<2>(d, l, (t + 1) & 3) * 4;
+        const double *q2 = slot + line_node<2>(d, l, (t + 2) & 3) * 4;
+        const double *q3 = slot + line_node<2>(d, l, (t + 3) & 3) * 4;
+        const double *qt = slot + node * 4;
+        const double w1 = 0.5 * dsplit_j<double, 1>(t), w2 = 0.5 * dsplit_j<double, 2>(t);
+        const double w3 = 0.5 * dsplit_j<double, 3>(t), w0 = dfull_diag(t);
+        const double h = d == 0 ? ei.metric[0] : ei.metric[1];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double acc = w0 * qt[k] + w1 * q1[k] + w2 * q2[k] + w3 * q3[k];
+            if (t == 0 || t == 3) acc += slot[4 * NPE + k * NFN + (2 * d + (t == 3 ? 1 : 0)) * NLINE + l];
+            bstore<double>(h * acc, field_rsrc<double>(a.grad, d * 4 + k, field), o8);
+        }
+    }
+    if (bad) atomicOr(a.err, bad);
+}
+
+// Stage kernel with viscous terms (double precision, 2D): inviscid part with the
+// EC or a dissipative surface flux and EC flux differencing or the weak form,
+// plus the BR1 divergence of the viscous flux.
+template <int KIND>
+__global__ void __launch_bounds__(64 * PERRK_MAX_WPB) ns_stage_kernel(const StageArgs a, const double *coef)
+{
+    constexpr int NPE = 16, EPW = 4, NFN = SG<2>::NFN, NPP = SG<2>::NPP, NPD = SG<2>::NPD, NLINE = SG<2>::NLINE;
+    constexpr int SLOT = NS_SLOT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *lds = reinterpret_cast<double *>(smem_raw);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int eslot = wave * EPW + lane / NPE;
+    const int node = lane % NPE;
+    const int epb = (int)(blockDim.x >> 6) * EPW;
+    const int li = xcd_block(blockIdx.x, gridDim.x) * epb + eslot;
+    const bool valid = li < a.n_active;
+    double *slot = lds + (size_t)eslot * SLOT;
+    const double gam = a.gam, inv_gm1 = a.inv_gm1;
+    const double kappa = a.gam * a.mu / ((a.gam - 1.0) * a.prandtl);
+    NsLoad L;
+    ns_load<KIND>(a, coef, (uint32_t)(valid ? li : a.n_active - 1), lane, node, L);
+    const size_t field = (size_t)a.nelem * NPE;
+    const uint32_t o8 = ((uint32_t)L.e * NPE + node) * 8u, n8 = ((uint32_t)L.nb * NPE + L.nn) * 8u;
+    double go[8], gn[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        go[k] = bload<double>(field_rsrc<double>(a.grad, k, field), o8);
+        gn[k] = bload<double>(field_rsrc<double>(a.grad, k, field), n8);
+    }
+    double dacc[4];
+    if constexpr (KIND == SK_LAST) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dacc[v] = a.d_has ? bload<double>(field_rsrc<double>(a.d_out, v, field), o8) : 0.0;
+    }
+    int bad = 0;
+    double u[4], un[4];
+    combine<4, double, KIND>(L.own, L.dt, L.c1, L.cp, u);
+    combine<4, double, KIND>(L.nr, L.dt, L.nc1, L.ncp, un);
+    Prim<double, 2> me, pn;
+    make_prim<double, 2>(u, a.gm1, me, bad);
+    make_prim<double, 2>(un, a.gm1, pn, bad);
+    {
+        double *q = slot + node * 4;
+        q[0] = me.rho;
+        q[1] = me.v[0];
+        q[2] = me.v[1];
+        q[3] = me.p;
+        double *g = slot + NS_OFF_G;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g[k * NPE + node] = go[k];
+        // viscous flux of the own node in both directions
+        double fx[3], fy[3];
+        ns_vflux(0, me.v[0], me.v[1], go, a.mu, kappa, fx);
+        ns_vflux(1, me.v[0], me.v[1], go, a.mu, kappa, fy);
+        double *fvn = slot + NS_OFF_FVN;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            fvn[c * NPE + node] = fx[c];
+            fvn[(3 + c) * NPE + node] = fy[c];
+        }
+    }
+    wave_lds_sync();
+
+    // ---- faces: inviscid flux (ghost states at the x ends) and viscous face terms
+    if (L.fv) {
+        Prim<double, 2> PO;
+        {
+            const double *q = slot + L.F.own * 4;
+            PO.rho = q[0];
+            PO.v[0] = q[1];
+            PO.v[1] = q[2];
+            PO.p = q[3];
+            PO.beta = PO.rho * rcp64(PO.p);
+        }
+        const bool bnd = ns_boundary(L);
+        const double tt = elt(a.cs, (uint32_t)L.cs).t + a.c_stage * L.dt;
+        double rw = 0.0, vw = 0.0, pw = 1.0;
+        if (bnd) viscous_shock(L.F.side ? a.x_hi : a.x_lo, tt, gam, a.mu, rw, vw, pw);
+        Prim<double, 2> PG = pn;
+        if (bnd) {
+            if (L.F.side) {
+                PG = PO;  // free outflow: the trace itself
+            } else {      // inflow: the exact state
+                PG.rho = rw;
+                PG.v[0] = vw;
+                PG.v[1] = 0.0;
+                PG.p = pw;
+                PG.beta = rw * rcp64(pw);
+            }
+        }
+        const bool sd = L.F.side != 0;
+        Prim<double, 2> A, B;
+        A.rho = sd ? PO.rho : PG.rho;
+        B.rho = sd ? PG.rho : PO.rho;
+        A.p = sd ? PO.p : PG.p;
+        B.p = sd ? PG.p : PO.p;
+        A.beta = sd ? PO.beta : PG.beta;
+        B.beta = sd ? PG.beta : PO.beta;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            A.v[k] = sd ? PO.v[k] : PG.v[k];
+            B.v[k] = sd ? PG.v[k] : PO.v[k];
+        }
+        double fs[4];
+        if (a.flux != PERRK_FLUX_EC) flux_diss<double, 2>(a.flux, L.F.d, A, B, gam, inv_gm1, fs);
+        else flux_ec<double, 2>(L.F.d, A, B, inv_gm1, fs);
+        const double lift = sd ? 6.0 : -6.0;
+        double *sf = slot + NS_OFF_SF;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sf[v * NFN + L.F.q] = lift * fs[v];
+        // viscous: F* - F_own at the own face node
+        const double *fvn = slot + NS_OFF_FVN + (L.F.d == 0 ? 0 : 3 * NPE);
+        double fo[3], fstar[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fo[c] = fvn[c * NPE + L.F.own];
+        if (bnd) {
+            double gown[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) gown[k] = slot[NS_OFF_G + k * NPE + L.F.own];
+            ns_vflux(L.F.d, vw, 0.0, gown, a.mu, kappa, fstar);
+        } else {
+            double fn[3];
+            ns_vflux(L.F.d, pn.v[0], pn.v[1], gn, a.mu, kappa, fn);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fstar[c] = 0.5 * (fo[c] + fn[c]);
+        }
+        double *sfv = slot + NS_OFF_SFV;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sfv[c * NFN + L.F.q] = lift * (fstar[c] - fo[c]);
+    }
+
+    // ---- inviscid pair fluxes (EC or central)
+#pragma unroll
+    for (int rd = 0; rd < PairRounds<2, 2>::N; ++rd) {
+        int es, dd, l, k;
+        pair_of<2, 2>(rd, lane, es, dd, l, k);
+        int ta, tb;
+        pair_pos(k, ta, tb);
+        double *ps = lds + (size_t)(wave * EPW + es) * SLOT;
+        Prim<double, 2> A, B;
+        {
+            const double *qa = ps + line_node<2>(dd, l, ta) * 4, *qb = ps + line_node<2>(dd, l, tb) * 4;
+            A.rho = qa[0];
+            A.v[0] = qa[1];
+            A.v[1] = qa[2];
+            A.p = qa[3];
+            A.beta = A.rho * rcp64(A.p);
+            B.rho = qb[0];
+            B.v[0] = qb[1];
+            B.v[1] = qb[2];
+            B.p = qb[3];
+            B.beta = B.rho * rcp64(B.p);
+        }
+        double f[4];
+        if (a.volume) flux_central<double, 2>(dd, A, B, inv_gm1, f);
+        else flux_ec<double, 2>(dd, A, B, inv_gm1, f);
+        double *vf = ps + NS_OFF_VF;
+        const int p = dd * NPD + l * 6 + k;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) vf[v * NPP + p] = f[v];
+    }
+    wave_lds_sync();
+
+    // ---- gather: inviscid (split form) and viscous (full derivative) per direction
+    const ElemInfo ei = elt(a.elem, (uint32_t)L.e);
+    double k[4] = {0.0, 0.0, 0.0, 0.0};
+    {
+        const double *sf = slot + NS_OFF_SF, *vf = slot + NS_OFF_VF;
+        const double *fvn = slot + NS_OFF_FVN, *sfv = slot + NS_OFF_SFV;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const int t = node_pos(d, node), l = node_line<2>(d, node);
+            const int pb = d * NPD + l * 6;
+            const int p1 = pb + pair_k<1>(t), p2 = pb + pair_k<2>(t), p3 = pb + pair_k<3>(t);
+            const double w1 = dsplit_j<double, 1>(t), w2 = dsplit_j<double, 2>(t), w3 = dsplit_j<double, 3>(t);
+            const int qf = (2 * d + (t == 3 ? 1 : 0)) * NLINE + l;
+            const double h = d == 0 ? ei.metric[0] : ei.metric[1];
+            double ai[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                ai[v] = w1 * vf[v * NPP + p1] + w2 * vf[v * NPP + p2] + w3 * vf[v * NPP + p3];
+                if (t == 0 || t == 3) ai[v] += sf[v * NFN + qf];
+                k[v] -= h * ai[v];
+            }
+            const int n1 = line_node<2>(d, l, (t + 1) & 3), n2 = line_node<2>(d, l, (t + 2) & 3);
+            const int n3 = line_node<2>(d, l, (t + 3) & 3);
+            const double *fd = fvn + (d == 0 ? 0 : 3 * NPE);
+            const double w0 = dfull_diag(t);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double av = w0 * fd[c * NPE + node] + 0.5 * (w1 * fd[c * NPE + n1] + w2 * fd[c * NPE + n2] +
+                                                             w3 * fd[c * NPE + n3]);
+                if (t == 0 || t == 3) av += sfv[c * NFN + qf];
+                k[1 + c] += h * av;
+            }
+        }
+    }
+
+    if (valid) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if (KIND == SK_LAST) {
+                double dv = a.bs * k[v];
+                if (a.bsm1 != 0.0) dv += a.bsm1 * L.own.kp[v];
+                if (a.b1 != 0.0) dv += a.b1 * L.own.k1[v];
+                if (a.d_has) dv += dacc[v];
+                bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
+            } else {
+                bstore<double>(k[v], field_rsrc<double>(a.Kout, v, field), o8);
+                if (a.acc_mode) {
+                    double dv = a.b_acc * k[v];
+                    if (a.acc_mode == 2) dv += bload<double>(field_rsrc<double>(a.d_out, v, field), o8);
+                    bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
+                }
+            }
+        }
+    }
+    if (a.ep_partial != nullptr) {
+        double w[4];
+        entropy_vars<2>(u, gam, w);
+        double dot = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dot += w[v] * k[v];
+        double sm = node_weight<2>(node) * dot;
+#pragma unroll
+        for (int off = NPE / 2; off >= 1; off >>= 1) sm += __shfl_xor(sm, off);
+        if (valid && node == 0) a.ep_partial[L.e] = ei.jac * sm;
+    }
+    if (bad && valid) atomicOr(a.err, bad);
+}
+
 // ---------------------------------------------------------------- reductions
 // Sum of NC per-element partials over [b, e) by PERRK_RED_THREADS threads in a
 // fixed order (strided sequential sums, then a fixed tree).  Result in out on
@@ -2073,11 +2500,35 @@ hipError_t launch_mhd_stage_t(const StageArgs &a, const double *coef, LaunchCfg 
     return hipGetLastError();
 }
 
+// Navier-Stokes stage: the gradient pass over every element (its own stage
+// state, the neighbours' at the faces), then the stage kernel over the stage's
+// active elements.
+template <int KIND>
+hipError_t launch_ns_stage_t(const StageArgs &a, const double *coef, LaunchCfg cfg, hipStream_t s)
+{
+    const int wpb = cfg.epb_mult;
+    const int epb = wpb * 4;
+    if (a.n_all > 0) {
+        StageArgs g = a;
+        g.active = a.active_all;
+        g.n_active = a.n_all;
+        const int blocks = (g.n_active + epb - 1) / epb;
+        hipLaunchKernelGGL((ns_grad_kernel<KIND>), dim3(blocks), dim3(64 * wpb),
+                           (size_t)epb * NS_GRAD_SLOT * sizeof(double), s, g, coef);
+    }
+    if (a.n_active <= 0) return hipGetLastError();
+    const int blocks = (a.n_active + epb - 1) / epb;
+    hipLaunchKernelGGL((ns_stage_kernel<KIND>), dim3(blocks), dim3(64 * wpb), (size_t)epb * NS_SLOT * sizeof(double),
+                       s, a, coef);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 size_t stage_lds_bytes(int dim, int variant, int wpb, int sys)
 {
     if (sys == 1) return (size_t)wpb * 4 * MHD_SLOT * sizeof(double);
+    if (sys == 2) return (size_t)wpb * 4 * NS_SLOT * sizeof(double);
     if (variant == 1) {
         if (dim == 2) return (size_t)wpb * SG<2>::EPW * SL<2, float>::SLOT * sizeof(float);
         return (size_t)wpb * SG<3>::EPW * SL<3, float>::SLOT * sizeof(float);
@@ -2090,6 +2541,12 @@ hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArg
                         LaunchCfg cfg, hipStream_t s)
 {
     if (cfg.epb_mult < 1 || cfg.epb_mult > PERRK_MAX_WPB) return hipErrorInvalidValue;
+    if (a.viscous) {  // Navier-Stokes-Fourier: 2D, double precision
+        if (dim != 2 || variant != 0 || a.sys != 0) return hipErrorInvalidValue;
+        if (kind == SK_FIRST) return launch_ns_stage_t<SK_FIRST>(a, coef, cfg, s);
+        if (kind == SK_MID) return launch_ns_stage_t<SK_MID>(a, coef, cfg, s);
+        return launch_ns_stage_t<SK_LAST>(a, coef, cfg, s);
+    }
     if (a.sys == 1) {  // ideal GLM-MHD: 2D, double precision
         if (dim != 2 || variant != 0) return hipErrorInvalidValue;
         if (kind == SK_FIRST) return launch_mhd_stage_t<SK_FIRST>(a, coef, cfg, s);

@@ -35,7 +35,9 @@ class MeshDesc(ctypes.Structure):
                 ("n_elem_dir", ctypes.POINTER(ctypes.c_int32)),
                 ("face_coords", ctypes.POINTER(ctypes.c_double)), ("gas_gamma", ctypes.c_double),
                 ("surface_flux", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("volume_integral", ctypes.c_int32), ("system", ctypes.c_int32), ("glm_ch", ctypes.c_double)]
+                ("volume_integral", ctypes.c_int32), ("system", ctypes.c_int32), ("glm_ch", ctypes.c_double),
+                ("viscous", ctypes.c_int32), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
+                ("bc_x", ctypes.c_int32)]
 
 
 class PartitionDesc(ctypes.Structure):
@@ -153,7 +155,8 @@ class Descriptors:
     """Host-side descriptors (keeps the numpy buffers alive)."""
 
     def __init__(self, faces_per_case, levels, tableau, gas_gamma=1.4, surface_flux=FLUX_EC,
-                 precision=FP64, volume_integral=VOLUME_FLUX_DIFFERENCING, system=SYSTEM_EULER, glm_ch=0.0):
+                 precision=FP64, volume_integral=VOLUME_FLUX_DIFFERENCING, system=SYSTEM_EULER, glm_ch=0.0,
+                 viscous=0, mu=0.0, prandtl=0.75, bc_x=0):
         self.dim = len(faces_per_case[0])
         self.n_cases = len(faces_per_case)
         n = []
@@ -170,7 +173,7 @@ class Descriptors:
         self.b = np.ascontiguousarray(tableau["b"], dtype=np.float64)
         self.a_sub = np.ascontiguousarray(tableau["a_sub"], dtype=np.float64)
         self.mesh = MeshDesc(self.dim, self.n_cases, _ip(self.n), _dp(self.faces), gas_gamma, surface_flux,
-                             precision, volume_integral, system, glm_ch)
+                             precision, volume_integral, system, glm_ch, viscous, mu, prandtl, bc_x)
         self.part = PartitionDesc(len(self.E), _ip(self.levels))
         self.tab = TableauDesc(int(tableau["order"]), len(self.c), len(self.E), _ip(self.E), _dp(self.c),
                                _dp(self.b), _dp(self.a_sub))

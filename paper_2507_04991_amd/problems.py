@@ -16,6 +16,12 @@
              cells, gamma = 5/3, weak-form volume term, LLF surface flux, p = 3 with
              E = {10, ..., 14} assigned to the cells at random, c_h = 1.
 
+  viscous_shock  1.5D Navier-Stokes-Fourier viscous shock (Sec. 4.3.2): [-2, 2] x [0, 8/n]
+             with n cells in x (widths halved in [-1, 1]) and 2 in y, gamma = 5/3,
+             mu = 0.15, Pr = 3/4, HLLE surface flux, weak-form volume term, BR1,
+             exact inflow / outflow / moving isothermal walls at the x ends, p = 4 with
+             E = {6, 10} (10 on the fine cells), dt = 0.035 dx_min^2 / v.
+
 Levels by the shortest edge with one speed per case, step at 0.5 of the optimised
 stable step of the largest level (random assignments: of every assigned level).
 Every Euler mesh is graded geometrically (ratio 4, finest at the centre).
@@ -96,3 +102,17 @@ def alfven(seed=0, n=16):
     dt = 0.5 * float(np.min(np.asarray(tab["h_stab"])[lev] * h / speed))
     return dict(kind="alfven", name=f"alfven{n}_p3_E10-14_random", faces=[f], U0=U0, tab=tab, dt=np.array([dt]),
                 lev=[lev], flux=2, volume=1, system=1, glm_ch=1.0, gam=gam)
+
+
+def viscous_shock(seed=0, n=24):
+    gam, mu = 5.0 / 3.0, 0.15
+    fx = W.viscous_shock_faces(n)
+    f = [fx, W.uniform_faces(2, 0.0, 8.0 / n)]
+    U0 = W.viscous_shock_state(W.node_coords(f), 0.0, gam, mu)
+    tab = T.get_tableau(4, [6, 10])
+    wx = W.element_widths(f)[:, 0]
+    lev = np.where(wx < 0.75 * wx.max(), 1, 0).astype(np.int32)
+    dt = 0.035 * wx.min() ** 2
+    return dict(kind="viscous_shock", name=f"viscous_shock{n}_p4_E6-10", faces=[f], U0=U0, tab=tab,
+                dt=np.array([dt]), lev=[lev], flux=3, volume=1, system=0, viscous=1, mu=mu, prandtl=0.75, bc_x=1,
+                gam=gam)

@@ -94,6 +94,18 @@ def test_validate_glm_mhd_descriptors():
         assert st == P.EINVAL and word in msg, msg
     st, msg = desc(system=7).validate()
     assert st == P.EINVAL and "system" in msg, msg
+
+
+def test_validate_viscous_descriptors():
+    ok = dict(viscous=1, mu=0.15, prandtl=0.75)
+    assert desc(**ok).validate()[0] == P.OK
+    assert desc(bc_x=1, **ok).validate()[0] == P.OK
+    for bad, word in [(dict(precision=P.MIXED), "FP64"), (dict(mu=-1.0), "mu"), (dict(prandtl=0.0), "prandtl"),
+                      (dict(system=P.SYSTEM_GLM_MHD, glm_ch=1.0), "Euler"), (dict(viscous=2), "viscous")]:
+        st, msg = desc(**dict(ok, **bad)).validate()
+        assert st == P.EINVAL and word in msg, msg
+    st, msg = desc(bc_x=1).validate()  # the shock boundaries need the viscous terms
+    assert st == P.EINVAL and "viscous" in msg, msg
     d = desc()
     assert d.validate(P.default_options(fast_passes=0))[0] == P.EINVAL
     assert d.validate(P.default_options(bisect_lo=1.1))[0] == P.EINVAL
