@@ -696,7 +696,19 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
                         if (i < c->S - 2 && c->b[i] != 0.0) be += first_acc == i ? 8.0 : 16.0;  // d
                     }
                 }
+                if (c->viscous) be += 16.0;  // the gradients of the node (8 doubles per 4 DOF)
                 bytes += be * dofe * per_level[r];
+            }
+            if (c->viscous) {
+                // the gradient pass over every element: its stage state and the gradient write
+                for (int r = 0; r < c->R; ++r) {
+                    const double c1 = coef[(size_t)i * 2 * PERRK_MAXR + r];
+                    const double cp = coef[(size_t)i * 2 * PERRK_MAXR + PERRK_MAXR + r];
+                    double be = 8.0 + 16.0;
+                    if (i > 0 && c1 != 0.0) be += 8.0;
+                    if (i > 0 && cp != 0.0) be += 8.0;
+                    bytes += be * dofe * per_level[r];
+                }
             }
             c->stage_bytes[i] = bytes;
         }
