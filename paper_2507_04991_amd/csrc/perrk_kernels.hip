@@ -708,24 +708,41 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
 {
     constexpr int EPW = SG<DIM>::EPW, NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V;
     constexpr int SLOT = SL<DIM, T>::SLOT, PRIM = SL<DIM, T>::PRIM, NFN = SG<DIM>::NFN;
+    constexpr int NR = PairRounds<DIM, ND>::N;
+    // every round's two nodes are read before the first flux is formed (the
+    // pair-flux writes below may not be moved above these reads), so that one
+    // LDS latency is exposed instead of one per round and the rounds' flux
+    // arithmetic is independent
+    Prim<T, DIM> A[NR], B[NR];
+    int pv[NR];
+    bool ok[NR];
+    T *vfs[NR];
 #pragma unroll
-    for (int rd = 0; rd < PairRounds<DIM, ND>::N; ++rd) {
+    for (int rd = 0; rd < NR; ++rd) {
         int es, dd, l, k;
-        if (!pair_of<DIM, ND>(rd, lane, es, dd, l, k)) continue;
+        ok[rd] = pair_of<DIM, ND>(rd, lane, es, dd, l, k);
         int ta, tb;
         pair_pos(k, ta, tb);
         const int d = D0 + dd;
         T *slot = lds + (size_t)(wave * EPW + es) * SLOT;
-        Prim<T, DIM> A, B;
-        lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, ta), A);
-        lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, tb), B);
-        T f[V];
-        if (WEAK) flux_central<T, DIM>(d, A, B, inv_gm1, f);
-        else flux_ec<T, DIM>(d, A, B, inv_gm1, f);
-        T *vf = slot + PRIM + V * NFN;
-        const int p = dd * NPD + l * 6 + k;
+        if (ok[rd]) {
+            lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, ta), A[rd]);
+            lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, tb), B[rd]);
+        }
+        vfs[rd] = slot + PRIM + V * NFN;
+        pv[rd] = dd * NPD + l * 6 + k;
+    }
 #pragma unroll
-        for (int v = 0; v < V; ++v) vf[v * NPP + p] = f[v];
+    for (int rd = 0; rd < NR; ++rd) {
+        if (!ok[rd]) continue;
+        int es, dd, l, k;
+        pair_of<DIM, ND>(rd, lane, es, dd, l, k);
+        const int d = D0 + dd;
+        T f[V];
+        if (WEAK) flux_central<T, DIM>(d, A[rd], B[rd], inv_gm1, f);
+        else flux_ec<T, DIM>(d, A[rd], B[rd], inv_gm1, f);
+#pragma unroll
+        for (int v = 0; v < V; ++v) vfs[rd][v * NPP + pv[rd]] = f[v];
     }
 }
 
