@@ -49,6 +49,8 @@ def pick_levels(kind, lev, R, n, seed):
         return (np.arange(n) % R).astype(np.int32)
     if kind == "single":  # every element on the largest-E level: the single-level method
         return np.full(n, R - 1, dtype=np.int32)
+    if kind == "lowest":  # every element on the smallest-E level: the stages in between have no active element
+        return np.zeros(n, dtype=np.int32)
     raise ValueError(kind)
 
 

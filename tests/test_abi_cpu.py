@@ -109,3 +109,21 @@ def test_validate_viscous_descriptors():
     d = desc()
     assert d.validate(P.default_options(fast_passes=0))[0] == P.EINVAL
     assert d.validate(P.default_options(bisect_lo=1.1))[0] == P.EINVAL
+
+
+def test_validate_node_limit_and_case_count():
+    """All cases together may hold at most 2^29 nodes (a field of a node array then
+    fits a 32-bit byte offset): exactly 2^29 is accepted, one layer more rejected;
+    no cases at all is rejected."""
+    from paper_2507_04991_amd import tableau as T
+    tab = T.get_tableau(2, [3, 6])
+    for nz, ok in ((2, True), (3, False)):
+        f = [W.uniform_faces(2048, 0, 1), W.uniform_faces(2048, 0, 1), W.uniform_faces(nz, 0, 1)]
+        lev = np.zeros(2048 * 2048 * nz, dtype=np.int32)
+        st, msg = P.Descriptors([f], [lev], tab).validate()
+        assert (st == P.OK) == ok, msg
+        if not ok:
+            assert "2^29" in msg, msg
+    d = desc()
+    d.mesh.n_cases = 0
+    assert d.validate()[0] == P.EINVAL

@@ -57,7 +57,7 @@ def test_rhs_matches_oracle(P, oracle, dim, flux):
 
 @pytest.mark.parametrize("order,E,levels", [(2, (3, 6), "cfl"), (2, (3, 6), "random"),
                                             (3, (4, 6, 8, 12), "cfl"), (3, (4, 6, 8, 12), "roundrobin"),
-                                            (3, (4, 6, 8, 12), "single"),
+                                            (3, (4, 6, 8, 12), "single"), (3, (4, 6, 8, 12), "lowest"),
                                             (4, (5, 9, 14), "cfl"), (4, (5, 9, 14), "random")])
 def test_steps_match_oracle_2d(P, oracle, order, E, levels):
     f, U0, tab, dt, lev = problem_2d(order=order, E=E, levels=levels)
