@@ -172,7 +172,10 @@ typedef struct {
     int32_t use_graph;         /* 1: capture each step's launch sequence into a hipGraph */
     int32_t tune;              /* 1: at the first perrk_step, time every stage launch with 1, 2, 4 and 8
                                   wavefronts per workgroup on the caller's state and keep the fastest
-                                  per stage (results do not depend on the choice); 0: 4 for all */
+                                  per stage (results do not depend on the choice); 0: 4 for all
+                                  (1 for GLM-MHD, 2 for Navier-Stokes); -w (w = 1, 2, 4, 8): w for
+                                  all (PERRK_EINVAL from perrk_init if that needs more LDS per
+                                  workgroup than the device has) */
 } perrk_options;
 
 typedef struct {

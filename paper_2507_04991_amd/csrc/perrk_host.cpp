@@ -279,6 +279,8 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
         if (o->anchor != PERRK_ANCHOR_STEP && o->anchor != PERRK_ANCHOR_INITIAL) return ck.bad("bad anchor");
         if (o->guess != PERRK_GUESS_PREV && o->guess != PERRK_GUESS_MLP) return ck.bad("bad guess");
         if (o->fast_passes < 1 || o->fast_passes > 16) return ck.bad("fast_passes must be in 1..16");
+        if (o->tune != 0 && o->tune != 1 && o->tune != -1 && o->tune != -2 && o->tune != -4 && o->tune != -8)
+            return ck.bad("tune must be 1, 0, -1, -2, -4 or -8");
     }
     return PERRK_OK;
 }
@@ -605,15 +607,41 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
         for (int k = 0; k < 6; ++k)
             ei.nbr[k] = (int32_t)((uint32_t)ei.nbr[k] | ((uint32_t)elem[ei.nbr[k]].level << PERRK_NBR_SHIFT));
 
-    // active element list of every stage, in natural element order (spatial
-    // neighbours are processed together): stage i evaluates the levels with
-    // E >= S - i + 1, stage 1 every element
+    // tile of a 2D case mesh whose elements the active lists keep together: the
+    // elements of a workgroup of PERRK_MAX_WPB wavefronts (4 quadrilaterals each)
+    constexpr int ACT_TILE_X = 8, ACT_TILE_Y = 4;
+    static_assert(ACT_TILE_X * ACT_TILE_Y == 4 * PERRK_MAX_WPB, "one tile per full workgroup");
+    // active element list of every stage: stage i evaluates the levels with
+    // E >= S - i + 1, stage 1 every element.  3D lists follow the natural element
+    // order.  2D lists visit each case mesh by tiles of ACT_TILE_X x ACT_TILE_Y
+    // elements (row by row inside a tile), so that the 32 elements of a full
+    // workgroup are mostly each other's face neighbours; nbr[5], which 2D meshes
+    // do not need, then records for each face f (bits 6f .. 6f + 5) the
+    // neighbour's position in the same list relative to the entry's, as offset + 31
+    // for offsets in [-31, 31] and 63 otherwise.  The stage kernel takes the stage
+    // state of a neighbour that sits in its own workgroup from LDS.
+    std::vector<int64_t> visit;
+    visit.reserve((size_t)c->nelem);
+    for (int cs = 0; cs < m->n_cases; ++cs) {
+        const int64_t base = c->case_off[cs];
+        const int n0 = m->n_elem_dir[3 * cs], n1 = m->n_elem_dir[3 * cs + 1];
+        if (m->dim == 3) {
+            for (int64_t e = base; e < c->case_off[cs + 1]; ++e) visit.push_back(e);
+            continue;
+        }
+        for (int ty = 0; ty < n1; ty += ACT_TILE_Y)
+            for (int tx = 0; tx < n0; tx += ACT_TILE_X)
+                for (int iy = ty; iy < std::min(ty + ACT_TILE_Y, n1); ++iy)
+                    for (int ix = tx; ix < std::min(tx + ACT_TILE_X, n0); ++ix)
+                        visit.push_back(base + ix + (int64_t)n0 * iy);
+    }
     std::vector<ActiveEntry> order;
+    std::vector<int64_t> pos((size_t)c->nelem, -1);  // list position of each element in the current stage
     c->n_active.resize(c->S);
     c->active_off.resize(c->S + 1);
     for (int i = 0; i < c->S; ++i) {
         c->active_off[i] = (int64_t)order.size();
-        for (int64_t e = 0; e < c->nelem; ++e) {
+        for (const int64_t e : visit) {
             const int E = c->E[elem[e].level];
             if (i == 0 || i >= c->S - E + 1) {
                 ActiveEntry en{};
@@ -627,10 +655,26 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
                     en.nbr[4] = c->bc_x ? ((ix == 0 ? 1 : 0) | (ix == m->n_elem_dir[0] - 1 ? 2 : 0)) : 0;
                     en.nbr[5] = 0;
                 }
+                pos[(size_t)e] = (int64_t)order.size() - c->active_off[i];
                 order.push_back(en);
             }
         }
         c->n_active[i] = (int32_t)(order.size() - c->active_off[i]);
+        if (c->dim == 2) {
+            for (int64_t j = 0; j < c->n_active[i]; ++j) {
+                ActiveEntry &en = order[(size_t)(c->active_off[i] + j)];
+                uint32_t code = 0;
+                for (int f = 0; f < 4; ++f) {
+                    const int64_t q = pos[(size_t)((uint32_t)en.nbr[f] & PERRK_NBR_MASK)];
+                    const int64_t off = q - j;
+                    const uint32_t cf = (q >= 0 && off >= -31 && off <= 31) ? (uint32_t)(off + 31) : 63u;
+                    code |= cf << (6 * f);
+                }
+                en.nbr[5] = (int32_t)code;
+            }
+        }
+        for (int64_t j = 0; j < c->n_active[i]; ++j)
+            pos[(size_t)((uint32_t)order[(size_t)(c->active_off[i] + j)].elem_level & PERRK_NBR_MASK)] = -1;
     }
     c->active_off[c->S] = (int64_t)order.size();
     // per-stage coefficients (without dt): K_1 and K_{i-1} multipliers per level
@@ -738,6 +782,15 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
             c->max_lds = (size_t)lds;
+    }
+    if (c->opt.tune < 0) {  // one given launch shape for every stage
+        const int w = -c->opt.tune;
+        if (stage_lds_bytes(c->dim, c->precision == PERRK_MIXED_ALL ? 1 : 0, w, c->viscous ? 2 : c->sys) > c->max_lds) {
+            std::fprintf(stderr, "perrk_init: %d wavefronts per workgroup need more LDS than the device has\n", w);
+            return bail(PERRK_EINVAL);
+        }
+        c->cfg.epb_mult = w;
+        c->scfg.assign(c->S, c->cfg);
     }
     HIPINIT(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIPINIT(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));

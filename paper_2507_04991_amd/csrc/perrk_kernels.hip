@@ -541,6 +541,79 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// ---------------------------------------------------------------- per-element values
+// Every lane of an element slot needs the same per-element values: the active
+// entry, dt of the element's case, the level coefficients of the element and of
+// its face neighbours, the element's metric.  A few lanes load them and the
+// others take them by cross-lane reads: a load by every lane would move each
+// value through the vector memory path once per lane, and those repeated bytes
+// were close to half of the path's traffic in the stage kernels.
+
+// Lanes 2k and 2k + 1 load the two 16-byte halves of the active entry of the
+// wavefront's slot k (list index li0 + k, clamped to the list); other lanes
+// return zeros.
+template <int EPW>
+__device__ __forceinline__ int4 wave_entry_part(const void *active, int li0, int n_active, int lane)
+{
+    int4 r = make_int4(0, 0, 0, 0);
+    if (lane < 2 * EPW) {
+        const int j = min(li0 + (lane >> 1), n_active - 1);
+        r = elt(reinterpret_cast<const int4 *>(active), 2u * (uint32_t)j + (uint32_t)(lane & 1));
+    }
+    return r;
+}
+
+__device__ __forceinline__ int4 shfl4(const int4 &v, int src)
+{
+    return make_int4(__shfl(v.x, src), __shfl(v.y, src), __shfl(v.z, src), __shfl(v.w, src));
+}
+
+// Lanes 0 .. 2 PERRK_MAXR - 1 hold the stage's coefficient table (c_1 of level r
+// at lane r, c_p at lane PERRK_MAXR + r); coef_of reads entry j of it.
+__device__ __forceinline__ double wave_coef_table(const double *coef, int lane)
+{
+    return lane < 2 * PERRK_MAXR ? elt(coef, (uint32_t)lane) : 0.0;
+}
+
+// Lane k < EPW loads dt of slot k's case and the metric and Jacobian of slot k's
+// element (entry halves in `part`); the slot's lanes take them with slot_value.
+template <int DIM, int EPW>
+struct SlotVals {
+    double dt, h[DIM], jac;
+};
+
+template <int DIM, int EPW, bool DT>
+__device__ __forceinline__ SlotVals<DIM, EPW> wave_slot_vals(const StageArgs &a, const int4 &part, int lane)
+{
+    const int src = 2 * (lane % EPW);
+    const uint32_t ex = (uint32_t)__shfl(part.x, src) & PERRK_NBR_MASK;
+    const uint32_t cy = (uint32_t)__shfl(part.y, src);
+    SlotVals<DIM, EPW> r;
+    r.dt = 0.0;
+    r.jac = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) r.h[d] = 0.0;
+    if (lane < EPW) {
+        const ElemInfo &ek = elt(a.elem, ex);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) r.h[d] = ek.metric[d];
+        r.jac = ek.jac;
+        if (DT) r.dt = elt(a.cs, cy).dt;
+    }
+    return r;
+}
+
+// The values of slot es, for every lane of the slot; the metric and Jacobian in
+// an ElemInfo (its other fields are not used by the stage kernels).
+template <int DIM, int EPW>
+__device__ __forceinline__ void slot_value(const SlotVals<DIM, EPW> &v, int es, double &dt, ElemInfo &ei)
+{
+    dt = __shfl(v.dt, es);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ei.metric[d] = d < DIM ? __shfl(v.h[d < DIM ? d : 0], es) : 0.0;
+    ei.jac = __shfl(v.jac, es);
+}
+
 // ---------------------------------------------------------------- stage kernel
 // LDS per element slot (flux precision T):
 //   prim[NPE][NQ]   own stage state per node: rho, v_0..v_{DIM-1}, p
@@ -832,16 +905,17 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int eslot = wave * EPW + lane / NPE;
+    const int es = lane / NPE;
+    const int eslot = wave * EPW + es;
     const int node = lane % NPE;
     const int epb = (int)(blockDim.x >> 6) * EPW;
-    const int li = xcd_block(blockIdx.x, gridDim.x) * epb + eslot;
-    const bool valid = li < a.n_active;
-    // the active entry in two 16-byte loads: {element | level, case, nbr 0, nbr 1},
-    // {nbr 2 .. nbr 5}
-    const int4 *ap = reinterpret_cast<const int4 *>(a.active);
-    const uint32_t ai = (uint32_t)(valid ? li : a.n_active - 1);
-    const int4 act = elt(ap, 2u * ai), act2 = elt(ap, 2u * ai + 1u);
+    const int li0 = xcd_block(blockIdx.x, gridDim.x) * epb + wave * EPW;  // the wavefront's first entry
+    const bool valid = li0 + es < a.n_active;
+    // the active entries {element | level, case, nbr 0, nbr 1}, {nbr 2 .. nbr 5}
+    // and the coefficient table, loaded by a few lanes
+    const int4 part = wave_entry_part<EPW>(a.active, li0, a.n_active, lane);
+    const double cf = KIND != SK_FIRST ? wave_coef_table(coef, lane) : 0.0;
+    const int4 act = shfl4(part, 2 * es), act2 = shfl4(part, 2 * es + 1);
     const int e = (int)((uint32_t)act.x & PERRK_NBR_MASK);
     const int lvl = (int)((uint32_t)act.x >> PERRK_NBR_SHIFT);
     T *slot = lds + (size_t)eslot * SLOT;
@@ -849,11 +923,11 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     int bad = 0;
 
     // ---- loads
-    double dt = 0.0, c1 = 0.0, cp = 0.0;
+    const SlotVals<DIM, EPW> sv = wave_slot_vals<DIM, EPW, KIND != SK_FIRST>(a, part, lane);
+    double c1 = 0.0, cp = 0.0;
     if (KIND != SK_FIRST) {
-        dt = elt(a.cs, (uint32_t)act.y).dt;
-        c1 = elt(coef, (uint32_t)lvl);
-        cp = elt(coef, (uint32_t)(PERRK_MAXR + lvl));
+        c1 = __shfl(cf, lvl);
+        cp = __shfl(cf, PERRK_MAXR + lvl);
     }
     NodeRaw<V, KT> own;
     load_raw<DIM, KT, KIND>(a, e, node, own);
@@ -880,23 +954,35 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     bool fv[FR];
     NodeRaw<V, KT> nr[FR];
     double nc1[FR], ncp[FR];
+    int nnr[FR], lk[FR];  // the neighbour's node; its element slot in this workgroup, else -1
 #pragma unroll
     for (int r = 0; r < FR; ++r) {
-        int nn;
-        fv[r] = face_node<DIM>(r, lane, F[r], nn);
+        fv[r] = face_node<DIM>(r, lane, F[r], nnr[r]);
         const int f = 2 * F[r].d + F[r].side;
         const uint32_t w = (uint32_t)(f < 2 ? (f == 0 ? act.z : act.w)
                                             : sel4<int>(f - 2, act2.x, act2.y, act2.z, act2.w));
         const int nb = (int)(w & PERRK_NBR_MASK);
+        lk[r] = -1;
+        if constexpr (DIM == 2) {
+            // 2D lists record the neighbour's list position relative to the entry's
+            const int code = (int)(((uint32_t)act2.w >> (6 * f)) & 63u);
+            const int t = eslot + code - 31;
+            if (code != 63 && t >= 0 && t < epb) lk[r] = t;
+        }
+        // (cross-lane reads with every lane active: a lane that is switched off
+        // does not provide its value)
         nc1[r] = 0.0;
         ncp[r] = 0.0;
         if (KIND != SK_FIRST) {
             const int lv = (int)(w >> PERRK_NBR_SHIFT);
-            nc1[r] = elt(coef, (uint32_t)lv);
-            ncp[r] = elt(coef, (uint32_t)(PERRK_MAXR + lv));
+            nc1[r] = __shfl(cf, lv);
+            ncp[r] = __shfl(cf, PERRK_MAXR + lv);
         }
-        load_raw<DIM, KT, KIND>(a, nb, nn, nr[r]);
+        if (lk[r] < 0) load_raw<DIM, KT, KIND>(a, nb, nnr[r], nr[r]);
     }
+    double dt;
+    ElemInfo ei;
+    slot_value<DIM, EPW>(sv, es, dt, ei);
 
     // ---- own stage state, published in LDS; neighbour states (same case, hence
     // the same dt) kept in registers.  Single-precision stages form the states in
@@ -913,6 +999,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
             for (int v = 0; v < V; ++v) u[v] = (double)uf[v];  // for the entropy production
 #pragma unroll
             for (int r = 0; r < FR; ++r) {
+                if (lk[r] >= 0) continue;
                 float unf[V];
                 combine_f32<V, KT, KIND>(nr[r], dt, nc1[r], ncp[r], unf);
                 prim_f32<DIM>(unf, a.gm1, PN[r], bad);
@@ -922,6 +1009,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
             make_prim<T, DIM>(u, a.gm1, me, bad);
 #pragma unroll
             for (int r = 0; r < FR; ++r) {
+                if (lk[r] >= 0) continue;
                 double un[V];
                 combine<V, KT, KIND>(nr[r], dt, nc1[r], ncp[r], un);
                 make_prim<T, DIM>(un, a.gm1, PN[r], bad);
@@ -929,7 +1017,17 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         }
         lds_put_prim<T, DIM>(slot, node, me);
     }
-    wave_lds_sync();
+    if constexpr (DIM == 2) {
+        // every slot's state is published before any lane reads a neighbour's from
+        // its slot (formed by the neighbour's own lanes with the same arithmetic);
+        // slots are not written in the primitives' area after this point
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < FR; ++r)
+            if (lk[r] >= 0) lds_get_prim<T, DIM>(lds + (size_t)lk[r] * SLOT, nnr[r], PN[r]);
+    } else {
+        wave_lds_sync();
+    }
 
     // ---- surface fluxes, lifted: +6 f* on right faces, -6 f* on left (+-1/q_boundary)
 #pragma unroll
@@ -962,7 +1060,6 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     }
 
     // ---- volume fluxes and the gather
-    const ElemInfo ei = elt(a.elem, (uint32_t)e);
     T du[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) du[v] = 0;

@@ -109,6 +109,11 @@ def test_validate_viscous_descriptors():
     d = desc()
     assert d.validate(P.default_options(fast_passes=0))[0] == P.EINVAL
     assert d.validate(P.default_options(bisect_lo=1.1))[0] == P.EINVAL
+    for tune in (1, 0, -1, -2, -4, -8):
+        assert d.validate(P.default_options(tune=tune))[0] == P.OK
+    for tune in (2, -3, -16):
+        st, msg = d.validate(P.default_options(tune=tune))
+        assert st == P.EINVAL and "tune" in msg, msg
 
 
 def test_validate_node_limit_and_case_count():

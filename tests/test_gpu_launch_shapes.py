@@ -1,0 +1,95 @@
+"""Launch shapes through the C ABI: every stage launched with 1, 2, 4 or 8
+wavefronts per workgroup (options.tune = -w) gives bit-identical states.
+
+In 2D the active lists keep tiles of each case mesh together and a neighbour that
+sits in the same workgroup is read from LDS instead of global memory, so the split
+between the two paths changes with the workgroup size.  Cases: three case meshes
+whose sizes are not multiples of the tile (partial tiles, periodic wrap inside a
+tile, a 2 x 2 mesh whose two x neighbours are the same element), random levels
+(partial active lists at the middle stages), FP64 and mixed precision; a 3D mesh
+for comparison.  The FP64 states are also checked against the oracle per case.
+"""
+import numpy as np
+import pytest
+
+from tests.helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+WPB = (1, 2, 4, 8)
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_04991_amd import perrk
+    perrk.lib()
+    return perrk
+
+
+def ensemble_2d():
+    from paper_2507_04991_amd import tableau as T
+    from paper_2507_04991_amd import workloads as W
+    tab = T.get_tableau(3, [4, 6, 8, 12])
+    rng = np.random.default_rng(11)
+    faces, U0s, levs, dts = [], [], [], []
+    for n in ((13, 9), (2, 2), (10, 6)):
+        fy = W.graded_faces(n[1], 0, 10) if n[1] % 2 == 0 and n[1] >= 4 else W.uniform_faces(n[1], 0, 10)
+        f = [W.uniform_faces(n[0], 0, 10), fy]
+        U0 = W.vortex_state(W.node_coords(f), strength=rng.uniform(1, 4), centre=tuple(rng.uniform(3, 7, 2)))
+        dt, _ = T.assign_levels(tab, W.element_widths(f).min(axis=1), W.max_wave_speed(U0, 2))
+        lev = rng.integers(0, len(tab["E"]), size=n[0] * n[1]).astype(np.int32)
+        ratio = W.element_widths(f).min(axis=1) / W.max_wave_speed(U0, 2)
+        dt = min(dt, 0.5 * float(np.min(np.asarray(tab["h_stab"])[lev] * ratio)))
+        faces.append(f), U0s.append(U0), levs.append(lev), dts.append(dt)
+    return tab, faces, U0s, levs, dts
+
+
+def run(P, tab, faces, U0s, levs, dts, precision, w, nsteps=3):
+    d = P.Descriptors(faces, levs, tab, precision=precision)
+    st = P.Stepper(d, P.default_options(tune=-w))
+    u = torch.tensor(np.concatenate(U0s, axis=1), device="cuda").contiguous()
+    gam = []
+    for _ in range(nsteps):
+        infos = st.step(u, np.array(dts))
+        assert all(i["flags"] == 0 for i in infos)
+        gam.append([i["gamma"] for i in infos])
+    out = u.cpu().numpy()
+    st.close()
+    return out, np.array(gam)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_2d_states_identical_for_every_workgroup_size(P, oracle, precision):
+    tab, faces, U0s, levs, dts = ensemble_2d()
+    res = {}
+    for w in WPB:
+        print(f"case 2d ensemble precision={precision} waves per workgroup {w}", flush=True)
+        res[w] = run(P, tab, faces, U0s, levs, dts, precision, w)
+    for w in WPB[1:]:
+        assert np.array_equal(res[w][0], res[1][0]), w
+        assert np.array_equal(res[w][1], res[1][1]), w
+    if precision == 0:
+        Ug, off = res[1][0], 0
+        for f, U0, lev, dt in zip(faces, U0s, levs, dts):
+            t = oracle.Tableau(tab["order"], tab["c"], tab["b"], tab["a_sub"], tab["E"])
+            Uref, _, _ = oracle.run(oracle.Mesh(f), t, lev, U0, dt, 3)
+            ne = U0.shape[1]
+            assert rel_err(Ug[:, off:off + ne], Uref) < 1e-12
+            off += ne
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_3d_states_identical_for_every_workgroup_size(P, precision):
+    from tests.helpers import problem_3d
+    f, U0, tab, dt, lev = problem_3d(levels="random")
+    res = {}
+    for w in WPB:
+        print(f"case 3d precision={precision} waves per workgroup {w}", flush=True)
+        res[w] = run(P, tab, [f], [U0], [lev], [dt], precision, w, nsteps=2)
+    for w in WPB[1:]:
+        assert np.array_equal(res[w][0], res[1][0]), w
+        assert np.array_equal(res[w][1], res[1][1]), w
