@@ -911,11 +911,26 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     const int epb = (int)(blockDim.x >> 6) * EPW;
     const int li0 = xcd_block(blockIdx.x, gridDim.x) * epb + wave * EPW;  // the wavefront's first entry
     const bool valid = li0 + es < a.n_active;
-    // the active entries {element | level, case, nbr 0, nbr 1}, {nbr 2 .. nbr 5}
-    // and the coefficient table, loaded by a few lanes
-    const int4 part = wave_entry_part<EPW>(a.active, li0, a.n_active, lane);
-    const double cf = KIND != SK_FIRST ? wave_coef_table(coef, lane) : 0.0;
-    const int4 act = shfl4(part, 2 * es), act2 = shfl4(part, 2 * es + 1);
+    // Single-precision stages (bound by the vector memory path) load the active
+    // entries {element | level, case, nbr 0, nbr 1}, {nbr 2 .. nbr 5}, the
+    // coefficient table, dt and the metric with a few lanes and broadcast them,
+    // and take a neighbour in the workgroup from LDS; double-precision stages
+    // (bound by their arithmetic, where the broadcasts and the second path
+    // would lengthen each wavefront) load them per lane.
+    constexpr bool WL = sizeof(T) == 4;
+    constexpr bool LOCAL = WL && DIM == 2;
+    const int4 part = WL ? wave_entry_part<EPW>(a.active, li0, a.n_active, lane) : make_int4(0, 0, 0, 0);
+    const double cf = (WL && KIND != SK_FIRST) ? wave_coef_table(coef, lane) : 0.0;
+    int4 act, act2;
+    if constexpr (WL) {
+        act = shfl4(part, 2 * es);
+        act2 = shfl4(part, 2 * es + 1);
+    } else {
+        const int4 *ap = reinterpret_cast<const int4 *>(a.active);
+        const uint32_t ai = (uint32_t)(valid ? li0 + es : a.n_active - 1);
+        act = elt(ap, 2u * ai);
+        act2 = elt(ap, 2u * ai + 1u);
+    }
     const int e = (int)((uint32_t)act.x & PERRK_NBR_MASK);
     const int lvl = (int)((uint32_t)act.x >> PERRK_NBR_SHIFT);
     T *slot = lds + (size_t)eslot * SLOT;
@@ -923,11 +938,12 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     int bad = 0;
 
     // ---- loads
-    const SlotVals<DIM, EPW> sv = wave_slot_vals<DIM, EPW, KIND != SK_FIRST>(a, part, lane);
+    SlotVals<DIM, EPW> sv{};
+    if constexpr (WL) sv = wave_slot_vals<DIM, EPW, KIND != SK_FIRST>(a, part, lane);
     double c1 = 0.0, cp = 0.0;
     if (KIND != SK_FIRST) {
-        c1 = __shfl(cf, lvl);
-        cp = __shfl(cf, PERRK_MAXR + lvl);
+        c1 = WL ? __shfl(cf, lvl) : elt(coef, (uint32_t)lvl);
+        cp = WL ? __shfl(cf, PERRK_MAXR + lvl) : elt(coef, (uint32_t)(PERRK_MAXR + lvl));
     }
     NodeRaw<V, KT> own;
     load_raw<DIM, KT, KIND>(a, e, node, own);
@@ -963,7 +979,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
                                             : sel4<int>(f - 2, act2.x, act2.y, act2.z, act2.w));
         const int nb = (int)(w & PERRK_NBR_MASK);
         lk[r] = -1;
-        if constexpr (DIM == 2) {
+        if constexpr (LOCAL) {
             // 2D lists record the neighbour's list position relative to the entry's
             const int code = (int)(((uint32_t)act2.w >> (6 * f)) & 63u);
             const int t = eslot + code - 31;
@@ -975,14 +991,22 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         ncp[r] = 0.0;
         if (KIND != SK_FIRST) {
             const int lv = (int)(w >> PERRK_NBR_SHIFT);
-            nc1[r] = __shfl(cf, lv);
-            ncp[r] = __shfl(cf, PERRK_MAXR + lv);
+            nc1[r] = WL ? __shfl(cf, lv) : elt(coef, (uint32_t)lv);
+            ncp[r] = WL ? __shfl(cf, PERRK_MAXR + lv) : elt(coef, (uint32_t)(PERRK_MAXR + lv));
         }
         if (lk[r] < 0) load_raw<DIM, KT, KIND>(a, nb, nnr[r], nr[r]);
     }
-    double dt;
+    double dt = 0.0;
     ElemInfo ei;
-    slot_value<DIM, EPW>(sv, es, dt, ei);
+    if constexpr (WL) {
+        slot_value<DIM, EPW>(sv, es, dt, ei);
+    } else {
+        if (KIND != SK_FIRST) dt = elt(a.cs, (uint32_t)act.y).dt;
+        const ElemInfo &eg = elt(a.elem, (uint32_t)e);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ei.metric[d] = d < DIM ? eg.metric[d] : 0.0;
+        ei.jac = eg.jac;
+    }
 
     // ---- own stage state, published in LDS; neighbour states (same case, hence
     // the same dt) kept in registers.  Single-precision stages form the states in
@@ -1017,7 +1041,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         }
         lds_put_prim<T, DIM>(slot, node, me);
     }
-    if constexpr (DIM == 2) {
+    if constexpr (LOCAL) {
         // every slot's state is published before any lane reads a neighbour's from
         // its slot (formed by the neighbour's own lanes with the same arithmetic);
         // slots are not written in the primitives' area after this point
