@@ -53,6 +53,7 @@ struct perrk_ctx {
     double *d_coef = nullptr;  // [S][2 * PERRK_MAXR]
     void *d_K1 = nullptr, *d_Ka = nullptr, *d_Kb = nullptr;
     double *d_k64_1 = nullptr, *d_k64_sm1 = nullptr;  // mixed: double copies of K_1 / K_{S-1} when b != 0
+    float *d_U32 = nullptr;  // mixed modes: U_n rounded to single precision (written by the first stage)
     double *d_d = nullptr, *d_ep = nullptr, *d_partial = nullptr, *d_H = nullptr, *d_dt = nullptr;
     int32_t *d_err = nullptr;
     float *d_mlp = nullptr;
@@ -291,7 +292,7 @@ void free_all(perrk_ctx *c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     void *dev[] = {c->d_elem, c->d_active, c->d_case_off, c->d_cs, c->d_coef, c->d_K1, c->d_Ka,
                    c->d_Kb, c->d_d, c->d_ep, c->d_partial, c->d_H, c->d_dt, c->d_err, c->d_mlp,
-                   c->d_k64_1, c->d_k64_sm1, c->d_grad};
+                   c->d_k64_1, c->d_k64_sm1, c->d_grad, c->d_U32};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     void *host[] = {c->h_dt, c->h_cs, c->h_err, c->h_H};
@@ -329,6 +330,8 @@ void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int
 {
     a = StageArgs{};
     a.U = u;
+    a.U32 = c->d_U32;
+    a.U32_out = i == 0 ? c->d_U32 : nullptr;
     a.elem = c->d_elem;
     a.cs = c->d_cs;
     a.err = c->d_err;
@@ -722,8 +725,12 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
                 const double cp = coef[(size_t)i * 2 * PERRK_MAXR + PERRK_MAXR + r];
                 const bool mixed = c->precision == PERRK_MIXED;
                 const bool last = (i == c->S - 1);
-                double be = 8.0;  // U_n
+                // single-precision stages after the first read U_n in single precision;
+                // the first stage writes that copy
+                const bool f32 = c->precision == PERRK_MIXED_ALL || (mixed && c->b[i] == 0.0);
+                double be = (i > 0 && f32) ? 4.0 : 8.0;  // U_n
                 if (i == 0) {
+                    if (c->precision != PERRK_FP64) be += 4.0;       // write its single-precision copy
                     be += kb;                                         // write K_1
                     if (mixed && c->b[0] != 0.0 && c->S > 1) be += 8.0;  // its double copy
                 } else {
@@ -806,6 +813,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipMalloc(&c->d_Kb, ks * M));
     HIPINIT(hipMalloc(&c->d_d, sizeof(double) * M));
     if (c->viscous) HIPINIT(hipMalloc(&c->d_grad, sizeof(double) * 8 * (size_t)c->nelem * c->npe));
+    if (c->precision != PERRK_FP64) HIPINIT(hipMalloc(&c->d_U32, sizeof(float) * M));
     if (c->precision == PERRK_MIXED) {
         if (c->b[0] != 0.0) HIPINIT(hipMalloc(&c->d_k64_1, sizeof(double) * M));
         if (c->S >= 3 && c->b[c->S - 2] != 0.0) HIPINIT(hipMalloc(&c->d_k64_sm1, sizeof(double) * M));

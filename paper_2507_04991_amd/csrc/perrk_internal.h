@@ -78,6 +78,8 @@ struct RelaxParams {
 // in device memory: coef[r] multiplies K_1, coef[PERRK_MAXR + r] multiplies K_{i-1}.
 struct StageArgs {
     const double *U;          // U_n (caller state)
+    const float *U32;         // U_n rounded to single precision (read by single-precision stages after the first)
+    float *U32_out;           // first stage: writes that copy (every element runs the first stage), or NULL
     const void *K1;           // K_1 (stage storage type)
     const void *Kp;           // K_{i-1}
     void *Kout;               // K_i (stage storage type); unused for the last stage

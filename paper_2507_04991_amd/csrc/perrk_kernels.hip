@@ -35,6 +35,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace {
 
 template <int DIM>
@@ -422,9 +424,12 @@ __device__ __forceinline__ double entropy_diff(const double *u, const double *du
 // depends only on the element index, so a lane issues all of them at once;
 // K_{i-1} is read even where its coefficient is zero (it may then hold stale
 // values, which the combination discards by selection, never by multiplication).
-template <int V, typename KT>
+// Single-precision stages after the first read U_n from its single-precision
+// copy (UT = float): they round U_n to single precision anyway, so the copy
+// gives the same bits with half the bytes.
+template <int V, typename KT, typename UT = double>
 struct NodeRaw {
-    double u[V];
+    UT u[V];
     KT k1[V], kp[V];
 };
 
@@ -470,15 +475,16 @@ __device__ __forceinline__ const T &elt(const T *base, uint32_t i)
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (uint32_t)sizeof(T));
 }
 
-template <int DIM, typename KT, int KIND>
-__device__ __forceinline__ void load_raw(const StageArgs &a, int e, int node, NodeRaw<Geo<DIM>::V, KT> &r)
+template <int DIM, typename KT, int KIND, typename UT>
+__device__ __forceinline__ void load_raw(const StageArgs &a, int e, int node, NodeRaw<Geo<DIM>::V, KT, UT> &r)
 {
     constexpr int NPE = Geo<DIM>::NPE, V = Geo<DIM>::V;
     const size_t field = (size_t)a.nelem * NPE;
     const uint32_t n = (uint32_t)e * NPE + node;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        r.u[v] = bload<double>(field_rsrc<double>(a.U, v, field), n * 8u);
+        if constexpr (sizeof(UT) == 4) r.u[v] = bload<float>(field_rsrc<float>(a.U32, v, field), n * 4u);
+        else r.u[v] = bload<double>(field_rsrc<double>(a.U, v, field), n * 8u);
         if (KIND != SK_FIRST) {
             r.k1[v] = bload<KT>(field_rsrc<KT>(a.K1, v, field), n * (uint32_t)sizeof(KT));
             r.kp[v] = bload<KT>(field_rsrc<KT>(a.Kp, v, field), n * (uint32_t)sizeof(KT));
@@ -504,8 +510,8 @@ __device__ __forceinline__ void combine(const NodeRaw<V, KT> &r, double dt, doub
 
 // The same in single precision (stages whose fluxes are single precision): U_n is
 // rounded first, the combination is formed in single precision.
-template <int V, typename KT, int KIND>
-__device__ __forceinline__ void combine_f32(const NodeRaw<V, KT> &r, double dt, double c1, double cp, float *u)
+template <int V, typename KT, int KIND, typename UT>
+__device__ __forceinline__ void combine_f32(const NodeRaw<V, KT, UT> &r, double dt, double c1, double cp, float *u)
 {
     const float fdt = (float)dt, fc1 = (float)c1, fcp = (float)cp;
 #pragma unroll
@@ -819,10 +825,10 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
     }
 }
 
-// Adds (2/h_d) [sum_{m != t} Dsplit[t][m] f#(t, m) + lifted surface flux] of the
-// directions [d0, d0 + nd) to du (node lane).
+// Adds -(2/h_d) [sum_{m != t} Dsplit[t][m] f#(t, m) + lifted surface flux] of the
+// directions [d0, d0 + nd) to du (node lane); hn[d] = -(2/h_d) in flux precision.
 template <int DIM, typename T, int D0, int ND>
-__device__ __forceinline__ void gather(const T *slot, int node, const ElemInfo &ei, T *du)
+__device__ __forceinline__ void gather(const T *slot, int node, const T *hn, T *du)
 {
     constexpr int d0 = D0, nd = ND;
     constexpr int NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V, PRIM = SL<DIM, T>::PRIM;
@@ -851,9 +857,8 @@ __device__ __forceinline__ void gather(const T *slot, int node, const ElemInfo &
 #pragma unroll
             for (int v = 0; v < V; ++v) acc[v] += sf[v * NFN + q];
         }
-        const T h = (T)(d == 0 ? ei.metric[0] : (d == 1 ? ei.metric[1] : ei.metric[2]));
 #pragma unroll
-        for (int v = 0; v < V; ++v) du[v] += h * acc[v];
+        for (int v = 0; v < V; ++v) du[v] += hn[d] * acc[v];
     }
 }
 
@@ -945,7 +950,9 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         c1 = WL ? __shfl(cf, lvl) : elt(coef, (uint32_t)lvl);
         cp = WL ? __shfl(cf, PERRK_MAXR + lvl) : elt(coef, (uint32_t)(PERRK_MAXR + lvl));
     }
-    NodeRaw<V, KT> own;
+    // single-precision stages after the first read the single-precision copy of U_n
+    using UT = typename std::conditional<sizeof(T) == 4 && KIND != SK_FIRST, float, double>::type;
+    NodeRaw<V, KT, UT> own;
     load_raw<DIM, KT, KIND>(a, e, node, own);
     // last stage: the double-precision copies of K_1 / K_{S-1} that enter d are
     // loaded here too, so that their latency overlaps the flux work
@@ -968,7 +975,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     }
     FaceNode<DIM> F[FR];
     bool fv[FR];
-    NodeRaw<V, KT> nr[FR];
+    NodeRaw<V, KT, UT> nr[FR];
     double nc1[FR], ncp[FR];
     int nnr[FR], lk[FR];  // the neighbour's node; its element slot in this workgroup, else -1
 #pragma unroll
@@ -1041,6 +1048,15 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         }
         lds_put_prim<T, DIM>(slot, node, me);
     }
+    if constexpr (KIND == SK_FIRST) {
+        // the single-precision copy of U_n for the later single-precision stages
+        if (a.U32_out != nullptr && valid) {
+            const size_t field = (size_t)a.nelem * NPE;
+            const uint32_t o4 = ((uint32_t)e * NPE + node) * 4u;
+#pragma unroll
+            for (int v = 0; v < V; ++v) bstore<float>((float)own.u[v], field_rsrc<float>(a.U32_out, v, field), o4);
+        }
+    }
     if constexpr (LOCAL) {
         // every slot's state is published before any lane reads a neighbour's from
         // its slot (formed by the neighbour's own lanes with the same arithmetic);
@@ -1083,7 +1099,10 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         for (int v = 0; v < V; ++v) sf[v * NFN + F[r].q] = lift * fs[v];
     }
 
-    // ---- volume fluxes and the gather
+    // ---- volume fluxes and the gather, which sums K_i = -(volume + surface terms)
+    T hn[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) hn[d] = -(T)ei.metric[d];
     T du[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) du[v] = 0;
@@ -1091,19 +1110,19 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     if (weak) volume_pairs<DIM, T, 0, 2, true>(lds, wave, lane, inv_gm1);
     else volume_pairs<DIM, T, 0, 2, false>(lds, wave, lane, inv_gm1);
     wave_lds_sync();
-    gather<DIM, T, 0, 2>(slot, node, ei, du);
+    gather<DIM, T, 0, 2>(slot, node, hn, du);
     if constexpr (DIM == 3) {
         wave_lds_sync();
         if (weak) volume_pairs<DIM, T, 2, 1, true>(lds, wave, lane, inv_gm1);
         else volume_pairs<DIM, T, 2, 1, false>(lds, wave, lane, inv_gm1);
         wave_lds_sync();
-        gather<DIM, T, 2, 1>(slot, node, ei, du);
+        gather<DIM, T, 2, 1>(slot, node, hn, du);
     }
 
-    // K_i in double, and as stored
+    // K_i in double (for d, the double copy and the entropy production)
     double k[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) k[v] = -(double)du[v];
+    for (int v = 0; v < V; ++v) k[v] = (double)du[v];
 
     if (valid) {
         const size_t field = (size_t)a.nelem * NPE;
@@ -1122,7 +1141,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
                 if (a.d_has) dv += dacc[v];
                 bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
             } else {
-                bstore<KT>((KT)k[v], field_rsrc<KT>(a.Kout, v, field), ok);
+                bstore<KT>((KT)du[v], field_rsrc<KT>(a.Kout, v, field), ok);
                 if (a.k64_out) bstore<double>(k[v], field_rsrc<double>(a.k64_out, v, field), o8);
                 if (a.acc_mode) {
                     double dv = a.b_acc * k[v];
@@ -1140,7 +1159,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         double dot = 0.0;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const double kv = (KIND == SK_LAST || a.k64_out || sizeof(KT) == 8) ? k[v] : (double)(KT)k[v];
+            const double kv = (KIND == SK_LAST || a.k64_out || sizeof(KT) == 8) ? k[v] : (double)(KT)du[v];
             dot += w[v] * kv;
         }
         double sm = node_weight<DIM>(node) * dot;
