@@ -371,16 +371,18 @@ __device__ __forceinline__ void flux_diss(int kind, int d, const Prim<T, DIM> &L
 
 // Entropy variables of s = -rho log(p rho^-gamma):
 // w = (gamma - log(p rho^-gamma) - (gamma-1) rho |v|^2 / (2p), (gamma-1) rho v / p, -(gamma-1) rho / p).
+// (Reciprocals by rcp64: the stage epilogues form these per node, and correctly
+// rounded divisions would cost about as much as one logarithm.)
 template <int DIM>
 __device__ __forceinline__ void entropy_vars(const double *u, double gam, double *w)
 {
     const double rho = u[0];
-    const double ir = 1.0 / rho;
+    const double ir = rcp64(rho);
     double m2 = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) m2 += u[1 + k] * u[1 + k];
     const double p = (gam - 1.0) * (u[DIM + 1] - 0.5 * m2 * ir);
-    const double rp = rho / p;
+    const double rp = rho * rcp64(p);
     const double g1rp = (gam - 1.0) * rp;
     w[0] = gam - (log(p) - gam * log(rho)) - 0.5 * g1rp * m2 * ir * ir;
 #pragma unroll
