@@ -477,8 +477,11 @@ __device__ __forceinline__ const T &elt(const T *base, uint32_t i)
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (uint32_t)sizeof(T));
 }
 
+// kp_on = false skips the K_{i-1} loads (their coefficient is zero: the first
+// stage a level evaluates after the first).
 template <int DIM, typename KT, int KIND, typename UT>
-__device__ __forceinline__ void load_raw(const StageArgs &a, int e, int node, NodeRaw<Geo<DIM>::V, KT, UT> &r)
+__device__ __forceinline__ void load_raw(const StageArgs &a, int e, int node, NodeRaw<Geo<DIM>::V, KT, UT> &r,
+                                         bool kp_on = true)
 {
     constexpr int NPE = Geo<DIM>::NPE, V = Geo<DIM>::V;
     const size_t field = (size_t)a.nelem * NPE;
@@ -489,7 +492,7 @@ __device__ __forceinline__ void load_raw(const StageArgs &a, int e, int node, No
         else r.u[v] = bload<double>(field_rsrc<double>(a.U, v, field), n * 8u);
         if (KIND != SK_FIRST) {
             r.k1[v] = bload<KT>(field_rsrc<KT>(a.K1, v, field), n * (uint32_t)sizeof(KT));
-            r.kp[v] = bload<KT>(field_rsrc<KT>(a.Kp, v, field), n * (uint32_t)sizeof(KT));
+            r.kp[v] = kp_on ? bload<KT>(field_rsrc<KT>(a.Kp, v, field), n * (uint32_t)sizeof(KT)) : (KT)0;
         }
     }
 }
@@ -955,7 +958,9 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     // single-precision stages after the first read the single-precision copy of U_n
     using UT = typename std::conditional<sizeof(T) == 4 && KIND != SK_FIRST, float, double>::type;
     NodeRaw<V, KT, UT> own;
-    load_raw<DIM, KT, KIND>(a, e, node, own);
+    // single-precision stages have their level coefficients at hand already (from
+    // cross-lane reads) and skip K_{i-1} where its coefficient is zero
+    load_raw<DIM, KT, KIND>(a, e, node, own, !WL || cp != 0.0);
     // last stage: the double-precision copies of K_1 / K_{S-1} that enter d are
     // loaded here too, so that their latency overlaps the flux work
     double dacc[V];  // last stage: the contributions to d accumulated by earlier stages
@@ -1003,7 +1008,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
             nc1[r] = WL ? __shfl(cf, lv) : elt(coef, (uint32_t)lv);
             ncp[r] = WL ? __shfl(cf, PERRK_MAXR + lv) : elt(coef, (uint32_t)(PERRK_MAXR + lv));
         }
-        if (lk[r] < 0) load_raw<DIM, KT, KIND>(a, nb, nnr[r], nr[r]);
+        if (lk[r] < 0) load_raw<DIM, KT, KIND>(a, nb, nnr[r], nr[r], !WL || ncp[r] != 0.0);
     }
     double dt = 0.0;
     ElemInfo ei;
