@@ -830,10 +830,34 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
     }
 }
 
+// Gather table of the single-precision stages, one copy per wavefront in LDS
+// (16 words; lanes 0-15 copy it from here at the start): for each position t on
+// a line, Dsplit[t][(t + j) & 3] for j = 1, 2, 3 in single precision and the
+// three pair indices pair_k<j>(t) in 4-bit fields.  Each lane reads its row with
+// one LDS load per direction instead of forming six values by selection.
+constexpr uint32_t gtab_word(int i)
+{
+    const int t = i >> 2, j = i & 3;
+    if (j == 3) {
+        const int k1[4] = {0, 3, 5, 2}, k2[4] = {1, 4, 1, 4}, k3[4] = {2, 0, 3, 5};
+        return (uint32_t)(k1[t] | (k2[t] << 4) | (k3[t] << 8));
+    }
+    const float w[3][4] = {{(float)(5.0 * PHI), (float)SQ5, (float)PHI, (float)-1.0},
+                           {(float)(-5.0 * (PHI - 1.0)), (float)(-(PHI - 1.0)), (float)(PHI - 1.0),
+                            (float)(5.0 * (PHI - 1.0))},
+                           {(float)1.0, (float)(-PHI), (float)(-SQ5), (float)(-5.0 * PHI)}};
+    return __builtin_bit_cast(uint32_t, w[j][t]);
+}
+__device__ const uint32_t GATHER_TAB[16] = {
+    gtab_word(0), gtab_word(1), gtab_word(2),  gtab_word(3),  gtab_word(4),  gtab_word(5),  gtab_word(6),  gtab_word(7),
+    gtab_word(8), gtab_word(9), gtab_word(10), gtab_word(11), gtab_word(12), gtab_word(13), gtab_word(14), gtab_word(15)};
+constexpr int GTAB_WORDS = 16;
+
 // Adds -(2/h_d) [sum_{m != t} Dsplit[t][m] f#(t, m) + lifted surface flux] of the
-// directions [d0, d0 + nd) to du (node lane); hn[d] = -(2/h_d) in flux precision.
+// directions [d0, d0 + nd) to du (node lane); hn[d] = -(2/h_d) in flux precision;
+// tab: the wavefront's gather table (single precision only).
 template <int DIM, typename T, int D0, int ND>
-__device__ __forceinline__ void gather(const T *slot, int node, const T *hn, T *du)
+__device__ __forceinline__ void gather(const T *slot, int node, const T *hn, const T *tab, T *du)
 {
     constexpr int d0 = D0, nd = ND;
     constexpr int NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V, PRIM = SL<DIM, T>::PRIM;
@@ -849,8 +873,25 @@ __device__ __forceinline__ void gather(const T *slot, int node, const T *hn, T *
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[v] = 0;
         const int pb = dd * NPD + l * 6;
-        const int p1 = pb + pair_k<1>(t), p2 = pb + pair_k<2>(t), p3 = pb + pair_k<3>(t);
-        const T w1 = dsplit_j<T, 1>(t), w2 = dsplit_j<T, 2>(t), w3 = dsplit_j<T, 3>(t);
+        int p1, p2, p3;
+        T w1, w2, w3;
+        if constexpr (sizeof(T) == 4) {
+            const float4 row = *reinterpret_cast<const float4 *>(tab + 4 * t);
+            const uint32_t pk = __builtin_bit_cast(uint32_t, row.w);
+            w1 = row.x;
+            w2 = row.y;
+            w3 = row.z;
+            p1 = pb + (int)(pk & 15u);
+            p2 = pb + (int)((pk >> 4) & 15u);
+            p3 = pb + (int)(pk >> 8);
+        } else {
+            p1 = pb + pair_k<1>(t);
+            p2 = pb + pair_k<2>(t);
+            p3 = pb + pair_k<3>(t);
+            w1 = dsplit_j<T, 1>(t);
+            w2 = dsplit_j<T, 2>(t);
+            w3 = dsplit_j<T, 3>(t);
+        }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             acc[v] += w1 * vf[v * NPP + p1];
@@ -946,6 +987,9 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     T *slot = lds + (size_t)eslot * SLOT;
     const T inv_gm1 = (T)a.inv_gm1;
     int bad = 0;
+    // single precision: the wavefront's gather table after the workgroup's element slots
+    T *gtab = WL ? lds + (size_t)epb * SLOT + wave * GTAB_WORDS : nullptr;
+    const uint32_t gword = (WL && lane < GTAB_WORDS) ? elt(GATHER_TAB, (uint32_t)lane) : 0u;
 
     // ---- loads
     SlotVals<DIM, EPW> sv{};
@@ -1054,6 +1098,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
             }
         }
         lds_put_prim<T, DIM>(slot, node, me);
+        if (WL && lane < GTAB_WORDS) reinterpret_cast<uint32_t *>(gtab)[lane] = gword;
     }
     if constexpr (KIND == SK_FIRST) {
         // the single-precision copy of U_n for the later single-precision stages
@@ -1117,13 +1162,13 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     if (weak) volume_pairs<DIM, T, 0, 2, true>(lds, wave, lane, inv_gm1);
     else volume_pairs<DIM, T, 0, 2, false>(lds, wave, lane, inv_gm1);
     wave_lds_sync();
-    gather<DIM, T, 0, 2>(slot, node, hn, du);
+    gather<DIM, T, 0, 2>(slot, node, hn, gtab, du);
     if constexpr (DIM == 3) {
         wave_lds_sync();
         if (weak) volume_pairs<DIM, T, 2, 1, true>(lds, wave, lane, inv_gm1);
         else volume_pairs<DIM, T, 2, 1, false>(lds, wave, lane, inv_gm1);
         wave_lds_sync();
-        gather<DIM, T, 2, 1>(slot, node, hn, du);
+        gather<DIM, T, 2, 1>(slot, node, hn, gtab, du);
     }
 
     // K_i in double (for d, the double copy and the entropy production)
@@ -2620,7 +2665,8 @@ hipError_t launch_stage_t(const StageArgs &a, const double *coef, LaunchCfg cfg,
     const int epb = wpb * EPW;
     if (a.n_active <= 0) return hipSuccess;
     const int blocks = (a.n_active + epb - 1) / epb;
-    const size_t lds = (size_t)epb * SLOT * sizeof(T);
+    // single precision: the element slots, then one gather table per wavefront
+    const size_t lds = ((size_t)epb * SLOT + (sizeof(T) == 4 ? (size_t)wpb * GTAB_WORDS : 0)) * sizeof(T);
     hipLaunchKernelGGL((stage_kernel<DIM, T, KT, FLUX, KIND>), dim3(blocks), dim3(64 * wpb), lds, s, a, coef);
     return hipGetLastError();
 }
@@ -2693,9 +2739,9 @@ size_t stage_lds_bytes(int dim, int variant, int wpb, int sys)
 {
     if (sys == 1) return (size_t)wpb * 4 * MHD_SLOT * sizeof(double);
     if (sys == 2) return (size_t)wpb * 4 * NS_SLOT * sizeof(double);
-    if (variant == 1) {
-        if (dim == 2) return (size_t)wpb * SG<2>::EPW * SL<2, float>::SLOT * sizeof(float);
-        return (size_t)wpb * SG<3>::EPW * SL<3, float>::SLOT * sizeof(float);
+    if (variant == 1) {  // element slots and the wavefronts' gather tables
+        if (dim == 2) return (size_t)wpb * (SG<2>::EPW * SL<2, float>::SLOT + GTAB_WORDS) * sizeof(float);
+        return (size_t)wpb * (SG<3>::EPW * SL<3, float>::SLOT + GTAB_WORDS) * sizeof(float);
     }
     if (dim == 2) return (size_t)wpb * SG<2>::EPW * SL<2, double>::SLOT * sizeof(double);
     return (size_t)wpb * SG<3>::EPW * SL<3, double>::SLOT * sizeof(double);
