@@ -260,3 +260,31 @@ def test_mixed_precision_bounds(P, oracle, dim, precision):
     S = len(tab["c"])
     print("mixed step: max abs err", errU, "bound", S * dt * bound_K)
     assert errU <= S * dt * bound_K
+
+
+@pytest.mark.parametrize("dim,precision", [("2d", 1), ("3d", 1), ("2d", 2)])
+def test_mixed_step_follows_a_state_the_caller_replaced(P, oracle, dim, precision):
+    """Single-precision stages read U_n from a single-precision copy that the first
+    stage writes every step: after the caller overwrites u between two steps, the
+    second step starts from the new state (within the mixed-precision step bound
+    against the oracle's step from that state), not from the old copy."""
+    if dim == "2d":
+        f, U0, tab, dt, lev = problem_2d()
+        _, U1, _, _, _ = problem_2d(ic="random", seed=3)
+        ndim = 2
+    else:
+        f, U0, tab, dt, lev = problem_3d()
+        _, U1, _, _, _ = problem_3d(seed=5)
+        ndim = 3
+    st, u = make(P, f, U0, tab, lev, precision=precision)
+    st.step(u, dt)
+    u.copy_(torch.tensor(U1, dtype=torch.float64, device="cuda"))
+    info = st.step(u, dt)[0]
+    assert abs(info["r"]) <= 1e-12 and info["flags"] == 0
+    Uref, _ = oracle.step(omesh(oracle, f), otab(oracle, tab), lev, U1, dt)
+    from paper_2507_04991_amd import workloads as W
+    hmin = W.element_widths(f).min()
+    bound = len(tab["c"]) * dt * 32 * np.finfo(np.float32).eps * (2.0 / hmin) * flux_scale(U1, ndim)
+    errU = np.abs(u.cpu().numpy() - Uref).max()
+    print("replaced state, mixed step: max abs err", errU, "bound", bound)
+    assert errU <= bound
