@@ -476,7 +476,7 @@ int enqueue_step(perrk_ctx *c, double *u)
         for (int p = 0; p < c->opt.fast_passes; ++p) {
             HIPCHECK(c, mark_begin(c));
             HIPCHECK(c, launch_relax_pass(c->dim, c->sys, u, c->d_d, c->d_elem, c->d_cs, c->d_partial, c->nelem, c->gam,
-                                          c->stream));
+                                          p == 0, c->stream));
             HIPCHECK(c, mark_end(c, PERRK_K_RESIDUAL, c->pass_bytes));
             HIPCHECK(c, mark_begin(c));
             HIPCHECK(c, launch_relax_finalize(c->d_cs, c->d_case_off, c->n_cases, c->d_partial, c->rp, c->stream));

@@ -136,7 +136,7 @@ hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_ca
                                 const double *ep_partial, int64_t nelem, RelaxParams rp,
                                 const float *mlp, hipStream_t s);
 hipError_t launch_relax_pass(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
-                             const CaseState *cs, double *partial, int64_t nelem, double gam,
+                             const CaseState *cs, double *partial, int64_t nelem, double gam, bool first,
                              hipStream_t s);
 hipError_t launch_relax_finalize(CaseState *cs, const int64_t *case_off, int n_cases,
                                  const double *partial, RelaxParams rp, hipStream_t s);

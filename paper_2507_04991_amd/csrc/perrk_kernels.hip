@@ -2248,7 +2248,7 @@ struct Sys {
 
 // Per-element residual partials: J sum q Delta s at gamma, J sum q w(u + gamma dt d) . dt d,
 // J sum q Delta s at gamma_b (only while opening a bracket), sum |d|.
-template <int DIM, int SYS>
+template <int DIM, int SYS, bool PRELOAD = false>
 __device__ __forceinline__ void relax_element(const double *U, const double *dd, const ElemInfo *elem,
                                               const CaseState *cs, double *partial, int64_t nelem,
                                               double gam, int64_t e, int node, bool valid)
@@ -2260,18 +2260,25 @@ __device__ __forceinline__ void relax_element(const double *U, const double *dd,
     const bool live = valid && st != RS_DONE && st != RS_FALLBACK && st != RS_EVAL1;
     const bool eval1 = valid && st == RS_EVAL1;
     double sr = 0.0, srp = 0.0, srb = 0.0, sabs = 0.0;
-    if (live || eval1) {
-        const double g = eval1 ? 1.0 : C.gamma;
-        const double dt = C.dt;
-        double u[V], dv[V];
-        const size_t field = (size_t)nelem * NPE;
-        const uint32_t o8 = ((uint32_t)e * NPE + (uint32_t)node) * 8u;
+    // PRELOAD (the first pass of a step, where every case is being solved): the
+    // node loads are issued with the case-state loads instead of after them
+    double u[V], dv[V];
+    const size_t field = (size_t)nelem * NPE;
+    const uint32_t o8 = ((uint32_t)e * NPE + (uint32_t)node) * 8u;
+    auto load_node = [&]() {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             u[v] = bload<double>(field_rsrc<double>(U, v, field), o8);
             dv[v] = bload<double>(field_rsrc<double>(dd, v, field), o8);
-            sabs += fabs(dv[v]);
         }
+    };
+    if (PRELOAD) load_node();
+    if (live || eval1) {
+        const double g = eval1 ? 1.0 : C.gamma;
+        const double dt = C.dt;
+        if (!PRELOAD) load_node();
+#pragma unroll
+        for (int v = 0; v < V; ++v) sabs += fabs(dv[v]);
         const double q = node_weight<DIM>(node);
         double ds, wd;
         if constexpr (SYS == 1) relax_node_mhd(u, dv, g, dt, gam, ds, wd);
@@ -2479,7 +2486,7 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
     C.gamma_acc = 1.0;
 }
 
-template <int DIM, int SYS>
+template <int DIM, int SYS, bool FIRST>
 __global__ void __launch_bounds__(256)
 relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const CaseState *cs,
                   double *partial, int64_t nelem, double gam)
@@ -2492,20 +2499,22 @@ relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const 
     const int64_t eb = (int64_t)blk * (blockDim.x >> 6) * EPW;
     int64_t ee = eb + (int64_t)(blockDim.x >> 6) * EPW - 1;
     if (ee >= nelem) ee = nelem - 1;
-    if (threadIdx.x == 0) {
-        int live = 0;
-        for (int c = elem[eb].case_id; c <= elem[ee].case_id; ++c) {
-            const int st = cs[c].state;
-            live |= (st != RS_DONE && st != RS_FALLBACK);
+    if (!FIRST) {  // (in the first pass of a step every case is live)
+        if (threadIdx.x == 0) {
+            int live = 0;
+            for (int c = elem[eb].case_id; c <= elem[ee].case_id; ++c) {
+                const int st = cs[c].state;
+                live |= (st != RS_DONE && st != RS_FALLBACK);
+            }
+            s_live = live;
         }
-        s_live = live;
+        __syncthreads();
+        if (!s_live) return;
     }
-    __syncthreads();
-    if (!s_live) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t e0 = ((int64_t)blk * (blockDim.x >> 6) + wave) * EPW + lane / NPE;
     const bool valid = e0 < nelem;
-    relax_element<DIM, SYS>(U, d, elem, cs, partial, nelem, gam, valid ? e0 : nelem - 1, lane % NPE, valid);
+    relax_element<DIM, SYS, FIRST>(U, d, elem, cs, partial, nelem, gam, valid ? e0 : nelem - 1, lane % NPE, valid);
 }
 
 __global__ void __launch_bounds__(PERRK_RED_THREADS)
@@ -2779,21 +2788,25 @@ hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_ca
 }
 
 hipError_t launch_relax_pass(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
-                             const CaseState *cs, double *partial, int64_t nelem, double gam,
+                             const CaseState *cs, double *partial, int64_t nelem, double gam, bool first,
                              hipStream_t s)
 {
     const int epw = dim == 2 ? 4 : 1;
     const int64_t waves = (nelem + epw - 1) / epw;
     const int64_t blocks = (waves + 3) / 4;
-    if (sys == 1)
-        hipLaunchKernelGGL((relax_pass_kernel<2, 1>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
-                           partial, nelem, gam);
-    else if (dim == 2)
-        hipLaunchKernelGGL((relax_pass_kernel<2, 0>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
-                           partial, nelem, gam);
-    else
-        hipLaunchKernelGGL((relax_pass_kernel<3, 0>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, elem, cs,
-                           partial, nelem, gam);
+#define PERRK_PASS(D, SY)                                                                                   \
+    do {                                                                                                   \
+        if (first)                                                                                         \
+            hipLaunchKernelGGL((relax_pass_kernel<D, SY, true>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, \
+                               elem, cs, partial, nelem, gam);                                             \
+        else                                                                                               \
+            hipLaunchKernelGGL((relax_pass_kernel<D, SY, false>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, \
+                               elem, cs, partial, nelem, gam);                                             \
+    } while (0)
+    if (sys == 1) PERRK_PASS(2, 1);
+    else if (dim == 2) PERRK_PASS(2, 0);
+    else PERRK_PASS(3, 0);
+#undef PERRK_PASS
     return hipGetLastError();
 }
 
