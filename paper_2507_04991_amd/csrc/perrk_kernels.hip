@@ -424,8 +424,9 @@ __device__ __forceinline__ double entropy_diff(const double *u, const double *du
 
 // Raw data of one node for its stage state: U_n, K_1 and K_{i-1}.  Every load
 // depends only on the element index, so a lane issues all of them at once;
-// K_{i-1} is read even where its coefficient is zero (it may then hold stale
-// values, which the combination discards by selection, never by multiplication).
+// double-precision stages read K_{i-1} even where its coefficient is zero (it
+// may then hold stale values, which the combination discards by selection,
+// never by multiplication), single-precision stages skip it there.
 // Single-precision stages after the first read U_n from its single-precision
 // copy (UT = float): they round U_n to single precision anyway, so the copy
 // gives the same bits with half the bytes.
@@ -962,7 +963,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     const int epb = (int)(blockDim.x >> 6) * EPW;
     const int li0 = xcd_block(blockIdx.x, gridDim.x) * epb + wave * EPW;  // the wavefront's first entry
     const bool valid = li0 + es < a.n_active;
-    // Single-precision stages (bound by the vector memory path) load the active
+    // Single-precision stages (bound by memory latency as much as by arithmetic) load the active
     // entries {element | level, case, nbr 0, nbr 1}, {nbr 2 .. nbr 5}, the
     // coefficient table, dt and the metric with a few lanes and broadcast them,
     // and take a neighbour in the workgroup from LDS; double-precision stages
