@@ -213,7 +213,10 @@ int perrk_init(const perrk_mesh_desc *mesh, const perrk_partition_desc *part,
 
 /* One P-ERRK step of every case, in place on u_dev (FP64, layout above,
  * caller-owned).  dt: [n_cases] host array of step sizes (> 0).  Work is
- * enqueued on the context's stream.  info: [n_cases] host array or NULL; with
+ * enqueued on the context's stream.  Every step reads u_dev afresh (in the
+ * mixed modes its first stage also writes the library's single-precision copy
+ * of U_n that the later single-precision stages read), so the caller may
+ * change u_dev between steps.  info: [n_cases] host array or NULL; with
  * NULL the call does not synchronise (errors are then reported by the next
  * call that synchronises); with info the call waits for the step and fills it.
  * A step that forms a non-physical state leaves u_dev unmodified and returns
