@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--viscous", type=float, default=None, metavar="MU",
                     help="add the Navier-Stokes-Fourier terms (BR1, Pr 0.72) with viscosity MU (2D Euler workloads; "
                          "double precision)")
+    ap.add_argument("--tgv-n", type=int, default=32, metavar="N",
+                    help="elements per direction of the Taylor-Green mesh (64: 84 M DOF, beyond the Infinity Cache)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="time the mixed variant only")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -267,7 +269,8 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "seconds_per_copy": sec,
                           "GBps_read_plus_write": 2 * n * 8 / sec / 1e9}), flush=True)
         return
-    wl = {"ensemble": workload_ensemble, "tgv": workload_tgv, "alfven": workload_alfven}[args.workload]()
+    wl = {"ensemble": workload_ensemble, "tgv": lambda: workload_tgv(n=args.tgv_n),
+          "alfven": workload_alfven}[args.workload]()
     mhd = wl.get("system", 0) == 1
     if args.viscous is not None:
         if mhd or len(wl["faces"][0]) != 2:

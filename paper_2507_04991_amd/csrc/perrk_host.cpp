@@ -614,9 +614,13 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     // elements of a workgroup of PERRK_MAX_WPB wavefronts (4 quadrilaterals each)
     constexpr int ACT_TILE_X = 8, ACT_TILE_Y = 4;
     static_assert(ACT_TILE_X * ACT_TILE_Y == 4 * PERRK_MAX_WPB, "one tile per full workgroup");
+    // 3D lists visit each case mesh by cubes of ACT_TILE_3D^3 elements (x fastest
+    // inside a cube): a neighbour in y or z is then processed a few dozen
+    // elements before or after an element rather than a whole plane, so the
+    // face-node reads of neighbours mostly hit the XCD's L2.
+    constexpr int ACT_TILE_3D = 8;
     // active element list of every stage: stage i evaluates the levels with
-    // E >= S - i + 1, stage 1 every element.  3D lists follow the natural element
-    // order.  2D lists visit each case mesh by tiles of ACT_TILE_X x ACT_TILE_Y
+    // E >= S - i + 1, stage 1 every element.  2D lists visit each case mesh by tiles of ACT_TILE_X x ACT_TILE_Y
     // elements (row by row inside a tile), so that the 32 elements of a full
     // workgroup are mostly each other's face neighbours; nbr[5], which 2D meshes
     // do not need, then records for each face f (bits 6f .. 6f + 5) the
@@ -629,7 +633,14 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
         const int64_t base = c->case_off[cs];
         const int n0 = m->n_elem_dir[3 * cs], n1 = m->n_elem_dir[3 * cs + 1];
         if (m->dim == 3) {
-            for (int64_t e = base; e < c->case_off[cs + 1]; ++e) visit.push_back(e);
+            const int n2 = m->n_elem_dir[3 * cs + 2];
+            for (int tz = 0; tz < n2; tz += ACT_TILE_3D)
+                for (int ty = 0; ty < n1; ty += ACT_TILE_3D)
+                    for (int tx = 0; tx < n0; tx += ACT_TILE_3D)
+                        for (int iz = tz; iz < std::min(tz + ACT_TILE_3D, n2); ++iz)
+                            for (int iy = ty; iy < std::min(ty + ACT_TILE_3D, n1); ++iy)
+                                for (int ix = tx; ix < std::min(tx + ACT_TILE_3D, n0); ++ix)
+                                    visit.push_back(base + ix + (int64_t)n0 * (iy + (int64_t)n1 * iz));
             continue;
         }
         for (int ty = 0; ty < n1; ty += ACT_TILE_Y)
