@@ -82,6 +82,8 @@ def lib():
         for fn in ("or_mhd_flux_ec", "or_mhd_flux_llf", "or_mhd_flux_central"):
             getattr(_lib, fn).argtypes = [i, p, p, d, d, p]
         _lib.or_mhd_nonconservative.argtypes = [i, p, d, p, p]
+        _lib.or_mhd_cfast.restype = d
+        _lib.or_mhd_cfast.argtypes = [i, p, d]
         _lib.or_mhd_entropy.restype = d
         _lib.or_mhd_entropy.argtypes = [p, d]
         _lib.or_mhd_entropy_vars.argtypes = [p, d, p]
@@ -191,6 +193,11 @@ def mhd_flux_llf(direction, uL, uR, gam=1.4, c_h=0.0):
 
 def mhd_flux_central(direction, uL, uR, gam=1.4, c_h=0.0):
     return _mhd2("or_mhd_flux_central", direction, uL, uR, gam, c_h)
+
+
+def mhd_cfast(direction, u, gam=1.4) -> float:
+    """Fast magnetosonic speed in direction n (the LLF wave speed of GLM-MHD)."""
+    return lib().or_mhd_cfast(direction, _ptr(_f64(u)), gam)
 
 
 def mhd_nonconservative(direction, u, gam=1.4):

@@ -475,7 +475,7 @@ void or_mhd_flux_ec(int dir, const double *uL, const double *uR, double gam, dou
 /* Fast magnetosonic speed in direction n:
  *   c_f^2 = (a^2 + |B|^2/rho + sqrt((a^2 + |B|^2/rho)^2 - 4 a^2 B_n^2/rho)) / 2,
  * a^2 = gamma p / rho. */
-static double or_mhd_cfast(int dir, const double *u, double gam)
+double or_mhd_cfast(int dir, const double *u, double gam)
 {
     double rho, v[3], p, B[3], psi;
     or_mhd_prim(u, gam, &rho, v, &p, B, &psi);

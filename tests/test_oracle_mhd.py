@@ -199,3 +199,76 @@ def test_alfven_run_converges(oracle):
         J = (w[:, 0] * w[:, 1] / 4.0)[:, None] * np.outer(q1, q1).reshape(1, 16)
         errs.append(float((np.abs(U[5] - Ue[5]) * J).sum()) / 2.0)
     assert math.log2(errs[0] / errs[1]) > 2.5, errs
+
+
+def _prim_state(rho, v, p, B, psi=0.0, gam=G):
+    v, B = np.asarray(v, float), np.asarray(B, float)
+    return np.concatenate([[rho], rho * v, [p / (gam - 1) + 0.5 * rho * v @ v + 0.5 * B @ B + 0.5 * psi ** 2], B,
+                           [psi]])
+
+
+def test_fast_speed_limits(oracle):
+    """The fast magnetosonic speed of the LLF flux (Sec. 4.3.3) in its three
+    closed-form limits: no field gives the sound speed a = sqrt(gamma p / rho); a
+    field normal to the direction gives c_f^2 = a^2 + |B|^2 / rho; a field along
+    the direction gives max(a, |B_n| / sqrt(rho)).  A sound-speed-only or a
+    normal-component-only speed fails the second limit."""
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        rho, p = rng.uniform(0.3, 3.0), rng.uniform(0.1, 3.0)
+        v = rng.uniform(-1, 1, 3)
+        a = math.sqrt(G * p / rho)
+        for d in range(3):
+            assert abs(oracle.mhd_cfast(d, _prim_state(rho, v, p, [0, 0, 0]), G) - a) <= 1e-14 * a
+            B = rng.uniform(-2, 2, 3)
+            B[d] = 0.0
+            cf = oracle.mhd_cfast(d, _prim_state(rho, v, p, B), G)
+            ref = math.sqrt(a * a + (B @ B) / rho)
+            assert abs(cf - ref) <= 1e-14 * ref, (cf, ref)
+            Bn = np.zeros(3)
+            Bn[d] = rng.uniform(-3, 3)
+            cf = oracle.mhd_cfast(d, _prim_state(rho, v, p, Bn), G)
+            ref = max(a, abs(Bn[d]) / math.sqrt(rho))
+            assert abs(cf - ref) <= 1e-13 * ref, (cf, ref)
+
+
+def test_fast_speed_is_largest_characteristic_speed(oracle):
+    """v_n +- c_f are the extreme eigenvalues of the quasi-linear form of the
+    system in direction n (flux Jacobian plus the Powell and GLM terms
+    Phi e_{B_n}^T + Phi_n e_psi^T, cleaning speed 0), here from a central
+    finite-difference Jacobian of the oracle's physical flux: the eigenvalues
+    are real (the system is hyperbolic) and the largest and smallest are
+    v_n + c_f and v_n - c_f."""
+    rng = np.random.default_rng(12)
+    for gam in (G, 5.0 / 3.0):
+        for _ in range(12):
+            rho, p = rng.uniform(0.4, 2.0), rng.uniform(0.2, 2.0)
+            u = _prim_state(rho, rng.normal(size=3), p, rng.normal(size=3), 0.0, gam)
+            for d in range(3):
+                A = np.zeros((9, 9))
+                for k in range(9):
+                    h = 1e-6 * max(1.0, abs(u[k]))
+                    e = np.zeros(9)
+                    e[k] = h
+                    A[:, k] = (oracle.mhd_flux_phys(d, u + e, gam, 0.0) - oracle.mhd_flux_phys(d, u - e, gam, 0.0)) / (2 * h)
+                phi, phin = oracle.mhd_nonconservative(d, u, gam)
+                A[:, 5 + d] += phi
+                A[:, 8] += phin
+                ev = np.linalg.eigvals(A)
+                vn, cf = u[1 + d] / u[0], oracle.mhd_cfast(d, u, gam)
+                assert np.abs(ev.imag).max() < 1e-6
+                assert abs(ev.real.max() - (vn + cf)) < 1e-7 * (abs(vn) + cf)
+                assert abs(ev.real.min() - (vn - cf)) < 1e-7 * (abs(vn) + cf)
+
+
+def test_llf_dissipation_speed_is_fast_speed(oracle):
+    """The LLF flux differs from the central flux by -lambda (u_R - u_L) / 2 with
+    lambda = max(|v_n| + c_f) of the two sides, read back component by component."""
+    rng = np.random.default_rng(13)
+    for _ in range(30):
+        uL, uR = rand_mhd(rng), rand_mhd(rng)
+        for d in range(3):
+            diff = oracle.mhd_flux_llf(d, uL, uR, G, 0.6) - oracle.mhd_flux_central(d, uL, uR, G, 0.6)
+            lam = max(abs(uL[1 + d] / uL[0]) + oracle.mhd_cfast(d, uL, G),
+                      abs(uR[1 + d] / uR[0]) + oracle.mhd_cfast(d, uR, G))
+            assert np.allclose(diff, -0.5 * lam * (uR - uL), rtol=1e-12, atol=1e-13)
