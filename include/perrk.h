@@ -114,9 +114,11 @@ typedef struct {
     int32_t dim;               /* 2 or 3 */
     int32_t n_cases;           /* >= 1: independent meshes advanced together */
     const int32_t *n_elem_dir; /* [n_cases][3] elements per direction, >= 2 each (third = 1 in 2D);
-                                  all cases together at most 2^29 nodes (elements x 4^dim), so
-                                  that the byte offset of a node in one field fits in 32 bits:
-                                  33.5 M quadrilaterals or 8.4 M hexahedra */
+                                  all cases together fewer than 2^29 nodes (elements x 4^dim),
+                                  so that an FP64 field spans less than 4 GiB and the byte
+                                  offset of a node in it fits in 32 bits: at most 2^25 - 1
+                                  quadrilaterals or 2^23 - 1 hexahedra; larger meshes are
+                                  rejected with PERRK_EINVAL */
     const double *face_coords; /* per case, per direction: n+1 increasing face positions, concatenated;
                                   the domain is periodic in every direction */
     double gas_gamma;          /* ratio of specific heats (> 1) */

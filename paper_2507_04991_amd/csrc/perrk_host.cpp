@@ -203,8 +203,8 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
         total += ne;
     }
     const int64_t npe = m->dim == 2 ? 16 : 64;
-    if (total * npe > ((int64_t)1 << 29))
-        return ck.bad("too many nodes (%lld elements x %lld > 2^29)", (long long)total, (long long)npe);
+    if (!perrk_node_count_ok(total * npe))
+        return ck.bad("too many nodes (%lld elements x %lld >= 2^29)", (long long)total, (long long)npe);
     const int S = t->S, R = t->n_levels;
     if (t->order < 2 || t->order > 4) return ck.bad("order must be 2, 3 or 4");
     if (S < 2 || S > PERRK_MAXS) return ck.bad("S must be in 2..%d", PERRK_MAXS);

@@ -15,6 +15,24 @@
 #define PERRK_RED_THREADS 1024  // block size of every per-case reduction (fixed: results depend on it)
 #define PERRK_MLP_NW 1377
 
+// Node arrays are addressed by buffer instructions with one 32-bit byte range
+// per field.  An FP64 field of n nodes spans 8 n bytes, so every case together
+// must hold fewer than 2^29 nodes: at exactly 2^29 the range 2^32 no longer
+// fits 32 bits.  The host rejects larger meshes (perrk_node_count_ok); the
+// kernels build ranges with perrk_buffer_range, which saturates rather than
+// wraps, so even a range computed past the limit never reads as zero.
+#define PERRK_MAX_NODES (((int64_t)1 << 29) - 1)
+
+__host__ __device__ constexpr bool perrk_node_count_ok(int64_t nodes)
+{
+    return nodes >= 0 && nodes <= PERRK_MAX_NODES;
+}
+
+__host__ __device__ constexpr uint32_t perrk_buffer_range(uint64_t elems, uint64_t elem_bytes)
+{
+    return elems * elem_bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)(elems * elem_bytes);
+}
+
 // Per-element geometry and bookkeeping (natural element order, all cases).
 struct ElemInfo {
     int32_t nbr[6];     // periodic neighbours -x, +x, -y, +y, -z, +z: global element index in

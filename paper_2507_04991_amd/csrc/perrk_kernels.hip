@@ -440,7 +440,8 @@ struct NodeRaw {
 // field (base = array + v * field, range = the field's bytes; scalar registers)
 // and one 32-bit byte offset per lane, shared by every field and array of the
 // same element size, so an access costs no vector address arithmetic.  The
-// node count of all cases is limited to 2^29, so a field spans less than 4 GiB.
+// node count of all cases stays below 2^29 (PERRK_MAX_NODES), so an FP64 field
+// spans less than 4 GiB and every lane offset fits 32 bits.
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
 constexpr int RSRC_WORD3 = 0x00020000;  // word 3 of a raw gfx9 buffer resource: 32-bit data format
@@ -449,7 +450,7 @@ template <typename T>
 __device__ __forceinline__ Rsrc field_rsrc(const void *base, int v, size_t field)
 {
     T *p = const_cast<T *>(static_cast<const T *>(base)) + (size_t)v * field;
-    return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)(uint32_t)(field * sizeof(T)), RSRC_WORD3);
+    return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)perrk_buffer_range(field, sizeof(T)), RSRC_WORD3);
 }
 
 template <typename T>

@@ -117,18 +117,27 @@ def test_validate_viscous_descriptors():
 
 
 def test_validate_node_limit_and_case_count():
-    """All cases together may hold at most 2^29 nodes (a field of a node array then
-    fits a 32-bit byte offset): exactly 2^29 is accepted, one layer more rejected;
-    no cases at all is rejected."""
+    """All cases together must hold fewer than 2^29 nodes, so that an FP64 field of
+    a node array spans less than 4 GiB and its byte range fits a 32-bit buffer
+    descriptor (at exactly 2^29 it would wrap to 0).  2D meshes of 2^25 - 1, 2^25
+    and 2^25 + 1 quadrilaterals (2^29 - 16, 2^29 and 2^29 + 16 nodes): the first is
+    accepted, the other two rejected; a 3D mesh of 2^23 hexahedra (2^29 nodes) is
+    rejected too; no cases at all is rejected."""
     from paper_2507_04991_amd import tableau as T
     tab = T.get_tableau(2, [3, 6])
-    for nz, ok in ((2, True), (3, False)):
-        f = [W.uniform_faces(2048, 0, 1), W.uniform_faces(2048, 0, 1), W.uniform_faces(nz, 0, 1)]
-        lev = np.zeros(2048 * 2048 * nz, dtype=np.int32)
+    # 2^25 - 1 = 18631 * 1801, 2^25 = 4096 * 8192, 2^25 + 1 = 8283 * 4051
+    for (nx, ny), ok in (((18631, 1801), True), ((4096, 8192), False), ((8283, 4051), False)):
+        assert nx * ny * 16 - (1 << 29) in ((-16,) if ok else (0, 16))
+        f = [W.uniform_faces(nx, 0, 1), W.uniform_faces(ny, 0, 1)]
+        lev = np.zeros(nx * ny, dtype=np.int32)
         st, msg = P.Descriptors([f], [lev], tab).validate()
-        assert (st == P.OK) == ok, msg
+        assert (st == P.OK) == ok, (nx, ny, msg)
         if not ok:
             assert "2^29" in msg, msg
+        del lev
+    f = [W.uniform_faces(2048, 0, 1), W.uniform_faces(2048, 0, 1), W.uniform_faces(2, 0, 1)]
+    st, msg = P.Descriptors([f], [np.zeros(2048 * 2048 * 2, dtype=np.int32)], tab).validate()
+    assert st == P.EINVAL and "2^29" in msg, msg
     d = desc()
     d.mesh.n_cases = 0
     assert d.validate()[0] == P.EINVAL
