@@ -219,28 +219,47 @@ int perrk_init(const perrk_mesh_desc *mesh, const perrk_partition_desc *part,
  * mixed modes its first stage also writes the library's single-precision copy
  * of U_n that the later single-precision stages read), so the caller may
  * change u_dev between steps.  info: [n_cases] host array or NULL; with
- * NULL the call does not synchronise (errors are then reported by the next
- * call that synchronises); with info the call waits for the step and fills it.
- * A step that forms a non-physical state leaves u_dev unmodified and returns
- * PERRK_ENONPHYS or PERRK_ENONFINITE (when it synchronises). */
+ * NULL the call does not synchronise; with info the call waits for the step
+ * and fills it.  A step that forms a non-physical (rho <= 0 or p <= 0) or
+ * non-finite stage state in any case is rejected: u_dev is left unmodified
+ * and so is the state carried to the next step (t, gamma history, entropy
+ * offset; see perrk_get_relaxation_state).  A step with info reports its own
+ * rejection as PERRK_ENONPHYS or PERRK_ENONFINITE; the rejection of a step
+ * called with info = NULL is reported, with the same codes, by the next step
+ * called with info (whose own result is then valid and in info; the message
+ * says which step failed).  Each step starts afresh: an earlier rejection
+ * never makes a later step skip its update. */
 int perrk_step(perrk_ctx *ctx, void *u_dev, const double *dt, perrk_step_info *info);
 
 /* H[c] = discrete total entropy of case c of u_dev: sum over elements of
- * J_e sum_nodes q s(u) (Sec. 2.3).  Synchronises.  H: [n_cases] host. */
+ * J_e sum_nodes q s(u) (Sec. 2.3).  Synchronises.  H: [n_cases] host.
+ * Returns PERRK_ENONPHYS if a node has rho <= 0 or p <= 0, PERRK_ENONFINITE
+ * if a node or a sum is not finite (H is still written); such an error
+ * concerns this call only and never affects a later step. */
 int perrk_entropy(perrk_ctx *ctx, const void *u_dev, double *H);
 
 /* k_dev = F(u_dev) on every element: the semidiscretisation the stages
  * evaluate.  k_dev has the stage storage type: double (FP64) or float
  * (MIXED, MIXED_ALL: single-precision fluxes), same layout as u_dev.
- * Asynchronous on the context's stream. */
+ * Asynchronous on the context's stream.  A non-physical u_dev is not
+ * reported (k_dev then holds whatever the fluxes give) and never affects a
+ * later step. */
 int perrk_rhs(perrk_ctx *ctx, const void *u_dev, void *k_dev);
 
-/* Previous accepted gamma per case (the Newton starting value) and the
- * accumulated entropy offset H(U_n) - H(U_0) used by PERRK_ANCHOR_INITIAL:
- * read or restore (checkpoint / resume).  Arrays are [n_cases] host. */
-int perrk_get_relaxation_state(perrk_ctx *ctx, double *gamma_prev, double *h_offset, double *t);
+/* Per-case state that one step hands to the next: the previous accepted gamma
+ * (the Newton starting value), the accumulated entropy offset H(U_n) - H(U_0)
+ * used by PERRK_ANCHOR_INITIAL, the relaxed time t, the last three accepted
+ * gamma - 1 (most recent first; features of the learned guess) and the number
+ * of accepted steps (the learned guess is used from the fourth step on).
+ * Read or restore (checkpoint / resume: a context restored from these values
+ * continues bitwise as the one they were read from).  Host arrays, each may be
+ * NULL (not read / not changed): gamma_prev, h_offset, t, n_steps [n_cases],
+ * gamma_hist [n_cases][3].  Set: gamma_prev must be finite and > 0 and
+ * n_steps >= 0, else PERRK_EINVAL with nothing changed.  Both synchronise. */
+int perrk_get_relaxation_state(perrk_ctx *ctx, double *gamma_prev, double *h_offset, double *t,
+                               double *gamma_hist, int32_t *n_steps);
 int perrk_set_relaxation_state(perrk_ctx *ctx, const double *gamma_prev, const double *h_offset,
-                               const double *t);
+                               const double *t, const double *gamma_hist, const int32_t *n_steps);
 
 /* Learned initial guess (guess = PERRK_GUESS_MLP): a multilayer perceptron
  * 8 -> 32 -> 32 -> 1 (tanh hidden layers), float32.  weights: 1379 values, the

@@ -334,7 +334,7 @@ void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int
     a.U32_out = i == 0 ? c->d_U32 : nullptr;
     a.elem = c->d_elem;
     a.cs = c->d_cs;
-    a.err = c->d_err;
+    a.err = c->d_err + ERR_STEP;
     a.nelem = c->nelem;
     a.gam = c->gam;
     a.gm1 = c->gam - 1.0;
@@ -458,6 +458,7 @@ int autotune(perrk_ctx *c, double *u)
 // Enqueues one full step on ctx->stream (no host synchronisation).
 int enqueue_step(perrk_ctx *c, double *u)
 {
+    HIPCHECK(c, launch_clear_err(c->d_err + ERR_STEP, 1, c->stream));
     for (int i = 0; i < c->S; ++i) {
         StageArgs a;
         int variant = 0, kind = 0;
@@ -485,7 +486,7 @@ int enqueue_step(perrk_ctx *c, double *u)
     }
     HIPCHECK(c, mark_begin(c));
     HIPCHECK(c, launch_relax_complete(c->dim, c->sys, u, c->d_d, c->d_elem, c->d_cs, c->d_case_off, c->n_cases,
-                                      c->d_partial, c->nelem, c->gam, c->rp, c->stream));
+                                      c->d_partial, c->nelem, c->gam, c->rp, c->d_err, c->stream));
     HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
     HIPCHECK(c, mark_begin(c));
     HIPCHECK(c, launch_final_update(c->dim, c->sys, u, c->d_d, c->d_elem, c->d_cs, c->d_err, c->nelem, c->stream));
@@ -833,11 +834,11 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipMalloc(&c->d_partial, sizeof(double) * 4 * c->nelem));
     HIPINIT(hipMalloc(&c->d_H, sizeof(double) * c->n_cases));
     HIPINIT(hipMalloc(&c->d_dt, sizeof(double) * c->n_cases * perrk_ctx::NRING));
-    HIPINIT(hipMalloc(&c->d_err, sizeof(int32_t)));
+    HIPINIT(hipMalloc(&c->d_err, sizeof(int32_t) * ERR_WORDS));
     HIPINIT(hipMalloc(&c->d_mlp, sizeof(float) * (PERRK_MLP_NW + 18)));
     HIPINIT(hipHostMalloc(&c->h_dt, sizeof(double) * c->n_cases * perrk_ctx::NRING, 0));
     HIPINIT(hipHostMalloc(&c->h_cs, sizeof(CaseState) * c->n_cases, 0));
-    HIPINIT(hipHostMalloc(&c->h_err, sizeof(int32_t), 0));
+    HIPINIT(hipHostMalloc(&c->h_err, sizeof(int32_t) * ERR_WORDS, 0));
     HIPINIT(hipHostMalloc(&c->h_H, sizeof(double) * c->n_cases, 0));
     HIPINIT(hipMemcpyAsync(c->d_elem, elem.data(), sizeof(ElemInfo) * c->nelem, hipMemcpyHostToDevice, c->stream));
     HIPINIT(hipMemcpyAsync(c->d_active, order.data(), sizeof(ActiveEntry) * order.size(), hipMemcpyHostToDevice,
@@ -846,7 +847,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
                            hipMemcpyHostToDevice, c->stream));
     HIPINIT(hipMemcpyAsync(c->d_coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, c->stream));
     HIPINIT(launch_init_cases(c->d_cs, c->n_cases, c->stream));
-    HIPINIT(launch_clear_err(c->d_err, c->stream));
+    HIPINIT(launch_clear_err(c->d_err, ERR_WORDS, c->stream));
     HIPINIT(hipStreamSynchronize(c->stream));
 #undef HIPINIT
     *out = c;
@@ -937,7 +938,7 @@ int perrk_step(perrk_ctx *c, void *u_dev, const double *dt, perrk_step_info *inf
     HIPCHECK(c, hipStreamWaitEvent(c->user_stream, c->ev_out, 0));
     if (!info) return PERRK_OK;
     HIPCHECK(c, hipMemcpyAsync(c->h_cs, c->d_cs, sizeof(CaseState) * c->n_cases, hipMemcpyDeviceToHost, c->stream));
-    HIPCHECK(c, hipMemcpyAsync(c->h_err, c->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->h_err, c->d_err, sizeof(int32_t) * ERR_WORDS, hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     int status = PERRK_OK;
     for (int i = 0; i < c->n_cases; ++i) {
@@ -953,12 +954,18 @@ int perrk_step(perrk_ctx *c, void *u_dev, const double *dt, perrk_step_info *inf
         I.flags = C.flags;
         if (C.flags & PERRK_FLAG_FALLBACK) status = PERRK_WARN_FALLBACK;
     }
-    if (*c->h_err) {
-        const int e = *c->h_err;
-        HIPCHECK(c, launch_clear_err(c->d_err, c->stream));
+    // err[ERR_PENDING] holds this step's error and those of earlier steps that
+    // did not synchronise; reporting clears it
+    const int e_now = c->h_err[ERR_STEP], e_all = c->h_err[ERR_PENDING];
+    if (e_all) {
+        HIPCHECK(c, launch_clear_err(c->d_err + ERR_PENDING, 1, c->stream));
         HIPCHECK(c, hipStreamSynchronize(c->stream));
-        if (e & 1) return fail(c, PERRK_ENONPHYS, "non-physical state (rho <= 0 or p <= 0) formed; u unmodified");
-        return fail(c, PERRK_ENONFINITE, "non-finite state formed; u unmodified");
+        const int e = e_now ? e_now : e_all;
+        const char *what = (e & 1) ? "non-physical state (rho <= 0 or p <= 0)" : "non-finite state";
+        const int code = (e & 1) ? PERRK_ENONPHYS : PERRK_ENONFINITE;
+        if (e_now) return fail(c, code, "%s formed; u unmodified, step rejected", what);
+        return fail(c, code, "%s formed in an earlier step called without info (that step was rejected and "
+                    "left u unmodified); this step completed", what);
     }
     return status;
 }
@@ -968,11 +975,17 @@ int perrk_entropy(perrk_ctx *c, const void *u_dev, double *H)
     if (!c || !u_dev || !H) return fail(c, PERRK_EINVAL, "null argument");
     HIPCHECK(c, hipEventRecord(c->ev_in, c->user_stream));
     HIPCHECK(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
+    HIPCHECK(c, launch_clear_err(c->d_err + ERR_ENTROPY, 1, c->stream));
     HIPCHECK(c, launch_entropy(c->dim, c->sys, static_cast<const double *>(u_dev), c->d_elem, c->d_partial, c->d_H,
-                               c->d_case_off, c->n_cases, c->nelem, c->gam, c->d_err, c->stream));
+                               c->d_case_off, c->n_cases, c->nelem, c->gam, c->d_err + ERR_ENTROPY, c->stream));
     HIPCHECK(c, hipMemcpyAsync(c->h_H, c->d_H, sizeof(double) * c->n_cases, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->h_err + ERR_ENTROPY, c->d_err + ERR_ENTROPY, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     std::memcpy(H, c->h_H, sizeof(double) * c->n_cases);
+    const int e = c->h_err[ERR_ENTROPY];
+    if (e & 1) return fail(c, PERRK_ENONPHYS, "entropy of a non-physical state (rho <= 0 or p <= 0)");
+    if (e) return fail(c, PERRK_ENONFINITE, "entropy of a non-finite state");
     return PERRK_OK;
 }
 
@@ -990,7 +1003,7 @@ int perrk_rhs(perrk_ctx *c, const void *u_dev, void *k_dev)
     a.active = c->d_active;
     a.n_active = (int32_t)c->nelem;
     a.cs = c->d_cs;
-    a.err = c->d_err;
+    a.err = c->d_err + ERR_RHS;  // never read: the right-hand side reports no error
     a.nelem = c->nelem;
     a.gam = c->gam;
     a.gm1 = c->gam - 1.0;
@@ -1015,31 +1028,43 @@ int perrk_rhs(perrk_ctx *c, const void *u_dev, void *k_dev)
     return PERRK_OK;
 }
 
-int perrk_get_relaxation_state(perrk_ctx *c, double *gamma_prev, double *h_offset, double *t)
+int perrk_get_relaxation_state(perrk_ctx *c, double *gamma_prev, double *h_offset, double *t,
+                               double *gamma_hist, int32_t *n_steps)
 {
     if (!c) return PERRK_EINVAL;
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     HIPCHECK(c, hipMemcpy(c->h_cs, c->d_cs, sizeof(CaseState) * c->n_cases, hipMemcpyDeviceToHost));
     for (int i = 0; i < c->n_cases; ++i) {
-        if (gamma_prev) gamma_prev[i] = c->h_cs[i].gamma_prev;
-        if (h_offset) h_offset[i] = c->h_cs[i].offset;
-        if (t) t[i] = c->h_cs[i].t;
+        const CaseState &C = c->h_cs[i];
+        if (gamma_prev) gamma_prev[i] = C.gamma_prev;
+        if (h_offset) h_offset[i] = C.offset;
+        if (t) t[i] = C.t;
+        if (gamma_hist)
+            for (int j = 0; j < 3; ++j) gamma_hist[3 * i + j] = C.ghist[j];
+        if (n_steps) n_steps[i] = C.nsteps;
     }
     return PERRK_OK;
 }
 
-int perrk_set_relaxation_state(perrk_ctx *c, const double *gamma_prev, const double *h_offset, const double *t)
+int perrk_set_relaxation_state(perrk_ctx *c, const double *gamma_prev, const double *h_offset, const double *t,
+                               const double *gamma_hist, const int32_t *n_steps)
 {
     if (!c) return PERRK_EINVAL;
+    for (int i = 0; i < c->n_cases; ++i) {  // validate everything before changing anything
+        if (gamma_prev && !(gamma_prev[i] > 0.0 && std::isfinite(gamma_prev[i])))
+            return fail(c, PERRK_EINVAL, "gamma_prev[%d] must be finite and > 0", i);
+        if (n_steps && n_steps[i] < 0) return fail(c, PERRK_EINVAL, "n_steps[%d] must be >= 0", i);
+    }
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     HIPCHECK(c, hipMemcpy(c->h_cs, c->d_cs, sizeof(CaseState) * c->n_cases, hipMemcpyDeviceToHost));
     for (int i = 0; i < c->n_cases; ++i) {
-        if (gamma_prev) {
-            if (!(gamma_prev[i] > 0.0)) return fail(c, PERRK_EINVAL, "gamma_prev must be > 0");
-            c->h_cs[i].gamma_prev = gamma_prev[i];
-        }
-        if (h_offset) c->h_cs[i].offset = h_offset[i];
-        if (t) c->h_cs[i].t = t[i];
+        CaseState &C = c->h_cs[i];
+        if (gamma_prev) C.gamma_prev = gamma_prev[i];
+        if (h_offset) C.offset = h_offset[i];
+        if (t) C.t = t[i];
+        if (gamma_hist)
+            for (int j = 0; j < 3; ++j) C.ghist[j] = gamma_hist[3 * i + j];
+        if (n_steps) C.nsteps = n_steps[i];
     }
     HIPCHECK(c, hipMemcpy(c->d_cs, c->h_cs, sizeof(CaseState) * c->n_cases, hipMemcpyHostToDevice));
     return PERRK_OK;

@@ -15,6 +15,15 @@
 #define PERRK_RED_THREADS 1024  // block size of every per-case reduction (fixed: results depend on it)
 #define PERRK_MLP_NW 1377
 
+// Words of the device error array (bit 1: rho <= 0 or p <= 0, bit 2: non-finite).
+enum {
+    ERR_STEP = 0,     // errors of the step in flight; cleared as each step starts
+    ERR_PENDING = 1,  // errors of steps not yet reported; cleared when a step with info reports them
+    ERR_RHS = 2,      // written by perrk_rhs, never read
+    ERR_ENTROPY = 3,  // errors of perrk_entropy; cleared as it starts
+    ERR_WORDS = 4
+};
+
 // Node arrays are addressed by buffer instructions with one 32-bit byte range
 // per field.  An FP64 field of n nodes spans 8 n bytes, so every case together
 // must hold fewer than 2^29 nodes: at exactly 2^29 the range 2^32 no longer
@@ -161,13 +170,13 @@ hipError_t launch_relax_finalize(CaseState *cs, const int64_t *case_off, int n_c
 hipError_t launch_relax_complete(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                                  CaseState *cs, const int64_t *case_off, int n_cases,
                                  double *partial, int64_t nelem, double gam, RelaxParams rp,
-                                 hipStream_t s);
+                                 const int32_t *err, hipStream_t s);
 hipError_t launch_final_update(int dim, int sys, double *U, const double *d, const ElemInfo *elem,
-                               const CaseState *cs, const int32_t *err, int64_t nelem,
+                               const CaseState *cs, int32_t *err, int64_t nelem,
                                hipStream_t s);
 hipError_t launch_entropy(int dim, int sys, const double *U, const ElemInfo *elem, double *partial,
                           double *H_out, const int64_t *case_off, int n_cases, int64_t nelem,
                           double gam, int32_t *err, hipStream_t s);
 hipError_t launch_init_cases(CaseState *cs, int n_cases, hipStream_t s);
 hipError_t launch_set_dt(CaseState *cs, const double *dt, int n_cases, hipStream_t s);
-hipError_t launch_clear_err(int32_t *err, hipStream_t s);
+hipError_t launch_clear_err(int32_t *err, int n, hipStream_t s);  // err[0..n-1] = 0

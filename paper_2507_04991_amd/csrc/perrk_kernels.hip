@@ -2533,12 +2533,15 @@ relax_finalize_kernel(CaseState *cs, const int64_t *case_off, const double *part
 // Runs the remaining residual evaluations of each case inside one workgroup
 // (rarely needed: Newton usually converges within the launched passes), then
 // the per-step bookkeeping.  Every evaluation uses the same per-element code and
-// the same fixed-order sum as the launched passes.
+// the same fixed-order sum as the launched passes.  A step that formed a
+// non-physical or non-finite stage state (err[0] != 0) is rejected: the final
+// update leaves u alone, so time, entropy offset and gamma history stay as
+// they were too.
 template <int DIM, int SYS>
 __global__ void __launch_bounds__(PERRK_RED_THREADS)
 relax_complete_kernel(const double *U, const double *d, const ElemInfo *elem, CaseState *cs,
                       const int64_t *case_off, double *partial, int64_t nelem, double gam,
-                      RelaxParams rp)
+                      RelaxParams rp, const int32_t *err)
 {
     constexpr int NPE = Geo<DIM>::NPE, EPW = Geo<DIM>::EPW;
     const int c = blockIdx.x;
@@ -2588,6 +2591,7 @@ relax_complete_kernel(const double *U, const double *d, const ElemInfo *elem, Ca
             C.flags |= PERRK_FLAG_FALLBACK;
             C.state = RS_DONE;
         }
+        if (err[0] != 0) return;
         C.t += C.gamma_acc * C.dt;
         C.offset += C.H_delta;
         C.ghist[2] = C.ghist[1];
@@ -2598,14 +2602,20 @@ relax_complete_kernel(const double *U, const double *d, const ElemInfo *elem, Ca
     }
 }
 
-// U <- U + gamma dt d, two doubles per thread; skipped entirely after an error.
+// U <- U + gamma dt d, two doubles per thread; skipped entirely after an error
+// of this step (err[0]), which is then added to the errors not yet reported
+// (err[1]).
 template <int DIM, int SYS>
 __global__ void __launch_bounds__(256)
 final_update_kernel(double *U, const double *d, const ElemInfo *elem, const CaseState *cs,
-                    const int32_t *err, int64_t nelem)
+                    int32_t *err, int64_t nelem)
 {
     constexpr int NPE = Sys<DIM, SYS>::NPE, V = Sys<DIM, SYS>::V;
-    if (*err != 0) return;
+    const int32_t e_step = err[0];
+    if (e_step != 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) err[1] |= e_step;
+        return;
+    }
     const int64_t n2 = (int64_t)V * nelem * NPE / 2;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -2636,10 +2646,19 @@ entropy_elem_kernel(const double *U, const ElemInfo *elem, double *partial, int6
 #pragma unroll
     for (int v = 0; v < V; ++v) u[v] = U[((size_t)v * nelem + e) * NPE + node];
     double s = node_weight<DIM>(node) * (SYS == 1 ? mhd_entropy_density(u, gam) : entropy_density<DIM>(u, gam));
+    int bad = 0;
+    if constexpr (SYS == 1) {
+        PrimM P;
+        make_prim_mhd(u, gam - 1.0, P, bad);
+    } else {
+        Prim<double, DIM> P;
+        make_prim<double, DIM>(u, gam - 1.0, P, bad);
+    }
 #pragma unroll
     for (int off = NPE / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
     if (valid && node == 0) partial[e] = elem[e].jac * s;
-    if (valid && !isfinite(s) && node == 0) atomicOr(err, 2);
+    if (valid && node == 0 && !isfinite(s)) bad |= 2;
+    if (valid && bad) atomicOr(err, (bad & 1) ? 1 : bad);
 }
 
 __global__ void __launch_bounds__(PERRK_RED_THREADS)
@@ -2657,7 +2676,10 @@ __global__ void set_dt_kernel(CaseState *cs, const double *dt, int n)
     if (i < n) cs[i].dt = dt[i];
 }
 
-__global__ void clear_err_kernel(int32_t *err) { *err = 0; }
+__global__ void clear_err_kernel(int32_t *err, int n)
+{
+    if ((int)threadIdx.x < n) err[threadIdx.x] = 0;
+}
 
 __global__ void init_cases_kernel(CaseState *cs, int n)
 {
@@ -2822,22 +2844,22 @@ hipError_t launch_relax_finalize(CaseState *cs, const int64_t *case_off, int n_c
 
 hipError_t launch_relax_complete(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                                  CaseState *cs, const int64_t *case_off, int n_cases, double *partial,
-                                 int64_t nelem, double gam, RelaxParams rp, hipStream_t s)
+                                 int64_t nelem, double gam, RelaxParams rp, const int32_t *err, hipStream_t s)
 {
     if (sys == 1)
         hipLaunchKernelGGL((relax_complete_kernel<2, 1>), dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, U, d,
-                           elem, cs, case_off, partial, nelem, gam, rp);
+                           elem, cs, case_off, partial, nelem, gam, rp, err);
     else if (dim == 2)
         hipLaunchKernelGGL((relax_complete_kernel<2, 0>), dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, U, d,
-                           elem, cs, case_off, partial, nelem, gam, rp);
+                           elem, cs, case_off, partial, nelem, gam, rp, err);
     else
         hipLaunchKernelGGL((relax_complete_kernel<3, 0>), dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, U, d,
-                           elem, cs, case_off, partial, nelem, gam, rp);
+                           elem, cs, case_off, partial, nelem, gam, rp, err);
     return hipGetLastError();
 }
 
 hipError_t launch_final_update(int dim, int sys, double *U, const double *d, const ElemInfo *elem,
-                               const CaseState *cs, const int32_t *err, int64_t nelem, hipStream_t s)
+                               const CaseState *cs, int32_t *err, int64_t nelem, hipStream_t s)
 {
     const int npe = dim == 2 ? 16 : 64;
     const int64_t n2 = (int64_t)(sys == 1 ? MHD_V : dim + 2) * nelem * npe / 2;
@@ -2887,8 +2909,8 @@ hipError_t launch_set_dt(CaseState *cs, const double *dt, int n_cases, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_clear_err(int32_t *err, hipStream_t s)
+hipError_t launch_clear_err(int32_t *err, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(clear_err_kernel, dim3(1), dim3(1), 0, s, err);
+    hipLaunchKernelGGL(clear_err_kernel, dim3(1), dim3(64), 0, s, err, n);
     return hipGetLastError();
 }

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+from collections import namedtuple
 
 import numpy as np
 
@@ -22,6 +23,9 @@ FP64, MIXED, MIXED_ALL = 0, 1, 2
 ANCHOR_STEP, ANCHOR_INITIAL = 0, 1
 GUESS_PREV, GUESS_MLP = 0, 1
 FLAG_BISECT, FLAG_FALLBACK, FLAG_TRIVIAL = 1, 2, 4
+
+
+RelaxationState = namedtuple("RelaxationState", "gamma_prev h_offset t gamma_hist n_steps")
 
 
 class PerrkError(RuntimeError):
@@ -103,7 +107,8 @@ def lib():
         L.perrk_rhs.argtypes = [p, p, p]
         L.perrk_rhs.restype = ctypes.c_int
         for fn in ("perrk_get_relaxation_state", "perrk_set_relaxation_state"):
-            getattr(L, fn).argtypes = [p, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)]
+            getattr(L, fn).argtypes = [p, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
+                                       ctypes.POINTER(d), ctypes.POINTER(ctypes.c_int32)]
             getattr(L, fn).restype = ctypes.c_int
         L.perrk_set_guess_model.argtypes = [p, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                             ctypes.POINTER(ctypes.c_float)]
@@ -244,14 +249,23 @@ class Stepper:
         return k
 
     def relaxation_state(self):
-        g, h, tt = np.zeros(self.n_cases), np.zeros(self.n_cases), np.zeros(self.n_cases)
-        self._check(lib().perrk_get_relaxation_state(self.ctx, _dp(g), _dp(h), _dp(tt)))
-        return g, h, tt
+        """RelaxationState(gamma_prev, h_offset, t, gamma_hist [n, 3], n_steps) per case."""
+        n = self.n_cases
+        g, h, tt, gh = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros((n, 3))
+        ns = np.zeros(n, dtype=np.int32)
+        self._check(lib().perrk_get_relaxation_state(self.ctx, _dp(g), _dp(h), _dp(tt), _dp(gh),
+                                                     ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return RelaxationState(g, h, tt, gh, ns)
 
-    def set_relaxation_state(self, gamma_prev=None, h_offset=None, t=None):
-        arr = [None if x is None else np.ascontiguousarray(np.broadcast_to(x, (self.n_cases,)), dtype=np.float64)
+    def set_relaxation_state(self, gamma_prev=None, h_offset=None, t=None, gamma_hist=None, n_steps=None):
+        n = self.n_cases
+        arr = [None if x is None else np.ascontiguousarray(np.broadcast_to(x, (n,)), dtype=np.float64)
                for x in (gamma_prev, h_offset, t)]
+        arr.append(None if gamma_hist is None
+                   else np.ascontiguousarray(np.broadcast_to(gamma_hist, (n, 3)), dtype=np.float64))
         ptrs = [None if x is None else _dp(x) for x in arr]
+        ns = None if n_steps is None else np.ascontiguousarray(np.broadcast_to(n_steps, (n,)), dtype=np.int32)
+        ptrs.append(None if ns is None else ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         self._check(lib().perrk_set_relaxation_state(self.ctx, *ptrs))
 
     def set_guess_model(self, weights, mean, scale):

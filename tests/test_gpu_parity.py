@@ -157,25 +157,93 @@ def test_async_steps_equal_synchronous_steps(P):
     assert np.array_equal(st.relaxation_state()[0], st2.relaxation_state()[0])
 
 
-def test_nonphysical_state_rejected_and_u_unmodified(P):
-    f, U0, tab, dt, lev = problem_2d()
+def _bad_states(U0):
     bad = U0.copy()
     bad[0, 7, 5] = -0.5
-    st, u = make(P, f, bad, tab, lev)
-    before = u.clone()
-    with pytest.raises(P.PerrkError) as ei:
-        st.step(u, dt)
-    assert ei.value.status == P.ENONPHYS
-    assert torch.equal(u, before)
     nan = U0.copy()
     nan[3, 2, 1] = np.nan
-    st, u = make(P, f, nan, tab, lev)
+    return [("nonphys", bad), ("nonfinite", nan)]
+
+
+def _same_state(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("anchor", ["step", "initial"])
+def test_nonphysical_state_rejected_and_u_unmodified(P, anchor):
+    """A step that forms a non-physical or non-finite state is rejected: u and the
+    state carried to the next step (gamma_prev, entropy offset, time, gamma
+    history, step count) stay as they were; the next valid step then equals the
+    step of a context that never saw the rejected one, bitwise."""
+    f, U0, tab, dt, lev = problem_2d()
+    opt = dict(anchor=P.ANCHOR_INITIAL if anchor == "initial" else P.ANCHOR_STEP)
+    st, u = make(P, f, U0, tab, lev, **opt)
+    ref, uref = make(P, f, U0, tab, lev, **opt)
+    for _ in range(3):
+        st.step(u, dt)
+        ref.step(uref, dt)
+    good = u.clone()
+    for name, badU in _bad_states(U0):
+        before = st.relaxation_state()
+        u.copy_(torch.tensor(badU, device="cuda"))
+        ubad = u.clone()
+        with pytest.raises(P.PerrkError) as ei:
+            st.step(u, dt)
+        assert ei.value.status == (P.ENONPHYS if name == "nonphys" else P.ENONFINITE)
+        assert torch.equal(u.nan_to_num(), ubad.nan_to_num()) and torch.equal(u.isnan(), ubad.isnan())
+        assert _same_state(st.relaxation_state(), before), name
+        u.copy_(good)
+    info = st.step(u, dt)[0]
+    iref = ref.step(uref, dt)[0]
+    assert info["flags"] == 0 and info == iref
+    assert torch.equal(u, uref)
+    assert _same_state(st.relaxation_state(), ref.relaxation_state())
+    st.close()
+    ref.close()
+
+
+def test_rejected_async_step_reported_by_next_synchronous_step(P):
+    """A rejected step called without info leaves u and the carried state alone;
+    the next step with info completes (u advances as from a fresh context) and
+    reports the earlier rejection; the step after that reports nothing."""
+    f, U0, tab, dt, lev = problem_2d()
+    st, u = make(P, f, _bad_states(U0)[0][1], tab, lev)
+    ubad = u.clone()
+    st.step(u, dt, info=False)
+    torch.cuda.synchronize()
+    assert torch.equal(u, ubad)
+    s0 = st.relaxation_state()
+    assert s0.n_steps[0] == 0 and s0.t[0] == 0.0
+    u.copy_(torch.tensor(U0, device="cuda"))
     with pytest.raises(P.PerrkError) as ei:
         st.step(u, dt)
-    assert ei.value.status == P.ENONFINITE
-    # the context recovers once the error has been reported
-    u.copy_(torch.tensor(U0, device="cuda"))
-    assert st.step(u, dt)[0]["flags"] == 0
+    assert ei.value.status == P.ENONPHYS and "earlier step" in str(ei.value)
+    ref, uref = make(P, f, U0, tab, lev)
+    ref.step(uref, dt)
+    assert torch.equal(u, uref)
+    assert _same_state(st.relaxation_state(), ref.relaxation_state())
+    assert st.step(u, dt)[0] == ref.step(uref, dt)[0]
+    assert torch.equal(u, uref)
+    st.close()
+    ref.close()
+
+
+def test_entropy_error_reported_and_not_carried_into_steps(P):
+    """perrk_entropy of a non-physical / non-finite state returns ENONPHYS /
+    ENONFINITE; the next step on a valid state advances u and returns OK."""
+    f, U0, tab, dt, lev = problem_2d()
+    st, u = make(P, f, U0, tab, lev)
+    ref, uref = make(P, f, U0, tab, lev)
+    for name, badU in _bad_states(U0):
+        with pytest.raises(P.PerrkError) as ei:
+            st.entropy(torch.tensor(badU, device="cuda").contiguous())
+        assert ei.value.status == (P.ENONPHYS if name == "nonphys" else P.ENONFINITE)
+        st.rhs(torch.tensor(badU, device="cuda").contiguous())
+        info = st.step(u, dt)[0]
+        assert info == ref.step(uref, dt)[0] and info["flags"] == 0
+        assert torch.equal(u, uref)
+    st.close()
+    ref.close()
 
 
 def test_solver_fallbacks_match_oracle(P, oracle):

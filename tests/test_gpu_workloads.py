@@ -75,7 +75,7 @@ def test_vortex16_100_steps_fp64(P, oracle):
         assert abs(info["gamma"] - h["gamma"]) <= 1e-12, n
         assert abs(info["r"]) <= 1e-12, n
     assert rel_err(u.cpu().numpy(), Uref) < 1e-12
-    _, _, t = st.relaxation_state()
+    t = st.relaxation_state().t
     assert abs(t[0] - tref) <= 1e-12 * tref
     st.close()
 
@@ -184,26 +184,40 @@ def test_ensemble_full_size_sampled(P, oracle, precision):
     st.close()
 
 
-def test_checkpoint_resume_bitwise(P):
-    """State and relaxation state saved after some steps and restored into a new
-    context continue bitwise identically."""
+@pytest.mark.parametrize("guess", ["prev", "mlp"])
+def test_checkpoint_resume_bitwise(P, guess):
+    """State and relaxation state (gamma_prev, entropy offset, time, gamma history,
+    step count) saved after some steps and restored into a new context continue
+    bitwise identically, with the previous-gamma guess and with the learned guess
+    (whose features are the gamma history; it is used from the fourth step on)."""
+    from paper_2507_04991_amd import learned_guess as L
     from paper_2507_04991_amd import problems
     prob = problems.vortex16()
     dt = prob["dt"]
-    st, u = stepper(P, prob)
-    for _ in range(4):
+    opt = dict(guess=P.GUESS_MLP) if guess == "mlp" else {}
+
+    def fresh():
+        st, u = stepper(P, prob, precision=P.MIXED if guess == "mlp" else P.FP64, **opt)
+        if guess == "mlp":
+            st.set_guess_model(*L.load(L.DEFAULT_MODEL))
+        return st, u
+
+    st, u = fresh()
+    for _ in range(5):
         st.step(u, dt)
     u_saved = u.clone()
-    g, off, t = st.relaxation_state()
-    for _ in range(3):
-        st.step(u, dt)
-    st2, _ = stepper(P, prob)
-    st2.set_relaxation_state(g, off, t)
+    saved = st.relaxation_state()
+    assert saved.n_steps[0] == 5 and saved.gamma_hist[0, 0] == saved.gamma_prev[0] - 1.0
+    infos = [st.step(u, dt)[0] for _ in range(3)]
+    st2, _ = fresh()
+    st2.set_relaxation_state(**saved._asdict())
     u2 = u_saved.clone()
-    for _ in range(3):
-        st2.step(u2, dt)
+    infos2 = [st2.step(u2, dt)[0] for _ in range(3)]
     assert torch.equal(u, u2)
-    assert np.array_equal(st.relaxation_state()[2], st2.relaxation_state()[2])
+    assert [i["passes"] for i in infos] == [i["passes"] for i in infos2]
+    a, b = st.relaxation_state(), st2.relaxation_state()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
     st.close()
     st2.close()
 
