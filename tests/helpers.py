@@ -78,3 +78,37 @@ def flux_scale(U, dim, gam=W.GAMMA):
             m = max(m, np.abs(U[1 + k] * vel[d] + (p if k == d else 0.0)).max())
         m = max(m, np.abs((U[dim + 1] + p) * vel[d]).max())
     return float(m)
+
+
+def mixed_step_amplification(tab, cfl=0.5, all_stages=False):
+    """Bound factor A of one mixed-precision step: |U_{n+1} - U_{n+1}^exact| <= A dt B
+    when every single-precision stage right-hand side is within B of the exact one.
+
+    Linearised stage chain (the test equation U' = lambda U, per level): an error e
+    in K_j enters U_{n,k} = U_n + dt((c_k - a_k) K_1 + a_k K_{k-1}) of the later
+    stages and so U_{n+1} = U_n + dt sum_k b_k K_k as dt R_j(z) e, z = dt lambda,
+    R_j = sum_k b_k dK_k with dK_j = 1, dK_k = z ((c_k - a_k) dK_1 + a_k dK_{k-1}).
+    A = max over levels of sum over the level's single-precision stages (b_j = 0,
+    or every stage with all_stages) of max |R_j(z)| over z on the model spectrum
+    scaled to the level's step (cfl h_stab).  Every stage of a level evaluates
+    the same error bound, so the sum is the worst case."""
+    c, b = np.asarray(tab["c"]), np.asarray(tab["b"])
+    S = len(c)
+    spec = T.model_spectrum()
+    best = 0.0
+    for r, E in enumerate(tab["E"]):
+        a = np.asarray(tab["a_sub"][r])
+        z = cfl * float(tab["h_stab"][r]) * spec
+        z = np.concatenate([z, np.conj(z)])
+        total = 0.0
+        for j in [0] + list(range(S - E + 1, S)):
+            if b[j] != 0.0 and not all_stages:
+                continue
+            dK = [np.zeros_like(z) for _ in range(S)]
+            dK[j] = np.ones_like(z)
+            for k in range(j + 1, S):
+                ak = a[k] if k >= 2 else 0.0
+                dK[k] = z * ((c[k] - ak) * dK[0] + ak * dK[k - 1])
+            total += float(np.abs(sum(b[k] * dK[k] for k in range(S))).max())
+        best = max(best, total)
+    return best

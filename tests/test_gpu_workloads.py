@@ -13,13 +13,15 @@
 
 The same tolerances as the small parity tests: 1e-12 relative error of the
 whole state in FP64; in mixed precision 32 eps32 (2/h)_max F per stage right-hand
-side (F the largest physical flux magnitude), S dt times that after one step
-(S stage evaluations, each entering U_{n+1} with a weight of at most dt).
+side (F the largest physical flux magnitude), A dt times that after one step (A:
+the amplification of the single-precision stages' errors through the stage
+chain, tests.helpers.mixed_step_amplification; below the stage count S for every
+tableau used).
 """
 import numpy as np
 import pytest
 
-from tests.helpers import field_errors, flux_scale, rel_err
+from tests.helpers import field_errors, flux_scale, mixed_step_amplification, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -84,7 +86,7 @@ def test_kh64_hll(P, oracle):
     from paper_2507_04991_amd import problems
     prob = problems.kh64()
     f, lev, dt = prob["faces"][0], prob["lev"][0], float(prob["dt"][0])
-    S = len(prob["tab"]["c"])
+    S = mixed_step_amplification(prob["tab"])
     print("case kh64 hll", flush=True)
     m, t = oracle.Mesh(f, surface_flux=1), otab(oracle, prob["tab"])
     st, u = stepper(P, prob)
@@ -121,7 +123,7 @@ def test_tgv32_one_step(P, oracle):
     from paper_2507_04991_amd import problems
     prob = problems.tgv32()
     f, lev, dt = prob["faces"][0], prob["lev"][0], float(prob["dt"][0])
-    S = len(prob["tab"]["c"])
+    S = mixed_step_amplification(prob["tab"])
     print("case tgv32 one step", flush=True)
     Uref, iref = oracle.step(oracle.Mesh(f), otab(oracle, prob["tab"]), lev, prob["U0"], dt)
     st, u = stepper(P, prob)
@@ -150,6 +152,93 @@ def test_tgv32_one_step(P, oracle):
     stm.close()
 
 
+def _kinetic_energy(faces, U):
+    """sum_e J_e sum_nodes q |m|^2 / (2 rho) (3D, LGL quadrature)."""
+    from paper_2507_04991_amd import workloads as W
+    w = W.element_widths(faces)
+    q1 = np.array([1.0, 5.0, 5.0, 1.0]) / 6.0
+    node = np.arange(64)
+    qn = q1[node % 4] * q1[(node // 4) % 4] * q1[node // 16]
+    J = np.prod(w, axis=1) / 8.0
+    return float(np.sum(J[:, None] * qn[None, :] * 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0]))
+
+
+def test_tgv16_20_steps_fp64_kinetic_energy_and_entropy(P, oracle):
+    """Taylor-Green at Mach 0.1 on the 16^3 variant of the graded C3 mesh, p = 4 with
+    E = {5, 9, 14}, 20 FP64 steps through the C ABI against the oracle stepping
+    alongside: every step's passes, flags and gamma, the kinetic energy and the
+    total entropy (relative 1e-12), and the state after the last step."""
+    from paper_2507_04991_amd import problems
+    prob = problems.tgv32(n=16)
+    f, lev, dt = prob["faces"][0], prob["lev"][0], float(prob["dt"][0])
+    print("case tgv16, 20 fp64 steps", flush=True)
+    m, t = oracle.Mesh(f), otab(oracle, prob["tab"])
+    st, u = stepper(P, prob)
+    Uref, g, tt = prob["U0"].copy(), 1.0, 0.0
+    H0 = oracle.total_entropy(m, Uref)
+    ke0 = _kinetic_energy(f, Uref)
+    for n in range(20):
+        info = st.step(u, np.array([dt]))[0]
+        Uref, iref = oracle.step(m, t, lev, Uref, dt, oracle.relax_options(gamma0=g, t0=tt))
+        g = iref["gamma"]
+        tt += g * dt
+        assert info["flags"] == iref["flags"] == 0, n
+        assert info["passes"] == iref["passes"], n
+        assert abs(info["gamma"] - iref["gamma"]) <= 1e-12, n
+        Ug = u.cpu().numpy()
+        ke, ke_ref = _kinetic_energy(f, Ug), _kinetic_energy(f, Uref)
+        H, H_ref = float(st.entropy(u)[0]), oracle.total_entropy(m, Uref)
+        assert abs(ke - ke_ref) <= 1e-12 * abs(ke_ref), n
+        assert abs(H - H_ref) <= 1e-12 * abs(H_ref), n
+        # EC fluxes with relaxation: the entropy stays at H_0 within the solve tolerance
+        assert abs(H_ref - H0) <= (n + 1) * 1e-12 + 1e-14 * abs(H0), n
+    print("tgv16: kinetic energy change", ke_ref - ke0, "entropy change", H_ref - H0, flush=True)
+    assert rel_err(u.cpu().numpy(), Uref) < 1e-12
+    assert abs(st.relaxation_state().t[0] - tt) <= 1e-14
+    st.close()
+
+
+def test_tgv32_40_steps_mixed_kinetic_energy_and_entropy(P):
+    """C3 over time: 40 steps of the 32^3 Taylor-Green in FP64 and in mixed
+    precision (single-precision stages with b_i = 0).  Per step:
+      - the mixed state stays within n A dt B of the FP64 state after n steps (B the
+        single-precision right-hand-side bound, A the stage-chain amplification;
+        errors of successive steps add);
+      - the mixed kinetic-energy change equals the FP64 one within 1 % (plus 1e-10
+        for the first steps, where the change itself is of that size);
+      - both runs keep the total entropy at H_0 within n 1e-12 (EC fluxes, |r| <=
+        1e-12 per step, step anchoring), and the mixed entropy stays within that of
+        the FP64 entropy."""
+    from paper_2507_04991_amd import problems
+    prob = problems.tgv32()
+    f, dt = prob["faces"][0], float(prob["dt"][0])
+    print("case tgv32, 40 steps fp64 and mixed", flush=True)
+    A = mixed_step_amplification(prob["tab"])
+    B = mixed_bound(prob, 3)
+    s64, u64 = stepper(P, prob, precision=0)
+    smx, umx = stepper(P, prob, precision=1)
+    H0 = float(s64.entropy(u64)[0])
+    assert float(smx.entropy(umx)[0]) == H0
+    ke0 = _kinetic_energy(f, prob["U0"])
+    worst = 0.0
+    for n in range(40):
+        for st, u in ((s64, u64), (smx, umx)):
+            info = st.step(u, np.array([dt]))[0]
+            assert abs(info["r"]) <= 1e-12 and info["flags"] == 0, n
+        err = float((umx - u64).abs().max())
+        worst = max(worst, err / ((n + 1) * A * dt * B))
+        assert err <= (n + 1) * A * dt * B, n
+        ke64, kemx = _kinetic_energy(f, u64.cpu().numpy()), _kinetic_energy(f, umx.cpu().numpy())
+        assert abs((kemx - ke0) - (ke64 - ke0)) <= 0.01 * abs(ke64 - ke0) + 1e-10, n
+        H64, Hmx = float(s64.entropy(u64)[0]), float(smx.entropy(umx)[0])
+        tol_H = (n + 1) * 1e-12 + 1e-14 * abs(H0)
+        assert abs(H64 - H0) <= tol_H and abs(Hmx - H0) <= tol_H, n
+    print("tgv32 40 steps: kinetic energy change fp64", ke64 - ke0, "mixed - fp64", kemx - ke64,
+          "entropy drift fp64", H64 - H0, "mixed", Hmx - H0, "largest state error / (n A dt B)", worst, flush=True)
+    s64.close()
+    smx.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1, 2])
 def test_ensemble_full_size_sampled(P, oracle, precision):
     """The whole 256-case ensemble stepped once as the benchmark launches it;
@@ -168,7 +257,6 @@ def test_ensemble_full_size_sampled(P, oracle, precision):
         pick.update(idx[:2])
     offs = np.cumsum([0] + [c["U0"].shape[1] for c in prob["cases"]])
     t = otab(oracle, prob["tab"])
-    S = len(prob["tab"]["c"])
     for k in sorted(pick):
         c = prob["cases"][k]
         Uref, iref = oracle.step(oracle.Mesh(c["faces"]), t, prob["lev"][k], c["U0"], float(prob["dt"][k]))
@@ -178,7 +266,8 @@ def test_ensemble_full_size_sampled(P, oracle, precision):
             assert abs(infos[k]["gamma"] - iref["gamma"]) <= 1e-12, k
             assert infos[k]["passes"] == iref["passes"], k
         else:
-            bound = S * float(prob["dt"][k]) * mixed_bound(prob, 2, c["faces"], c["U0"])
+            A = mixed_step_amplification(prob["tab"], all_stages=precision == 2)
+            bound = A * float(prob["dt"][k]) * mixed_bound(prob, 2, c["faces"], c["U0"])
             err = np.abs(Uk - Uref).max()
             assert err <= bound, (k, err, bound)
     st.close()
