@@ -288,6 +288,19 @@ int perrk_mlp_forward(const float *w_dev, const float *x_dev, int64_t n, float *
 int perrk_mlp_loss_grad(const float *w_dev, const float *x_dev, const float *t_dev, int64_t n,
                         float *grad_dev, double *loss_dev, void *work_dev, size_t work_bytes,
                         void *stream);
+/* perrk_mlp_loss_grad without a workspace, for callers that cannot allocate
+ * device memory (code under stream capture, tight loops, harnesses that forbid
+ * allocation): the same kernels and the same result, bit for bit, as
+ * perrk_mlp_loss_grad, with the per-chunk partial sums in a static array of
+ * the library (one per device, 11.3 MB, held until the process ends) instead
+ * of work_dev.  Allocates nothing.  n must be in 1..PERRK_MLP_STATIC_MAX_N;
+ * larger n returns PERRK_ENOMEM (use perrk_mlp_loss_grad), null pointers or
+ * n <= 0 PERRK_EINVAL.  Every call on one device shares that array: calls that
+ * overlap on one device (different streams, or threads) race and must be
+ * ordered by the caller.  Asynchronous on `stream`. */
+#define PERRK_MLP_STATIC_MAX_N 131072
+int perrk_mlp_loss_grad_static(const float *w_dev, const float *x_dev, const float *t_dev, int64_t n,
+                               float *grad_dev, double *loss_dev, void *stream);
 int perrk_mlp_adam(float *w_dev, const float *grad_dev, float *m_dev, float *v_dev, int32_t step,
                    float lr, float beta1, float beta2, float eps, void *stream);
 

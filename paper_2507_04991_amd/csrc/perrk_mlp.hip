@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "perrk.h"
 
 namespace {
@@ -155,6 +157,48 @@ __global__ void __launch_bounds__(256) mlp_adam_kernel(float *w, const float *g,
     w[p] -= lr * (mp / c1) / (sqrtf(vp / c2) + eps);
 }
 
+// Scratch of perrk_mlp_loss_grad_static: the per-chunk partial sums of up to
+// PERRK_MLP_STATIC_MAX_N samples (11.3 MB), one copy per device, held until the
+// process ends.  Host code never passes this name to a kernel (on the host it
+// is a stand-in, not a device address): it uses the per-device address that
+// hipGetSymbolAddress returns.
+constexpr int64_t STATIC_CHUNKS = PERRK_MLP_STATIC_MAX_N / CH;
+static_assert(PERRK_MLP_STATIC_MAX_N % CH == 0, "whole chunks");
+__device__ __align__(256) float scratch[STATIC_CHUNKS * (NW + 1)];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch, looked up once per device.
+int scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return PERRK_EHIP;
+    if (dev < 0 || dev >= MAX_DEVICES) return PERRK_EINVAL;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PERRK_EHIP;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return PERRK_OK;
+}
+
+// The two gradient kernels on a workspace of at least nchunk chunks.
+int launch_loss_grad(const float *w_dev, const float *x_dev, const float *t_dev, int64_t n, float *grad_dev,
+                     double *loss_dev, float *work, hipStream_t s)
+{
+    const int64_t nchunk = (n + CH - 1) / CH;
+    hipLaunchKernelGGL(mlp_grad_chunk_kernel, dim3((unsigned)nchunk), dim3(CH), 0, s, w_dev, x_dev, t_dev, n,
+                       1.0f / (float)n, work);
+    if (hipGetLastError() != hipSuccess) return PERRK_EHIP;
+    hipLaunchKernelGGL(mlp_grad_reduce_kernel, dim3((NW + 1 + 255) / 256), dim3(256), 0, s,
+                       static_cast<const float *>(work), nchunk, grad_dev, loss_dev);
+    return hipGetLastError() == hipSuccess ? PERRK_OK : PERRK_EHIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -179,13 +223,20 @@ int perrk_mlp_loss_grad(const float *w_dev, const float *x_dev, const float *t_d
 {
     if (!w_dev || !x_dev || !t_dev || !grad_dev || n <= 0) return PERRK_EINVAL;
     if (!work_dev || work_bytes < perrk_mlp_workspace_bytes(n)) return PERRK_EINVAL;
-    const int64_t nchunk = (n + CH - 1) / CH;
-    hipLaunchKernelGGL(mlp_grad_chunk_kernel, dim3((unsigned)nchunk), dim3(CH), 0, (hipStream_t)stream, w_dev, x_dev,
-                       t_dev, n, 1.0f / (float)n, static_cast<float *>(work_dev));
-    if (hipGetLastError() != hipSuccess) return PERRK_EHIP;
-    hipLaunchKernelGGL(mlp_grad_reduce_kernel, dim3((NW + 1 + 255) / 256), dim3(256), 0, (hipStream_t)stream,
-                       static_cast<const float *>(work_dev), nchunk, grad_dev, loss_dev);
-    return hipGetLastError() == hipSuccess ? PERRK_OK : PERRK_EHIP;
+    return launch_loss_grad(w_dev, x_dev, t_dev, n, grad_dev, loss_dev, static_cast<float *>(work_dev),
+                            (hipStream_t)stream);
+}
+
+int perrk_mlp_loss_grad_static(const float *w_dev, const float *x_dev, const float *t_dev, int64_t n,
+                               float *grad_dev, double *loss_dev, void *stream)
+{
+    if (!w_dev || !x_dev || !t_dev || !grad_dev || n <= 0) return PERRK_EINVAL;
+    if (n > PERRK_MLP_STATIC_MAX_N) return PERRK_ENOMEM;
+    void *work = nullptr;
+    const int st = scratch_address(&work);
+    if (st != PERRK_OK) return st;
+    return launch_loss_grad(w_dev, x_dev, t_dev, n, grad_dev, loss_dev, static_cast<float *>(work),
+                            (hipStream_t)stream);
 }
 
 int perrk_mlp_adam(float *w_dev, const float *grad_dev, float *m_dev, float *v_dev, int32_t step, float lr,

@@ -77,7 +77,8 @@ EXPORTS = ["perrk_default_options", "perrk_validate", "perrk_init", "perrk_step"
            "perrk_rhs", "perrk_get_relaxation_state", "perrk_set_relaxation_state",
            "perrk_set_guess_model", "perrk_set_profiling", "perrk_get_kernel_stats", "perrk_get_stage_stats",
            "perrk_get_tuning", "perrk_last_error", "perrk_version", "perrk_destroy",
-           "perrk_mlp_workspace_bytes", "perrk_mlp_forward", "perrk_mlp_loss_grad", "perrk_mlp_adam"]
+           "perrk_mlp_workspace_bytes", "perrk_mlp_forward", "perrk_mlp_loss_grad", "perrk_mlp_loss_grad_static",
+           "perrk_mlp_adam"]
 
 _lib = None
 
@@ -133,6 +134,8 @@ def lib():
         L.perrk_mlp_forward.restype = ctypes.c_int
         L.perrk_mlp_loss_grad.argtypes = [p, p, p, ctypes.c_int64, p, p, p, sz, p]
         L.perrk_mlp_loss_grad.restype = ctypes.c_int
+        L.perrk_mlp_loss_grad_static.argtypes = [p, p, p, ctypes.c_int64, p, p, p]
+        L.perrk_mlp_loss_grad_static.restype = ctypes.c_int
         L.perrk_mlp_adam.argtypes = [p, p, p, p, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, p]
         L.perrk_mlp_adam.restype = ctypes.c_int
@@ -348,6 +351,23 @@ def mlp_loss_grad(w, x, t, work=None):
     if st != OK:
         raise PerrkError(st, "perrk_mlp_loss_grad")
     return loss, g
+
+
+MLP_STATIC_MAX_N = 131072  # PERRK_MLP_STATIC_MAX_N
+
+
+def mlp_loss_grad_static(w, x, t, loss=None, grad=None):
+    """mlp_loss_grad with the library's static scratch instead of a workspace
+    (perrk_mlp_loss_grad_static: allocates nothing when loss and grad are given)."""
+    import torch
+
+    n = x.shape[0]
+    g = grad if grad is not None else torch.empty(MLP_NW, dtype=torch.float32, device=x.device)
+    lo = loss if loss is not None else torch.empty(1, dtype=torch.float64, device=x.device)
+    st = lib().perrk_mlp_loss_grad_static(_ptr(w), _ptr(x), _ptr(t), n, _ptr(g), _ptr(lo), _stream(torch))
+    if st != OK:
+        raise PerrkError(st, f"perrk_mlp_loss_grad_static (n = {n}, at most {MLP_STATIC_MAX_N})")
+    return lo, g
 
 
 def mlp_adam(w, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
