@@ -402,8 +402,8 @@ def main():
     if ", float, float, mid>" in dom:
         # the single-precision stages read U_n from its single-precision copy (4 B per
         # DOF); counted with U_n in double precision, as the planned 20 B per active DOF
-        extra = 4.0 * fp32_mid_active_dof(wl, plan[0][1]) * args.steps
-        b20 = g["bytes"] + extra
+        u64_bytes = 4.0 * fp32_mid_active_dof(wl, plan[0][1]) * args.steps
+        b20 = g["bytes"] + u64_bytes
         roofline.update(bytes_per_launch_fp64_state=b20 / g["launches"],
                         achieved_fp64_state=b20 / (g["ms"] * 1e-3) / 1e9,
                         frac_fp64_state=b20 / (g["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)

@@ -42,6 +42,11 @@ struct perrk_ctx {
     size_t max_lds = 65536;         // LDS bytes a workgroup may use on this device
     std::vector<int32_t> n_active;  // per stage
     std::vector<int64_t> active_off;  // start of each stage's list in d_active
+    // viscous terms: per stage, the elements whose gradients the stage reads (its
+    // active elements and their face neighbours), a list in d_active as well
+    std::vector<int32_t> n_grad;
+    std::vector<int64_t> grad_off;
+    std::vector<std::vector<int64_t>> grad_per_level;
     // streams and events
     hipStream_t user_stream = nullptr, stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -58,6 +63,7 @@ struct perrk_ctx {
     int32_t *d_err = nullptr;
     float *d_mlp = nullptr;
     bool have_mlp = false;
+    bool fused_first = false;  // the last stage evaluates the first relaxation residual
     // pinned host staging
     static constexpr int NRING = 8;
     double *h_dt = nullptr;  // [NRING][n_cases]
@@ -349,6 +355,10 @@ void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int
     a.grad = c->d_grad;
     a.active_all = c->d_active;  // the first stage's list holds every element
     a.n_all = (int32_t)c->nelem;
+    if (c->viscous) {  // the gradient pass: the stage's active elements and their neighbours
+        a.active_all = c->d_active + c->grad_off[i];
+        a.n_all = c->n_grad[i];
+    }
     a.c_stage = c->c[i];
     a.x_lo = c->x_lo;
     a.x_hi = c->x_hi;
@@ -379,6 +389,7 @@ void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int
     a.ep_partial = nullptr;
     for (size_t j = 0; j < c->bstages.size(); ++j)
         if (c->bstages[j] == i) a.ep_partial = c->d_ep + j * (size_t)c->nelem;
+    a.rx_partial = (kind == SK_LAST && c->fused_first) ? c->d_partial : nullptr;
     // MIXED: stages entering d and dH are evaluated in double precision
     const bool mixed = c->precision == PERRK_MIXED;
     variant = c->precision == PERRK_FP64 ? 0 : (mixed && c->b[i] != 0.0 ? 2 : 1);
@@ -455,14 +466,24 @@ int autotune(perrk_ctx *c, double *u)
     return PERRK_OK;
 }
 
-// Enqueues one full step on ctx->stream (no host synchronisation).
+// Enqueues one full step on ctx->stream (no host synchronisation).  With the
+// Euler stage kernel, the solver is prepared before the last stage, whose epilogue
+// evaluates the first residual at each case's starting gamma; otherwise the
+// solver is prepared after the last stage and the first residual pass does it.
 int enqueue_step(perrk_ctx *c, double *u)
 {
     HIPCHECK(c, launch_clear_err(c->d_err + ERR_STEP, 1, c->stream));
+    const float *mlp = c->have_mlp ? c->d_mlp : nullptr;
     for (int i = 0; i < c->S; ++i) {
         StageArgs a;
         int variant = 0, kind = 0;
         stage_setup(c, u, i, a, variant, kind);
+        if (kind == SK_LAST && c->fused_first) {
+            HIPCHECK(c, mark_begin(c));
+            HIPCHECK(c, launch_relax_prepare(c->d_cs, c->d_case_off, c->n_cases, c->d_ep, c->nelem, c->rp, mlp, 1,
+                                             nullptr, c->stream));
+            HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
+        }
         HIPCHECK(c, mark_begin(c));
         HIPCHECK(c, launch_stage(c->dim, variant, c->flux, kind, a, stage_coef(c, i), c->scfg[i], c->stream));
         HIPCHECK(c, mark_end(c, kind == SK_FIRST ? PERRK_K_STAGE_FIRST
@@ -470,11 +491,12 @@ int enqueue_step(perrk_ctx *c, double *u)
                              c->stage_bytes[i], i));
     }
     HIPCHECK(c, mark_begin(c));
-    HIPCHECK(c, launch_relax_prepare(c->d_cs, c->d_case_off, c->n_cases, c->d_ep, c->nelem, c->rp,
-                                     c->have_mlp ? c->d_mlp : nullptr, c->stream));
+    HIPCHECK(c, launch_relax_prepare(c->d_cs, c->d_case_off, c->n_cases, c->d_ep, c->nelem, c->rp, mlp,
+                                     c->fused_first ? 2 : 0, c->d_partial, c->stream));
     HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
     if (c->rp.relax) {
-        for (int p = 0; p < c->opt.fast_passes; ++p) {
+        // launched residual passes: fast_passes evaluations in all, the fused one included
+        for (int p = c->fused_first ? 1 : 0; p < c->opt.fast_passes; ++p) {
             HIPCHECK(c, mark_begin(c));
             HIPCHECK(c, launch_relax_pass(c->dim, c->sys, u, c->d_d, c->d_elem, c->d_cs, c->d_partial, c->nelem, c->gam,
                                           p == 0, c->stream));
@@ -692,6 +714,34 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
             pos[(size_t)((uint32_t)order[(size_t)(c->active_off[i] + j)].elem_level & PERRK_NBR_MASK)] = -1;
     }
     c->active_off[c->S] = (int64_t)order.size();
+    if (c->viscous) {
+        // BR1 needs the gradients at the nodes of a stage's active elements and at the
+        // face nodes of their neighbours: the gradient pass of stage i runs over the
+        // active elements and their face neighbours (in the first stage's order)
+        c->n_grad.assign(c->S, 0);
+        c->grad_off.assign(c->S, 0);
+        c->grad_per_level.assign(c->S, std::vector<int64_t>(c->R, 0));
+        std::vector<char> need((size_t)c->nelem);
+        for (int i = 0; i < c->S; ++i) {
+            std::fill(need.begin(), need.end(), 0);
+            for (int64_t j = 0; j < c->n_active[i]; ++j) {
+                const ActiveEntry &en = order[(size_t)(c->active_off[i] + j)];
+                need[(size_t)((uint32_t)en.elem_level & PERRK_NBR_MASK)] = 1;
+                for (int f = 0; f < 2 * m->dim; ++f)
+                    need[(size_t)((uint32_t)elem[(uint32_t)en.elem_level & PERRK_NBR_MASK].nbr[f] & PERRK_NBR_MASK)] = 1;
+            }
+            c->grad_off[i] = (int64_t)order.size();
+            for (int64_t j = 0; j < c->n_active[0]; ++j) {
+                ActiveEntry en = order[(size_t)(c->active_off[0] + j)];
+                const int64_t e = (uint32_t)en.elem_level & PERRK_NBR_MASK;
+                if (!need[(size_t)e]) continue;
+                en.nbr[5] = 0;
+                order.push_back(en);
+                c->grad_per_level[i][elem[e].level]++;
+            }
+            c->n_grad[i] = (int32_t)(order.size() - c->grad_off[i]);
+        }
+    }
     // per-stage coefficients (without dt): K_1 and K_{i-1} multipliers per level
     std::vector<double> coef((size_t)c->S * 2 * PERRK_MAXR, 0.0);
     for (int i = 1; i < c->S; ++i)
@@ -712,8 +762,14 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     rp.relax = o.relax;
     rp.guess = o.guess;
     rp.nb = (int)c->bstages.size();
-    for (int j = 0; j < rp.nb && j < PERRK_MAXB; ++j) rp.bw[j] = c->b[c->bstages[j]];
+    rp.nb_pre = 0;
+    for (int j = 0; j < rp.nb && j < PERRK_MAXB; ++j) {
+        rp.bw[j] = c->b[c->bstages[j]];
+        if (c->bstages[j] < c->S - 1) rp.nb_pre = j + 1;
+    }
     c->rp = rp;
+    // the Euler stage kernel's last stage evaluates the first residual of the solve
+    c->fused_first = c->sys == PERRK_SYSTEM_EULER && !c->viscous;
     // GLM-MHD: 27 KB of LDS per wavefront; Navier-Stokes: 19 KB
     c->cfg.epb_mult = c->sys == PERRK_SYSTEM_GLM_MHD ? 1 : (c->viscous ? 2 : 4);
     c->scfg.assign(c->S, c->cfg);
@@ -740,7 +796,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
                 // single-precision stages after the first read U_n in single precision;
                 // the first stage writes that copy
                 const bool f32 = c->precision == PERRK_MIXED_ALL || (mixed && c->b[i] == 0.0);
-                double be = (i > 0 && f32) ? 4.0 : 8.0;  // U_n
+                double be = (i > 0 && i < c->S - 1 && f32) ? 4.0 : 8.0;  // U_n (double in the last stage)
                 if (i == 0) {
                     if (c->precision != PERRK_FP64) be += 4.0;       // write its single-precision copy
                     be += kb;                                         // write K_1
@@ -763,14 +819,15 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
                 bytes += be * dofe * per_level[r];
             }
             if (c->viscous) {
-                // the gradient pass over every element: its stage state and the gradient write
+                // the gradient pass over the stage's active elements and their neighbours:
+                // its stage state and the gradient write
                 for (int r = 0; r < c->R; ++r) {
                     const double c1 = coef[(size_t)i * 2 * PERRK_MAXR + r];
                     const double cp = coef[(size_t)i * 2 * PERRK_MAXR + PERRK_MAXR + r];
                     double be = 8.0 + 16.0;
                     if (i > 0 && c1 != 0.0) be += 8.0;
                     if (i > 0 && cp != 0.0) be += 8.0;
-                    bytes += be * dofe * per_level[r];
+                    bytes += be * dofe * c->grad_per_level[i][r];
                 }
             }
             c->stage_bytes[i] = bytes;
@@ -908,7 +965,7 @@ int perrk_step(perrk_ctx *c, void *u_dev, const double *dt, perrk_step_info *inf
             HIPCHECK(c, hipStreamSynchronize(c->stream));
             // a residual pass moves bytes only for the cases still being solved
             HIPCHECK(c, hipMemcpy(c->h_cs, c->d_cs, sizeof(CaseState) * c->n_cases, hipMemcpyDeviceToHost));
-            int pass = 0;
+            int pass = c->fused_first ? 1 : 0;  // evaluations before the first launched pass
             for (int k = 0; k < c->npev / 2; ++k) {
                 float ms = 0.0f;
                 HIPCHECK(c, hipEventElapsedTime(&ms, c->pev[2 * k], c->pev[2 * k + 1]));

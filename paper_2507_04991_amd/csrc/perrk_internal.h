@@ -97,7 +97,8 @@ struct RelaxParams {
     double tol_r, tol_step, bis_lo, bis_hi;
     int32_t max_newton, max_bisect, anchor, relax;
     int32_t guess;
-    int32_t nb;          // number of b != 0 stages (entropy-production slots)
+    int32_t nb;          // number of b != 0 stages (entropy-production slots, in stage order)
+    int32_t nb_pre;      // those before the last stage (their sums are known before it runs)
     double bw[PERRK_MAXB];  // their weights
 };
 
@@ -137,6 +138,8 @@ struct StageArgs {
     double *k64_out;          // optional double copy of K_i (b_i != 0 stages in mixed precision)
     const double *k64_1;      // last stage: double copies of K_1 and K_{S-1}, or NULL to read the
     const double *k64_sm1;    //   stage storage
+    double *rx_partial;       // last stage: [nelem][4] partials of the first residual evaluation
+                              //   at each case's gamma (as a residual pass writes them), or NULL
 };
 
 // Stage kernel variants.
@@ -159,9 +162,13 @@ size_t stage_lds_bytes(int dim, int variant, int wpb, int sys);
 // Navier-Stokes stage kernel (2D, variant 0 only).  sys: PERRK_SYSTEM_*.
 hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArgs &a, const double *coef,
                         LaunchCfg cfg, hipStream_t s);
+// phase 0: after the last stage, everything below; 1: before the last stage (the
+// entropy production of the earlier stages, solver reset, starting gamma); 2: after
+// a last stage that evaluated the first residual (its entropy production, dH, and
+// the solver update from that evaluation).
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases,
                                 const double *ep_partial, int64_t nelem, RelaxParams rp,
-                                const float *mlp, hipStream_t s);
+                                const float *mlp, int phase, const double *rx_partial, hipStream_t s);
 hipError_t launch_relax_pass(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                              const CaseState *cs, double *partial, int64_t nelem, double gam, bool first,
                              hipStream_t s);

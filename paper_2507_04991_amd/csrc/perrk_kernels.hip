@@ -98,8 +98,6 @@ __device__ __forceinline__ double node_weight(int node)
 #define C_R4 (-428.0 / 14175.0)
 #define C_R5 (-10196.0 / 467775.0)
 #define C_R6 (-10719068.0 / 638512875.0)
-#define C_R7 (-25865068.0 / 1915538625.0)
-#define C_R8 (-5472607916.0 / 488462349375.0)
 
 // 1/x as every kernel computes it: the hardware reciprocal in single precision,
 // the refined one below in double (the same expression wherever a value must
@@ -419,6 +417,58 @@ __device__ __forceinline__ double entropy_diff(const double *u, const double *du
     const double dp = (gam - 1.0) * (du[DIM + 1] - (mdm + 0.5 * dm2) / rho1 + drho * m2 / (2.0 * rho * rho1));
     const double p1 = p + dp;
     return -drho * (log(p1) - gam * log(rho1)) - rho * (log1p(dp / p) - gam * log1p(drho / rho));
+}
+
+// log1p(x): series x - x^2/2 + ... + x^9/9 for |x| < 1e-2 (omitted term < 1e-20/10),
+// the library function otherwise.
+__device__ __forceinline__ double log1p_small(double x)
+{
+    if (fabs(x) < 1.0e-2)
+        return x * (1.0 + x * (-1.0 / 2.0 + x * (1.0 / 3.0 + x * (-1.0 / 4.0 + x * (1.0 / 5.0 + x * (-1.0 / 6.0 +
+               x * (1.0 / 7.0 + x * (-1.0 / 8.0 + x * (1.0 / 9.0)))))))));
+    return log1p(x);
+}
+
+// At one node, with du = g dt d: the entropy difference s(u + du) - s(u)
+// (cancellation-free form) and w(u + du) . (dt d), sharing the intermediate
+// quantities.  With rho' = rho + drho, p' = p + dp:
+//   s' - s = -drho log(p' rho'^-gamma) - rho [log1p(dp/p) - gamma log1p(drho/rho)],
+//   log(p' rho'^-gamma) = log(p rho^-gamma) + log1p(dp/p) - gamma log1p(drho/rho),
+//   w' = (gamma - log(p' rho'^-gamma) - (gamma-1) |m'|^2 / (2 rho' p'), (gamma-1) m'/p', -(gamma-1) rho'/p').
+template <int DIM>
+__device__ __forceinline__ void relax_node(const double *u, const double *dv, double g, double dt, double gam,
+                                           double &ds, double &wd)
+{
+    const double rho = u[0];
+    double du[DIM + 2];
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) du[v] = g * dt * dv[v];
+    const double drho = du[0], rho1 = rho + drho;
+    // reciprocals by rcp64 (within an ulp; a correctly rounded division costs
+    // about three times as many instructions, and this runs per node and pass)
+    const double ir = rcp64(rho), ir1 = rcp64(rho1);
+    double mdm = 0.0, dm2 = 0.0, m2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        mdm += u[1 + k] * du[1 + k];
+        dm2 += du[1 + k] * du[1 + k];
+        m2 += u[1 + k] * u[1 + k];
+    }
+    const double g1 = gam - 1.0;
+    const double p = g1 * (u[DIM + 1] - 0.5 * m2 * ir);
+    const double dp = g1 * (du[DIM + 1] - (mdm + 0.5 * dm2) * ir1 + 0.5 * drho * m2 * ir * ir1);
+    const double p1 = p + dp;
+    const double lp = log1p_small(dp * rcp64(p)), lr = log1p_small(drho * ir);
+    const double sth0 = log(p) - gam * log(rho);
+    const double sth1 = sth0 + lp - gam * lr;
+    ds = -drho * sth1 - rho * (lp - gam * lr);
+    const double ip1 = rcp64(p1);
+    const double m12 = m2 + 2.0 * mdm + dm2;
+    double dot = (gam - sth1 - 0.5 * g1 * m12 * ir1 * ip1) * dv[0];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) dot += g1 * (u[1 + k] + du[1 + k]) * ip1 * dv[1 + k];
+    dot += -g1 * rho1 * ip1 * dv[DIM + 1];
+    wd = dt * dot;
 }
 
 
@@ -1001,8 +1051,9 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         c1 = WL ? __shfl(cf, lvl) : elt(coef, (uint32_t)lvl);
         cp = WL ? __shfl(cf, PERRK_MAXR + lvl) : elt(coef, (uint32_t)(PERRK_MAXR + lvl));
     }
-    // single-precision stages after the first read the single-precision copy of U_n
-    using UT = typename std::conditional<sizeof(T) == 4 && KIND != SK_FIRST, float, double>::type;
+    // single-precision middle stages read the single-precision copy of U_n (the last
+    // stage reads U_n in double precision: the first residual evaluation needs it)
+    using UT = typename std::conditional<sizeof(T) == 4 && KIND == SK_MID, float, double>::type;
     NodeRaw<V, KT, UT> own;
     // single-precision stages have their level coefficients at hand already (from
     // cross-lane reads) and skip K_{i-1} where its coefficient is zero
@@ -1178,22 +1229,30 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
 #pragma unroll
     for (int v = 0; v < V; ++v) k[v] = (double)du[v];
 
+    // last stage: the direction d = b_S K_S + b_{S-1} K_{S-1} + b_1 K_1 (+ earlier terms)
+    double dvv[V];
+    if constexpr (KIND == SK_LAST) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            double dv = a.bs * k[v];
+            double ksm1 = (double)own.kp[v], k1 = (double)own.k1[v];
+            if constexpr (sizeof(T) == 8) {
+                if (a.k64_sm1) ksm1 = k64sm1[v];
+                if (a.k64_1) k1 = k64_1[v];
+            }
+            if (a.bsm1 != 0.0) dv += a.bsm1 * ksm1;
+            if (a.b1 != 0.0) dv += a.b1 * k1;
+            if (a.d_has) dv += dacc[v];
+            dvv[v] = dv;
+        }
+    }
     if (valid) {
         const size_t field = (size_t)a.nelem * NPE;
         const uint32_t n = (uint32_t)e * NPE + node, o8 = n * 8u, ok = n * (uint32_t)sizeof(KT);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             if (KIND == SK_LAST) {
-                double dv = a.bs * k[v];
-                double ksm1 = (double)own.kp[v], k1 = (double)own.k1[v];
-                if constexpr (sizeof(T) == 8) {
-                    if (a.k64_sm1) ksm1 = k64sm1[v];
-                    if (a.k64_1) k1 = k64_1[v];
-                }
-                if (a.bsm1 != 0.0) dv += a.bsm1 * ksm1;
-                if (a.b1 != 0.0) dv += a.b1 * k1;
-                if (a.d_has) dv += dacc[v];
-                bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
+                bstore<double>(dvv[v], field_rsrc<double>(a.d_out, v, field), o8);
             } else {
                 bstore<KT>((KT)du[v], field_rsrc<KT>(a.Kout, v, field), ok);
                 if (a.k64_out) bstore<double>(k[v], field_rsrc<double>(a.k64_out, v, field), o8);
@@ -1202,6 +1261,39 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
                     if (a.acc_mode == 2) dv += bload<double>(field_rsrc<double>(a.d_out, v, field), o8);
                     bstore<double>(dv, field_rsrc<double>(a.d_out, v, field), o8);
                 }
+            }
+        }
+    }
+    if constexpr (KIND == SK_LAST) {
+        // the first residual evaluation of the relaxation solve, at the case's starting
+        // value gamma_0: per element J sum q [s(u_n + gamma_0 dt d) - s(u_n)],
+        // J sum q w(u_n + gamma_0 dt d) . dt d and sum |d|, with the same per-node
+        // arithmetic and the same butterfly as a residual pass, so the partials are
+        // those a pass over the stored d would give, bit for bit
+        if (a.rx_partial != nullptr) {
+            const double g0 = elt(a.cs, (uint32_t)act.y).gamma;
+            double un[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) un[v] = (double)own.u[v];
+            double sabs = 0.0;
+#pragma unroll
+            for (int v = 0; v < V; ++v) sabs += fabs(dvv[v]);
+            double ds, wd;
+            relax_node<DIM>(un, dvv, g0, dt, a.gam, ds, wd);
+            const double q = node_weight<DIM>(node);
+            double sr = q * ds, srp = q * wd;
+#pragma unroll
+            for (int off = NPE / 2; off >= 1; off >>= 1) {
+                sr += __shfl_xor(sr, off);
+                srp += __shfl_xor(srp, off);
+                sabs += __shfl_xor(sabs, off);
+            }
+            if (valid && node == 0) {
+                double *pp = a.rx_partial + (size_t)e * 4;
+                pp[0] = ei.jac * sr;
+                pp[1] = ei.jac * srp;
+                pp[2] = 0.0;
+                pp[3] = sabs;
             }
         }
     }
@@ -2115,17 +2207,34 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) ns_stage_kernel(const Stag
 // ---------------------------------------------------------------- reductions
 // Sum of NC per-element partials over [b, e) by PERRK_RED_THREADS threads in a
 // fixed order (strided sequential sums, then a fixed tree).  Result in out on
-// every thread.
+// every thread.  Each thread issues the loads of CS_AHEAD of its elements before
+// adding them (in the same order), so that a large case is not summed at one
+// memory latency per element.
+constexpr int CS_AHEAD = 8;
+
 template <int NC>
 __device__ __forceinline__ void case_sum(const double *part, int stride, int64_t b, int64_t e,
                                          double *out)
 {
     __shared__ double red[NC][PERRK_RED_THREADS];
     const int t = threadIdx.x;
+    constexpr int64_t T = PERRK_RED_THREADS;
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int64_t i = b + t; i < e; i += PERRK_RED_THREADS) {
+    int64_t i = b + t;
+    for (; i + (CS_AHEAD - 1) * T < e; i += CS_AHEAD * T) {
+        double x[CS_AHEAD][NC];
+#pragma unroll
+        for (int k = 0; k < CS_AHEAD; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[k][c] = part[(size_t)(i + k * T) * stride + c];
+#pragma unroll
+        for (int k = 0; k < CS_AHEAD; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] += x[k][c];
+    }
+    for (; i < e; i += T) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c] += part[(size_t)i * stride + c];
     }
@@ -2142,58 +2251,6 @@ __device__ __forceinline__ void case_sum(const double *part, int stride, int64_t
 #pragma unroll
     for (int c = 0; c < NC; ++c) out[c] = red[c][0];
     __syncthreads();
-}
-
-// log1p(x): series x - x^2/2 + ... + x^9/9 for |x| < 1e-2 (omitted term < 1e-20/10),
-// the library function otherwise.
-__device__ __forceinline__ double log1p_small(double x)
-{
-    if (fabs(x) < 1.0e-2)
-        return x * (1.0 + x * (-1.0 / 2.0 + x * (1.0 / 3.0 + x * (-1.0 / 4.0 + x * (1.0 / 5.0 + x * (-1.0 / 6.0 +
-               x * (1.0 / 7.0 + x * (-1.0 / 8.0 + x * (1.0 / 9.0)))))))));
-    return log1p(x);
-}
-
-// At one node, with du = g dt d: the entropy difference s(u + du) - s(u)
-// (cancellation-free form) and w(u + du) . (dt d), sharing the intermediate
-// quantities.  With rho' = rho + drho, p' = p + dp:
-//   s' - s = -drho log(p' rho'^-gamma) - rho [log1p(dp/p) - gamma log1p(drho/rho)],
-//   log(p' rho'^-gamma) = log(p rho^-gamma) + log1p(dp/p) - gamma log1p(drho/rho),
-//   w' = (gamma - log(p' rho'^-gamma) - (gamma-1) |m'|^2 / (2 rho' p'), (gamma-1) m'/p', -(gamma-1) rho'/p').
-template <int DIM>
-__device__ __forceinline__ void relax_node(const double *u, const double *dv, double g, double dt, double gam,
-                                           double &ds, double &wd)
-{
-    const double rho = u[0];
-    double du[DIM + 2];
-#pragma unroll
-    for (int v = 0; v < DIM + 2; ++v) du[v] = g * dt * dv[v];
-    const double drho = du[0], rho1 = rho + drho;
-    // reciprocals by rcp64 (within an ulp; a correctly rounded division costs
-    // about three times as many instructions, and this runs per node and pass)
-    const double ir = rcp64(rho), ir1 = rcp64(rho1);
-    double mdm = 0.0, dm2 = 0.0, m2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        mdm += u[1 + k] * du[1 + k];
-        dm2 += du[1 + k] * du[1 + k];
-        m2 += u[1 + k] * u[1 + k];
-    }
-    const double g1 = gam - 1.0;
-    const double p = g1 * (u[DIM + 1] - 0.5 * m2 * ir);
-    const double dp = g1 * (du[DIM + 1] - (mdm + 0.5 * dm2) * ir1 + 0.5 * drho * m2 * ir * ir1);
-    const double p1 = p + dp;
-    const double lp = log1p_small(dp * rcp64(p)), lr = log1p_small(drho * ir);
-    const double sth0 = log(p) - gam * log(rho);
-    const double sth1 = sth0 + lp - gam * lr;
-    ds = -drho * sth1 - rho * (lp - gam * lr);
-    const double ip1 = rcp64(p1);
-    const double m12 = m2 + 2.0 * mdm + dm2;
-    double dot = (gam - sth1 - 0.5 * g1 * m12 * ir1 * ip1) * dv[0];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) dot += g1 * (u[1 + k] + du[1 + k]) * ip1 * dv[1 + k];
-    dot += -g1 * rho1 * ip1 * dv[DIM + 1];
-    wd = dt * dot;
 }
 
 // The same for ideal GLM-MHD (nine variables): the pressure change gains
@@ -2399,29 +2456,62 @@ __device__ void relax_update(CaseState &C, const double *S, const RelaxParams &r
     }
 }
 
-// One workgroup per case, before the first residual pass: sums the stage
-// entropy production of the case (fixed order), forms dH = dt sum_i b_i e_i,
-// resets the solver state and sets the first evaluation point (the previous
-// gamma, or that plus the learned increment).
+// One workgroup per case.  Phases 0 (after the last stage) and 1 (before it, when
+// the last stage evaluates the first residual): sums the stage entropy production
+// of the b_i != 0 stages known so far in a fixed order, resets the solver state
+// and sets the first evaluation point (the previous gamma, or that plus the
+// learned increment); phase 0 also forms dH = dt sum_i b_i e_i.  Phase 2 (after
+// such a last stage): adds the last stage's entropy production, forms dH and
+// advances the solver with the evaluation the last stage made, as
+// relax_finalize_kernel does after a residual pass.
 __global__ void __launch_bounds__(PERRK_RED_THREADS)
 relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, int64_t nelem,
-                     RelaxParams rp, const float *mlp)
+                     RelaxParams rp, const float *mlp, int phase, const double *rx_partial)
 {
     __shared__ float sx[8], sh1[32], sh2[32];
     const int c = blockIdx.x;
     const int64_t b = case_off[c], e = case_off[c + 1];
+    CaseState &C = cs[c];
+    if (phase == 2) {
+        double ej[PERRK_MAXB] = {};
+        for (int j = rp.nb_pre; j < rp.nb; ++j) {
+            double o[1];
+            case_sum<1>(ep + (size_t)j * nelem, 1, b, e, o);
+            ej[j] = o[0];
+        }
+        double S[4];
+        case_sum<4>(rx_partial, 4, b, e, S);
+        if (threadIdx.x != 0) return;
+        double dH = 0.0;
+        for (int j = 0; j < rp.nb; ++j) {
+            if (j >= rp.nb_pre) C.e[j] = ej[j];
+            dH += rp.bw[j] * C.e[j];
+        }
+        C.dH = C.dt * dH;
+        if (C.state == RS_NEWTON) {
+            relax_update(C, S, rp);
+        } else if (C.state == RS_EVAL1) {  // no relaxation: the step's bookkeeping at gamma = 1
+            const double off = (rp.anchor == 1) ? C.offset : 0.0;
+            C.gamma_acc = 1.0;
+            C.H_delta = S[0];
+            C.r = S[0] - C.dH + off;
+            C.state = RS_DONE;
+        }  // (RS_BIS_INIT: no Newton budget; the residual passes open the bracket)
+        return;
+    }
+    const int nsum = phase == 0 ? rp.nb : rp.nb_pre;
     double ej[PERRK_MAXB] = {};
-    for (int j = 0; j < rp.nb; ++j) {
+    for (int j = 0; j < nsum; ++j) {
         double o[1];
         case_sum<1>(ep + (size_t)j * nelem, 1, b, e, o);
         ej[j] = o[0];
     }
-    CaseState &C = cs[c];
     // learned guess of the increment gamma_n - gamma_{n-1} (MLP 8-32-32-1, tanh; the
     // weights are followed by the feature mean[8], scale[8] and the output scale and
     // shift).  Features, formed in double precision: the last two increments of
-    // gamma, gamma_{n-1} - 1, dt, and the stage entropy-production terms of this step
-    // divided by the sum of their magnitudes (zero-padded to four).
+    // gamma, gamma_{n-1} - 1, dt, and the entropy production of this step's b_i != 0
+    // stages before the last stage divided by the sum of their magnitudes
+    // (zero-padded to four).
     const bool learned = rp.guess == 1 && mlp != nullptr && C.nsteps >= 3;
     const float *W1 = mlp, *b1 = W1 + 256, *W2 = b1 + 32, *b2 = W2 + 1024, *W3 = b2 + 32, *b3 = W3 + 32;
     const float *mean = b3 + 1, *scale = mean + 8, *oscale = scale + 8;
@@ -2433,8 +2523,8 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
             x[2] = C.ghist[0];
             x[3] = C.dt;
             double sabs = 0.0;
-            for (int j = 0; j < rp.nb; ++j) sabs += fabs(ej[j]);
-            for (int j = 0; j < 4; ++j) x[4 + j] = (j < rp.nb && sabs > 0.0) ? ej[j] / sabs : 0.0;
+            for (int j = 0; j < rp.nb_pre; ++j) sabs += fabs(ej[j]);
+            for (int j = 0; j < 4; ++j) x[4 + j] = (j < rp.nb_pre && sabs > 0.0) ? ej[j] / sabs : 0.0;
             for (int i = 0; i < 8; ++i) sx[i] = (float)((x[i] - (double)mean[i]) * (double)scale[i]);
         }
         __syncthreads();
@@ -2455,11 +2545,11 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
     }
     if (threadIdx.x != 0) return;
     double dH = 0.0;
-    for (int j = 0; j < rp.nb; ++j) {
+    for (int j = 0; j < nsum; ++j) {
         C.e[j] = ej[j];
         dH += rp.bw[j] * ej[j];
     }
-    C.dH = C.dt * dH;
+    if (phase == 0) C.dH = C.dt * dH;
     C.k = 0;
     C.iters = 0;
     C.passes = 0;
@@ -2479,6 +2569,7 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
     C.gamma_b = g0;
     C.H_delta = 0.0;
     C.state = rp.relax ? RS_NEWTON : RS_EVAL1;
+    if (!rp.relax) C.gamma = 1.0;  // the step's bookkeeping evaluation is at gamma = 1
     if (rp.relax && rp.max_newton <= 0) {  // no Newton budget: open the bracket at once
         C.state = RS_BIS_INIT;
         C.flags |= PERRK_FLAG_BISECT;
@@ -2804,10 +2895,11 @@ hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArg
 }
 
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases, const double *ep,
-                                int64_t nelem, RelaxParams rp, const float *mlp, hipStream_t s)
+                                int64_t nelem, RelaxParams rp, const float *mlp, int phase,
+                                const double *rx_partial, hipStream_t s)
 {
     hipLaunchKernelGGL(relax_prepare_kernel, dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, cs, case_off,
-                       ep, nelem, rp, mlp);
+                       ep, nelem, rp, mlp, phase, rx_partial);
     return hipGetLastError();
 }
 

@@ -3,12 +3,13 @@
 A small network (8 -> 32 -> 32 -> 1, tanh) predicts the increment
 gamma_n - gamma_{n-1} of a case's relaxation parameter from: the last two
 increments, gamma_{n-1} - 1, the step size and the entropy-production terms of
-this step's first four stages with b_i != 0 (divided by the sum of the
-magnitudes of all of them, zero-padded to four).  It is trained on (features, increment) pairs logged
-from the method's own solves, with the library's HIP forward / gradient / Adam
-kernels; the step evaluates it before the first residual pass once a case has
-taken three steps.  Newton and bisection still decide the accepted gamma, so
-the guess only changes how many passes a step needs.
+this step's stages with b_i != 0 that come before the last stage (divided by the
+sum of their magnitudes, zero-padded to four).  It is trained on (features,
+increment) pairs logged from the method's own solves, with the library's HIP
+forward / gradient / Adam kernels; the step evaluates it before the last stage
+(whose epilogue makes the first residual evaluation at the predicted point)
+once a case has taken three steps.  Newton and bisection still decide the
+accepted gamma, so the guess only changes how many evaluations a step needs.
 
 The feature definition here matches the one evaluated on the device.
 """
@@ -25,21 +26,29 @@ MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
 DEFAULT_MODEL = os.path.join(MODEL_DIR, "guess_vortex_ensemble_p3.npz")
 
 
-def features(ghist, dt, e, nb):
-    """ghist: [3] previous gamma - 1 (most recent first); e: stage entropy production [nb]."""
+def pre_last_count(tab):
+    """Stages with b_i != 0 before the last stage (their entropy production is known
+    when the guess is made)."""
+    b = np.asarray(tab["b"])
+    return int(np.count_nonzero(b[:-1]))
+
+
+def features(ghist, dt, e, nb_pre):
+    """ghist: [3] previous gamma - 1 (most recent first); e: entropy production of the
+    b_i != 0 stages in stage order, of which the first nb_pre come before the last stage."""
     x = np.zeros(NFEAT)
     x[0] = ghist[0] - ghist[1]
     x[1] = ghist[1] - ghist[2]
     x[2] = ghist[0]
     x[3] = dt
-    s = float(np.sum(np.abs(e[:nb])))
-    m = min(nb, 4)
+    s = float(np.sum(np.abs(e[:nb_pre])))
+    m = min(nb_pre, 4)
     if s > 0.0:
         x[4:4 + m] = np.asarray(e[:m]) / s
     return x
 
 
-def collect(stepper, u, dt, steps, nb):
+def collect(stepper, u, dt, steps, nb_pre):
     """Advance `steps` synchronous steps, logging one (features, gamma_n - gamma_{n-1})
     pair per case and step once the case has three earlier gammas.  Steps whose
     solve fell back or was trivial are skipped.  Returns X, Y, the passes of the
@@ -53,7 +62,7 @@ def collect(stepper, u, dt, steps, nb):
         for c, inf in enumerate(infos):
             g1 = inf["gamma"] - 1.0
             if inf["flags"] == 0 and step >= 3:
-                X.append(features(hist[c], dt[c], np.asarray(inf["e"]), nb))
+                X.append(features(hist[c], dt[c], np.asarray(inf["e"]), nb_pre))
                 Y.append(g1 - hist[c, 0])
                 passes.append(inf["passes"])
                 prev.append(hist[c, 0])
@@ -174,7 +183,7 @@ def main(argv=None):
     d = P.Descriptors(prob["faces"], prob["lev"], prob["tab"], precision=P.MIXED)
     st = P.Stepper(d, P.default_options())
     u = torch.tensor(prob["U0"], device="cuda").contiguous()
-    X, Y, passes, prev = collect(st, u, prob["dt"], args.steps, nb=int(np.count_nonzero(prob["tab"]["b"])))
+    X, Y, passes, prev = collect(st, u, prob["dt"], args.steps, nb_pre=pre_last_count(prob["tab"]))
     st.close()
     if args.save_data:
         np.savez(args.save_data, X=X, Y=Y, passes=passes, prev=prev)

@@ -96,14 +96,14 @@ def test_step_uses_learned_increment(P):
     st = P.Stepper(d, P.default_options(guess=P.GUESS_MLP, tol_r=1.0e30))
     st.set_guess_model(full, mean, scale)
     u = dev(U0)
-    nb = int(np.count_nonzero(tab["b"]))
+    nb_pre = L.pre_last_count(tab)
     hist = np.zeros(3)
     gamma_prev = 1.0
     for step in range(6):
         inf = st.step(u, np.array([dt]))[0]
         expect = gamma_prev
         if step >= 3:
-            x = L.features(hist, dt, np.asarray(inf["e"]), nb)
+            x = L.features(hist, dt, np.asarray(inf["e"]), nb_pre)
             xn = ((x - mean.astype(np.float64)) * scale.astype(np.float64)).astype(np.float32)
             y = M.forward(w.astype(np.float64), xn[None, :].astype(np.float64))[0]
             expect = gamma_prev + (y * float(full[-2]) + float(full[-1]))

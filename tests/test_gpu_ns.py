@@ -90,28 +90,60 @@ def test_viscous_shock_steps_match_oracle(P, oracle):
         assert info["passes"] == iref["passes"], n
         assert abs(info["gamma"] - iref["gamma"]) <= 1e-12, n
         assert rel_err(u.cpu().numpy(), Uref) < 1e-12, n
-    assert abs(st.relaxation_state()[2][0] - tt) <= 1e-14
+    assert abs(st.relaxation_state().t[0] - tt) <= 1e-14
     st.close()
 
 
-def test_viscous_shock_converges_under_refinement(P):
+# the relaxation solver settings of Sec. 4.3.2: bisection only, on [0.8, 1.2], at
+# most 25 bisection steps (an evaluation is still accepted only with |r| <= 1e-12)
+BISECT = dict(max_newton=0, bisect_lo=0.8, bisect_hi=1.2, max_bisect=25)
+BISECT_ORACLE = dict(max_newton=0, bis_lo=0.8, bis_hi=1.2, max_bisect=25)
+
+
+def test_viscous_shock_bisection_steps_match_oracle(P, oracle):
+    """With the Sec. 4.3.2 solver settings: passes, flags and gamma of every step
+    equal the oracle's, and the state matches to 1e-12."""
+    from paper_2507_04991_amd import problems
+    pb = problems.viscous_shock(n=12)
+    f, lev, dt = pb["faces"][0], pb["lev"][0], float(pb["dt"][0])
+    print("case ns viscous shock, bisection settings, 5 steps", flush=True)
+    st, u = make(P, f, pb["U0"], pb["tab"], lev, 3, 1, 1, **BISECT)
+    m, t = omesh(oracle, f, 3, 1, 1), otab(oracle, pb["tab"])
+    Uref, g, tt = pb["U0"].copy(), 1.0, 0.0
+    for n in range(5):
+        info = st.step(u, np.array([dt]))[0]
+        Uref, iref = oracle.step(m, t, lev, Uref, dt, oracle.relax_options(gamma0=g, t0=tt, **BISECT_ORACLE))
+        g = iref["gamma"]
+        tt += g * dt
+        assert info["flags"] == iref["flags"] == P.FLAG_BISECT, n
+        assert info["passes"] == iref["passes"], n
+        assert abs(info["gamma"] - iref["gamma"]) <= 1e-12 and abs(info["r"]) <= 1e-12, n
+        assert rel_err(u.cpu().numpy(), Uref) < 1e-12, n
+    st.close()
+
+
+@pytest.mark.parametrize("solver", ["newton", "bisection"])
+def test_viscous_shock_converges_under_refinement(P, solver):
     """Sec. 4.3.2 study: p = 4, E = {6, 10}, k = 3, dt = 0.035 dx_min^2, to t = 0.5
     on 12, 24 and 48 cells: the domain-normalised L1 error of the momentum falls
     at an observed order above 3.5 (the oracle gives 3.3e-5 and 1.8e-6 on the
-    first two meshes)."""
+    first two meshes); with Newton from the previous gamma and with the paper's
+    bisection settings (every step then accepts a bisection point)."""
     from paper_2507_04991_amd import problems
     from paper_2507_04991_amd import workloads as W
+    opt = BISECT if solver == "bisection" else {}
     errs = []
     for n in (12, 24, 48):
         pb = problems.viscous_shock(n=n)
         f, lev, dt = pb["faces"][0], pb["lev"][0], float(pb["dt"][0])
-        st, u = make(P, f, pb["U0"], pb["tab"], lev, 3, 1, 1)
+        st, u = make(P, f, pb["U0"], pb["tab"], lev, 3, 1, 1, **opt)
         nsteps = int(math.ceil(0.5 / dt))
         for _ in range(nsteps - 1):
             st.step(u, np.array([dt]), info=False)
         info = st.step(u, np.array([dt]))[0]
-        assert info["flags"] == 0
-        t = st.relaxation_state()[2][0]
+        assert info["flags"] == (P.FLAG_BISECT if solver == "bisection" else 0)
+        assert abs(info["r"]) <= 1e-12
+        t = st.relaxation_state().t[0]
         co = W.node_coords(f)
         Ue = W.viscous_shock_state(co, t, GAM, MU)
         w = W.element_widths(f)
