@@ -32,6 +32,7 @@
 // independent of the launch shape, so results are bitwise reproducible.
 
 #include "perrk_internal.h"
+#include "perrk_log.h"
 
 #include <math.h>
 
@@ -91,7 +92,8 @@ __device__ __forceinline__ double node_weight(int node)
 // coefficients of the reciprocal power series): in double precision for
 // u < 2.5e-3, truncated after u^6; in single precision for u < 1e-2, truncated
 // after u^3 (the omitted terms are below the rounding unit).  Otherwise from
-// log1p((a-b)/b) (the hardware logarithm of the ratio in single precision).
+// log1p((a-b)/b) (flog1p in double precision, the hardware logarithm of the
+// ratio in single), with reciprocals instead of divisions.
 #define C_R1 (-1.0 / 3.0)
 #define C_R2 (-4.0 / 45.0)
 #define C_R3 (-44.0 / 945.0)
@@ -122,6 +124,14 @@ __device__ __forceinline__ double rcp64(double x)
 template <>
 __device__ __forceinline__ double recip<double>(double x) { return rcp64(x); }
 
+// Double-precision logarithms of the entropy arithmetic (perrk_log.h: range
+// reduction to [sqrt(1/2), sqrt(2)) and the atanh series; a few ulp).
+struct Rcp64 {
+    __device__ double operator()(double x) const { return rcp64(x); }
+};
+__device__ __forceinline__ double flog(double x) { return perrk_log::log_f64(x, Rcp64{}); }
+__device__ __forceinline__ double flog1p(double x) { return perrk_log::log1p_f64(x, Rcp64{}); }
+
 __device__ __forceinline__ double lmean(double a, double b)
 {
     const double d = a - b, s = a + b;
@@ -131,7 +141,7 @@ __device__ __forceinline__ double lmean(double a, double b)
         const double P = 1.0 + u * (C_R1 + u * (C_R2 + u * (C_R3 + u * (C_R4 + u * (C_R5 + u * C_R6)))));
         return 0.5 * s * P;
     }
-    return d / log1p(d / b);
+    return d * rcp64(flog1p(d * rcp64(b)));
 }
 
 __device__ __forceinline__ double inv_lmean(double a, double b)
@@ -144,7 +154,7 @@ __device__ __forceinline__ double inv_lmean(double a, double b)
                          u * (1.0 / 11.0 + u * (1.0 / 13.0))))));
         return 2.0 * rs * F;
     }
-    return log1p(d / b) / d;
+    return flog1p(d * rcp64(b)) * rcp64(d);
 }
 
 __device__ __forceinline__ float lmean(float a, float b)
@@ -382,7 +392,7 @@ __device__ __forceinline__ void entropy_vars(const double *u, double gam, double
     const double p = (gam - 1.0) * (u[DIM + 1] - 0.5 * m2 * ir);
     const double rp = rho * rcp64(p);
     const double g1rp = (gam - 1.0) * rp;
-    w[0] = gam - (log(p) - gam * log(rho)) - 0.5 * g1rp * m2 * ir * ir;
+    w[0] = gam - (flog(p) - gam * flog(rho)) - 0.5 * g1rp * m2 * ir * ir;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) w[1 + k] = g1rp * u[1 + k] * ir;
     w[DIM + 1] = -g1rp;
@@ -396,37 +406,17 @@ __device__ __forceinline__ double entropy_density(const double *u, double gam)
 #pragma unroll
     for (int k = 0; k < DIM; ++k) m2 += u[1 + k] * u[1 + k];
     const double p = (gam - 1.0) * (u[DIM + 1] - 0.5 * m2 / u[0]);
-    return -u[0] * (log(p) - gam * log(u[0]));
-}
-
-// s(u + du) - s(u) without cancellation: with rho' = rho + drho,
-// dp = (gamma-1) [dE - (m.dm + |dm|^2/2) / rho' + drho |m|^2 / (2 rho rho')] = p' - p and
-// s' - s = -drho (log p' - gamma log rho') - rho [log1p(dp/p) - gamma log1p(drho/rho)].
-template <int DIM>
-__device__ __forceinline__ double entropy_diff(const double *u, const double *du, double gam)
-{
-    const double rho = u[0], drho = du[0], rho1 = rho + drho;
-    double mdm = 0.0, dm2 = 0.0, m2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        mdm += u[1 + k] * du[1 + k];
-        dm2 += du[1 + k] * du[1 + k];
-        m2 += u[1 + k] * u[1 + k];
-    }
-    const double p = (gam - 1.0) * (u[DIM + 1] - 0.5 * m2 / rho);
-    const double dp = (gam - 1.0) * (du[DIM + 1] - (mdm + 0.5 * dm2) / rho1 + drho * m2 / (2.0 * rho * rho1));
-    const double p1 = p + dp;
-    return -drho * (log(p1) - gam * log(rho1)) - rho * (log1p(dp / p) - gam * log1p(drho / rho));
+    return -u[0] * (flog(p) - gam * flog(u[0]));
 }
 
 // log1p(x): series x - x^2/2 + ... + x^9/9 for |x| < 1e-2 (omitted term < 1e-20/10),
-// the library function otherwise.
+// flog1p otherwise.
 __device__ __forceinline__ double log1p_small(double x)
 {
     if (fabs(x) < 1.0e-2)
         return x * (1.0 + x * (-1.0 / 2.0 + x * (1.0 / 3.0 + x * (-1.0 / 4.0 + x * (1.0 / 5.0 + x * (-1.0 / 6.0 +
                x * (1.0 / 7.0 + x * (-1.0 / 8.0 + x * (1.0 / 9.0)))))))));
-    return log1p(x);
+    return flog1p(x);
 }
 
 // At one node, with du = g dt d: the entropy difference s(u + du) - s(u)
@@ -459,7 +449,7 @@ __device__ __forceinline__ void relax_node(const double *u, const double *dv, do
     const double dp = g1 * (du[DIM + 1] - (mdm + 0.5 * dm2) * ir1 + 0.5 * drho * m2 * ir * ir1);
     const double p1 = p + dp;
     const double lp = log1p_small(dp * rcp64(p)), lr = log1p_small(drho * ir);
-    const double sth0 = log(p) - gam * log(rho);
+    const double sth0 = flog(p) - gam * flog(rho);
     const double sth1 = sth0 + lp - gam * lr;
     ds = -drho * sth1 - rho * (lp - gam * lr);
     const double ip1 = rcp64(p1);
@@ -1516,7 +1506,7 @@ __device__ __forceinline__ void mhd_entropy_vars(const double *u, double gam, do
     }
     const double p = (gam - 1.0) * (u[4] - 0.5 * m2 * ir - 0.5 * B2 - 0.5 * u[8] * u[8]);
     const double g1rp = (gam - 1.0) * rho / p;
-    w[0] = gam - (log(p) - gam * log(rho)) - 0.5 * g1rp * m2 * ir * ir;
+    w[0] = gam - (flog(p) - gam * flog(rho)) - 0.5 * g1rp * m2 * ir * ir;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         w[1 + k] = g1rp * u[1 + k] * ir;
@@ -1536,7 +1526,7 @@ __device__ __forceinline__ double mhd_entropy_density(const double *u, double ga
     }
     const double rho = u[0];
     const double p = (gam - 1.0) * (u[4] - 0.5 * m2 / rho - 0.5 * B2 - 0.5 * u[8] * u[8]);
-    return -rho * (log(p) - gam * log(rho));
+    return -rho * (flog(p) - gam * flog(rho));
 }
 
 template <int KIND>
@@ -2281,7 +2271,7 @@ __device__ __forceinline__ void relax_node_mhd(const double *u, const double *dv
                             - (u[8] * du[8] + 0.5 * du[8] * du[8]));
     const double p1 = p + dp;
     const double lp = log1p_small(dp / p), lr = log1p_small(drho * ir);
-    const double sth0 = log(p) - gam * log(rho);
+    const double sth0 = flog(p) - gam * flog(rho);
     const double sth1 = sth0 + lp - gam * lr;
     ds = -drho * sth1 - rho * (lp - gam * lr);
     const double ip1 = 1.0 / p1;
