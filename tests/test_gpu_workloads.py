@@ -313,8 +313,9 @@ def test_checkpoint_resume_bitwise(P, guess):
 
 def test_learned_guess_gain_on_held_out_cases(P):
     """The shipped network (trained on another seed's ensemble) against the
-    previous-gamma guess on held-out cases: both accept only certified roots;
-    the mean number of residual passes per step is reported and must not grow."""
+    previous-gamma guess on 128 held-out cases over 60 steps: both accept only
+    certified roots, and the network saves at least 0.01 residual evaluations
+    per case and step (measured: 1.708 -> 1.685; the runs are deterministic)."""
     from paper_2507_04991_amd import learned_guess as L
     from paper_2507_04991_amd import problems
     prob = problems.ensemble(7, 128)
@@ -322,4 +323,19 @@ def test_learned_guess_gain_on_held_out_cases(P):
     print("held-out residual passes per step:", out, flush=True)
     for v in out.values():
         assert v["r_max"] <= 1e-12 and v["flags"] == 0
-    assert out["learned"]["passes_mean"] <= out["prev"]["passes_mean"] + 1e-9
+    assert out["learned"]["passes_mean"] <= out["prev"]["passes_mean"] - 0.01
+
+
+def test_taylor_green_accepts_gamma_one_at_the_first_evaluation(P):
+    """The Taylor-Green leg of the learned guess: with the EC flux at Mach 0.1
+    every step's first evaluation, at the previous gamma, is already a certified
+    root (gamma = 1), in FP64 and mixed precision, so no guess can save an
+    evaluation there (10 steps of the 32^3 mesh)."""
+    from paper_2507_04991_amd import problems
+    prob = problems.tgv32()
+    for prec in (0, 1):
+        st, u = stepper(P, prob, precision=prec)
+        for n in range(10):
+            info = st.step(u, prob["dt"])[0]
+            assert info["passes"] == 1 and info["flags"] == 0 and abs(info["r"]) <= 1e-12, (prec, n, info)
+        st.close()
