@@ -262,15 +262,20 @@ int perrk_set_relaxation_state(perrk_ctx *ctx, const double *gamma_prev, const d
                                const double *t, const double *gamma_hist, const int32_t *n_steps);
 
 /* Learned initial guess (guess = PERRK_GUESS_MLP): a multilayer perceptron
- * 8 -> 32 -> 32 -> 1 (tanh hidden layers), float32.  weights: 1379 values, the
- * 1377 network parameters W1[32][8], b1[32], W2[32][32], b2[32], W3[1][32],
- * b3[1] followed by the output scale and shift.  Features per case: the last
- * three accepted gamma - 1, dt, and the entropy-production terms of the stages
- * with b_i != 0 normalised by the sum of their magnitudes (padded with zeros
- * to four); each feature is normalised as (x - mean[k]) * scale[k].  The guess
- * is gamma = 1 + shift + scale_out * network output (predictions outside
- * |gamma - 1| < 0.5 are ignored).  Newton/bisection still decide the accepted
- * gamma.  Host arrays; copied. */
+ * 8 -> 32 -> 32 -> 1 (tanh hidden layers), float32, predicting the increment
+ * gamma_n - gamma_{n-1} of each case.  weights: 1379 values, the 1377 network
+ * parameters W1[32][8], b1[32], W2[32][32], b2[32], W3[1][32], b3[1] followed
+ * by the output scale and shift.  Features per case, formed in double
+ * precision: the last two accepted increments (gamma_{n-1} - gamma_{n-2},
+ * gamma_{n-2} - gamma_{n-3}), gamma_{n-1} - 1, dt, and the entropy-production
+ * terms of this step's stages with b_i != 0 that come before the last stage,
+ * divided by the sum of their magnitudes (padded with zeros to four); each
+ * feature is normalised as (x - mean[k]) * scale[k].  The first evaluation
+ * point is gamma_{n-1} + shift + scale_out * network output; a prediction that
+ * is not finite, has magnitude >= 0.1 or would make gamma <= 0 is ignored
+ * (gamma_{n-1} is used).  The network is used once a case has taken three
+ * steps.  Newton/bisection still decide the accepted gamma.  Host arrays;
+ * copied. */
 int perrk_set_guess_model(perrk_ctx *ctx, const float *weights, const float *mean,
                           const float *scale);
 
