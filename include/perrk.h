@@ -178,7 +178,13 @@ typedef struct {
                                   (1 for GLM-MHD, 2 for Navier-Stokes); -w (w = 1, 2, 4, 8): w for
                                   all (PERRK_EINVAL from perrk_init if that needs more LDS per
                                   workgroup than the device has) */
+    int32_t tile;              /* element tiles the active lists keep together: 0 = chosen by the
+                                  autotuner with tune = 1 (tile 1 otherwise); 1..PERRK_TILES fixed:
+                                  2D tiles of 32 quadrilaterals (a full workgroup) 8x4, 4x8, 16x2,
+                                  32x1; 3D cubes of 8^3, 4^3, 16^3 hexahedra, or whole rows.  Results
+                                  do not depend on the tile. */
 } perrk_options;
+#define PERRK_TILES 4
 
 typedef struct {
     double gamma;      /* accepted relaxation parameter; the solution is at t_n + gamma dt */
@@ -193,7 +199,7 @@ typedef struct {
 
 /* Default options: relax = 1, max_newton = 10, tol_r = 1e-12, tol_step = 1e-15,
  * anchor = STEP, max_bisect = 60, bracket [0.8, 1.2], guess = PREV,
- * fast_passes = 3, use_graph = 1, tune = 1. */
+ * fast_passes = 3, use_graph = 1, tune = 1, tile = 0. */
 void perrk_default_options(perrk_options *opts);
 
 /* Validates every descriptor on the host (no GPU call): tableau structure,

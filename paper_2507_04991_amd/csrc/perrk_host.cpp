@@ -47,6 +47,10 @@ struct perrk_ctx {
     std::vector<int32_t> n_grad;
     std::vector<int64_t> grad_off;
     std::vector<std::vector<int64_t>> grad_per_level;
+    std::vector<ElemInfo> h_elem;  // element table (host copy)
+    std::vector<int32_t> h_dims;   // [n_cases][3] elements per direction
+    int tile = 1;                  // element tile of the active lists (1..PERRK_TILES)
+    size_t n_list = 0;             // entries in d_active
     // streams and events
     hipStream_t user_stream = nullptr, stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -288,6 +292,7 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
         if (o->fast_passes < 1 || o->fast_passes > 16) return ck.bad("fast_passes must be in 1..16");
         if (o->tune != 0 && o->tune != 1 && o->tune != -1 && o->tune != -2 && o->tune != -4 && o->tune != -8)
             return ck.bad("tune must be 1, 0, -1, -2, -4 or -8");
+        if (o->tile < 0 || o->tile > PERRK_TILES) return ck.bad("tile must be in 0..%d", PERRK_TILES);
     }
     return PERRK_OK;
 }
@@ -329,6 +334,129 @@ hipError_t mark_end(perrk_ctx *c, int cls, double bytes, int stage = -1)
     c->pbytes[c->npev / 2] = bytes;
     c->npev += 2;
     return e;
+}
+
+// Element tiles the active lists keep together (option `tile`, 1..PERRK_TILES).
+// 2D: tiles of 32 quadrilaterals, the elements of a full workgroup of
+// PERRK_MAX_WPB wavefronts (4 quadrilaterals each), 8 x 4, 4 x 8, 16 x 2 or 32 x 1,
+// row by row inside a tile.  3D: cubes of 8^3, 4^3 or 16^3 hexahedra (x fastest
+// inside a cube), or whole rows (x fastest).
+constexpr int TILE_2D[PERRK_TILES][2] = {{8, 4}, {4, 8}, {16, 2}, {32, 1}};
+constexpr int TILE_3D[PERRK_TILES] = {8, 4, 16, 0};
+
+const char *tile_name(int dim, int tile)
+{
+    static const char *const n2[PERRK_TILES] = {"8x4", "4x8", "16x2", "32x1"};
+    static const char *const n3[PERRK_TILES] = {"8^3", "4^3", "16^3", "rows"};
+    return dim == 2 ? n2[tile - 1] : n3[tile - 1];
+}
+
+// Active element list of every stage (stage i evaluates the levels with
+// E >= S - i + 1, 0-based; stage 1 every element) in the element order of the
+// tile choice, and with viscous terms the gradient lists; fills n_active,
+// active_off (and n_grad, grad_off, grad_per_level).  The lists' sizes do not
+// depend on the tile.  In 2D, nbr[5], which 2D meshes do not need, records for
+// each face f (bits 6f .. 6f + 5) the neighbour's position in the same list
+// relative to the entry's, as offset + 31 for offsets in [-31, 31] and 63
+// otherwise: the stage kernel takes the stage state of a neighbour that sits in
+// its own workgroup from LDS.
+void build_lists(perrk_ctx *c, int tile, std::vector<ActiveEntry> &order)
+{
+    const std::vector<ElemInfo> &elem = c->h_elem;
+    std::vector<int64_t> visit;
+    visit.reserve((size_t)c->nelem);
+    for (int cs = 0; cs < c->n_cases; ++cs) {
+        const int64_t base = c->case_off[cs];
+        const int n0 = c->h_dims[3 * cs], n1 = c->h_dims[3 * cs + 1];
+        if (c->dim == 3) {
+            const int n2 = c->h_dims[3 * cs + 2];
+            const int q = TILE_3D[tile - 1] > 0 ? TILE_3D[tile - 1] : std::max(n0, std::max(n1, n2));
+            for (int tz = 0; tz < n2; tz += q)
+                for (int ty = 0; ty < n1; ty += q)
+                    for (int tx = 0; tx < n0; tx += q)
+                        for (int iz = tz; iz < std::min(tz + q, n2); ++iz)
+                            for (int iy = ty; iy < std::min(ty + q, n1); ++iy)
+                                for (int ix = tx; ix < std::min(tx + q, n0); ++ix)
+                                    visit.push_back(base + ix + (int64_t)n0 * (iy + (int64_t)n1 * iz));
+            continue;
+        }
+        const int qx = TILE_2D[tile - 1][0], qy = TILE_2D[tile - 1][1];
+        for (int ty = 0; ty < n1; ty += qy)
+            for (int tx = 0; tx < n0; tx += qx)
+                for (int iy = ty; iy < std::min(ty + qy, n1); ++iy)
+                    for (int ix = tx; ix < std::min(tx + qx, n0); ++ix)
+                        visit.push_back(base + ix + (int64_t)n0 * iy);
+    }
+    order.clear();
+    std::vector<int64_t> pos((size_t)c->nelem, -1);  // list position of each element in the current stage
+    c->n_active.assign(c->S, 0);
+    c->active_off.assign(c->S + 1, 0);
+    for (int i = 0; i < c->S; ++i) {
+        c->active_off[i] = (int64_t)order.size();
+        for (const int64_t e : visit) {
+            const int E = c->E[elem[e].level];
+            if (i == 0 || i >= c->S - E + 1) {
+                ActiveEntry en{};
+                en.elem_level = (int32_t)((uint32_t)e | ((uint32_t)elem[e].level << PERRK_NBR_SHIFT));
+                en.case_id = elem[e].case_id;
+                for (int k = 0; k < 6; ++k) en.nbr[k] = elem[e].nbr[k];
+                if (c->dim == 2) {
+                    // 2D meshes have no z neighbours: that word holds the boundary flags of the
+                    // viscous-shock set-up (bit 0: left x face, bit 1: right x face)
+                    const int ix = (int)(e % c->h_dims[0]);
+                    en.nbr[4] = c->bc_x ? ((ix == 0 ? 1 : 0) | (ix == c->h_dims[0] - 1 ? 2 : 0)) : 0;
+                    en.nbr[5] = 0;
+                }
+                pos[(size_t)e] = (int64_t)order.size() - c->active_off[i];
+                order.push_back(en);
+            }
+        }
+        c->n_active[i] = (int32_t)(order.size() - c->active_off[i]);
+        if (c->dim == 2) {
+            for (int64_t j = 0; j < c->n_active[i]; ++j) {
+                ActiveEntry &en = order[(size_t)(c->active_off[i] + j)];
+                uint32_t code = 0;
+                for (int f = 0; f < 4; ++f) {
+                    const int64_t q = pos[(size_t)((uint32_t)en.nbr[f] & PERRK_NBR_MASK)];
+                    const int64_t off = q - j;
+                    const uint32_t cf = (q >= 0 && off >= -31 && off <= 31) ? (uint32_t)(off + 31) : 63u;
+                    code |= cf << (6 * f);
+                }
+                en.nbr[5] = (int32_t)code;
+            }
+        }
+        for (int64_t j = 0; j < c->n_active[i]; ++j)
+            pos[(size_t)((uint32_t)order[(size_t)(c->active_off[i] + j)].elem_level & PERRK_NBR_MASK)] = -1;
+    }
+    c->active_off[c->S] = (int64_t)order.size();
+    if (c->viscous) {
+        // BR1 needs the gradients at the nodes of a stage's active elements and at the
+        // face nodes of their neighbours: the gradient pass of stage i runs over the
+        // active elements and their face neighbours (in the first stage's order)
+        c->n_grad.assign(c->S, 0);
+        c->grad_off.assign(c->S, 0);
+        c->grad_per_level.assign(c->S, std::vector<int64_t>(c->R, 0));
+        std::vector<char> need((size_t)c->nelem);
+        for (int i = 0; i < c->S; ++i) {
+            std::fill(need.begin(), need.end(), 0);
+            for (int64_t j = 0; j < c->n_active[i]; ++j) {
+                const ActiveEntry &en = order[(size_t)(c->active_off[i] + j)];
+                need[(size_t)((uint32_t)en.elem_level & PERRK_NBR_MASK)] = 1;
+                for (int f = 0; f < 2 * c->dim; ++f)
+                    need[(size_t)((uint32_t)elem[(uint32_t)en.elem_level & PERRK_NBR_MASK].nbr[f] & PERRK_NBR_MASK)] = 1;
+            }
+            c->grad_off[i] = (int64_t)order.size();
+            for (int64_t j = 0; j < c->n_active[0]; ++j) {
+                ActiveEntry en = order[(size_t)(c->active_off[0] + j)];
+                const int64_t e = (uint32_t)en.elem_level & PERRK_NBR_MASK;
+                if (!need[(size_t)e]) continue;
+                en.nbr[5] = 0;
+                order.push_back(en);
+                c->grad_per_level[i][elem[e].level]++;
+            }
+            c->n_grad[i] = (int32_t)(order.size() - c->grad_off[i]);
+        }
+    }
 }
 
 // Arguments, kernel variant and kind of stage i.
@@ -403,65 +531,104 @@ void stage_setup(perrk_ctx *c, double *u, int i, StageArgs &a, int &variant, int
 
 const double *stage_coef(const perrk_ctx *c, int i) { return c->d_coef + (size_t)i * 2 * PERRK_MAXR; }
 
-// Picks the wavefronts per workgroup of every stage launch by timing the
-// candidates on the caller's state, stage by stage in step order (a stage
-// launch only reads U_n and earlier stage registers, so repeating it is
-// harmless; results do not depend on the launch shape).
+// Rebuilds the active lists for element tile `tile` and uploads them (same size
+// for every tile).
+int use_tile(perrk_ctx *c, int tile)
+{
+    std::vector<ActiveEntry> order;
+    build_lists(c, tile, order);
+    if (order.size() != c->n_list) return fail(c, PERRK_EHIP, "internal: list size changed with the tile");
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipMemcpy(c->d_active, order.data(), sizeof(ActiveEntry) * order.size(), hipMemcpyHostToDevice));
+    c->tile = tile;
+    return PERRK_OK;
+}
+
+// Picks the wavefronts per workgroup of every stage launch, and (option tile =
+// 0) the element tile of the active lists, by timing the candidates on the
+// caller's state: for each tile, every stage in step order with 1, 2, 4 and 8
+// wavefronts per workgroup (a stage launch only reads U_n and earlier stage
+// registers, so repeating it is harmless); the tile with the smallest sum of
+// its stages' best times is kept, with those launch shapes.  Results do not
+// depend on the tile or the launch shape.
 int autotune(perrk_ctx *c, double *u)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHECK(c, hipEventCreate(&e0));
     HIPCHECK(c, hipEventCreate(&e1));
-    std::string rep = "autotuned waves per workgroup (stage: choice [ms per candidate 1/2/4/8]):";
-    int status = PERRK_OK;
-    for (int i = 0; i < c->S && status == PERRK_OK; ++i) {
-        StageArgs a;
-        int variant = 0, kind = 0;
-        stage_setup(c, u, i, a, variant, kind);
-        int best = c->cfg.epb_mult;
-        float best_ms = 1e30f;
+    const int first_tile = c->opt.tile > 0 ? c->opt.tile : 1;
+    const int last_tile = c->opt.tile > 0 ? c->opt.tile : PERRK_TILES;
+    std::string rep;
+    int status = PERRK_OK, best_tile = c->tile;
+    double best_sum = 1e300;
+    std::vector<LaunchCfg> best_cfg = c->scfg;
+    for (int tile = first_tile; tile <= last_tile && status == PERRK_OK; ++tile) {
+        if (tile != c->tile && (status = use_tile(c, tile)) != PERRK_OK) break;
+        std::vector<LaunchCfg> cfg = c->scfg;
+        double sum = 0.0;
         char buf[160];
-        std::snprintf(buf, sizeof buf, " %d:", i + 1);
-        std::string line = buf;
-        for (int wpb = 1; wpb <= PERRK_MAX_WPB; wpb *= 2) {
-            if (stage_lds_bytes(c->dim, variant, wpb, c->viscous ? 2 : c->sys) > c->max_lds) {
-                line += " -";
-                continue;
-            }
-            const LaunchCfg cf{wpb};
-            if (launch_stage(c->dim, variant, c->flux, kind, a, stage_coef(c, i), cf, c->stream) != hipSuccess) {
-                (void)hipGetLastError();
-                line += " x";
-                continue;
-            }
-            float tmin = 1e30f;
-            for (int r = 0; r < 3; ++r) {
-                if (hipEventRecord(e0, c->stream) != hipSuccess ||
-                    launch_stage(c->dim, variant, c->flux, kind, a, stage_coef(c, i), cf, c->stream) != hipSuccess ||
-                    hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    status = fail(c, PERRK_EHIP, "autotuning launch failed: %s", hipGetErrorString(hipGetLastError()));
-                    break;
+        std::snprintf(buf, sizeof buf, "tile %s: waves per workgroup (stage: choice [ms per candidate 1/2/4/8]):",
+                      tile_name(c->dim, tile));
+        std::string tline = buf;
+        for (int i = 0; i < c->S && status == PERRK_OK; ++i) {
+            StageArgs a;
+            int variant = 0, kind = 0;
+            stage_setup(c, u, i, a, variant, kind);
+            int best = c->cfg.epb_mult;
+            float best_ms = 1e30f;
+            std::snprintf(buf, sizeof buf, " %d:", i + 1);
+            std::string line = buf;
+            for (int wpb = 1; wpb <= PERRK_MAX_WPB; wpb *= 2) {
+                if (stage_lds_bytes(c->dim, variant, wpb, c->viscous ? 2 : c->sys) > c->max_lds) {
+                    line += " -";
+                    continue;
                 }
-                float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                tmin = std::min(tmin, ms);
+                const LaunchCfg cf{wpb};
+                if (launch_stage(c->dim, variant, c->flux, kind, a, stage_coef(c, i), cf, c->stream) != hipSuccess) {
+                    (void)hipGetLastError();
+                    line += " x";
+                    continue;
+                }
+                float tmin = 1e30f;
+                for (int r = 0; r < 3; ++r) {
+                    if (hipEventRecord(e0, c->stream) != hipSuccess ||
+                        launch_stage(c->dim, variant, c->flux, kind, a, stage_coef(c, i), cf, c->stream) != hipSuccess ||
+                        hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                        status = fail(c, PERRK_EHIP, "autotuning launch failed: %s",
+                                      hipGetErrorString(hipGetLastError()));
+                        break;
+                    }
+                    float ms = 0.0f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    tmin = std::min(tmin, ms);
+                }
+                if (status != PERRK_OK) break;
+                std::snprintf(buf, sizeof buf, " %.4f", tmin);
+                line += buf;
+                if (tmin < best_ms) {
+                    best_ms = tmin;
+                    best = wpb;
+                }
             }
-            if (status != PERRK_OK) break;
-            std::snprintf(buf, sizeof buf, " %.4f", tmin);
-            line += buf;
-            if (tmin < best_ms) {
-                best_ms = tmin;
-                best = wpb;
-            }
+            cfg[i].epb_mult = best;
+            sum += best_ms;
+            std::snprintf(buf, sizeof buf, " -> %d;", best);
+            tline += line + buf;
         }
-        c->scfg[i].epb_mult = best;
-        std::snprintf(buf, sizeof buf, " -> %d;", best);
-        rep += line + buf;
+        std::snprintf(buf, sizeof buf, " sum %.4f ms. ", sum);
+        rep += tline + buf;
+        if (status == PERRK_OK && sum < best_sum) {
+            best_sum = sum;
+            best_tile = tile;
+            best_cfg = cfg;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status != PERRK_OK) return status;
-    c->tune_report = rep;
+    if (best_tile != c->tile && (status = use_tile(c, best_tile)) != PERRK_OK) return status;
+    c->scfg = best_cfg;
+    c->tune_report = std::string("Chosen: tile ") + tile_name(c->dim, best_tile) + ". Autotuned: " + rep;
     c->tuned = true;
     return PERRK_OK;
 }
@@ -536,6 +703,7 @@ void perrk_default_options(perrk_options *o)
     o->fast_passes = 3;
     o->use_graph = 1;
     o->tune = 1;
+    o->tile = 0;
 }
 
 int perrk_validate(const perrk_mesh_desc *mesh, const perrk_partition_desc *part,
@@ -633,115 +801,12 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
         for (int k = 0; k < 6; ++k)
             ei.nbr[k] = (int32_t)((uint32_t)ei.nbr[k] | ((uint32_t)elem[ei.nbr[k]].level << PERRK_NBR_SHIFT));
 
-    // tile of a 2D case mesh whose elements the active lists keep together: the
-    // elements of a workgroup of PERRK_MAX_WPB wavefronts (4 quadrilaterals each)
-    constexpr int ACT_TILE_X = 8, ACT_TILE_Y = 4;
-    static_assert(ACT_TILE_X * ACT_TILE_Y == 4 * PERRK_MAX_WPB, "one tile per full workgroup");
-    // 3D lists visit each case mesh by cubes of ACT_TILE_3D^3 elements (x fastest
-    // inside a cube): a neighbour in y or z is then processed a few dozen
-    // elements before or after an element rather than a whole plane, so the
-    // face-node reads of neighbours mostly hit the XCD's L2.
-    constexpr int ACT_TILE_3D = 8;
-    // active element list of every stage: stage i evaluates the levels with
-    // E >= S - i + 1, stage 1 every element.  2D lists visit each case mesh by tiles of ACT_TILE_X x ACT_TILE_Y
-    // elements (row by row inside a tile), so that the 32 elements of a full
-    // workgroup are mostly each other's face neighbours; nbr[5], which 2D meshes
-    // do not need, then records for each face f (bits 6f .. 6f + 5) the
-    // neighbour's position in the same list relative to the entry's, as offset + 31
-    // for offsets in [-31, 31] and 63 otherwise.  The stage kernel takes the stage
-    // state of a neighbour that sits in its own workgroup from LDS.
-    std::vector<int64_t> visit;
-    visit.reserve((size_t)c->nelem);
-    for (int cs = 0; cs < m->n_cases; ++cs) {
-        const int64_t base = c->case_off[cs];
-        const int n0 = m->n_elem_dir[3 * cs], n1 = m->n_elem_dir[3 * cs + 1];
-        if (m->dim == 3) {
-            const int n2 = m->n_elem_dir[3 * cs + 2];
-            for (int tz = 0; tz < n2; tz += ACT_TILE_3D)
-                for (int ty = 0; ty < n1; ty += ACT_TILE_3D)
-                    for (int tx = 0; tx < n0; tx += ACT_TILE_3D)
-                        for (int iz = tz; iz < std::min(tz + ACT_TILE_3D, n2); ++iz)
-                            for (int iy = ty; iy < std::min(ty + ACT_TILE_3D, n1); ++iy)
-                                for (int ix = tx; ix < std::min(tx + ACT_TILE_3D, n0); ++ix)
-                                    visit.push_back(base + ix + (int64_t)n0 * (iy + (int64_t)n1 * iz));
-            continue;
-        }
-        for (int ty = 0; ty < n1; ty += ACT_TILE_Y)
-            for (int tx = 0; tx < n0; tx += ACT_TILE_X)
-                for (int iy = ty; iy < std::min(ty + ACT_TILE_Y, n1); ++iy)
-                    for (int ix = tx; ix < std::min(tx + ACT_TILE_X, n0); ++ix)
-                        visit.push_back(base + ix + (int64_t)n0 * iy);
-    }
+    c->h_elem.swap(elem);  // kept: the autotuner rebuilds the lists for other tiles
+    c->h_dims.assign(m->n_elem_dir, m->n_elem_dir + 3 * m->n_cases);
+    c->tile = o.tile > 0 ? o.tile : 1;
     std::vector<ActiveEntry> order;
-    std::vector<int64_t> pos((size_t)c->nelem, -1);  // list position of each element in the current stage
-    c->n_active.resize(c->S);
-    c->active_off.resize(c->S + 1);
-    for (int i = 0; i < c->S; ++i) {
-        c->active_off[i] = (int64_t)order.size();
-        for (const int64_t e : visit) {
-            const int E = c->E[elem[e].level];
-            if (i == 0 || i >= c->S - E + 1) {
-                ActiveEntry en{};
-                en.elem_level = (int32_t)((uint32_t)e | ((uint32_t)elem[e].level << PERRK_NBR_SHIFT));
-                en.case_id = elem[e].case_id;
-                for (int k = 0; k < 6; ++k) en.nbr[k] = elem[e].nbr[k];
-                if (c->dim == 2) {
-                    // 2D meshes have no z neighbours: that word holds the boundary flags of the
-                    // viscous-shock set-up (bit 0: left x face, bit 1: right x face)
-                    const int ix = (int)(e % m->n_elem_dir[0]);
-                    en.nbr[4] = c->bc_x ? ((ix == 0 ? 1 : 0) | (ix == m->n_elem_dir[0] - 1 ? 2 : 0)) : 0;
-                    en.nbr[5] = 0;
-                }
-                pos[(size_t)e] = (int64_t)order.size() - c->active_off[i];
-                order.push_back(en);
-            }
-        }
-        c->n_active[i] = (int32_t)(order.size() - c->active_off[i]);
-        if (c->dim == 2) {
-            for (int64_t j = 0; j < c->n_active[i]; ++j) {
-                ActiveEntry &en = order[(size_t)(c->active_off[i] + j)];
-                uint32_t code = 0;
-                for (int f = 0; f < 4; ++f) {
-                    const int64_t q = pos[(size_t)((uint32_t)en.nbr[f] & PERRK_NBR_MASK)];
-                    const int64_t off = q - j;
-                    const uint32_t cf = (q >= 0 && off >= -31 && off <= 31) ? (uint32_t)(off + 31) : 63u;
-                    code |= cf << (6 * f);
-                }
-                en.nbr[5] = (int32_t)code;
-            }
-        }
-        for (int64_t j = 0; j < c->n_active[i]; ++j)
-            pos[(size_t)((uint32_t)order[(size_t)(c->active_off[i] + j)].elem_level & PERRK_NBR_MASK)] = -1;
-    }
-    c->active_off[c->S] = (int64_t)order.size();
-    if (c->viscous) {
-        // BR1 needs the gradients at the nodes of a stage's active elements and at the
-        // face nodes of their neighbours: the gradient pass of stage i runs over the
-        // active elements and their face neighbours (in the first stage's order)
-        c->n_grad.assign(c->S, 0);
-        c->grad_off.assign(c->S, 0);
-        c->grad_per_level.assign(c->S, std::vector<int64_t>(c->R, 0));
-        std::vector<char> need((size_t)c->nelem);
-        for (int i = 0; i < c->S; ++i) {
-            std::fill(need.begin(), need.end(), 0);
-            for (int64_t j = 0; j < c->n_active[i]; ++j) {
-                const ActiveEntry &en = order[(size_t)(c->active_off[i] + j)];
-                need[(size_t)((uint32_t)en.elem_level & PERRK_NBR_MASK)] = 1;
-                for (int f = 0; f < 2 * m->dim; ++f)
-                    need[(size_t)((uint32_t)elem[(uint32_t)en.elem_level & PERRK_NBR_MASK].nbr[f] & PERRK_NBR_MASK)] = 1;
-            }
-            c->grad_off[i] = (int64_t)order.size();
-            for (int64_t j = 0; j < c->n_active[0]; ++j) {
-                ActiveEntry en = order[(size_t)(c->active_off[0] + j)];
-                const int64_t e = (uint32_t)en.elem_level & PERRK_NBR_MASK;
-                if (!need[(size_t)e]) continue;
-                en.nbr[5] = 0;
-                order.push_back(en);
-                c->grad_per_level[i][elem[e].level]++;
-            }
-            c->n_grad[i] = (int32_t)(order.size() - c->grad_off[i]);
-        }
-    }
+    build_lists(c, c->tile, order);
+    c->n_list = order.size();
     // per-stage coefficients (without dt): K_1 and K_{i-1} multipliers per level
     std::vector<double> coef((size_t)c->S * 2 * PERRK_MAXR, 0.0);
     for (int i = 1; i < c->S; ++i)
@@ -780,7 +845,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
         const double dofe = (double)c->V * c->npe;  // DOF per element
         const double kb = c->precision == PERRK_FP64 ? 8.0 : 4.0;
         std::vector<int64_t> per_level(c->R, 0);
-        for (int64_t e = 0; e < c->nelem; ++e) per_level[elem[e].level]++;
+        for (int64_t e = 0; e < c->nelem; ++e) per_level[c->h_elem[e].level]++;
         c->stage_bytes.assign(c->S, 0.0);
         int first_acc = -1;  // first stage with b_i != 0 other than 1, S-1, S
         for (int j = 1; j < c->S - 2 && first_acc < 0; ++j)
@@ -897,7 +962,8 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipHostMalloc(&c->h_cs, sizeof(CaseState) * c->n_cases, 0));
     HIPINIT(hipHostMalloc(&c->h_err, sizeof(int32_t) * ERR_WORDS, 0));
     HIPINIT(hipHostMalloc(&c->h_H, sizeof(double) * c->n_cases, 0));
-    HIPINIT(hipMemcpyAsync(c->d_elem, elem.data(), sizeof(ElemInfo) * c->nelem, hipMemcpyHostToDevice, c->stream));
+    HIPINIT(hipMemcpyAsync(c->d_elem, c->h_elem.data(), sizeof(ElemInfo) * c->nelem, hipMemcpyHostToDevice,
+                           c->stream));
     HIPINIT(hipMemcpyAsync(c->d_active, order.data(), sizeof(ActiveEntry) * order.size(), hipMemcpyHostToDevice,
                            c->stream));
     HIPINIT(hipMemcpyAsync(c->d_case_off, c->case_off.data(), sizeof(int64_t) * (c->n_cases + 1),
@@ -929,7 +995,7 @@ int perrk_step(perrk_ctx *c, void *u_dev, const double *dt, perrk_step_info *inf
     HIPCHECK(c, hipMemcpyAsync(ddt, hdt, sizeof(double) * c->n_cases, hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipEventRecord(c->ring_ev[slot], c->stream));
     HIPCHECK(c, launch_set_dt(c->d_cs, ddt, c->n_cases, c->stream));
-    if (c->opt.tune && !c->tuned) {
+    if (c->opt.tune == 1 && !c->tuned) {
         const int st = autotune(c, static_cast<double *>(u_dev));
         if (st != PERRK_OK) return st;
     }
@@ -1180,11 +1246,12 @@ int perrk_get_tuning(perrk_ctx *c, char *buf, size_t len)
     std::string w;
     for (const LaunchCfg &x : c->scfg) w += (w.empty() ? "" : ",") + std::to_string(x.epb_mult);
     std::snprintf(buf, len,
-                  "system=%s dim=%d precision=%s flux=%s volume=%s stage_waves_per_workgroup=[%s] fast_passes=%d "
-                  "graph=%d %s",
-                  c->sys == PERRK_SYSTEM_GLM_MHD ? "glm_mhd" : "euler", c->dim, c->precision == PERRK_MIXED ? "mixed" : (c->precision == PERRK_MIXED_ALL ? "mixed_all" : "fp64"),
-                  flux_names[c->flux], c->volume ? "weak" : "flux_differencing", w.c_str(), c->opt.fast_passes,
-                  c->opt.use_graph, c->tuned ? c->tune_report.c_str() : "(not tuned)");
+                  "system=%s dim=%d precision=%s flux=%s volume=%s tile=%s stage_waves_per_workgroup=[%s] "
+                  "fast_passes=%d graph=%d %s",
+                  c->sys == PERRK_SYSTEM_GLM_MHD ? "glm_mhd" : "euler", c->dim,
+                  c->precision == PERRK_MIXED ? "mixed" : (c->precision == PERRK_MIXED_ALL ? "mixed_all" : "fp64"),
+                  flux_names[c->flux], c->volume ? "weak" : "flux_differencing", tile_name(c->dim, c->tile), w.c_str(),
+                  c->opt.fast_passes, c->opt.use_graph, c->tuned ? c->tune_report.c_str() : "(not tuned)");
     return PERRK_OK;
 }
 

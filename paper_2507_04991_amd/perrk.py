@@ -22,6 +22,7 @@ SYSTEM_EULER, SYSTEM_GLM_MHD = 0, 1
 FP64, MIXED, MIXED_ALL = 0, 1, 2
 ANCHOR_STEP, ANCHOR_INITIAL = 0, 1
 GUESS_PREV, GUESS_MLP = 0, 1
+TILES = 4  # PERRK_TILES
 FLAG_BISECT, FLAG_FALLBACK, FLAG_TRIVIAL = 1, 2, 4
 
 
@@ -58,7 +59,8 @@ class Options(ctypes.Structure):
     _fields_ = [("relax", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("tol_r", ctypes.c_double),
                 ("tol_step", ctypes.c_double), ("anchor", ctypes.c_int32), ("max_bisect", ctypes.c_int32),
                 ("bisect_lo", ctypes.c_double), ("bisect_hi", ctypes.c_double), ("guess", ctypes.c_int32),
-                ("fast_passes", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tune", ctypes.c_int32)]
+                ("fast_passes", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tune", ctypes.c_int32),
+                ("tile", ctypes.c_int32)]
 
 
 class StepInfo(ctypes.Structure):
@@ -294,8 +296,8 @@ class Stepper:
         return [dict(ms=s.ms, bytes=s.bytes, launches=s.launches) for s in arr]
 
     def tuning(self):
-        buf = ctypes.create_string_buffer(4096)
-        lib().perrk_get_tuning(self.ctx, buf, 4096)
+        buf = ctypes.create_string_buffer(16384)
+        lib().perrk_get_tuning(self.ctx, buf, 16384)
         return buf.value.decode()
 
     def close(self):

@@ -114,6 +114,11 @@ def test_validate_viscous_descriptors():
     for tune in (2, -3, -16):
         st, msg = d.validate(P.default_options(tune=tune))
         assert st == P.EINVAL and "tune" in msg, msg
+    for tile in range(0, P.TILES + 1):
+        assert d.validate(P.default_options(tile=tile))[0] == P.OK
+    for tile in (-1, P.TILES + 1):
+        st, msg = d.validate(P.default_options(tile=tile))
+        assert st == P.EINVAL and "tile" in msg, msg
 
 
 def test_validate_node_limit_and_case_count():

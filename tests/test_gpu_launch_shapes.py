@@ -1,5 +1,7 @@
 """Launch shapes through the C ABI: every stage launched with 1, 2, 4 or 8
-wavefronts per workgroup (options.tune = -w) gives bit-identical states.
+wavefronts per workgroup (options.tune = -w), and the active lists built with
+every element tile (options.tile = 1..4), give bit-identical states; so does
+the autotuner's own choice (tune = 1, tile = 0), which the tuning report names.
 
 In 2D the active lists keep tiles of each case mesh together and a neighbour that
 sits in the same workgroup is read from LDS instead of global memory, so the split
@@ -48,9 +50,9 @@ def ensemble_2d():
     return tab, faces, U0s, levs, dts
 
 
-def run(P, tab, faces, U0s, levs, dts, precision, w, nsteps=3):
+def run(P, tab, faces, U0s, levs, dts, precision, w, nsteps=3, tile=1):
     d = P.Descriptors(faces, levs, tab, precision=precision)
-    st = P.Stepper(d, P.default_options(tune=-w))
+    st = P.Stepper(d, P.default_options(tune=-w, tile=tile) if w > 0 else P.default_options())
     u = torch.tensor(np.concatenate(U0s, axis=1), device="cuda").contiguous()
     gam = []
     for _ in range(nsteps):
@@ -58,6 +60,11 @@ def run(P, tab, faces, U0s, levs, dts, precision, w, nsteps=3):
         assert all(i["flags"] == 0 for i in infos)
         gam.append([i["gamma"] for i in infos])
     out = u.cpu().numpy()
+    if w > 0:
+        assert "(not tuned)" in st.tuning() and f"stage_waves_per_workgroup=[{','.join([str(w)] * len(tab['c']))}]" \
+            in st.tuning(), st.tuning()
+    else:
+        assert "Chosen: tile" in st.tuning(), st.tuning()
     st.close()
     return out, np.array(gam)
 
@@ -93,3 +100,22 @@ def test_3d_states_identical_for_every_workgroup_size(P, precision):
     for w in WPB[1:]:
         assert np.array_equal(res[w][0], res[1][0]), w
         assert np.array_equal(res[w][1], res[1][1]), w
+
+
+@pytest.mark.parametrize("dim", ["2d", "3d"])
+def test_states_identical_for_every_element_tile(P, dim):
+    from tests.helpers import problem_3d
+    if dim == "2d":
+        tab, faces, U0s, levs, dts = ensemble_2d()
+    else:
+        f, U0, tab, dt, lev = problem_3d(n=(6, 4, 8), levels="random")
+        faces, U0s, levs, dts = [f], [U0], [lev], [dt]
+    res = {}
+    for tile in range(1, P.TILES + 1):
+        print(f"case {dim} mixed precision, element tile {tile}", flush=True)
+        res[tile] = run(P, tab, faces, U0s, levs, dts, 1, 4, nsteps=2, tile=tile)
+    print(f"case {dim} mixed precision, autotuned", flush=True)
+    res[0] = run(P, tab, faces, U0s, levs, dts, 1, 0, nsteps=2)
+    for tile in res:
+        assert np.array_equal(res[tile][0], res[1][0]), tile
+        assert np.array_equal(res[tile][1], res[1][1]), tile
