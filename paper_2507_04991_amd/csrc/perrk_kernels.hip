@@ -2496,12 +2496,13 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
         case_sum<1>(ep + (size_t)j * nelem, 1, b, e, o);
         ej[j] = o[0];
     }
-    // learned guess of the increment gamma_n - gamma_{n-1} (MLP 8-32-32-1, tanh; the
-    // weights are followed by the feature mean[8], scale[8] and the output scale and
-    // shift).  Features, formed in double precision: the last two increments of
-    // gamma, gamma_{n-1} - 1, dt, and the entropy production of this step's b_i != 0
-    // stages before the last stage divided by the sum of their magnitudes
-    // (zero-padded to four).
+    // learned guess of the increment of the root, gamma*_n - gamma*_{n-1} (MLP
+    // 8-32-32-1, tanh; the weights are followed by the feature mean[8], scale[8] and the
+    // output scale and shift).  Features, formed in double precision from the history
+    // of roots (ghist, see the step bookkeeping): the last two increments,
+    // gamma*_{n-1} - 1, dt, and the entropy production of this step's b_i != 0 stages
+    // before the last stage divided by the sum of their magnitudes (zero-padded to
+    // four).  The first evaluation point is gamma*_{n-1} plus the prediction.
     const bool learned = rp.guess == 1 && mlp != nullptr && C.nsteps >= 3;
     const float *W1 = mlp, *b1 = W1 + 256, *W2 = b1 + 32, *b2 = W2 + 1024, *W3 = b2 + 32, *b3 = W3 + 32;
     const float *mean = b3 + 1, *scale = mean + 8, *oscale = scale + 8;
@@ -2553,7 +2554,8 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
         float y = b3[0];
         for (int i = 0; i < 32; ++i) y += W3[i] * sh2[i];
         const double pred = (double)y * (double)oscale[0] + (double)oscale[1];
-        if (isfinite(pred) && fabs(pred) < 0.1 && g0 + pred > 0.0) g0 += pred;
+        const double base = 1.0 + C.ghist[0];
+        if (isfinite(pred) && fabs(pred) < 0.1 && base + pred > 0.0) g0 = base + pred;
     }
     C.gamma = g0;
     C.gamma_b = g0;
@@ -2675,9 +2677,18 @@ relax_complete_kernel(const double *U, const double *d, const ElemInfo *elem, Ca
         if (err[0] != 0) return;
         C.t += C.gamma_acc * C.dt;
         C.offset += C.H_delta;
+        // history of the learned guess: the root itself rather than the accepted point.
+        // An evaluation accepted by Newton gave r and r' there, and one more Newton step
+        // locates the root far inside the acceptance band |r| <= tol_r, where the
+        // accepted points scatter by about tol_r / |r'| from step to step
+        double groot = C.gamma_acc;
+        if (C.flags == 0 && C.passes > 0 && isfinite(C.r) && isfinite(C.rp) && C.rp != 0.0) {
+            const double corr = C.r / C.rp;
+            if (fabs(corr) < 1e-6) groot -= corr;
+        }
         C.ghist[2] = C.ghist[1];
         C.ghist[1] = C.ghist[0];
-        C.ghist[0] = C.gamma_acc - 1.0;
+        C.ghist[0] = groot - 1.0;
         C.gamma_prev = C.gamma_acc;
         C.nsteps += 1;
     }

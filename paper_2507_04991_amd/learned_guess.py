@@ -1,10 +1,13 @@
 """Learned initial guess for the relaxation solve.
 
 A small network (8 -> 32 -> 32 -> 1, tanh) predicts the increment
-gamma_n - gamma_{n-1} of a case's relaxation parameter from: the last two
-increments, gamma_{n-1} - 1, the step size and the entropy-production terms of
-this step's stages with b_i != 0 that come before the last stage (divided by the
-sum of their magnitudes, zero-padded to four).  It is trained on (features,
+gamma*_n - gamma*_{n-1} of the root of a case's relaxation equation from: the
+last two increments, gamma*_{n-1} - 1, the step size and the entropy-production
+terms of this step's stages with b_i != 0 that come before the last stage
+(divided by the sum of their magnitudes, zero-padded to four).  gamma*_n is the
+root located by one Newton step from the accepted point of step n (whose
+evaluation gave r and r'), which the library keeps as the case's gamma history;
+the accepted points themselves scatter inside the acceptance band |r| <= tol_r.  It is trained on (features,
 increment) pairs logged from the method's own solves, with the library's HIP
 forward / gradient / Adam kernels; the step evaluates it before the last stage
 (whose epilogue makes the first residual evaluation at the predicted point)
@@ -49,25 +52,25 @@ def features(ghist, dt, e, nb_pre):
 
 
 def collect(stepper, u, dt, steps, nb_pre):
-    """Advance `steps` synchronous steps, logging one (features, gamma_n - gamma_{n-1})
-    pair per case and step once the case has three earlier gammas.  Steps whose
-    solve fell back or was trivial are skipped.  Returns X, Y, the passes of the
-    logged steps and the previous gamma of each logged pair."""
+    """Advance `steps` synchronous steps, logging one (features, gamma*_n - gamma*_{n-1})
+    pair per case and step once the case has three earlier roots (the library's
+    gamma history, read after every step).  Steps whose solve fell back or was
+    trivial are skipped.  Returns X, Y, the passes of the logged steps and the
+    previous root - 1 of each logged pair."""
     n = stepper.n_cases
     dt = np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,))
-    hist = np.zeros((n, 3))
+    hist = stepper.relaxation_state().gamma_hist.copy()
     X, Y, passes, prev = [], [], [], []
     for step in range(steps):
         infos = stepper.step(u, dt)
+        new = stepper.relaxation_state().gamma_hist
         for c, inf in enumerate(infos):
-            g1 = inf["gamma"] - 1.0
             if inf["flags"] == 0 and step >= 3:
                 X.append(features(hist[c], dt[c], np.asarray(inf["e"]), nb_pre))
-                Y.append(g1 - hist[c, 0])
+                Y.append(new[c, 0] - hist[c, 0])
                 passes.append(inf["passes"])
                 prev.append(hist[c, 0])
-            hist[c, 1:] = hist[c, :2].copy()
-            hist[c, 0] = g1
+        hist = new.copy()
     return np.array(X), np.array(Y), np.array(passes), np.array(prev)
 
 

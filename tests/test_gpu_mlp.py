@@ -77,8 +77,9 @@ def test_training_fits_a_smooth_target(P):
 
 def test_step_uses_learned_increment(P):
     """With every first evaluation accepted (tol_r huge), the accepted gamma is the
-    first evaluation point: gamma_prev for the first three steps of a case, then
-    gamma_prev plus the network's increment for the features of that step."""
+    first evaluation point: gamma_prev for the first three steps of a case, then the
+    previous root (the case's gamma history, one Newton step from the previous
+    accepted point) plus the network's increment for the features of that step."""
     import sys
     import os
     sys.path.insert(0, os.path.dirname(__file__))
@@ -97,20 +98,21 @@ def test_step_uses_learned_increment(P):
     st.set_guess_model(full, mean, scale)
     u = dev(U0)
     nb_pre = L.pre_last_count(tab)
-    hist = np.zeros(3)
-    gamma_prev = 1.0
     for step in range(6):
+        rs = st.relaxation_state()
+        hist, gamma_prev = rs.gamma_hist[0].copy(), rs.gamma_prev[0]
         inf = st.step(u, np.array([dt]))[0]
         expect = gamma_prev
         if step >= 3:
             x = L.features(hist, dt, np.asarray(inf["e"]), nb_pre)
             xn = ((x - mean.astype(np.float64)) * scale.astype(np.float64)).astype(np.float32)
             y = M.forward(w.astype(np.float64), xn[None, :].astype(np.float64))[0]
-            expect = gamma_prev + (y * float(full[-2]) + float(full[-1]))
+            expect = (1.0 + hist[0]) + (y * float(full[-2]) + float(full[-1]))
             assert abs(expect - gamma_prev) > 1e-6  # the guess moved the point
         assert inf["passes"] == 1
         assert abs(inf["gamma"] - expect) <= 1e-9, (step, inf["gamma"], expect)
-        hist[1:] = hist[:2].copy()
-        hist[0] = inf["gamma"] - 1.0
-        gamma_prev = inf["gamma"]
+        # the history holds the root one Newton step from the accepted point
+        after = st.relaxation_state()
+        assert abs(after.gamma_prev[0] - inf["gamma"]) == 0.0
+        assert abs((1.0 + after.gamma_hist[0, 0]) - inf["gamma"]) <= 1e-6
     st.close()

@@ -296,7 +296,7 @@ def test_checkpoint_resume_bitwise(P, guess):
         st.step(u, dt)
     u_saved = u.clone()
     saved = st.relaxation_state()
-    assert saved.n_steps[0] == 5 and saved.gamma_hist[0, 0] == saved.gamma_prev[0] - 1.0
+    assert saved.n_steps[0] == 5 and abs(saved.gamma_hist[0, 0] - (saved.gamma_prev[0] - 1.0)) <= 1e-9
     infos = [st.step(u, dt)[0] for _ in range(3)]
     st2, _ = fresh()
     st2.set_relaxation_state(**saved._asdict())
@@ -314,8 +314,8 @@ def test_checkpoint_resume_bitwise(P, guess):
 def test_learned_guess_gain_on_held_out_cases(P):
     """The shipped network (trained on another seed's ensemble) against the
     previous-gamma guess on 128 held-out cases over 60 steps: both accept only
-    certified roots, and the network saves at least 0.01 residual evaluations
-    per case and step (measured: 1.708 -> 1.685; the runs are deterministic)."""
+    certified roots, and the network saves at least 0.02 residual evaluations
+    per case and step (measured: 1.708 -> 1.665; the runs are deterministic)."""
     from paper_2507_04991_amd import learned_guess as L
     from paper_2507_04991_amd import problems
     prob = problems.ensemble(7, 128)
@@ -323,7 +323,7 @@ def test_learned_guess_gain_on_held_out_cases(P):
     print("held-out residual passes per step:", out, flush=True)
     for v in out.values():
         assert v["r_max"] <= 1e-12 and v["flags"] == 0
-    assert out["learned"]["passes_mean"] <= out["prev"]["passes_mean"] - 0.01
+    assert out["learned"]["passes_mean"] <= out["prev"]["passes_mean"] - 0.02
 
 
 def test_taylor_green_accepts_gamma_one_at_the_first_evaluation(P):
