@@ -254,9 +254,11 @@ int perrk_rhs(perrk_ctx *ctx, const void *u_dev, void *k_dev);
 
 /* Per-case state that one step hands to the next: the previous accepted gamma
  * (the Newton starting value), the accumulated entropy offset H(U_n) - H(U_0)
- * used by PERRK_ANCHOR_INITIAL, the relaxed time t, the last three accepted
- * gamma - 1 (most recent first; features of the learned guess) and the number
- * of accepted steps (the learned guess is used from the fourth step on).
+ * used by PERRK_ANCHOR_INITIAL, the relaxed time t, the last three roots
+ * gamma* - 1 (most recent first: each step's accepted gamma moved by one more
+ * Newton step -r/r' when Newton accepted it; the history of the learned guess)
+ * and the number of accepted steps (the learned guess is used from the fourth
+ * step on).
  * Read or restore (checkpoint / resume: a context restored from these values
  * continues bitwise as the one they were read from).  Host arrays, each may be
  * NULL (not read / not changed): gamma_prev, h_offset, t, n_steps [n_cases],
@@ -269,17 +271,18 @@ int perrk_set_relaxation_state(perrk_ctx *ctx, const double *gamma_prev, const d
 
 /* Learned initial guess (guess = PERRK_GUESS_MLP): a multilayer perceptron
  * 8 -> 32 -> 32 -> 1 (tanh hidden layers), float32, predicting the increment
- * gamma_n - gamma_{n-1} of each case.  weights: 1379 values, the 1377 network
+ * gamma*_n - gamma*_{n-1} of the root of each case (the root history of
+ * perrk_get_relaxation_state).  weights: 1379 values, the 1377 network
  * parameters W1[32][8], b1[32], W2[32][32], b2[32], W3[1][32], b3[1] followed
  * by the output scale and shift.  Features per case, formed in double
- * precision: the last two accepted increments (gamma_{n-1} - gamma_{n-2},
- * gamma_{n-2} - gamma_{n-3}), gamma_{n-1} - 1, dt, and the entropy-production
- * terms of this step's stages with b_i != 0 that come before the last stage,
- * divided by the sum of their magnitudes (padded with zeros to four); each
- * feature is normalised as (x - mean[k]) * scale[k].  The first evaluation
- * point is gamma_{n-1} + shift + scale_out * network output; a prediction that
- * is not finite, has magnitude >= 0.1 or would make gamma <= 0 is ignored
- * (gamma_{n-1} is used).  The network is used once a case has taken three
+ * precision: the last two increments of the root (gamma*_{n-1} - gamma*_{n-2},
+ * gamma*_{n-2} - gamma*_{n-3}), gamma*_{n-1} - 1, dt, and the
+ * entropy-production terms of this step's stages with b_i != 0 that come
+ * before the last stage, divided by the sum of their magnitudes (padded with
+ * zeros to four); each feature is normalised as (x - mean[k]) * scale[k].  The
+ * first evaluation point is gamma*_{n-1} + shift + scale_out * network output;
+ * a prediction that is not finite, has magnitude >= 0.1 or would make gamma
+ * <= 0 is ignored (the previous accepted gamma is used).  The network is used once a case has taken three
  * steps.  Newton/bisection still decide the accepted gamma.  Host arrays;
  * copied. */
 int perrk_set_guess_model(perrk_ctx *ctx, const float *weights, const float *mean,
