@@ -144,6 +144,25 @@ def test_graph_and_eager_bitwise_identical_and_deterministic(P):
         assert o[1] == outs[0][1]
 
 
+@pytest.mark.parametrize("dim,precision", [("2d", 0), ("2d", 1), ("3d", 1)])
+def test_launched_passes_do_not_change_results(P, dim, precision):
+    """The number of residual passes launched per step (fast_passes 1, 2, 3, 16;
+    the rest run in the per-case completion kernel with the same per-element code
+    and sums) leaves every state, gamma and pass count bit for bit unchanged; the
+    tolerance 1e-14 forces several evaluations per step."""
+    f, U0, tab, dt, lev = problem_2d(order=3, E=(4, 6, 8, 12)) if dim == "2d" else problem_3d()
+    res = {}
+    for fp in (1, 2, 3, 16):
+        st, u = make(P, f, U0, tab, lev, precision=precision, fast_passes=fp, tol_r=1e-14)
+        infos = [st.step(u, dt)[0] for _ in range(3)]
+        res[fp] = (u.cpu().numpy(), [(i["gamma"], i["passes"], i["flags"]) for i in infos])
+        st.close()
+    assert max(p for _, p, _ in res[1][1]) >= 2, res[1][1]
+    for fp in (2, 3, 16):
+        assert np.array_equal(res[fp][0], res[1][0]), fp
+        assert res[fp][1] == res[1][1], (fp, res[fp][1], res[1][1])
+
+
 def test_async_steps_equal_synchronous_steps(P):
     f, U0, tab, dt, lev = problem_2d(order=4, E=(5, 9, 14))
     st, u = make(P, f, U0, tab, lev)
