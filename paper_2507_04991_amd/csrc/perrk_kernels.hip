@@ -736,20 +736,69 @@ __device__ __forceinline__ int pair_k(int t)
     return sel4<int>(t, 2, 0, 3, 5);
 }
 
+// Face nodes of a wavefront: EPW * NFN of them (64 in 2D, 96 in 3D), spread over
+// the lanes in FR rounds; face node g = lane + 64 r belongs to element slot
+// g / NFN, which is the lane's own slot (2D: 16 face nodes per quadrilateral;
+// 3D: one element per wavefront).
+template <int DIM>
+struct FaceRounds {
+    static constexpr int N = (SG<DIM>::EPW * SG<DIM>::NFN + 63) / 64;
+};
+
+template <int DIM>
+struct FaceNode {
+    int q, d, side, own;  // face-node slot, direction, side (1 = +), own node on the face
+};
+
+template <int DIM>
+__device__ __forceinline__ bool face_node(int r, int lane, FaceNode<DIM> &F, int &nn)
+{
+    constexpr int EPW = SG<DIM>::EPW, NFN = SG<DIM>::NFN, NLINE = SG<DIM>::NLINE;
+    const int g = lane + 64 * r;
+    const int es = g / NFN;
+    F.q = g - es * NFN;
+    const int f = F.q / NLINE, l = F.q - f * NLINE;
+    F.d = f >> 1;
+    F.side = f & 1;
+    F.own = line_node<DIM>(F.d, l, F.side ? 3 : 0);
+    nn = line_node<DIM>(F.d, l, F.side ? 0 : 3);  // matching node of the neighbour
+    return g < EPW * NFN;
+}
+
 // Lane -> node pair of round rd over the directions [D0, D0 + ND): element slot
 // es, direction offset dd, line l, pair k.  Bit fields of the lane index:
-//   2D (ND = 2): 4 slots x 2 directions x 4 lines x 2 pairs per round, 3 rounds;
-//   3D, ND = 2:  2 directions x 16 lines x 2 pairs per round, 3 rounds;
-//   3D, ND = 1:  16 lines x 4 pairs, then 16 lines x 2 pairs on lanes 0..31.
+//   2D (ND = 2): 4 slots x 2 directions x 4 lines x 2 pairs per round
+//                (lane = 16 es + 8 dd + 2 l + k - 2 rd), 3 rounds;
+//   3D, ND = 2:  2 directions x 16 lines x 2 pairs per round (lane = 32 dd + 2 l +
+//                k - 2 rd), 3 rounds; with UNI, round 0 holds pairs k = 0..3 of every
+//                line in direction D0 (lane = 4 l + k), round 2 the same in direction
+//                D0 + 1 and round 1 the pairs k = 4, 5 of both (lane = 32 dd + 2 l +
+//                k - 4), so that two of the three rounds form their fluxes in a
+//                direction fixed at compile time;
+//   3D, ND = 1:  round 0: lane = 4 l + k; round 1: pairs k = 4, 5 on lanes 0..31
+//                (2 l + k - 4), with UNI on lanes 32..63, leaving lanes 0..31 to the
+//                surface fluxes of the faces normal to D0 merged into that round.
 template <int DIM, int ND>
 struct PairRounds {
     static_assert(DIM == 3 || ND == 2, "2D evaluates both directions in one phase");
     static constexpr int N = (DIM == 3 && ND == 1) ? 2 : 3;
 };
 
-template <int DIM, int ND>
+template <int DIM, int ND, bool UNI = false>
 __device__ __forceinline__ bool pair_of(int rd, int lane, int &es, int &dd, int &l, int &k)
 {
+    if (DIM == 3 && ND == 1) {
+        es = 0;
+        dd = 0;
+        if (rd == 0) {
+            l = lane >> 2;
+            k = lane & 3;
+            return true;
+        }
+        l = (lane >> 1) & 15;
+        k = 4 + (lane & 1);
+        return UNI ? lane >= 32 : lane < 32;
+    }
     if (DIM == 2) {
         es = lane >> 4;
         dd = (lane >> 3) & 1;
@@ -758,21 +807,22 @@ __device__ __forceinline__ bool pair_of(int rd, int lane, int &es, int &dd, int 
         return true;
     }
     es = 0;
-    if (ND == 2) {
+    if (!UNI) {
         dd = lane >> 5;
         l = (lane >> 1) & 15;
         k = 2 * rd + (lane & 1);
         return true;
     }
-    dd = 0;
-    if (rd == 0) {
+    if (rd != 1) {
+        dd = rd == 0 ? 0 : 1;
         l = lane >> 2;
         k = lane & 3;
         return true;
     }
+    dd = lane >> 5;
     l = (lane >> 1) & 15;
     k = 4 + (lane & 1);
-    return lane < 32;
+    return true;
 }
 
 // Primitive variables of a node in LDS: rho, v_0..v_{DIM-1}, p, contiguous per
@@ -826,12 +876,34 @@ __device__ __forceinline__ void flux_central(int d, const Prim<T, DIM> &A, const
     f[DIM + 1] = (T)0.5 * ((ea + A.p) * va + (eb + B.p) * vb);
 }
 
+// Field-by-field choice between two node states (values, so that both stay in
+// registers).
+template <typename T, int DIM>
+__device__ __forceinline__ Prim<T, DIM> pick(bool c, const Prim<T, DIM> &X, const Prim<T, DIM> &Y)
+{
+    Prim<T, DIM> P;
+    P.rho = c ? X.rho : Y.rho;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) P.v[k] = c ? X.v[k] : Y.v[k];
+    P.p = c ? X.p : Y.p;
+    P.beta = c ? X.beta : Y.beta;
+    return P;
+}
+
 // Two-point volume fluxes of the pairs of directions [D0, D0 + ND), one pair per
 // lane and round, written to vf of the pair's element slot: the EC flux, or the
-// central flux for the weak form.
-template <int DIM, typename T, int D0, int ND, bool WEAK>
-__device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_gm1)
+// central flux for the weak form.  FACES (3D, ND = 1, EC surface flux): the free
+// lanes 0..31 of round 1 form the surface fluxes of face nodes 64..95, the faces
+// normal to D0, from the own face node in LDS and the neighbour's state PNF, and
+// write them lifted to sf, as the surface-flux rounds do for the other faces.
+// UNI: the pair mapping with rounds of one direction (used with FACES, whose
+// lanes it leaves free, and by the hexahedra's other phase in the same kernels).
+template <int DIM, typename T, int D0, int ND, bool WEAK, bool FACES = false, bool UNI = FACES>
+__device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_gm1,
+                                             const FaceNode<DIM> *FF = nullptr, const Prim<T, DIM> *PNF = nullptr,
+                                             bool fvf = false)
 {
+    static_assert(!FACES || (DIM == 3 && ND == 1 && !WEAK), "faces merge into the one-direction 3D phase");
     constexpr int EPW = SG<DIM>::EPW, NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V;
     constexpr int SLOT = SL<DIM, T>::SLOT, PRIM = SL<DIM, T>::PRIM, NFN = SG<DIM>::NFN;
     constexpr int NR = PairRounds<DIM, ND>::N;
@@ -843,15 +915,28 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
     int pv[NR];
     bool ok[NR];
     T *vfs[NR];
+    const bool face_lane = FACES && lane < 32;
 #pragma unroll
     for (int rd = 0; rd < NR; ++rd) {
         int es, dd, l, k;
-        ok[rd] = pair_of<DIM, ND>(rd, lane, es, dd, l, k);
+        ok[rd] = pair_of<DIM, ND, UNI>(rd, lane, es, dd, l, k);
         int ta, tb;
         pair_pos(k, ta, tb);
         const int d = D0 + dd;
         T *slot = lds + (size_t)(wave * EPW + es) * SLOT;
-        if (ok[rd]) {
+        if (FACES && rd == 1) {
+            // pair lanes read both nodes, face lanes their own face node; the face
+            // lanes' minus / plus states are then the own node and the neighbour in
+            // the order of the face's side
+            Prim<T, DIM> X, Y;
+            lds_get_prim<T, DIM>(slot, face_lane ? FF->own : line_node<DIM>(d, l, ta), X);
+            lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, tb), Y);  // (a node of the slot on every lane)
+            Y = pick<T, DIM>(face_lane, *PNF, Y);
+            const bool swap = face_lane && FF->side == 0;
+            A[rd] = pick<T, DIM>(swap, Y, X);
+            B[rd] = pick<T, DIM>(swap, X, Y);
+            ok[rd] = face_lane ? fvf : ok[rd];
+        } else if (ok[rd]) {
             lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, ta), A[rd]);
             lds_get_prim<T, DIM>(slot, line_node<DIM>(d, l, tb), B[rd]);
         }
@@ -862,13 +947,20 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
     for (int rd = 0; rd < NR; ++rd) {
         if (!ok[rd]) continue;
         int es, dd, l, k;
-        pair_of<DIM, ND>(rd, lane, es, dd, l, k);
+        pair_of<DIM, ND, UNI>(rd, lane, es, dd, l, k);
         const int d = D0 + dd;
         T f[V];
         if (WEAK) flux_central<T, DIM>(d, A[rd], B[rd], inv_gm1, f);
         else flux_ec<T, DIM>(d, A[rd], B[rd], inv_gm1, f);
+        if (FACES && rd == 1 && face_lane) {
+            const T lift = FF->side ? (T)6 : (T)-6;
+            T *sf = vfs[rd] - V * NFN;
 #pragma unroll
-        for (int v = 0; v < V; ++v) vfs[rd][v * NPP + pv[rd]] = f[v];
+            for (int v = 0; v < V; ++v) sf[v * NFN + FF->q] = lift * f[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) vfs[rd][v * NPP + pv[rd]] = f[v];
+        }
     }
 }
 
@@ -950,34 +1042,6 @@ __device__ __forceinline__ void gather(const T *slot, int node, const T *hn, con
     }
 }
 
-// Face nodes of a wavefront: EPW * NFN of them (64 in 2D, 96 in 3D), spread over
-// the lanes in FR rounds; face node g = lane + 64 r belongs to element slot
-// g / NFN, which is the lane's own slot (2D: 16 face nodes per quadrilateral;
-// 3D: one element per wavefront).
-template <int DIM>
-struct FaceRounds {
-    static constexpr int N = (SG<DIM>::EPW * SG<DIM>::NFN + 63) / 64;
-};
-
-template <int DIM>
-struct FaceNode {
-    int q, d, side, own;  // face-node slot, direction, side (1 = +), own node on the face
-};
-
-template <int DIM>
-__device__ __forceinline__ bool face_node(int r, int lane, FaceNode<DIM> &F, int &nn)
-{
-    constexpr int EPW = SG<DIM>::EPW, NFN = SG<DIM>::NFN, NLINE = SG<DIM>::NLINE;
-    const int g = lane + 64 * r;
-    const int es = g / NFN;
-    F.q = g - es * NFN;
-    const int f = F.q / NLINE, l = F.q - f * NLINE;
-    F.d = f >> 1;
-    F.side = f & 1;
-    F.own = line_node<DIM>(F.d, l, F.side ? 3 : 0);
-    nn = line_node<DIM>(F.d, l, F.side ? 0 : 3);  // matching node of the neighbour
-    return g < EPW * NFN;
-}
 
 }  // namespace
 
@@ -1164,9 +1228,14 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         wave_lds_sync();
     }
 
-    // ---- surface fluxes, lifted: +6 f* on right faces, -6 f* on left (+-1/q_boundary)
+    // ---- surface fluxes, lifted: +6 f* on right faces, -6 f* on left (+-1/q_boundary).
+    // Hexahedra with the EC surface flux form those of the faces normal to direction
+    // 2 (face nodes 64..95, the second round) in the half-empty last round of that
+    // direction's pairs instead.
+    constexpr bool MERGE = DIM == 3 && FLUX == 0;
 #pragma unroll
     for (int r = 0; r < FR; ++r) {
+        if (MERGE && r == 1) continue;
         if (!fv[r]) continue;
         Prim<T, DIM> PO;
         lds_get_prim<T, DIM>(slot, F[r].own, PO);
@@ -1202,11 +1271,22 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
 #pragma unroll
     for (int v = 0; v < V; ++v) du[v] = 0;
     const bool weak = FLUX && a.volume;  // uniform over the launch
-    if (weak) volume_pairs<DIM, T, 0, 2, true>(lds, wave, lane, inv_gm1);
-    else volume_pairs<DIM, T, 0, 2, false>(lds, wave, lane, inv_gm1);
-    wave_lds_sync();
-    gather<DIM, T, 0, 2>(slot, node, hn, gtab, du);
-    if constexpr (DIM == 3) {
+    if constexpr (MERGE) {
+        // direction 2 first (its pairs and the merged faces), then directions 0 and 1
+        volume_pairs<DIM, T, 2, 1, false, true>(lds, wave, lane, inv_gm1, &F[1], &PN[1], fv[1]);
+        wave_lds_sync();
+        gather<DIM, T, 2, 1>(slot, node, hn, gtab, du);
+        wave_lds_sync();
+        volume_pairs<DIM, T, 0, 2, false, false, true>(lds, wave, lane, inv_gm1);
+        wave_lds_sync();
+        gather<DIM, T, 0, 2>(slot, node, hn, gtab, du);
+    } else {
+        if (weak) volume_pairs<DIM, T, 0, 2, true>(lds, wave, lane, inv_gm1);
+        else volume_pairs<DIM, T, 0, 2, false>(lds, wave, lane, inv_gm1);
+        wave_lds_sync();
+        gather<DIM, T, 0, 2>(slot, node, hn, gtab, du);
+    }
+    if constexpr (DIM == 3 && !MERGE) {
         wave_lds_sync();
         if (weak) volume_pairs<DIM, T, 2, 1, true>(lds, wave, lane, inv_gm1);
         else volume_pairs<DIM, T, 2, 1, false>(lds, wave, lane, inv_gm1);
