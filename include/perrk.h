@@ -183,6 +183,12 @@ typedef struct {
                                   2D tiles of 32 quadrilaterals (a full workgroup) 8x4, 4x8, 16x2,
                                   32x1; 3D cubes of 8^3, 4^3, 16^3 hexahedra, or whole rows.  Results
                                   do not depend on the tile. */
+    int32_t phases;            /* 2D Euler with the EC surface flux and flux differencing: 0 = chosen
+                                  per stage by the autotuner with tune = 1 (1 otherwise); 1 = a stage
+                                  forms the pair fluxes of both directions in one phase and its face
+                                  fluxes in a round of their own; 2 = one direction at a time (pairs
+                                  and faces of x, then of y; half the LDS per element).  Ignored by
+                                  the other configurations.  Results do not depend on the choice. */
 } perrk_options;
 #define PERRK_TILES 4
 
@@ -199,7 +205,7 @@ typedef struct {
 
 /* Default options: relax = 1, max_newton = 10, tol_r = 1e-12, tol_step = 1e-15,
  * anchor = STEP, max_bisect = 60, bracket [0.8, 1.2], guess = PREV,
- * fast_passes = 3, use_graph = 1, tune = 1, tile = 0. */
+ * fast_passes = 3, use_graph = 1, tune = 1, tile = 0, phases = 0. */
 void perrk_default_options(perrk_options *opts);
 
 /* Validates every descriptor on the host (no GPU call): tableau structure,

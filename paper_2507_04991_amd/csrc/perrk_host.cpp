@@ -35,7 +35,8 @@ struct perrk_ctx {
     std::vector<int> bstages;  // stages with b_i != 0
     perrk_options opt{};
     RelaxParams rp{};
-    LaunchCfg cfg{4};               // default stage launch shape
+    LaunchCfg cfg{4, 0};            // default stage launch shape
+    bool can_one_dir = false;       // 2D Euler with the EC fluxes: stages may take one direction at a time
     std::vector<LaunchCfg> scfg;    // per stage (autotuned at the first step when opt.tune)
     bool tuned = false;
     std::string tune_report;
@@ -293,6 +294,7 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
         if (o->tune != 0 && o->tune != 1 && o->tune != -1 && o->tune != -2 && o->tune != -4 && o->tune != -8)
             return ck.bad("tune must be 1, 0, -1, -2, -4 or -8");
         if (o->tile < 0 || o->tile > PERRK_TILES) return ck.bad("tile must be in 0..%d", PERRK_TILES);
+        if (o->phases < 0 || o->phases > 2) return ck.bad("phases must be 0, 1 or 2");
     }
     return PERRK_OK;
 }
@@ -544,13 +546,19 @@ int use_tile(perrk_ctx *c, int tile)
     return PERRK_OK;
 }
 
-// Picks the wavefronts per workgroup of every stage launch, and (option tile =
-// 0) the element tile of the active lists, by timing the candidates on the
-// caller's state: for each tile, every stage in step order with 1, 2, 4 and 8
-// wavefronts per workgroup (a stage launch only reads U_n and earlier stage
+// Picks the wavefronts per workgroup of every stage launch, for 2D Euler with
+// the EC fluxes (option phases = 0) whether the stage takes the two directions
+// in one phase or one at a time, and (option tile = 0) the element tile of the
+// active lists, by timing the candidates on the caller's state: for each tile,
+// every stage in step order with 1, 2, 4 and 8 wavefronts per workgroup in
+// each phase structure (a stage launch only reads U_n and earlier stage
 // registers, so repeating it is harmless); the tile with the smallest sum of
-// its stages' best times is kept, with those launch shapes.  Results do not
-// depend on the tile or the launch shape.
+// its stages' best times is kept, with those launch shapes.  Each timed launch
+// follows what precedes it in a step, so that it meets the caches of a step:
+// the previous stage (with its chosen shape), or for stage 1 a pass over the
+// state like the final update's (a copy of u into the direction buffer, which
+// the step's stages overwrite).  Results do not depend on the tile, the phase
+// structure or the launch shape.
 int autotune(perrk_ctx *c, double *u)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -562,28 +570,41 @@ int autotune(perrk_ctx *c, double *u)
     int status = PERRK_OK, best_tile = c->tile;
     double best_sum = 1e300;
     std::vector<LaunchCfg> best_cfg = c->scfg;
+    const int od_first = c->can_one_dir && c->opt.phases == 0 ? 0 : c->cfg.one_dir;
+    const int od_last = c->can_one_dir && c->opt.phases == 0 ? 1 : c->cfg.one_dir;
     for (int tile = first_tile; tile <= last_tile && status == PERRK_OK; ++tile) {
         if (tile != c->tile && (status = use_tile(c, tile)) != PERRK_OK) break;
         std::vector<LaunchCfg> cfg = c->scfg;
         double sum = 0.0;
         char buf[160];
-        std::snprintf(buf, sizeof buf, "tile %s: waves per workgroup (stage: choice [ms per candidate 1/2/4/8]):",
-                      tile_name(c->dim, tile));
+        std::snprintf(buf, sizeof buf,
+                      "tile %s: waves per workgroup (stage: ms per candidate 1/2/4/8%s -> choice):",
+                      tile_name(c->dim, tile), od_last > od_first ? ", then the same one direction at a time" : "");
         std::string tline = buf;
         for (int i = 0; i < c->S && status == PERRK_OK; ++i) {
-            StageArgs a;
-            int variant = 0, kind = 0;
+            StageArgs a, ap;
+            int variant = 0, kind = 0, variant_p = 0, kind_p = 0;
             stage_setup(c, u, i, a, variant, kind);
-            int best = c->cfg.epb_mult;
+            if (i > 0) stage_setup(c, u, i - 1, ap, variant_p, kind_p);
+            // the launch that precedes stage i in a step
+            auto context = [&]() -> hipError_t {
+                if (i == 0)
+                    return hipMemcpyAsync(c->d_d, u, sizeof(double) * (size_t)c->V * c->nelem * c->npe,
+                                          hipMemcpyDeviceToDevice, c->stream);
+                return launch_stage(c->dim, variant_p, c->flux, kind_p, ap, stage_coef(c, i - 1), cfg[i - 1],
+                                    c->stream);
+            };
+            LaunchCfg best = c->cfg;
             float best_ms = 1e30f;
             std::snprintf(buf, sizeof buf, " %d:", i + 1);
             std::string line = buf;
-            for (int wpb = 1; wpb <= PERRK_MAX_WPB; wpb *= 2) {
-                if (stage_lds_bytes(c->dim, variant, wpb, c->viscous ? 2 : c->sys) > c->max_lds) {
+            for (int cand = 0; cand < 4 * (od_last - od_first + 1) && status == PERRK_OK; ++cand) {
+                const LaunchCfg cf{1 << (cand & 3), od_first + (cand >> 2)};
+                if (stage_lds_bytes(c->dim, variant, cf.epb_mult, c->viscous ? 2 : c->sys, cf.one_dir != 0) >
+                    c->max_lds) {
                     line += " -";
                     continue;
                 }
-                const LaunchCfg cf{wpb};
                 if (launch_stage(c->dim, variant, c->flux, kind, a, stage_coef(c, i), cf, c->stream) != hipSuccess) {
                     (void)hipGetLastError();
                     line += " x";
@@ -591,7 +612,7 @@ int autotune(perrk_ctx *c, double *u)
                 }
                 float tmin = 1e30f;
                 for (int r = 0; r < 3; ++r) {
-                    if (hipEventRecord(e0, c->stream) != hipSuccess ||
+                    if (context() != hipSuccess || hipEventRecord(e0, c->stream) != hipSuccess ||
                         launch_stage(c->dim, variant, c->flux, kind, a, stage_coef(c, i), cf, c->stream) != hipSuccess ||
                         hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                         status = fail(c, PERRK_EHIP, "autotuning launch failed: %s",
@@ -607,12 +628,12 @@ int autotune(perrk_ctx *c, double *u)
                 line += buf;
                 if (tmin < best_ms) {
                     best_ms = tmin;
-                    best = wpb;
+                    best = cf;
                 }
             }
-            cfg[i].epb_mult = best;
+            cfg[i] = best;
             sum += best_ms;
-            std::snprintf(buf, sizeof buf, " -> %d;", best);
+            std::snprintf(buf, sizeof buf, " -> %d%s;", best.epb_mult, best.one_dir ? " one direction at a time" : "");
             tline += line + buf;
         }
         std::snprintf(buf, sizeof buf, " sum %.4f ms. ", sum);
@@ -704,6 +725,7 @@ void perrk_default_options(perrk_options *o)
     o->use_graph = 1;
     o->tune = 1;
     o->tile = 0;
+    o->phases = 0;
 }
 
 int perrk_validate(const perrk_mesh_desc *mesh, const perrk_partition_desc *part,
@@ -835,8 +857,11 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     c->rp = rp;
     // the Euler stage kernel's last stage evaluates the first residual of the solve
     c->fused_first = c->sys == PERRK_SYSTEM_EULER && !c->viscous;
+    c->can_one_dir = c->fused_first && c->dim == 2 && c->flux == PERRK_FLUX_EC &&
+                     c->volume == PERRK_VOLUME_FLUX_DIFFERENCING;
     // GLM-MHD: 27 KB of LDS per wavefront; Navier-Stokes: 19 KB
     c->cfg.epb_mult = c->sys == PERRK_SYSTEM_GLM_MHD ? 1 : (c->viscous ? 2 : 4);
+    c->cfg.one_dir = c->can_one_dir && c->opt.phases == 2 ? 1 : 0;
     c->scfg.assign(c->S, c->cfg);
     c->sstats.assign(c->S, perrk_kernel_stat{});
 
@@ -926,7 +951,8 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     }
     if (c->opt.tune < 0) {  // one given launch shape for every stage
         const int w = -c->opt.tune;
-        if (stage_lds_bytes(c->dim, c->precision == PERRK_MIXED_ALL ? 1 : 0, w, c->viscous ? 2 : c->sys) > c->max_lds) {
+        if (stage_lds_bytes(c->dim, c->precision == PERRK_MIXED_ALL ? 1 : 0, w, c->viscous ? 2 : c->sys,
+                            c->cfg.one_dir != 0) > c->max_lds) {
             std::fprintf(stderr, "perrk_init: %d wavefronts per workgroup need more LDS than the device has\n", w);
             return bail(PERRK_EINVAL);
         }
@@ -1243,15 +1269,18 @@ int perrk_get_tuning(perrk_ctx *c, char *buf, size_t len)
 {
     static const char *const flux_names[] = {"ec", "hll", "llf", "hlle", "hllc", "central"};
     if (!c || !buf || !len) return PERRK_EINVAL;
-    std::string w;
-    for (const LaunchCfg &x : c->scfg) w += (w.empty() ? "" : ",") + std::to_string(x.epb_mult);
+    std::string w, od;
+    for (const LaunchCfg &x : c->scfg) {
+        w += (w.empty() ? "" : ",") + std::to_string(x.epb_mult);
+        od += (od.empty() ? "" : ",") + std::to_string(x.one_dir);
+    }
     std::snprintf(buf, len,
                   "system=%s dim=%d precision=%s flux=%s volume=%s tile=%s stage_waves_per_workgroup=[%s] "
-                  "fast_passes=%d graph=%d %s",
+                  "stage_one_direction_at_a_time=[%s] fast_passes=%d graph=%d %s",
                   c->sys == PERRK_SYSTEM_GLM_MHD ? "glm_mhd" : "euler", c->dim,
                   c->precision == PERRK_MIXED ? "mixed" : (c->precision == PERRK_MIXED_ALL ? "mixed_all" : "fp64"),
                   flux_names[c->flux], c->volume ? "weak" : "flux_differencing", tile_name(c->dim, c->tile), w.c_str(),
-                  c->opt.fast_passes, c->opt.use_graph, c->tuned ? c->tune_report.c_str() : "(not tuned)");
+                  od.c_str(), c->opt.fast_passes, c->opt.use_graph, c->tuned ? c->tune_report.c_str() : "(not tuned)");
     return PERRK_OK;
 }
 

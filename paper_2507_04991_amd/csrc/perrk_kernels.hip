@@ -132,13 +132,24 @@ struct Rcp64 {
 __device__ __forceinline__ double flog(double x) { return perrk_log::log_f64(x, Rcp64{}); }
 __device__ __forceinline__ double flog1p(double x) { return perrk_log::log1p_f64(x, Rcp64{}); }
 
+// The flux arithmetic below fixes every fused multiply-add explicitly (no
+// contraction left to the compiler), so that the same two-point flux gives the
+// same bits whatever the code around it: a direction known at compile time or
+// chosen per lane, states taken from LDS or from registers.
+
 __device__ __forceinline__ double lmean(double a, double b)
 {
+#pragma clang fp contract(off)
     const double d = a - b, s = a + b;
     const double rs = rcp64(s);
     const double z = d * rs, u = z * z;
     if (u < 2.5e-3) {
-        const double P = 1.0 + u * (C_R1 + u * (C_R2 + u * (C_R3 + u * (C_R4 + u * (C_R5 + u * C_R6)))));
+        double P = fma(u, C_R6, C_R5);
+        P = fma(u, P, C_R4);
+        P = fma(u, P, C_R3);
+        P = fma(u, P, C_R2);
+        P = fma(u, P, C_R1);
+        P = fma(u, P, 1.0);
         return 0.5 * s * P;
     }
     return d * rcp64(flog1p(d * rcp64(b)));
@@ -146,12 +157,17 @@ __device__ __forceinline__ double lmean(double a, double b)
 
 __device__ __forceinline__ double inv_lmean(double a, double b)
 {
+#pragma clang fp contract(off)
     const double d = a - b, s = a + b;
     const double rs = rcp64(s);
     const double z = d * rs, u = z * z;
     if (u < 2.5e-3) {
-        const double F = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0 + u * (1.0 / 9.0 +
-                         u * (1.0 / 11.0 + u * (1.0 / 13.0))))));
+        double F = fma(u, 1.0 / 13.0, 1.0 / 11.0);
+        F = fma(u, F, 1.0 / 9.0);
+        F = fma(u, F, 1.0 / 7.0);
+        F = fma(u, F, 1.0 / 5.0);
+        F = fma(u, F, 1.0 / 3.0);
+        F = fma(u, F, 1.0);
         return 2.0 * rs * F;
     }
     return flog1p(d * rcp64(b)) * rcp64(d);
@@ -159,21 +175,31 @@ __device__ __forceinline__ double inv_lmean(double a, double b)
 
 __device__ __forceinline__ float lmean(float a, float b)
 {
+#pragma clang fp contract(off)
     const float d = a - b, s = a + b;
     const float rs = __builtin_amdgcn_rcpf(s);
     const float z = d * rs, u = z * z;
-    if (u < 1.0e-2f)
-        return s * (0.5f + u * ((float)(0.5 * C_R1) + u * ((float)(0.5 * C_R2) + u * (float)(0.5 * C_R3))));
+    if (u < 1.0e-2f) {
+        float P = fmaf(u, (float)(0.5 * C_R3), (float)(0.5 * C_R2));
+        P = fmaf(u, P, (float)(0.5 * C_R1));
+        P = fmaf(u, P, 0.5f);
+        return s * P;
+    }
     return d * __builtin_amdgcn_rcpf(__logf(a * __builtin_amdgcn_rcpf(b)));
 }
 
 __device__ __forceinline__ float inv_lmean(float a, float b)
 {
+#pragma clang fp contract(off)
     const float d = a - b, s = a + b;
     const float rs = __builtin_amdgcn_rcpf(s);
     const float z = d * rs, u = z * z;
-    if (u < 1.0e-2f)
-        return rs * (2.0f + u * ((float)(2.0 / 3.0) + u * ((float)(2.0 / 5.0) + u * (float)(2.0 / 7.0))));
+    if (u < 1.0e-2f) {
+        float F = fmaf(u, (float)(2.0 / 7.0), (float)(2.0 / 5.0));
+        F = fmaf(u, F, (float)(2.0 / 3.0));
+        F = fmaf(u, F, 2.0f);
+        return rs * F;
+    }
     return __logf(a * __builtin_amdgcn_rcpf(b)) * __builtin_amdgcn_rcpf(d);
 }
 
@@ -268,6 +294,7 @@ __device__ __forceinline__ T vdir(const Prim<T, DIM> &P, int d)
 template <typename T, int DIM>
 __device__ __forceinline__ void flux_ec(int d, const Prim<T, DIM> &L, const Prim<T, DIM> &R, T inv_gm1, T *f)
 {
+#pragma clang fp contract(off)
     const T rm = lmean(L.rho, R.rho);
     const T ibm = inv_lmean(L.beta, R.beta);
     T va[DIM];  // arithmetic means of the velocity components
@@ -277,13 +304,13 @@ __device__ __forceinline__ void flux_ec(int d, const Prim<T, DIM> &L, const Prim
     const T vm = DIM == 2 ? (d == 0 ? va[0] : va[1]) : (d == 0 ? va[0] : (d == 1 ? va[1] : va[DIM - 1]));
     const T fr = rm * vm;
     const T pa = (T)0.5 * (L.p + R.p);
-    T vv = 0;
+    T vv = L.v[0] * R.v[0];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) vv += L.v[k] * R.v[k];
+    for (int k = 1; k < DIM; ++k) vv = fma(L.v[k], R.v[k], vv);
     f[0] = fr;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) f[1 + k] = fr * va[k] + (k == d ? pa : (T)0);
-    f[DIM + 1] = fr * ((T)0.5 * vv + inv_gm1 * ibm) + (T)0.5 * (L.p * vr + R.p * vl);
+    for (int k = 0; k < DIM; ++k) f[1 + k] = fma(fr, va[k], k == d ? pa : (T)0);
+    f[DIM + 1] = fma(fr, fma((T)0.5, vv, inv_gm1 * ibm), (T)0.5 * fma(L.p, vr, R.p * vl));
 }
 
 // Dissipative surface fluxes in direction d, selected at run time (the value is
@@ -684,14 +711,25 @@ struct SG {
 
 // Element slot in LDS, in words of T: primitives [node][NQ], then (single
 // precision only) rho/p per node, the lifted surface fluxes sf[V][NFN] and the
-// pair fluxes vf[V][NPP].  Double-precision slots recompute rho/p where they read
+// pair fluxes vf[V][VS].  Double-precision slots recompute rho/p where they read
 // a node (a smaller slot keeps more waves resident); single-precision slots store
-// it once per node, which saves a quarter-rate reciprocal per read.
-template <int DIM, typename T>
+// it once per node, which saves a quarter-rate reciprocal per read.  VS: pair
+// fluxes of one phase, NPP (two directions) or, where the directions are done
+// one at a time (SPLIT), NPD.
+template <int DIM, typename T, bool SPLIT = false>
 struct SL {
     static constexpr bool BETA = sizeof(T) == 4;
     static constexpr int PRIM = SG<DIM>::NQ * SG<DIM>::NPE + (BETA ? SG<DIM>::NPE : 0);
-    static constexpr int SLOT = PRIM + SG<DIM>::V * (SG<DIM>::NFN + SG<DIM>::NPP);  // LDS words per slot
+    static constexpr int VS = SPLIT ? SG<DIM>::NPD : SG<DIM>::NPP;
+    static constexpr int SLOT = PRIM + SG<DIM>::V * (SG<DIM>::NFN + VS);  // LDS words per slot
+};
+
+// Quadrilaterals with the EC fluxes can take the two directions one at a time
+// (pairs and faces of x, then of y: the same fluxes and sums in the same order),
+// which halves the pair-flux area of a slot; the autotuner chooses per stage.
+template <int DIM, int FLUX, bool ONE_DIR>
+struct SplitDirs {
+    static constexpr bool ON = ONE_DIR && DIM == 2 && FLUX == 0;
 };
 
 // Node of line l (the other coordinates) at position t along direction d.
@@ -964,6 +1002,58 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
     }
 }
 
+// One direction D of quadrilaterals (SPLIT slots): its 96 pairs per wavefront
+// and its 32 face nodes in two rounds, all with the EC flux in direction D.
+//   round 0: pairs k = 0..3, lane = 16 es + 4 l + k;
+//   round 1: the lanes whose face node (q = lane mod 16, faces of x for q < 8,
+//            of y for q >= 8) lies on a face normal to D form that face's flux
+//            from the own node in LDS and the neighbour's state PN; the other
+//            lanes take pairs k = 4, 5 (es = lane / 16, l = (lane / 2) mod 4).
+// Pair fluxes go to vf (NPD per variable), face fluxes lifted to sf, exactly as
+// the two-direction rounds and the surface-flux round store them.  The rounds
+// run one after the other (fewer registers held than reading both first).
+template <typename T, int D>
+__device__ __forceinline__ void pairs_and_faces_2d(T *lds, int wave, int lane, T inv_gm1, const FaceNode<2> &F,
+                                                   const Prim<T, 2> &PN)
+{
+    constexpr int EPW = SG<2>::EPW, NPD = SG<2>::NPD, V = SG<2>::V, NFN = SG<2>::NFN;
+    constexpr int SLOT = SL<2, T, true>::SLOT, PRIM = SL<2, T, true>::PRIM;
+    const int es = lane >> 4;
+    T *slot = lds + (size_t)(wave * EPW + es) * SLOT;
+    T *sf = slot + PRIM;
+    T *vf = sf + V * NFN;
+    const bool face_lane = ((lane >> 3) & 1) == D;
+    T f[V];
+    {
+        const int l = (lane >> 2) & 3, k = lane & 3;
+        int ta, tb;
+        pair_pos(k, ta, tb);
+        Prim<T, 2> A, B;
+        lds_get_prim<T, 2>(slot, line_node<2>(D, l, ta), A);
+        lds_get_prim<T, 2>(slot, line_node<2>(D, l, tb), B);
+        flux_ec<T, 2>(D, A, B, inv_gm1, f);
+#pragma unroll
+        for (int v = 0; v < V; ++v) vf[v * NPD + l * 6 + k] = f[v];
+    }
+    const int l = (lane >> 1) & 3, k = 4 + (lane & 1);
+    int ta, tb;
+    pair_pos(k, ta, tb);
+    Prim<T, 2> X, Y;
+    lds_get_prim<T, 2>(slot, face_lane ? F.own : line_node<2>(D, l, ta), X);
+    lds_get_prim<T, 2>(slot, line_node<2>(D, l, tb), Y);  // (a node of the slot on every lane)
+    Y = pick<T, 2>(face_lane, PN, Y);
+    const bool swap = face_lane && F.side == 0;
+    flux_ec<T, 2>(D, pick<T, 2>(swap, Y, X), pick<T, 2>(swap, X, Y), inv_gm1, f);
+    if (face_lane) {
+        const T lift = F.side ? (T)6 : (T)-6;
+#pragma unroll
+        for (int v = 0; v < V; ++v) sf[v * NFN + F.q] = lift * f[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) vf[v * NPD + l * 6 + k] = f[v];
+    }
+}
+
 // Gather table of the single-precision stages, one copy per wavefront in LDS
 // (16 words; lanes 0-15 copy it from here at the start): for each position t on
 // a line, Dsplit[t][(t + j) & 3] for j = 1, 2, 3 in single precision and the
@@ -990,11 +1080,12 @@ constexpr int GTAB_WORDS = 16;
 // Adds -(2/h_d) [sum_{m != t} Dsplit[t][m] f#(t, m) + lifted surface flux] of the
 // directions [d0, d0 + nd) to du (node lane); hn[d] = -(2/h_d) in flux precision;
 // tab: the wavefront's gather table (single precision only).
-template <int DIM, typename T, int D0, int ND>
+template <int DIM, typename T, int D0, int ND, int VS = SG<DIM>::NPP>
 __device__ __forceinline__ void gather(const T *slot, int node, const T *hn, const T *tab, T *du)
 {
+#pragma clang fp contract(off)
     constexpr int d0 = D0, nd = ND;
-    constexpr int NPD = SG<DIM>::NPD, NPP = SG<DIM>::NPP, V = SG<DIM>::V, PRIM = SL<DIM, T>::PRIM;
+    constexpr int NPD = SG<DIM>::NPD, NPP = VS, V = SG<DIM>::V, PRIM = SL<DIM, T>::PRIM;
     constexpr int NFN = SG<DIM>::NFN, NLINE = SG<DIM>::NLINE;
     const T *sf = slot + PRIM;
     const T *vf = sf + V * NFN;
@@ -1028,9 +1119,9 @@ __device__ __forceinline__ void gather(const T *slot, int node, const T *hn, con
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            acc[v] += w1 * vf[v * NPP + p1];
-            acc[v] += w2 * vf[v * NPP + p2];
-            acc[v] += w3 * vf[v * NPP + p3];
+            acc[v] = fma(w1, vf[v * NPP + p1], acc[v]);
+            acc[v] = fma(w2, vf[v * NPP + p2], acc[v]);
+            acc[v] = fma(w3, vf[v * NPP + p3], acc[v]);
         }
         if (t == 0 || t == 3) {
             const int q = (2 * d + (t == 3 ? 1 : 0)) * NLINE + l;
@@ -1038,7 +1129,7 @@ __device__ __forceinline__ void gather(const T *slot, int node, const T *hn, con
             for (int v = 0; v < V; ++v) acc[v] += sf[v * NFN + q];
         }
 #pragma unroll
-        for (int v = 0; v < V; ++v) du[v] += hn[d] * acc[v];
+        for (int v = 0; v < V; ++v) du[v] = fma(hn[d], acc[v], du[v]);
     }
 }
 
@@ -1054,10 +1145,11 @@ namespace {
 // element's own U_n / K_1 / K_{i-1}, dt, its level coefficients and the
 // neighbour words of its face nodes; then the neighbours' data at the matching
 // nodes.  A wavefront never waits for the other wavefronts of its workgroup.
-template <int DIM, typename T, typename KT, int FLUX, int KIND>
+template <int DIM, typename T, typename KT, int FLUX, int KIND, bool ONE_DIR>
 __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageArgs a, const double *coef)
 {
-    constexpr int NPE = SG<DIM>::NPE, V = SG<DIM>::V, EPW = SG<DIM>::EPW, SLOT = SL<DIM, T>::SLOT;
+    constexpr bool SPLIT = SplitDirs<DIM, FLUX, ONE_DIR>::ON;
+    constexpr int NPE = SG<DIM>::NPE, V = SG<DIM>::V, EPW = SG<DIM>::EPW, SLOT = SL<DIM, T, SPLIT>::SLOT;
     constexpr int PRIM = SL<DIM, T>::PRIM, NFN = SG<DIM>::NFN, FR = FaceRounds<DIM>::N;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
@@ -1232,10 +1324,12 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     // Hexahedra with the EC surface flux form those of the faces normal to direction
     // 2 (face nodes 64..95, the second round) in the half-empty last round of that
     // direction's pairs instead.
+    // Quadrilaterals with the EC surface flux form all their face fluxes in the
+    // rounds of the direction-by-direction phases below.
     constexpr bool MERGE = DIM == 3 && FLUX == 0;
 #pragma unroll
     for (int r = 0; r < FR; ++r) {
-        if (MERGE && r == 1) continue;
+        if (SPLIT || (MERGE && r == 1)) continue;
         if (!fv[r]) continue;
         Prim<T, DIM> PO;
         lds_get_prim<T, DIM>(slot, F[r].own, PO);
@@ -1271,7 +1365,16 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
 #pragma unroll
     for (int v = 0; v < V; ++v) du[v] = 0;
     const bool weak = FLUX && a.volume;  // uniform over the launch
-    if constexpr (MERGE) {
+    if constexpr (SPLIT) {
+        constexpr int NPD = SG<DIM>::NPD;
+        pairs_and_faces_2d<T, 0>(lds, wave, lane, inv_gm1, F[0], PN[0]);
+        wave_lds_sync();
+        gather<DIM, T, 0, 1, NPD>(slot, node, hn, gtab, du);
+        wave_lds_sync();
+        pairs_and_faces_2d<T, 1>(lds, wave, lane, inv_gm1, F[0], PN[0]);
+        wave_lds_sync();
+        gather<DIM, T, 1, 1, NPD>(slot, node, hn, gtab, du);
+    } else if constexpr (MERGE) {
         // direction 2 first (its pairs and the merged faces), then directions 0 and 1
         volume_pairs<DIM, T, 2, 1, false, true>(lds, wave, lane, inv_gm1, &F[1], &PN[1], fv[1]);
         wave_lds_sync();
@@ -2865,18 +2968,28 @@ __global__ void init_cases_kernel(CaseState *cs, int n)
     cs[c] = C;
 }
 
-template <int DIM, typename T, typename KT, int FLUX, int KIND>
-hipError_t launch_stage_t(const StageArgs &a, const double *coef, LaunchCfg cfg, hipStream_t s)
+template <int DIM, typename T, typename KT, int FLUX, int KIND, bool ONE_DIR>
+hipError_t launch_stage_s(const StageArgs &a, const double *coef, LaunchCfg cfg, hipStream_t s)
 {
-    constexpr int EPW = SG<DIM>::EPW, SLOT = SL<DIM, T>::SLOT;
+    constexpr int EPW = SG<DIM>::EPW, SLOT = SL<DIM, T, SplitDirs<DIM, FLUX, ONE_DIR>::ON>::SLOT;
     const int wpb = cfg.epb_mult;
     const int epb = wpb * EPW;
     if (a.n_active <= 0) return hipSuccess;
     const int blocks = (a.n_active + epb - 1) / epb;
     // single precision: the element slots, then one gather table per wavefront
     const size_t lds = ((size_t)epb * SLOT + (sizeof(T) == 4 ? (size_t)wpb * GTAB_WORDS : 0)) * sizeof(T);
-    hipLaunchKernelGGL((stage_kernel<DIM, T, KT, FLUX, KIND>), dim3(blocks), dim3(64 * wpb), lds, s, a, coef);
+    hipLaunchKernelGGL((stage_kernel<DIM, T, KT, FLUX, KIND, ONE_DIR>), dim3(blocks), dim3(64 * wpb), lds, s, a,
+                       coef);
     return hipGetLastError();
+}
+
+template <int DIM, typename T, typename KT, int FLUX, int KIND>
+hipError_t launch_stage_t(const StageArgs &a, const double *coef, LaunchCfg cfg, hipStream_t s)
+{
+    if constexpr (SplitDirs<DIM, FLUX, true>::ON) {
+        if (cfg.one_dir) return launch_stage_s<DIM, T, KT, FLUX, KIND, true>(a, coef, cfg, s);
+    }
+    return launch_stage_s<DIM, T, KT, FLUX, KIND, false>(a, coef, cfg, s);
 }
 
 template <int DIM, typename T, typename KT, int FLUX>
@@ -2943,15 +3056,18 @@ hipError_t launch_ns_stage_t(const StageArgs &a, const double *coef, LaunchCfg c
 
 }  // namespace
 
-size_t stage_lds_bytes(int dim, int variant, int wpb, int sys)
+size_t stage_lds_bytes(int dim, int variant, int wpb, int sys, bool one_dir)
 {
     if (sys == 1) return (size_t)wpb * 4 * MHD_SLOT * sizeof(double);
     if (sys == 2) return (size_t)wpb * 4 * NS_SLOT * sizeof(double);
+    const bool ec = one_dir;  // (quadrilaterals with the EC fluxes only)
     if (variant == 1) {  // element slots and the wavefronts' gather tables
-        if (dim == 2) return (size_t)wpb * (SG<2>::EPW * SL<2, float>::SLOT + GTAB_WORDS) * sizeof(float);
+        if (dim == 2)
+            return (size_t)wpb * (SG<2>::EPW * (ec ? SL<2, float, true>::SLOT : SL<2, float>::SLOT) + GTAB_WORDS) *
+                   sizeof(float);
         return (size_t)wpb * (SG<3>::EPW * SL<3, float>::SLOT + GTAB_WORDS) * sizeof(float);
     }
-    if (dim == 2) return (size_t)wpb * SG<2>::EPW * SL<2, double>::SLOT * sizeof(double);
+    if (dim == 2) return (size_t)wpb * SG<2>::EPW * (ec ? SL<2, double, true>::SLOT : SL<2, double>::SLOT) * sizeof(double);
     return (size_t)wpb * SG<3>::EPW * SL<3, double>::SLOT * sizeof(double);
 }
 

@@ -60,7 +60,7 @@ class Options(ctypes.Structure):
                 ("tol_step", ctypes.c_double), ("anchor", ctypes.c_int32), ("max_bisect", ctypes.c_int32),
                 ("bisect_lo", ctypes.c_double), ("bisect_hi", ctypes.c_double), ("guess", ctypes.c_int32),
                 ("fast_passes", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tune", ctypes.c_int32),
-                ("tile", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("phases", ctypes.c_int32)]
 
 
 class StepInfo(ctypes.Structure):

@@ -119,6 +119,11 @@ def test_validate_viscous_descriptors():
     for tile in (-1, P.TILES + 1):
         st, msg = d.validate(P.default_options(tile=tile))
         assert st == P.EINVAL and "tile" in msg, msg
+    for phases in (0, 1, 2):
+        assert d.validate(P.default_options(phases=phases))[0] == P.OK
+    for phases in (-1, 3):
+        st, msg = d.validate(P.default_options(phases=phases))
+        assert st == P.EINVAL and "phases" in msg, msg
 
 
 def test_validate_node_limit_and_case_count():

@@ -1,7 +1,9 @@
 """Launch shapes through the C ABI: every stage launched with 1, 2, 4 or 8
-wavefronts per workgroup (options.tune = -w), and the active lists built with
-every element tile (options.tile = 1..4), give bit-identical states; so does
-the autotuner's own choice (tune = 1, tile = 0), which the tuning report names.
+wavefronts per workgroup (options.tune = -w), the active lists built with
+every element tile (options.tile = 1..4), and the 2D stages with the EC fluxes
+run with both directions in one phase or one direction at a time
+(options.phases = 1, 2), give bit-identical states; so does the autotuner's own
+choice (tune = 1, tile = 0, phases = 0), which the tuning report names.
 
 In 2D the active lists keep tiles of each case mesh together and a neighbour that
 sits in the same workgroup is read from LDS instead of global memory, so the split
@@ -50,9 +52,9 @@ def ensemble_2d():
     return tab, faces, U0s, levs, dts
 
 
-def run(P, tab, faces, U0s, levs, dts, precision, w, nsteps=3, tile=1):
-    d = P.Descriptors(faces, levs, tab, precision=precision)
-    st = P.Stepper(d, P.default_options(tune=-w, tile=tile) if w > 0 else P.default_options())
+def run(P, tab, faces, U0s, levs, dts, precision, w, nsteps=3, tile=1, phases=1, flux=0):
+    d = P.Descriptors(faces, levs, tab, precision=precision, surface_flux=flux)
+    st = P.Stepper(d, P.default_options(tune=-w, tile=tile, phases=phases) if w > 0 else P.default_options())
     u = torch.tensor(np.concatenate(U0s, axis=1), device="cuda").contiguous()
     gam = []
     for _ in range(nsteps):
@@ -63,6 +65,8 @@ def run(P, tab, faces, U0s, levs, dts, precision, w, nsteps=3, tile=1):
     if w > 0:
         assert "(not tuned)" in st.tuning() and f"stage_waves_per_workgroup=[{','.join([str(w)] * len(tab['c']))}]" \
             in st.tuning(), st.tuning()
+        od = int(phases == 2 and len(faces[0]) == 2 and flux == 0)
+        assert f"stage_one_direction_at_a_time=[{','.join([str(od)] * len(tab['c']))}]" in st.tuning(), st.tuning()
     else:
         assert "Chosen: tile" in st.tuning(), st.tuning()
     st.close()
@@ -119,3 +123,46 @@ def test_states_identical_for_every_element_tile(P, dim):
     for tile in res:
         assert np.array_equal(res[tile][0], res[1][0]), tile
         assert np.array_equal(res[tile][1], res[1][1]), tile
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_2d_states_identical_for_both_phase_structures(P, precision):
+    """Quadrilaterals with the EC fluxes: pairs of both directions in one phase
+    with the faces in a round of their own, or one direction at a time with the
+    faces in the half-empty pair rounds, give the same bits (the same fluxes,
+    summed in the same order), at every workgroup size."""
+    tab, faces, U0s, levs, dts = ensemble_2d()
+    res = {}
+    for phases in (1, 2):
+        for w in (1, 4, 8):
+            print(f"case 2d ensemble precision={precision} phases={phases} waves per workgroup {w}", flush=True)
+            res[phases, w] = run(P, tab, faces, U0s, levs, dts, precision, w, nsteps=2, phases=phases)
+    for k in res:
+        assert np.array_equal(res[k][0], res[1, 1][0]), k
+        assert np.array_equal(res[k][1], res[1, 1][1]), k
+
+
+def test_phases_option_ignored_where_it_does_not_apply(P):
+    """The HLL surface flux and hexahedra keep their one phase structure."""
+    from tests.helpers import problem_3d
+    tab, faces, U0s, levs, dts = ensemble_2d()
+    a = run(P, tab, faces, U0s, levs, dts, 1, 4, nsteps=2, phases=1, flux=P.FLUX_HLL)
+    b = run(P, tab, faces, U0s, levs, dts, 1, 4, nsteps=2, phases=2, flux=P.FLUX_HLL)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    f, U0, tab, dt, lev = problem_3d(levels="random")
+    a = run(P, tab, [f], [U0], [lev], [dt], 1, 4, nsteps=2, phases=1)
+    b = run(P, tab, [f], [U0], [lev], [dt], 1, 4, nsteps=2, phases=2)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_autotuner_reports_the_phase_structure(P):
+    tab, faces, U0s, levs, dts = ensemble_2d()
+    d = P.Descriptors(faces, levs, tab, precision=1)
+    st = P.Stepper(d, P.default_options())
+    u = torch.tensor(np.concatenate(U0s, axis=1), device="cuda").contiguous()
+    st.step(u, np.array(dts))
+    rep = st.tuning()
+    st.close()
+    assert "then the same one direction at a time" in rep, rep
+    od = rep.split("stage_one_direction_at_a_time=[")[1].split("]")[0].split(",")
+    assert len(od) == len(tab["c"]) and set(od) <= {"0", "1"}, rep
