@@ -547,18 +547,19 @@ int use_tile(perrk_ctx *c, int tile)
 }
 
 // Picks the wavefronts per workgroup of every stage launch, for 2D Euler with
-// the EC fluxes (option phases = 0) whether the stage takes the two directions
-// in one phase or one at a time, and (option tile = 0) the element tile of the
-// active lists, by timing the candidates on the caller's state: for each tile,
-// every stage in step order with 1, 2, 4 and 8 wavefronts per workgroup in
-// each phase structure (a stage launch only reads U_n and earlier stage
-// registers, so repeating it is harmless); the tile with the smallest sum of
-// its stages' best times is kept, with those launch shapes.  Each timed launch
-// follows what precedes it in a step, so that it meets the caches of a step:
-// the previous stage (with its chosen shape), or for stage 1 a pass over the
-// state like the final update's (a copy of u into the direction buffer, which
-// the step's stages overwrite).  Results do not depend on the tile, the phase
-// structure or the launch shape.
+// the EC fluxes (option phases = 0) whether a stage with double-precision
+// fluxes takes the two directions in one phase or one at a time (single-
+// precision stages keep one phase: the selects cost them more than the smaller
+// slot gains), and (option tile = 0) the element tile of the active lists, by
+// timing the candidates on the caller's state: for each tile, every stage in
+// step order with 1, 2, 4 and 8 wavefronts per workgroup in each phase
+// structure (a stage launch only reads U_n and earlier stage registers, so
+// repeating it is harmless); the tile with the smallest sum of its stages'
+// best times is kept, with those launch shapes.  Each timed launch follows what
+// precedes it in a step, so that it meets the caches of a step: the previous
+// stage (with its chosen shape), or for stage 1 the other stages of a step
+// (which also move stage 1's own outputs out of the caches, as a step does).
+// Results do not depend on the tile, the phase structure or the launch shape.
 int autotune(perrk_ctx *c, double *u)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -586,19 +587,26 @@ int autotune(perrk_ctx *c, double *u)
             int variant = 0, kind = 0, variant_p = 0, kind_p = 0;
             stage_setup(c, u, i, a, variant, kind);
             if (i > 0) stage_setup(c, u, i - 1, ap, variant_p, kind_p);
-            // the launch that precedes stage i in a step
+            // the launches that precede stage i in a step
             auto context = [&]() -> hipError_t {
-                if (i == 0)
-                    return hipMemcpyAsync(c->d_d, u, sizeof(double) * (size_t)c->V * c->nelem * c->npe,
-                                          hipMemcpyDeviceToDevice, c->stream);
-                return launch_stage(c->dim, variant_p, c->flux, kind_p, ap, stage_coef(c, i - 1), cfg[i - 1],
-                                    c->stream);
+                if (i > 0)
+                    return launch_stage(c->dim, variant_p, c->flux, kind_p, ap, stage_coef(c, i - 1), cfg[i - 1],
+                                        c->stream);
+                for (int j = 1; j < c->S; ++j) {
+                    StageArgs aj;
+                    int vj = 0, kj = 0;
+                    stage_setup(c, u, j, aj, vj, kj);
+                    const hipError_t e = launch_stage(c->dim, vj, c->flux, kj, aj, stage_coef(c, j), c->cfg, c->stream);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
             };
             LaunchCfg best = c->cfg;
             float best_ms = 1e30f;
             std::snprintf(buf, sizeof buf, " %d:", i + 1);
             std::string line = buf;
-            for (int cand = 0; cand < 4 * (od_last - od_first + 1) && status == PERRK_OK; ++cand) {
+            const int od_top = variant == 1 ? od_first : od_last;  // (variant 1: single-precision fluxes)
+            for (int cand = 0; cand < 4 * (od_top - od_first + 1) && status == PERRK_OK; ++cand) {
                 const LaunchCfg cf{1 << (cand & 3), od_first + (cand >> 2)};
                 if (stage_lds_bytes(c->dim, variant, cf.epb_mult, c->viscous ? 2 : c->sys, cf.one_dir != 0) >
                     c->max_lds) {
