@@ -183,12 +183,14 @@ typedef struct {
                                   2D tiles of 32 quadrilaterals (a full workgroup) 8x4, 4x8, 16x2,
                                   32x1; 3D cubes of 8^3, 4^3, 16^3 hexahedra, or whole rows.  Results
                                   do not depend on the tile. */
-    int32_t phases;            /* 2D Euler with the EC surface flux and flux differencing: 0 = chosen
-                                  per stage by the autotuner with tune = 1 (1 otherwise); 1 = a stage
-                                  forms the pair fluxes of both directions in one phase and its face
-                                  fluxes in a round of their own; 2 = one direction at a time (pairs
-                                  and faces of x, then of y; half the LDS per element).  Ignored by
-                                  the other configurations.  Results do not depend on the choice. */
+    int32_t phases;            /* Euler with the EC surface flux and flux differencing: 0 = chosen per
+                                  stage with double-precision fluxes by the autotuner with tune = 1
+                                  (1 otherwise); 1 = a stage forms the pair fluxes of two directions
+                                  per phase (2D: x and y, faces in a round of their own; 3D: z with
+                                  the z faces, then x and y); 2 = one direction at a time, each with
+                                  its faces (2D: x, y; 3D: z, x, y; half the pair-flux LDS per
+                                  element).  Ignored by the other configurations.  Results do not
+                                  depend on the choice. */
 } perrk_options;
 #define PERRK_TILES 4
 

@@ -36,7 +36,7 @@ struct perrk_ctx {
     perrk_options opt{};
     RelaxParams rp{};
     LaunchCfg cfg{4, 0};            // default stage launch shape
-    bool can_one_dir = false;       // 2D Euler with the EC fluxes: stages may take one direction at a time
+    bool can_one_dir = false;       // Euler with the EC fluxes: stages may take one direction at a time
     std::vector<LaunchCfg> scfg;    // per stage (autotuned at the first step when opt.tune)
     bool tuned = false;
     std::string tune_report;
@@ -546,8 +546,8 @@ int use_tile(perrk_ctx *c, int tile)
     return PERRK_OK;
 }
 
-// Picks the wavefronts per workgroup of every stage launch, for 2D Euler with
-// the EC fluxes (option phases = 0) whether a stage with double-precision
+// Picks the wavefronts per workgroup of every stage launch, for Euler with the
+// EC fluxes (option phases = 0) whether a stage with double-precision
 // fluxes takes the two directions in one phase or one at a time (single-
 // precision stages keep one phase: the selects cost them more than the smaller
 // slot gains), and (option tile = 0) the element tile of the active lists, by
@@ -865,8 +865,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     c->rp = rp;
     // the Euler stage kernel's last stage evaluates the first residual of the solve
     c->fused_first = c->sys == PERRK_SYSTEM_EULER && !c->viscous;
-    c->can_one_dir = c->fused_first && c->dim == 2 && c->flux == PERRK_FLUX_EC &&
-                     c->volume == PERRK_VOLUME_FLUX_DIFFERENCING;
+    c->can_one_dir = c->fused_first && c->flux == PERRK_FLUX_EC && c->volume == PERRK_VOLUME_FLUX_DIFFERENCING;
     // GLM-MHD: 27 KB of LDS per wavefront; Navier-Stokes: 19 KB
     c->cfg.epb_mult = c->sys == PERRK_SYSTEM_GLM_MHD ? 1 : (c->viscous ? 2 : 4);
     c->cfg.one_dir = c->can_one_dir && c->opt.phases == 2 ? 1 : 0;

@@ -147,14 +147,14 @@ enum { SK_FIRST = 0, SK_MID = 1, SK_LAST = 2 };
 
 struct LaunchCfg {
     int epb_mult;   // wavefronts (of 64 lanes) per workgroup (1, 2, 4 or 8)
-    int one_dir;    // 2D Euler stages with the EC fluxes: 1 = the two directions' pairs and faces
-                    // one direction at a time (smaller LDS slot), 0 = both in one phase
+    int one_dir;    // Euler stages with the EC fluxes: 1 = the directions' pairs and faces one
+                    // direction at a time (smaller LDS slot), 0 = the two-direction phases
 };
 #define PERRK_MAX_WPB 8
 
 // Workgroup LDS bytes of a stage launch with wpb wavefronts per workgroup
 // (sys: PERRK_SYSTEM_*, or 2 for the Navier-Stokes stage kernel; one_dir: the
-// one-direction-at-a-time slots of quadrilaterals with the EC fluxes).
+// one-direction-at-a-time slots of the stages with the EC fluxes).
 size_t stage_lds_bytes(int dim, int variant, int wpb, int sys, bool one_dir);
 
 // Kernel launchers (perrk_kernels.hip).

@@ -724,12 +724,13 @@ struct SL {
     static constexpr int SLOT = PRIM + SG<DIM>::V * (SG<DIM>::NFN + VS);  // LDS words per slot
 };
 
-// Quadrilaterals with the EC fluxes can take the two directions one at a time
-// (pairs and faces of x, then of y: the same fluxes and sums in the same order),
-// which halves the pair-flux area of a slot; the autotuner chooses per stage.
+// Stages with the EC fluxes can take the directions one at a time (pairs and
+// faces of x, then of y; hexahedra z, x, y: the same fluxes and sums in the same
+// order), which halves the pair-flux area of a slot; the autotuner chooses per
+// stage.
 template <int DIM, int FLUX, bool ONE_DIR>
 struct SplitDirs {
-    static constexpr bool ON = ONE_DIR && DIM == 2 && FLUX == 0;
+    static constexpr bool ON = ONE_DIR && FLUX == 0;
 };
 
 // Node of line l (the other coordinates) at position t along direction d.
@@ -1002,48 +1003,52 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
     }
 }
 
-// One direction D of quadrilaterals (SPLIT slots): its 96 pairs per wavefront
-// and its 32 face nodes in two rounds, all with the EC flux in direction D.
-//   round 0: pairs k = 0..3, lane = 16 es + 4 l + k;
-//   round 1: the lanes whose face node (q = lane mod 16, faces of x for q < 8,
-//            of y for q >= 8) lies on a face normal to D form that face's flux
-//            from the own node in LDS and the neighbour's state PN; the other
-//            lanes take pairs k = 4, 5 (es = lane / 16, l = (lane / 2) mod 4).
+// One direction D at a time (SPLIT slots): the direction's pairs and the face
+// nodes of the faces normal to it in two rounds, all with the EC flux in
+// direction D.
+//   round 0: pairs k = 0..3 (2D: lane = 16 es + 4 l + k; 3D: lane = 4 l + k);
+//   round 1: the lanes whose face node (F, the neighbour's state PN) lies on a
+//            face normal to D form that face's flux from the own node in LDS and
+//            PN; the other lanes take pairs k = 4, 5 (2D: es = lane / 16,
+//            l = (lane / 2) mod 4; 3D: l = (lane / 2) mod 16).  2D face node of a
+//            lane: q = lane mod 16, x faces for q < 8; 3D: x faces on lanes 0..31
+//            and y faces on lanes 32..63 of the first face round, z faces on
+//            lanes 0..31 of the second.
 // Pair fluxes go to vf (NPD per variable), face fluxes lifted to sf, exactly as
 // the two-direction rounds and the surface-flux round store them.  The rounds
 // run one after the other (fewer registers held than reading both first).
-template <typename T, int D>
-__device__ __forceinline__ void pairs_and_faces_2d(T *lds, int wave, int lane, T inv_gm1, const FaceNode<2> &F,
-                                                   const Prim<T, 2> &PN)
+template <int DIM, typename T, int D>
+__device__ __forceinline__ void pairs_and_faces(T *lds, int wave, int lane, T inv_gm1, const FaceNode<DIM> &F,
+                                                const Prim<T, DIM> &PN)
 {
-    constexpr int EPW = SG<2>::EPW, NPD = SG<2>::NPD, V = SG<2>::V, NFN = SG<2>::NFN;
-    constexpr int SLOT = SL<2, T, true>::SLOT, PRIM = SL<2, T, true>::PRIM;
-    const int es = lane >> 4;
+    constexpr int EPW = SG<DIM>::EPW, NPD = SG<DIM>::NPD, V = SG<DIM>::V, NFN = SG<DIM>::NFN;
+    constexpr int SLOT = SL<DIM, T, true>::SLOT, PRIM = SL<DIM, T, true>::PRIM;
+    const int es = DIM == 2 ? lane >> 4 : 0;
     T *slot = lds + (size_t)(wave * EPW + es) * SLOT;
     T *sf = slot + PRIM;
     T *vf = sf + V * NFN;
-    const bool face_lane = ((lane >> 3) & 1) == D;
+    const bool face_lane = DIM == 2 ? ((lane >> 3) & 1) == D : (D == 1 ? lane >= 32 : lane < 32);
     T f[V];
     {
-        const int l = (lane >> 2) & 3, k = lane & 3;
+        const int l = DIM == 2 ? (lane >> 2) & 3 : lane >> 2, k = lane & 3;
         int ta, tb;
         pair_pos(k, ta, tb);
-        Prim<T, 2> A, B;
-        lds_get_prim<T, 2>(slot, line_node<2>(D, l, ta), A);
-        lds_get_prim<T, 2>(slot, line_node<2>(D, l, tb), B);
-        flux_ec<T, 2>(D, A, B, inv_gm1, f);
+        Prim<T, DIM> A, B;
+        lds_get_prim<T, DIM>(slot, line_node<DIM>(D, l, ta), A);
+        lds_get_prim<T, DIM>(slot, line_node<DIM>(D, l, tb), B);
+        flux_ec<T, DIM>(D, A, B, inv_gm1, f);
 #pragma unroll
         for (int v = 0; v < V; ++v) vf[v * NPD + l * 6 + k] = f[v];
     }
-    const int l = (lane >> 1) & 3, k = 4 + (lane & 1);
+    const int l = DIM == 2 ? (lane >> 1) & 3 : (lane >> 1) & 15, k = 4 + (lane & 1);
     int ta, tb;
     pair_pos(k, ta, tb);
-    Prim<T, 2> X, Y;
-    lds_get_prim<T, 2>(slot, face_lane ? F.own : line_node<2>(D, l, ta), X);
-    lds_get_prim<T, 2>(slot, line_node<2>(D, l, tb), Y);  // (a node of the slot on every lane)
-    Y = pick<T, 2>(face_lane, PN, Y);
+    Prim<T, DIM> X, Y;
+    lds_get_prim<T, DIM>(slot, face_lane ? F.own : line_node<DIM>(D, l, ta), X);
+    lds_get_prim<T, DIM>(slot, line_node<DIM>(D, l, tb), Y);  // (a node of the slot on every lane)
+    Y = pick<T, DIM>(face_lane, PN, Y);
     const bool swap = face_lane && F.side == 0;
-    flux_ec<T, 2>(D, pick<T, 2>(swap, Y, X), pick<T, 2>(swap, X, Y), inv_gm1, f);
+    flux_ec<T, DIM>(D, pick<T, DIM>(swap, Y, X), pick<T, DIM>(swap, X, Y), inv_gm1, f);
     if (face_lane) {
         const T lift = F.side ? (T)6 : (T)-6;
 #pragma unroll
@@ -1365,13 +1370,27 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
 #pragma unroll
     for (int v = 0; v < V; ++v) du[v] = 0;
     const bool weak = FLUX && a.volume;  // uniform over the launch
-    if constexpr (SPLIT) {
+    if constexpr (SPLIT && DIM == 2) {
         constexpr int NPD = SG<DIM>::NPD;
-        pairs_and_faces_2d<T, 0>(lds, wave, lane, inv_gm1, F[0], PN[0]);
+        pairs_and_faces<DIM, T, 0>(lds, wave, lane, inv_gm1, F[0], PN[0]);
         wave_lds_sync();
         gather<DIM, T, 0, 1, NPD>(slot, node, hn, gtab, du);
         wave_lds_sync();
-        pairs_and_faces_2d<T, 1>(lds, wave, lane, inv_gm1, F[0], PN[0]);
+        pairs_and_faces<DIM, T, 1>(lds, wave, lane, inv_gm1, F[0], PN[0]);
+        wave_lds_sync();
+        gather<DIM, T, 1, 1, NPD>(slot, node, hn, gtab, du);
+    } else if constexpr (SPLIT) {
+        // z first, as the merged two-phase form sums it
+        constexpr int NPD = SG<DIM>::NPD;
+        pairs_and_faces<DIM, T, 2>(lds, wave, lane, inv_gm1, F[FR - 1], PN[FR - 1]);
+        wave_lds_sync();
+        gather<DIM, T, 2, 1, NPD>(slot, node, hn, gtab, du);
+        wave_lds_sync();
+        pairs_and_faces<DIM, T, 0>(lds, wave, lane, inv_gm1, F[0], PN[0]);
+        wave_lds_sync();
+        gather<DIM, T, 0, 1, NPD>(slot, node, hn, gtab, du);
+        wave_lds_sync();
+        pairs_and_faces<DIM, T, 1>(lds, wave, lane, inv_gm1, F[0], PN[0]);
         wave_lds_sync();
         gather<DIM, T, 1, 1, NPD>(slot, node, hn, gtab, du);
     } else if constexpr (MERGE) {
@@ -3065,10 +3084,11 @@ size_t stage_lds_bytes(int dim, int variant, int wpb, int sys, bool one_dir)
         if (dim == 2)
             return (size_t)wpb * (SG<2>::EPW * (ec ? SL<2, float, true>::SLOT : SL<2, float>::SLOT) + GTAB_WORDS) *
                    sizeof(float);
-        return (size_t)wpb * (SG<3>::EPW * SL<3, float>::SLOT + GTAB_WORDS) * sizeof(float);
+        return (size_t)wpb * (SG<3>::EPW * (ec ? SL<3, float, true>::SLOT : SL<3, float>::SLOT) + GTAB_WORDS) *
+               sizeof(float);
     }
     if (dim == 2) return (size_t)wpb * SG<2>::EPW * (ec ? SL<2, double, true>::SLOT : SL<2, double>::SLOT) * sizeof(double);
-    return (size_t)wpb * SG<3>::EPW * SL<3, double>::SLOT * sizeof(double);
+    return (size_t)wpb * SG<3>::EPW * (ec ? SL<3, double, true>::SLOT : SL<3, double>::SLOT) * sizeof(double);
 }
 
 hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArgs &a, const double *coef,
