@@ -1209,25 +1209,6 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     // single-precision stages have their level coefficients at hand already (from
     // cross-lane reads) and skip K_{i-1} where its coefficient is zero
     load_raw<DIM, KT, KIND>(a, e, node, own, !WL || cp != 0.0);
-    // last stage: the double-precision copies of K_1 / K_{S-1} that enter d are
-    // loaded here too, so that their latency overlaps the flux work
-    double dacc[V];  // last stage: the contributions to d accumulated by earlier stages
-    if constexpr (KIND == SK_LAST) {
-        const size_t field = (size_t)a.nelem * NPE;
-        const uint32_t o8 = ((uint32_t)e * NPE + node) * 8u;
-#pragma unroll
-        for (int v = 0; v < V; ++v) dacc[v] = a.d_has ? bload<double>(field_rsrc<double>(a.d_out, v, field), o8) : 0.0;
-    }
-    double k64sm1[V], k64_1[V];  // (double-precision stages only; mixed precision keeps these copies)
-    if constexpr (KIND == SK_LAST && sizeof(T) == 8) {
-        const size_t field = (size_t)a.nelem * NPE;
-        const uint32_t o8 = ((uint32_t)e * NPE + node) * 8u;
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            k64sm1[v] = a.k64_sm1 ? bload<double>(field_rsrc<double>(a.k64_sm1, v, field), o8) : 0.0;
-            k64_1[v] = a.k64_1 ? bload<double>(field_rsrc<double>(a.k64_1, v, field), o8) : 0.0;
-        }
-    }
     FaceNode<DIM> F[FR];
     bool fv[FR];
     NodeRaw<V, KT, UT> nr[FR];
@@ -1416,6 +1397,25 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         gather<DIM, T, 2, 1>(slot, node, hn, gtab, du);
     }
 
+    // last stage: the double-precision copies of K_1 / K_{S-1} that enter d are
+    // loaded after the flux work (fewer registers held through it)
+    double dacc[V];  // last stage: the contributions to d accumulated by earlier stages
+    if constexpr (KIND == SK_LAST) {
+        const size_t field = (size_t)a.nelem * NPE;
+        const uint32_t o8 = ((uint32_t)e * NPE + node) * 8u;
+#pragma unroll
+        for (int v = 0; v < V; ++v) dacc[v] = a.d_has ? bload<double>(field_rsrc<double>(a.d_out, v, field), o8) : 0.0;
+    }
+    double k64sm1[V], k64_1[V];  // (double-precision stages only; mixed precision keeps these copies)
+    if constexpr (KIND == SK_LAST && sizeof(T) == 8) {
+        const size_t field = (size_t)a.nelem * NPE;
+        const uint32_t o8 = ((uint32_t)e * NPE + node) * 8u;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            k64sm1[v] = a.k64_sm1 ? bload<double>(field_rsrc<double>(a.k64_sm1, v, field), o8) : 0.0;
+            k64_1[v] = a.k64_1 ? bload<double>(field_rsrc<double>(a.k64_1, v, field), o8) : 0.0;
+        }
+    }
     // K_i in double (for d, the double copy and the entropy production)
     double k[V];
 #pragma unroll
