@@ -1,9 +1,9 @@
 """Launch shapes through the C ABI: every stage launched with 1, 2, 4 or 8
 wavefronts per workgroup (options.tune = -w), the active lists built with
-every element tile (options.tile = 1..4), and the 2D stages with the EC fluxes
-run with both directions in one phase or one direction at a time
-(options.phases = 1, 2), give bit-identical states; so does the autotuner's own
-choice (tune = 1, tile = 0, phases = 0), which the tuning report names.
+every element tile (options.tile = 1..4), and the stages with the EC fluxes run
+with two directions per phase or one direction at a time (options.phases = 1,
+2), give bit-identical states; so does the autotuner's own choice (tune = 1,
+tile = 0, phases = 0), which the tuning report names.
 
 In 2D the active lists keep tiles of each case mesh together and a neighbour that
 sits in the same workgroup is read from LDS instead of global memory, so the split
