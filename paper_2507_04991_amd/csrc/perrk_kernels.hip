@@ -585,15 +585,15 @@ __device__ __forceinline__ void combine(const NodeRaw<V, KT> &r, double dt, doub
 // The same in single precision (stages whose fluxes are single precision): U_n is
 // rounded first, the combination is formed in single precision.
 template <int V, typename KT, int KIND, typename UT>
-__device__ __forceinline__ void combine_f32(const NodeRaw<V, KT, UT> &r, double dt, double c1, double cp, float *u)
+__device__ __forceinline__ void combine_f32(const NodeRaw<V, KT, UT> &r, double dt, float c1, float cp, float *u)
 {
-    const float fdt = (float)dt, fc1 = (float)c1, fcp = (float)cp;
+    const float fdt = (float)dt, fc1 = c1, fcp = cp;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         float x = (float)r.u[v];
         if (KIND != SK_FIRST) {
             float s = fc1 * (float)r.k1[v];
-            s += (cp != 0.0) ? fcp * (float)r.kp[v] : 0.0f;
+            s += (cp != 0.0f) ? fcp * (float)r.kp[v] : 0.0f;
             x = x + fdt * s;
         }
         u[v] = x;
@@ -1174,7 +1174,10 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     constexpr bool WL = sizeof(T) == 4;
     constexpr bool LOCAL = WL && DIM == 2;
     const int4 part = WL ? wave_entry_part<EPW>(a.active, li0, a.n_active, lane) : make_int4(0, 0, 0, 0);
-    const double cf = (WL && KIND != SK_FIRST) ? wave_coef_table(coef, lane) : 0.0;
+    // level coefficients: single precision in single-precision stages (the precision
+    // their stage states are formed in), shuffled from the lanes that loaded them
+    using CT = typename std::conditional<WL, float, double>::type;
+    const CT cf = (WL && KIND != SK_FIRST) ? (CT)wave_coef_table(coef, lane) : (CT)0;
     int4 act, act2;
     if constexpr (WL) {
         act = shfl4(part, 2 * es);
@@ -1197,10 +1200,10 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     // ---- loads
     SlotVals<DIM, EPW> sv{};
     if constexpr (WL) sv = wave_slot_vals<DIM, EPW, KIND != SK_FIRST>(a, part, lane);
-    double c1 = 0.0, cp = 0.0;
+    CT c1 = 0, cp = 0;
     if (KIND != SK_FIRST) {
-        c1 = WL ? __shfl(cf, lvl) : elt(coef, (uint32_t)lvl);
-        cp = WL ? __shfl(cf, PERRK_MAXR + lvl) : elt(coef, (uint32_t)(PERRK_MAXR + lvl));
+        c1 = WL ? __shfl(cf, lvl) : (CT)elt(coef, (uint32_t)lvl);
+        cp = WL ? __shfl(cf, PERRK_MAXR + lvl) : (CT)elt(coef, (uint32_t)(PERRK_MAXR + lvl));
     }
     // single-precision middle stages read the single-precision copy of U_n (the last
     // stage reads U_n in double precision: the first residual evaluation needs it)
@@ -1208,11 +1211,11 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
     NodeRaw<V, KT, UT> own;
     // single-precision stages have their level coefficients at hand already (from
     // cross-lane reads) and skip K_{i-1} where its coefficient is zero
-    load_raw<DIM, KT, KIND>(a, e, node, own, !WL || cp != 0.0);
+    load_raw<DIM, KT, KIND>(a, e, node, own, !WL || cp != (CT)0);
     FaceNode<DIM> F[FR];
     bool fv[FR];
     NodeRaw<V, KT, UT> nr[FR];
-    double nc1[FR], ncp[FR];
+    CT nc1[FR], ncp[FR];
     int nnr[FR], lk[FR];  // the neighbour's node; its element slot in this workgroup, else -1
 #pragma unroll
     for (int r = 0; r < FR; ++r) {
@@ -1230,14 +1233,14 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         }
         // (cross-lane reads with every lane active: a lane that is switched off
         // does not provide its value)
-        nc1[r] = 0.0;
-        ncp[r] = 0.0;
+        nc1[r] = 0;
+        ncp[r] = 0;
         if (KIND != SK_FIRST) {
             const int lv = (int)(w >> PERRK_NBR_SHIFT);
-            nc1[r] = WL ? __shfl(cf, lv) : elt(coef, (uint32_t)lv);
-            ncp[r] = WL ? __shfl(cf, PERRK_MAXR + lv) : elt(coef, (uint32_t)(PERRK_MAXR + lv));
+            nc1[r] = WL ? __shfl(cf, lv) : (CT)elt(coef, (uint32_t)lv);
+            ncp[r] = WL ? __shfl(cf, PERRK_MAXR + lv) : (CT)elt(coef, (uint32_t)(PERRK_MAXR + lv));
         }
-        if (lk[r] < 0) load_raw<DIM, KT, KIND>(a, nb, nnr[r], nr[r], !WL || ncp[r] != 0.0);
+        if (lk[r] < 0) load_raw<DIM, KT, KIND>(a, nb, nnr[r], nr[r], !WL || ncp[r] != (CT)0);
     }
     double dt = 0.0;
     ElemInfo ei;
