@@ -73,6 +73,18 @@ __device__ __forceinline__ T dsplit_j(int t)
     return sel4<T>(t, (T)1.0, (T)(-PHI), (T)(-SQ5), (T)(-5.0 * PHI));
 }
 
+// Dsplit[t][(t + j) & 3] / 2: the weights of the Euler stage kernels' gather,
+// whose two-point fluxes come doubled (halving is exact).
+template <typename T, int J>
+__device__ __forceinline__ T dsplit_half_j(int t)
+{
+    if (J == 1) return sel4<T>(t, (T)(2.5 * PHI), (T)(0.5 * SQ5), (T)(0.5 * PHI), (T)-0.5);
+    if (J == 2)
+        return sel4<T>(t, (T)(-2.5 * (PHI - 1.0)), (T)(-0.5 * (PHI - 1.0)), (T)(0.5 * (PHI - 1.0)),
+                       (T)(2.5 * (PHI - 1.0)));
+    return sel4<T>(t, (T)0.5, (T)(-0.5 * PHI), (T)(-0.5 * SQ5), (T)(-2.5 * PHI));
+}
+
 // 1D LGL weights: 1/6 at the ends, 5/6 inside.
 __device__ __forceinline__ double lglw(int i) { return (i == 0 || i == 3) ? (1.0 / 6.0) : (5.0 / 6.0); }
 
@@ -291,12 +303,33 @@ __device__ __forceinline__ T vdir(const Prim<T, DIM> &P, int d)
 // Ranocha's entropy-conservative, kinetic-energy-preserving two-point flux in
 // direction d (runtime): f_rho = {rho}_log {v_d}, f_m = f_rho {v} + {p} e_d,
 // f_E = f_rho (v_L.v_R / 2 + 1 / ((gamma-1) {rho/p}_log)) + (p_L v_R,d + p_R v_L,d) / 2.
-template <typename T, int DIM>
+//
+// TWICE: returns 2 f, which saves the halvings of the means (every scaling by 2
+// is exact, so 2 f has the bits of f times two).
+template <typename T, int DIM, bool TWICE = false>
 __device__ __forceinline__ void flux_ec(int d, const Prim<T, DIM> &L, const Prim<T, DIM> &R, T inv_gm1, T *f)
 {
 #pragma clang fp contract(off)
     const T rm = lmean(L.rho, R.rho);
     const T ibm = inv_lmean(L.beta, R.beta);
+    if constexpr (TWICE) {
+        T sv[DIM];  // sums of the velocity components: twice their means
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) sv[k] = L.v[k] + R.v[k];
+        const T vl = vdir<T, DIM>(L, d), vr = vdir<T, DIM>(R, d);
+        const T svd = DIM == 2 ? (d == 0 ? sv[0] : sv[1]) : (d == 0 ? sv[0] : (d == 1 ? sv[1] : sv[DIM - 1]));
+        const T fr2 = rm * svd;     // 2 f_rho
+        const T fr = (T)0.5 * fr2;  // f_rho
+        const T sp = L.p + R.p;     // twice the mean pressure
+        T vv = L.v[0] * R.v[0];
+#pragma unroll
+        for (int k = 1; k < DIM; ++k) vv = fma(L.v[k], R.v[k], vv);
+        f[0] = fr2;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) f[1 + k] = fma(fr, sv[k], k == d ? sp : (T)0);
+        f[DIM + 1] = fma(fr2, fma((T)0.5, vv, inv_gm1 * ibm), fma(L.p, vr, R.p * vl));
+        return;
+    }
     T va[DIM];  // arithmetic means of the velocity components
 #pragma unroll
     for (int k = 0; k < DIM; ++k) va[k] = (T)0.5 * (L.v[k] + R.v[k]);
@@ -897,22 +930,25 @@ __device__ __forceinline__ void lds_get_prim(const T *slot, int node, Prim<T, DI
 // form sum_m Dsplit[t][m] f#(t, m) it gives D f - B f / q (the rows of D sum to
 // zero), which with the lifted surface flux is the strong form and, by the SBP
 // property q D + D^T q = B, exactly the standard weak form.
-template <typename T, int DIM>
+// TWICE: returns 2 f (the same sums without the final halving).
+template <typename T, int DIM, bool TWICE = false>
 __device__ __forceinline__ void flux_central(int d, const Prim<T, DIM> &A, const Prim<T, DIM> &B, T inv_gm1, T *f)
 {
+#pragma clang fp contract(off)
     const T va = vdir<T, DIM>(A, d), vb = vdir<T, DIM>(B, d);
-    T ka = 0, kb = 0;
+    T ka = A.v[0] * A.v[0], kb = B.v[0] * B.v[0];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        ka += A.v[k] * A.v[k];
-        kb += B.v[k] * B.v[k];
+    for (int k = 1; k < DIM; ++k) {
+        ka = fma(A.v[k], A.v[k], ka);
+        kb = fma(B.v[k], B.v[k], kb);
     }
+    const T h = TWICE ? (T)1 : (T)0.5;
     const T ma = A.rho * va, mb = B.rho * vb;
-    f[0] = (T)0.5 * (ma + mb);
+    f[0] = h * (ma + mb);
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) f[1 + k] = (T)0.5 * (ma * A.v[k] + mb * B.v[k] + (k == d ? A.p + B.p : (T)0));
-    const T ea = A.p * inv_gm1 + (T)0.5 * A.rho * ka, eb = B.p * inv_gm1 + (T)0.5 * B.rho * kb;
-    f[DIM + 1] = (T)0.5 * ((ea + A.p) * va + (eb + B.p) * vb);
+    for (int k = 0; k < DIM; ++k) f[1 + k] = h * (fma(ma, A.v[k], mb * B.v[k]) + (k == d ? A.p + B.p : (T)0));
+    const T ea = fma(A.p, inv_gm1, (T)0.5 * A.rho * ka), eb = fma(B.p, inv_gm1, (T)0.5 * B.rho * kb);
+    f[DIM + 1] = h * fma(ea + A.p, va, (eb + B.p) * vb);
 }
 
 // Field-by-field choice between two node states (values, so that both stay in
@@ -989,10 +1025,10 @@ __device__ __forceinline__ void volume_pairs(T *lds, int wave, int lane, T inv_g
         pair_of<DIM, ND, UNI>(rd, lane, es, dd, l, k);
         const int d = D0 + dd;
         T f[V];
-        if (WEAK) flux_central<T, DIM>(d, A[rd], B[rd], inv_gm1, f);
-        else flux_ec<T, DIM>(d, A[rd], B[rd], inv_gm1, f);
+        if (WEAK) flux_central<T, DIM, true>(d, A[rd], B[rd], inv_gm1, f);
+        else flux_ec<T, DIM, true>(d, A[rd], B[rd], inv_gm1, f);
         if (FACES && rd == 1 && face_lane) {
-            const T lift = FF->side ? (T)6 : (T)-6;
+            const T lift = FF->side ? (T)3 : (T)-3;  // (the flux is doubled)
             T *sf = vfs[rd] - V * NFN;
 #pragma unroll
             for (int v = 0; v < V; ++v) sf[v * NFN + FF->q] = lift * f[v];
@@ -1036,7 +1072,7 @@ __device__ __forceinline__ void pairs_and_faces(T *lds, int wave, int lane, T in
         Prim<T, DIM> A, B;
         lds_get_prim<T, DIM>(slot, line_node<DIM>(D, l, ta), A);
         lds_get_prim<T, DIM>(slot, line_node<DIM>(D, l, tb), B);
-        flux_ec<T, DIM>(D, A, B, inv_gm1, f);
+        flux_ec<T, DIM, true>(D, A, B, inv_gm1, f);
 #pragma unroll
         for (int v = 0; v < V; ++v) vf[v * NPD + l * 6 + k] = f[v];
     }
@@ -1048,9 +1084,9 @@ __device__ __forceinline__ void pairs_and_faces(T *lds, int wave, int lane, T in
     lds_get_prim<T, DIM>(slot, line_node<DIM>(D, l, tb), Y);  // (a node of the slot on every lane)
     Y = pick<T, DIM>(face_lane, PN, Y);
     const bool swap = face_lane && F.side == 0;
-    flux_ec<T, DIM>(D, pick<T, DIM>(swap, Y, X), pick<T, DIM>(swap, X, Y), inv_gm1, f);
+    flux_ec<T, DIM, true>(D, pick<T, DIM>(swap, Y, X), pick<T, DIM>(swap, X, Y), inv_gm1, f);
     if (face_lane) {
-        const T lift = F.side ? (T)6 : (T)-6;
+        const T lift = F.side ? (T)3 : (T)-3;  // (the flux is doubled)
 #pragma unroll
         for (int v = 0; v < V; ++v) sf[v * NFN + F.q] = lift * f[v];
     } else {
@@ -1061,7 +1097,7 @@ __device__ __forceinline__ void pairs_and_faces(T *lds, int wave, int lane, T in
 
 // Gather table of the single-precision stages, one copy per wavefront in LDS
 // (16 words; lanes 0-15 copy it from here at the start): for each position t on
-// a line, Dsplit[t][(t + j) & 3] for j = 1, 2, 3 in single precision and the
+// a line, Dsplit[t][(t + j) & 3] / 2 for j = 1, 2, 3 in single precision and the
 // three pair indices pair_k<j>(t) in 4-bit fields.  Each lane reads its row with
 // one LDS load per direction instead of forming six values by selection.
 constexpr uint32_t gtab_word(int i)
@@ -1071,10 +1107,10 @@ constexpr uint32_t gtab_word(int i)
         const int k1[4] = {0, 3, 5, 2}, k2[4] = {1, 4, 1, 4}, k3[4] = {2, 0, 3, 5};
         return (uint32_t)(k1[t] | (k2[t] << 4) | (k3[t] << 8));
     }
-    const float w[3][4] = {{(float)(5.0 * PHI), (float)SQ5, (float)PHI, (float)-1.0},
-                           {(float)(-5.0 * (PHI - 1.0)), (float)(-(PHI - 1.0)), (float)(PHI - 1.0),
-                            (float)(5.0 * (PHI - 1.0))},
-                           {(float)1.0, (float)(-PHI), (float)(-SQ5), (float)(-5.0 * PHI)}};
+    const float w[3][4] = {{(float)(2.5 * PHI), (float)(0.5 * SQ5), (float)(0.5 * PHI), (float)-0.5},
+                           {(float)(-2.5 * (PHI - 1.0)), (float)(-0.5 * (PHI - 1.0)), (float)(0.5 * (PHI - 1.0)),
+                            (float)(2.5 * (PHI - 1.0))},
+                           {(float)0.5, (float)(-0.5 * PHI), (float)(-0.5 * SQ5), (float)(-2.5 * PHI)}};
     return __builtin_bit_cast(uint32_t, w[j][t]);
 }
 __device__ const uint32_t GATHER_TAB[16] = {
@@ -1084,7 +1120,8 @@ constexpr int GTAB_WORDS = 16;
 
 // Adds -(2/h_d) [sum_{m != t} Dsplit[t][m] f#(t, m) + lifted surface flux] of the
 // directions [d0, d0 + nd) to du (node lane); hn[d] = -(2/h_d) in flux precision;
-// tab: the wavefront's gather table (single precision only).
+// tab: the wavefront's gather table (single precision only).  The pair fluxes
+// are stored doubled, 2 f#, and weighted by Dsplit / 2 (the same products).
 template <int DIM, typename T, int D0, int ND, int VS = SG<DIM>::NPP>
 __device__ __forceinline__ void gather(const T *slot, int node, const T *hn, const T *tab, T *du)
 {
@@ -1118,9 +1155,9 @@ __device__ __forceinline__ void gather(const T *slot, int node, const T *hn, con
             p1 = pb + pair_k<1>(t);
             p2 = pb + pair_k<2>(t);
             p3 = pb + pair_k<3>(t);
-            w1 = dsplit_j<T, 1>(t);
-            w2 = dsplit_j<T, 2>(t);
-            w3 = dsplit_j<T, 3>(t);
+            w1 = dsplit_half_j<T, 1>(t);
+            w2 = dsplit_half_j<T, 2>(t);
+            w3 = dsplit_half_j<T, 3>(t);
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -1338,9 +1375,14 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
         L.beta = sd ? PO.beta : PN[r].beta;
         R.beta = sd ? PN[r].beta : PO.beta;
         T fs[V];
-        if (FLUX && a.flux != PERRK_FLUX_EC) flux_diss<T, DIM>(a.flux, F[r].d, L, R, (T)a.gam, inv_gm1, fs);
-        else flux_ec<T, DIM>(F[r].d, L, R, inv_gm1, fs);
-        const T lift = sd ? (T)6 : (T)-6;
+        T lift;  // +-6 f* (the EC flux comes doubled: +-3)
+        if (FLUX && a.flux != PERRK_FLUX_EC) {
+            flux_diss<T, DIM>(a.flux, F[r].d, L, R, (T)a.gam, inv_gm1, fs);
+            lift = sd ? (T)6 : (T)-6;
+        } else {
+            flux_ec<T, DIM, true>(F[r].d, L, R, inv_gm1, fs);
+            lift = sd ? (T)3 : (T)-3;
+        }
         T *sf = slot + PRIM;
 #pragma unroll
         for (int v = 0; v < V; ++v) sf[v * NFN + F[r].q] = lift * fs[v];
