@@ -59,6 +59,11 @@ struct perrk_ctx {
     ElemInfo *d_elem = nullptr;
     ActiveEntry *d_active = nullptr;  // per stage: active elements with their neighbour words
     int64_t *d_case_off = nullptr;
+    // chunks of the per-case sums of cases of more than PERRK_RED_CHUNK elements
+    PrepChunks chunks;
+    int64_t *d_chunk_range = nullptr;
+    int32_t *d_case_chunk = nullptr;
+    double *d_chunk_sums = nullptr;
     CaseState *d_cs = nullptr;
     double *d_coef = nullptr;  // [S][2 * PERRK_MAXR]
     void *d_K1 = nullptr, *d_Ka = nullptr, *d_Kb = nullptr;
@@ -305,7 +310,8 @@ void free_all(perrk_ctx *c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     void *dev[] = {c->d_elem, c->d_active, c->d_case_off, c->d_cs, c->d_coef, c->d_K1, c->d_Ka,
                    c->d_Kb, c->d_d, c->d_ep, c->d_partial, c->d_H, c->d_dt, c->d_err, c->d_mlp,
-                   c->d_k64_1, c->d_k64_sm1, c->d_grad, c->d_U32};
+                   c->d_k64_1, c->d_k64_sm1, c->d_grad, c->d_U32, c->d_chunk_range, c->d_case_chunk,
+                   c->d_chunk_sums};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     void *host[] = {c->h_dt, c->h_cs, c->h_err, c->h_H};
@@ -677,7 +683,7 @@ int enqueue_step(perrk_ctx *c, double *u)
         if (kind == SK_LAST && c->fused_first) {
             HIPCHECK(c, mark_begin(c));
             HIPCHECK(c, launch_relax_prepare(c->d_cs, c->d_case_off, c->n_cases, c->d_ep, c->nelem, c->rp, mlp, 1,
-                                             nullptr, c->stream));
+                                             nullptr, c->chunks, c->stream));
             HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
         }
         HIPCHECK(c, mark_begin(c));
@@ -688,7 +694,7 @@ int enqueue_step(perrk_ctx *c, double *u)
     }
     HIPCHECK(c, mark_begin(c));
     HIPCHECK(c, launch_relax_prepare(c->d_cs, c->d_case_off, c->n_cases, c->d_ep, c->nelem, c->rp, mlp,
-                                     c->fused_first ? 2 : 0, c->d_partial, c->stream));
+                                     c->fused_first ? 2 : 0, c->d_partial, c->chunks, c->stream));
     HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
     if (c->rp.relax) {
         // launched residual passes: fast_passes evaluations in all, the fused one included
@@ -1002,6 +1008,34 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipMemcpyAsync(c->d_case_off, c->case_off.data(), sizeof(int64_t) * (c->n_cases + 1),
                            hipMemcpyHostToDevice, c->stream));
     HIPINIT(hipMemcpyAsync(c->d_coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, c->stream));
+    // chunks of the per-case sums of the cases of more than PERRK_RED_CHUNK elements
+    std::vector<int64_t> chunk_range;
+    std::vector<int32_t> case_chunk(c->n_cases + 1, 0);
+    for (int cs = 0; cs < c->n_cases; ++cs) {
+        case_chunk[cs] = (int32_t)(chunk_range.size() / 2);
+        const int64_t b = c->case_off[cs], e = c->case_off[cs + 1];
+        if (e - b > PERRK_RED_CHUNK)
+            for (int64_t k = b; k < e; k += PERRK_RED_CHUNK) {
+                chunk_range.push_back(k);
+                chunk_range.push_back(std::min<int64_t>(e, k + PERRK_RED_CHUNK));
+            }
+    }
+    case_chunk[c->n_cases] = (int32_t)(chunk_range.size() / 2);
+    if (!chunk_range.empty()) {
+        const size_t nch = chunk_range.size() / 2;
+        HIPINIT(hipMalloc(&c->d_chunk_range, sizeof(int64_t) * chunk_range.size()));
+        HIPINIT(hipMalloc(&c->d_case_chunk, sizeof(int32_t) * case_chunk.size()));
+        HIPINIT(hipMalloc(&c->d_chunk_sums, sizeof(double) * (PERRK_MAXB + 4) * nch));
+        HIPINIT(hipMemcpyAsync(c->d_chunk_range, chunk_range.data(), sizeof(int64_t) * chunk_range.size(),
+                               hipMemcpyHostToDevice, c->stream));
+        HIPINIT(hipMemcpyAsync(c->d_case_chunk, case_chunk.data(), sizeof(int32_t) * case_chunk.size(),
+                               hipMemcpyHostToDevice, c->stream));
+        c->chunks.n_chunks = (int)nch;
+        c->chunks.range = c->d_chunk_range;
+        c->chunks.case_chunk = c->d_case_chunk;
+        c->chunks.sums = c->d_chunk_sums;
+        HIPINIT(hipStreamSynchronize(c->stream));  // (the host vectors end here)
+    }
     HIPINIT(launch_init_cases(c->d_cs, c->n_cases, c->stream));
     HIPINIT(launch_clear_err(c->d_err, ERR_WORDS, c->stream));
     HIPINIT(hipStreamSynchronize(c->stream));

@@ -168,10 +168,19 @@ hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArg
 // phase 0: after the last stage, everything below; 1: before the last stage (the
 // entropy production of the earlier stages, solver reset, starting gamma); 2: after
 // a last stage that evaluated the first residual (its entropy production, dH, and
-// the solver update from that evaluation).
+// the solver update from that evaluation).  Cases of more than PERRK_RED_CHUNK
+// elements are summed in chunks first (ch; none when n_chunks = 0).
+#define PERRK_RED_CHUNK 8192  // elements per chunk of a large case's sums (fixed: results depend on it)
+struct PrepChunks {
+    int n_chunks = 0;                // chunks over all cases of more than PERRK_RED_CHUNK elements
+    const int64_t *range = nullptr;  // [n_chunks][2]: first and end element of each chunk
+    const int32_t *case_chunk = nullptr;  // [n_cases + 1]: case c's chunks [case_chunk[c], case_chunk[c+1])
+    double *sums = nullptr;          // [n_chunks][PERRK_MAXB + 4]
+};
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases,
                                 const double *ep_partial, int64_t nelem, RelaxParams rp,
-                                const float *mlp, int phase, const double *rx_partial, hipStream_t s);
+                                const float *mlp, int phase, const double *rx_partial, const PrepChunks &ch,
+                                hipStream_t s);
 hipError_t launch_relax_pass(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                              const CaseState *cs, double *partial, int64_t nelem, double gam, bool first,
                              hipStream_t s);

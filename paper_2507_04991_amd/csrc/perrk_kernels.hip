@@ -2693,6 +2693,55 @@ __device__ void relax_update(CaseState &C, const double *S, const RelaxParams &r
     }
 }
 
+// Per-case sums of the prepare kernel over a case of more than PERRK_RED_CHUNK
+// elements: the case is cut into chunks of PERRK_RED_CHUNK elements (the last one
+// shorter), one workgroup sums each chunk in the fixed order of case_sum, and
+// the prepare kernel adds the chunk sums in chunk order.  A case of at most
+// PERRK_RED_CHUNK elements is summed as before, over its elements.
+// chunk_sums[k][j]: the sum of ep_j over chunk k (j < PERRK_MAXB, the ones the
+// phase reduces), [k][PERRK_MAXB + i]: of the fused residual partial i (phase 2).
+constexpr int PREP_NV = PERRK_MAXB + 4;
+
+__global__ void __launch_bounds__(PERRK_RED_THREADS)
+prepare_chunks_kernel(const int64_t *chunk_range, const double *ep, int64_t nelem, RelaxParams rp, int phase,
+                      const double *rx_partial, double *chunk_sums)
+{
+    const int k = blockIdx.x;
+    const int64_t b = chunk_range[2 * k], e = chunk_range[2 * k + 1];
+    double *out = chunk_sums + (size_t)k * PREP_NV;
+    const int j0 = phase == 2 ? rp.nb_pre : 0, j1 = phase == 1 ? rp.nb_pre : rp.nb;
+    for (int j = j0; j < j1; ++j) {
+        double o[1];
+        case_sum<1>(ep + (size_t)j * nelem, 1, b, e, o);
+        if (threadIdx.x == 0) out[j] = o[0];
+    }
+    if (phase == 2) {
+        double S[4];
+        case_sum<4>(rx_partial, 4, b, e, S);
+        if (threadIdx.x == 0)
+            for (int i = 0; i < 4; ++i) out[PERRK_MAXB + i] = S[i];
+    }
+}
+
+// One per-case sum of the prepare kernel: over the case's elements [b, e), or
+// (a case cut into the chunks [k0, k1)) over the chunk sums in chunk order.
+// Component i of the NC-wide sum is chunk entry v0 + i.
+template <int NC>
+__device__ __forceinline__ void prep_sum(const double *part, int stride, int64_t b, int64_t e, int k0, int k1,
+                                         const double *chunk_sums, int v0, double *out)
+{
+    if (k1 - k0 < 2) {
+        case_sum<NC>(part, stride, b, e, out);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        double acc = chunk_sums[(size_t)k0 * PREP_NV + v0 + i];
+        for (int k = k0 + 1; k < k1; ++k) acc += chunk_sums[(size_t)k * PREP_NV + v0 + i];
+        out[i] = acc;
+    }
+}
+
 // One workgroup per case.  Phases 0 (after the last stage) and 1 (before it, when
 // the last stage evaluates the first residual): sums the stage entropy production
 // of the b_i != 0 stages known so far in a fixed order, resets the solver state
@@ -2703,21 +2752,23 @@ __device__ void relax_update(CaseState &C, const double *S, const RelaxParams &r
 // relax_finalize_kernel does after a residual pass.
 __global__ void __launch_bounds__(PERRK_RED_THREADS)
 relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, int64_t nelem,
-                     RelaxParams rp, const float *mlp, int phase, const double *rx_partial)
+                     RelaxParams rp, const float *mlp, int phase, const double *rx_partial,
+                     const int32_t *case_chunk, const double *chunk_sums)
 {
     __shared__ float sx[8], sh1[32], sh2[32];
     const int c = blockIdx.x;
     const int64_t b = case_off[c], e = case_off[c + 1];
+    const int k0 = case_chunk ? case_chunk[c] : 0, k1 = case_chunk ? case_chunk[c + 1] : 0;
     CaseState &C = cs[c];
     if (phase == 2) {
         double ej[PERRK_MAXB] = {};
         for (int j = rp.nb_pre; j < rp.nb; ++j) {
             double o[1];
-            case_sum<1>(ep + (size_t)j * nelem, 1, b, e, o);
+            prep_sum<1>(ep + (size_t)j * nelem, 1, b, e, k0, k1, chunk_sums, j, o);
             ej[j] = o[0];
         }
         double S[4];
-        case_sum<4>(rx_partial, 4, b, e, S);
+        prep_sum<4>(rx_partial, 4, b, e, k0, k1, chunk_sums, PERRK_MAXB, S);
         if (threadIdx.x != 0) return;
         double dH = 0.0;
         for (int j = 0; j < rp.nb; ++j) {
@@ -2740,7 +2791,7 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
     double ej[PERRK_MAXB] = {};
     for (int j = 0; j < nsum; ++j) {
         double o[1];
-        case_sum<1>(ep + (size_t)j * nelem, 1, b, e, o);
+        prep_sum<1>(ep + (size_t)j * nelem, 1, b, e, k0, k1, chunk_sums, j, o);
         ej[j] = o[0];
     }
     // learned guess of the increment of the root, gamma*_n - gamma*_{n-1} (MLP
@@ -3158,10 +3209,17 @@ hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArg
 
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases, const double *ep,
                                 int64_t nelem, RelaxParams rp, const float *mlp, int phase,
-                                const double *rx_partial, hipStream_t s)
+                                const double *rx_partial, const PrepChunks &ch, hipStream_t s)
 {
+    if (ch.n_chunks > 0) {
+        hipLaunchKernelGGL(prepare_chunks_kernel, dim3(ch.n_chunks), dim3(PERRK_RED_THREADS), 0, s, ch.range, ep,
+                           nelem, rp, phase, rx_partial, ch.sums);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
     hipLaunchKernelGGL(relax_prepare_kernel, dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, cs, case_off,
-                       ep, nelem, rp, mlp, phase, rx_partial);
+                       ep, nelem, rp, mlp, phase, rx_partial, ch.n_chunks > 0 ? ch.case_chunk : nullptr,
+                       ch.sums);
     return hipGetLastError();
 }
 
