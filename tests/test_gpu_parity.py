@@ -77,6 +77,28 @@ def test_steps_match_oracle_2d(P, oracle, order, E, levels):
         assert rel_err(u.cpu().numpy(), Uref) < 1e-12, n
 
 
+def test_large_case_chunked_sums_match_oracle(P, oracle):
+    """One case of 10,000 quadrilaterals: more than the 8192 elements up to which
+    a case's sums run in one workgroup, so the prepare kernel sums two chunks
+    and then the chunk sums.  Passes, gamma, dH and the state against the oracle."""
+    f, U0, tab, dt, lev = problem_2d(nx=100, ny=100, order=3, E=(4, 6, 8, 12), levels="cfl")
+    assert len(lev) == 10000
+    st, u = make(P, f, U0, tab, lev)
+    m, t = omesh(oracle, f), otab(oracle, tab)
+    Uref = U0.copy()
+    g = 1.0
+    for n in range(3):
+        print(f"case large 2d, step {n}", flush=True)
+        info = st.step(u, dt)[0]
+        Uref, iref = oracle.step(m, t, lev, Uref, dt, oracle.relax_options(gamma0=g))
+        g = iref["gamma"]
+        assert info["flags"] == iref["flags"] == 0
+        assert info["passes"] == iref["passes"]
+        assert abs(info["gamma"] - iref["gamma"]) <= 1e-12
+        assert abs(info["dH"] - iref["dH"]) <= 1e-13 * max(1.0, abs(iref["dH"]))
+        assert rel_err(u.cpu().numpy(), Uref) < 1e-12, n
+
+
 @pytest.mark.parametrize("precision", [0, 2])
 def test_classic_rk4_matches_dense_oracle(P, oracle, precision):
     """Relaxed classic RK4 (b_i != 0 in all four stages: d and dH accumulate stage
