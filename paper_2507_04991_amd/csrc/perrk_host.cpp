@@ -71,6 +71,7 @@ struct perrk_ctx {
     float *d_U32 = nullptr;  // mixed modes: U_n rounded to single precision (written by the first stage)
     double *d_d = nullptr, *d_ep = nullptr, *d_partial = nullptr, *d_H = nullptr, *d_dt = nullptr;
     int32_t *d_err = nullptr;
+    int32_t *d_live = nullptr;  // per launched residual pass: some case still needs it (fast_passes + 1 words)
     float *d_mlp = nullptr;
     bool have_mlp = false;
     bool fused_first = false;  // the last stage evaluates the first relaxation residual
@@ -311,7 +312,7 @@ void free_all(perrk_ctx *c)
     void *dev[] = {c->d_elem, c->d_active, c->d_case_off, c->d_cs, c->d_coef, c->d_K1, c->d_Ka,
                    c->d_Kb, c->d_d, c->d_ep, c->d_partial, c->d_H, c->d_dt, c->d_err, c->d_mlp,
                    c->d_k64_1, c->d_k64_sm1, c->d_grad, c->d_U32, c->d_chunk_range, c->d_case_chunk,
-                   c->d_chunk_sums};
+                   c->d_chunk_sums, c->d_live};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     void *host[] = {c->h_dt, c->h_cs, c->h_err, c->h_H};
@@ -674,7 +675,7 @@ int autotune(perrk_ctx *c, double *u)
 // solver is prepared after the last stage and the first residual pass does it.
 int enqueue_step(perrk_ctx *c, double *u)
 {
-    HIPCHECK(c, launch_clear_err(c->d_err + ERR_STEP, 1, c->stream));
+    HIPCHECK(c, launch_clear_step(c->d_err + ERR_STEP, c->d_live, c->opt.fast_passes + 1, c->stream));
     const float *mlp = c->have_mlp ? c->d_mlp : nullptr;
     for (int i = 0; i < c->S; ++i) {
         StageArgs a;
@@ -683,7 +684,7 @@ int enqueue_step(perrk_ctx *c, double *u)
         if (kind == SK_LAST && c->fused_first) {
             HIPCHECK(c, mark_begin(c));
             HIPCHECK(c, launch_relax_prepare(c->d_cs, c->d_case_off, c->n_cases, c->d_ep, c->nelem, c->rp, mlp, 1,
-                                             nullptr, c->chunks, c->stream));
+                                             nullptr, c->chunks, nullptr, c->stream));
             HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
         }
         HIPCHECK(c, mark_begin(c));
@@ -693,18 +694,20 @@ int enqueue_step(perrk_ctx *c, double *u)
                              c->stage_bytes[i], i));
     }
     HIPCHECK(c, mark_begin(c));
+    const int p0 = c->fused_first ? 1 : 0;  // the first launched pass
     HIPCHECK(c, launch_relax_prepare(c->d_cs, c->d_case_off, c->n_cases, c->d_ep, c->nelem, c->rp, mlp,
-                                     c->fused_first ? 2 : 0, c->d_partial, c->chunks, c->stream));
+                                     c->fused_first ? 2 : 0, c->d_partial, c->chunks, c->d_live + p0, c->stream));
     HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
     if (c->rp.relax) {
         // launched residual passes: fast_passes evaluations in all, the fused one included
-        for (int p = c->fused_first ? 1 : 0; p < c->opt.fast_passes; ++p) {
+        for (int p = p0; p < c->opt.fast_passes; ++p) {
             HIPCHECK(c, mark_begin(c));
             HIPCHECK(c, launch_relax_pass(c->dim, c->sys, u, c->d_d, c->d_elem, c->d_cs, c->d_partial, c->nelem, c->gam,
-                                          p == 0, c->stream));
+                                          p == 0, c->d_live + p, c->stream));
             HIPCHECK(c, mark_end(c, PERRK_K_RESIDUAL, c->pass_bytes));
             HIPCHECK(c, mark_begin(c));
-            HIPCHECK(c, launch_relax_finalize(c->d_cs, c->d_case_off, c->n_cases, c->d_partial, c->rp, c->stream));
+            HIPCHECK(c, launch_relax_finalize(c->d_cs, c->d_case_off, c->n_cases, c->d_partial, c->rp,
+                                              c->d_live + p, c->d_live + p + 1, c->stream));
             HIPCHECK(c, mark_end(c, PERRK_K_SOLVER, 0.0));
         }
     }
@@ -996,6 +999,7 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     HIPINIT(hipMalloc(&c->d_H, sizeof(double) * c->n_cases));
     HIPINIT(hipMalloc(&c->d_dt, sizeof(double) * c->n_cases * perrk_ctx::NRING));
     HIPINIT(hipMalloc(&c->d_err, sizeof(int32_t) * ERR_WORDS));
+    HIPINIT(hipMalloc(&c->d_live, sizeof(int32_t) * (16 + 1)));  // fast_passes <= 16
     HIPINIT(hipMalloc(&c->d_mlp, sizeof(float) * (PERRK_MLP_NW + 18)));
     HIPINIT(hipHostMalloc(&c->h_dt, sizeof(double) * c->n_cases * perrk_ctx::NRING, 0));
     HIPINIT(hipHostMalloc(&c->h_cs, sizeof(CaseState) * c->n_cases, 0));

@@ -180,12 +180,17 @@ struct PrepChunks {
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases,
                                 const double *ep_partial, int64_t nelem, RelaxParams rp,
                                 const float *mlp, int phase, const double *rx_partial, const PrepChunks &ch,
-                                hipStream_t s);
+                                int32_t *live, hipStream_t s);
+// live: one word per launched residual pass of a step, cleared when the step
+// begins (the prepare kernel raises the first pass's word, the finalize after
+// pass p that of pass p + 1; a pass and its finalize leave at once while theirs
+// is zero).
 hipError_t launch_relax_pass(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                              const CaseState *cs, double *partial, int64_t nelem, double gam, bool first,
-                             hipStream_t s);
+                             const int32_t *live, hipStream_t s);
 hipError_t launch_relax_finalize(CaseState *cs, const int64_t *case_off, int n_cases,
-                                 const double *partial, RelaxParams rp, hipStream_t s);
+                                 const double *partial, RelaxParams rp, const int32_t *live_in,
+                                 int32_t *live_out, hipStream_t s);
 hipError_t launch_relax_complete(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                                  CaseState *cs, const int64_t *case_off, int n_cases,
                                  double *partial, int64_t nelem, double gam, RelaxParams rp,
@@ -199,3 +204,5 @@ hipError_t launch_entropy(int dim, int sys, const double *U, const ElemInfo *ele
 hipError_t launch_init_cases(CaseState *cs, int n_cases, hipStream_t s);
 hipError_t launch_set_dt(CaseState *cs, const double *dt, int n_cases, hipStream_t s);
 hipError_t launch_clear_err(int32_t *err, int n, hipStream_t s);  // err[0..n-1] = 0
+// as a step begins: *err_step = 0 and live[0..n_live-1] = 0 (n_live <= 64)
+hipError_t launch_clear_step(int32_t *err_step, int32_t *live, int n_live, hipStream_t s);

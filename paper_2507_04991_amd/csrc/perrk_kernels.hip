@@ -742,16 +742,18 @@ struct SG {
     static constexpr int NQ = DIM + 2;
 };
 
-// Element slot in LDS, in words of T: primitives [node][NQ], then (single
-// precision only) rho/p per node, the lifted surface fluxes sf[V][NFN] and the
-// pair fluxes vf[V][VS].  Double-precision slots recompute rho/p where they read
-// a node (a smaller slot keeps more waves resident); single-precision slots store
-// it once per node, which saves a quarter-rate reciprocal per read.  VS: pair
+// Element slot in LDS, in words of T: primitives [node][NQ], then rho/p per
+// node where stored (BETA), the lifted surface fluxes sf[V][NFN] and the pair
+// fluxes vf[V][VS].  Single-precision slots and the one-direction slots of
+// quadrilaterals store rho/p once per node, which saves a quarter-rate
+// reciprocal per read; the other double-precision slots recompute it where they
+// read a node (their smaller slots keep more waves resident: a hexahedron's
+// one-direction slot already fills the LDS at four waves per SIMD).  VS: pair
 // fluxes of one phase, NPP (two directions) or, where the directions are done
 // one at a time (SPLIT), NPD.
 template <int DIM, typename T, bool SPLIT = false>
 struct SL {
-    static constexpr bool BETA = sizeof(T) == 4;
+    static constexpr bool BETA = sizeof(T) == 4 || (SPLIT && DIM == 2);
     static constexpr int PRIM = SG<DIM>::NQ * SG<DIM>::NPE + (BETA ? SG<DIM>::NPE : 0);
     static constexpr int VS = SPLIT ? SG<DIM>::NPD : SG<DIM>::NPP;
     static constexpr int SLOT = PRIM + SG<DIM>::V * (SG<DIM>::NFN + VS);  // LDS words per slot
@@ -898,10 +900,10 @@ __device__ __forceinline__ bool pair_of(int rd, int lane, int &es, int &dd, int 
 }
 
 // Primitive variables of a node in LDS: rho, v_0..v_{DIM-1}, p, contiguous per
-// node (one or two wide LDS reads); rho/p stored beside them in single
-// precision, formed on reading in double precision with the same expression
-// make_prim uses (so that both sides of a face see the same bits).
-template <typename T, int DIM>
+// node (one or two wide LDS reads); rho/p stored beside them (slots with BETA),
+// or formed on reading with the same expression make_prim uses (so that both
+// sides of a face, and both kinds of slot, see the same bits).
+template <typename T, int DIM, bool SPLIT = false>
 __device__ __forceinline__ void lds_put_prim(T *slot, int node, const Prim<T, DIM> &P)
 {
     constexpr int NQ = SG<DIM>::NQ, NPE = SG<DIM>::NPE;
@@ -910,10 +912,10 @@ __device__ __forceinline__ void lds_put_prim(T *slot, int node, const Prim<T, DI
 #pragma unroll
     for (int k = 0; k < DIM; ++k) q[1 + k] = P.v[k];
     q[DIM + 1] = P.p;
-    if constexpr (SL<DIM, T>::BETA) slot[NQ * NPE + node] = P.beta;
+    if constexpr (SL<DIM, T, SPLIT>::BETA) slot[NQ * NPE + node] = P.beta;
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool SPLIT = false>
 __device__ __forceinline__ void lds_get_prim(const T *slot, int node, Prim<T, DIM> &P)
 {
     constexpr int NQ = SG<DIM>::NQ, NPE = SG<DIM>::NPE;
@@ -922,7 +924,7 @@ __device__ __forceinline__ void lds_get_prim(const T *slot, int node, Prim<T, DI
 #pragma unroll
     for (int k = 0; k < DIM; ++k) P.v[k] = q[1 + k];
     P.p = q[DIM + 1];
-    if constexpr (SL<DIM, T>::BETA) P.beta = slot[NQ * NPE + node];
+    if constexpr (SL<DIM, T, SPLIT>::BETA) P.beta = slot[NQ * NPE + node];
     else P.beta = P.rho * recip<T>(P.p);
 }
 
@@ -1070,8 +1072,8 @@ __device__ __forceinline__ void pairs_and_faces(T *lds, int wave, int lane, T in
         int ta, tb;
         pair_pos(k, ta, tb);
         Prim<T, DIM> A, B;
-        lds_get_prim<T, DIM>(slot, line_node<DIM>(D, l, ta), A);
-        lds_get_prim<T, DIM>(slot, line_node<DIM>(D, l, tb), B);
+        lds_get_prim<T, DIM, true>(slot, line_node<DIM>(D, l, ta), A);
+        lds_get_prim<T, DIM, true>(slot, line_node<DIM>(D, l, tb), B);
         flux_ec<T, DIM, true>(D, A, B, inv_gm1, f);
 #pragma unroll
         for (int v = 0; v < V; ++v) vf[v * NPD + l * 6 + k] = f[v];
@@ -1080,8 +1082,8 @@ __device__ __forceinline__ void pairs_and_faces(T *lds, int wave, int lane, T in
     int ta, tb;
     pair_pos(k, ta, tb);
     Prim<T, DIM> X, Y;
-    lds_get_prim<T, DIM>(slot, face_lane ? F.own : line_node<DIM>(D, l, ta), X);
-    lds_get_prim<T, DIM>(slot, line_node<DIM>(D, l, tb), Y);  // (a node of the slot on every lane)
+    lds_get_prim<T, DIM, true>(slot, face_lane ? F.own : line_node<DIM>(D, l, ta), X);
+    lds_get_prim<T, DIM, true>(slot, line_node<DIM>(D, l, tb), Y);  // (a node of the slot on every lane)
     Y = pick<T, DIM>(face_lane, PN, Y);
     const bool swap = face_lane && F.side == 0;
     flux_ec<T, DIM, true>(D, pick<T, DIM>(swap, Y, X), pick<T, DIM>(swap, X, Y), inv_gm1, f);
@@ -1127,7 +1129,7 @@ __device__ __forceinline__ void gather(const T *slot, int node, const T *hn, con
 {
 #pragma clang fp contract(off)
     constexpr int d0 = D0, nd = ND;
-    constexpr int NPD = SG<DIM>::NPD, NPP = VS, V = SG<DIM>::V, PRIM = SL<DIM, T>::PRIM;
+    constexpr int NPD = SG<DIM>::NPD, NPP = VS, V = SG<DIM>::V, PRIM = SL<DIM, T, VS == NPD>::PRIM;
     constexpr int NFN = SG<DIM>::NFN, NLINE = SG<DIM>::NLINE;
     const T *sf = slot + PRIM;
     const T *vf = sf + V * NFN;
@@ -1192,7 +1194,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
 {
     constexpr bool SPLIT = SplitDirs<DIM, FLUX, ONE_DIR>::ON;
     constexpr int NPE = SG<DIM>::NPE, V = SG<DIM>::V, EPW = SG<DIM>::EPW, SLOT = SL<DIM, T, SPLIT>::SLOT;
-    constexpr int PRIM = SL<DIM, T>::PRIM, NFN = SG<DIM>::NFN, FR = FaceRounds<DIM>::N;
+    constexpr int PRIM = SL<DIM, T, SPLIT>::PRIM, NFN = SG<DIM>::NFN, FR = FaceRounds<DIM>::N;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1322,7 +1324,7 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
                 make_prim<T, DIM>(un, a.gm1, PN[r], bad);
             }
         }
-        lds_put_prim<T, DIM>(slot, node, me);
+        lds_put_prim<T, DIM, SPLIT>(slot, node, me);
         if (WL && lane < GTAB_WORDS) reinterpret_cast<uint32_t *>(gtab)[lane] = gword;
     }
     if constexpr (KIND == SK_FIRST) {
@@ -2742,6 +2744,17 @@ __device__ __forceinline__ void prep_sum(const double *part, int stride, int64_t
     }
 }
 
+// Residual passes of a step that find every case solved leave at once.  The
+// kernel that last updated the solver states before a pass (the prepare kernel,
+// then each finalize) raises the pass's word of live (cleared when the step
+// begins) for a case that still needs an evaluation; a pass, and the finalize
+// after it, read that one word first.  A pass that runs sees the same states as
+// without the word, so the results do not depend on it.
+__device__ __forceinline__ void mark_live(const CaseState &C, int32_t *live)
+{
+    if (live && C.state != RS_DONE && C.state != RS_FALLBACK) *live = 1;
+}
+
 // One workgroup per case.  Phases 0 (after the last stage) and 1 (before it, when
 // the last stage evaluates the first residual): sums the stage entropy production
 // of the b_i != 0 stages known so far in a fixed order, resets the solver state
@@ -2749,11 +2762,12 @@ __device__ __forceinline__ void prep_sum(const double *part, int stride, int64_t
 // learned increment); phase 0 also forms dH = dt sum_i b_i e_i.  Phase 2 (after
 // such a last stage): adds the last stage's entropy production, forms dH and
 // advances the solver with the evaluation the last stage made, as
-// relax_finalize_kernel does after a residual pass.
+// relax_finalize_kernel does after a residual pass.  Phases 0 and 2 raise *live
+// for the first launched pass (live is null in phase 1).
 __global__ void __launch_bounds__(PERRK_RED_THREADS)
 relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, int64_t nelem,
                      RelaxParams rp, const float *mlp, int phase, const double *rx_partial,
-                     const int32_t *case_chunk, const double *chunk_sums)
+                     const int32_t *case_chunk, const double *chunk_sums, int32_t *live)
 {
     __shared__ float sx[8], sh1[32], sh2[32];
     const int c = blockIdx.x;
@@ -2785,6 +2799,7 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
             C.r = S[0] - C.dH + off;
             C.state = RS_DONE;
         }  // (RS_BIS_INIT: no Newton budget; the residual passes open the bracket)
+        mark_live(C, live);
         return;
     }
     const int nsum = phase == 0 ? rp.nb : rp.nb_pre;
@@ -2867,12 +2882,13 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
         C.gamma_b = rp.bis_hi;
     }
     C.gamma_acc = 1.0;
+    mark_live(C, live);
 }
 
 template <int DIM, int SYS, bool FIRST>
 __global__ void __launch_bounds__(256)
 relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const CaseState *cs,
-                  double *partial, int64_t nelem, double gam)
+                  double *partial, int64_t nelem, double gam, const int32_t *live_in)
 {
     constexpr int NPE = Geo<DIM>::NPE, EPW = Geo<DIM>::EPW;
     // the block's elements are consecutive, so its cases are a contiguous range:
@@ -2883,6 +2899,7 @@ relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const 
     int64_t ee = eb + (int64_t)(blockDim.x >> 6) * EPW - 1;
     if (ee >= nelem) ee = nelem - 1;
     if (!FIRST) {  // (in the first pass of a step every case is live)
+        if (*live_in == 0) return;  // every case of the step is solved
         if (threadIdx.x == 0) {
             int live = 0;
             for (int c = elem[eb].case_id; c <= elem[ee].case_id; ++c) {
@@ -2900,15 +2917,22 @@ relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const 
     relax_element<DIM, SYS, FIRST>(U, d, elem, cs, partial, nelem, gam, valid ? e0 : nelem - 1, lane % NPE, valid);
 }
 
+// Solver update of each case after a residual pass (live_in: the pass's word;
+// live_out: the next pass's).
 __global__ void __launch_bounds__(PERRK_RED_THREADS)
-relax_finalize_kernel(CaseState *cs, const int64_t *case_off, const double *partial, RelaxParams rp)
+relax_finalize_kernel(CaseState *cs, const int64_t *case_off, const double *partial, RelaxParams rp,
+                      const int32_t *live_in, int32_t *live_out)
 {
+    if (*live_in == 0) return;  // the pass did not run
     const int c = blockIdx.x;
     const int st = cs[c].state;
-    if (st == RS_DONE || st == RS_FALLBACK || st == RS_EVAL1) return;
-    double S[4];
-    case_sum<4>(partial, 4, case_off[c], case_off[c + 1], S);
-    if (threadIdx.x == 0) relax_update(cs[c], S, rp);
+    if (st == RS_DONE || st == RS_FALLBACK) return;
+    if (st != RS_EVAL1) {
+        double S[4];
+        case_sum<4>(partial, 4, case_off[c], case_off[c + 1], S);
+        if (threadIdx.x == 0) relax_update(cs[c], S, rp);
+    }
+    if (threadIdx.x == 0) mark_live(cs[c], live_out);
 }
 
 // Runs the remaining residual evaluations of each case inside one workgroup
@@ -3071,6 +3095,12 @@ __global__ void clear_err_kernel(int32_t *err, int n)
     if ((int)threadIdx.x < n) err[threadIdx.x] = 0;
 }
 
+__global__ void clear_step_kernel(int32_t *err_step, int32_t *live, int n_live)
+{
+    if (threadIdx.x == 0) *err_step = 0;
+    if ((int)threadIdx.x < n_live) live[threadIdx.x] = 0;
+}
+
 __global__ void init_cases_kernel(CaseState *cs, int n)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -3209,7 +3239,7 @@ hipError_t launch_stage(int dim, int variant, int flux, int kind, const StageArg
 
 hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_cases, const double *ep,
                                 int64_t nelem, RelaxParams rp, const float *mlp, int phase,
-                                const double *rx_partial, const PrepChunks &ch, hipStream_t s)
+                                const double *rx_partial, const PrepChunks &ch, int32_t *live, hipStream_t s)
 {
     if (ch.n_chunks > 0) {
         hipLaunchKernelGGL(prepare_chunks_kernel, dim3(ch.n_chunks), dim3(PERRK_RED_THREADS), 0, s, ch.range, ep,
@@ -3219,13 +3249,13 @@ hipError_t launch_relax_prepare(CaseState *cs, const int64_t *case_off, int n_ca
     }
     hipLaunchKernelGGL(relax_prepare_kernel, dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, cs, case_off,
                        ep, nelem, rp, mlp, phase, rx_partial, ch.n_chunks > 0 ? ch.case_chunk : nullptr,
-                       ch.sums);
+                       ch.sums, phase == 1 ? nullptr : live);
     return hipGetLastError();
 }
 
 hipError_t launch_relax_pass(int dim, int sys, const double *U, const double *d, const ElemInfo *elem,
                              const CaseState *cs, double *partial, int64_t nelem, double gam, bool first,
-                             hipStream_t s)
+                             const int32_t *live, hipStream_t s)
 {
     const int epw = dim == 2 ? 4 : 1;
     const int64_t waves = (nelem + epw - 1) / epw;
@@ -3234,10 +3264,10 @@ hipError_t launch_relax_pass(int dim, int sys, const double *U, const double *d,
     do {                                                                                                   \
         if (first)                                                                                         \
             hipLaunchKernelGGL((relax_pass_kernel<D, SY, true>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, \
-                               elem, cs, partial, nelem, gam);                                             \
+                               elem, cs, partial, nelem, gam, live);                                       \
         else                                                                                               \
             hipLaunchKernelGGL((relax_pass_kernel<D, SY, false>), dim3((unsigned)blocks), dim3(256), 0, s, U, d, \
-                               elem, cs, partial, nelem, gam);                                             \
+                               elem, cs, partial, nelem, gam, live);                                       \
     } while (0)
     if (sys == 1) PERRK_PASS(2, 1);
     else if (dim == 2) PERRK_PASS(2, 0);
@@ -3247,10 +3277,10 @@ hipError_t launch_relax_pass(int dim, int sys, const double *U, const double *d,
 }
 
 hipError_t launch_relax_finalize(CaseState *cs, const int64_t *case_off, int n_cases, const double *partial,
-                                 RelaxParams rp, hipStream_t s)
+                                 RelaxParams rp, const int32_t *live_in, int32_t *live_out, hipStream_t s)
 {
     hipLaunchKernelGGL(relax_finalize_kernel, dim3(n_cases), dim3(PERRK_RED_THREADS), 0, s, cs, case_off,
-                       partial, rp);
+                       partial, rp, live_in, live_out);
     return hipGetLastError();
 }
 
@@ -3324,5 +3354,12 @@ hipError_t launch_set_dt(CaseState *cs, const double *dt, int n_cases, hipStream
 hipError_t launch_clear_err(int32_t *err, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(clear_err_kernel, dim3(1), dim3(64), 0, s, err, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_step(int32_t *err_step, int32_t *live, int n_live, hipStream_t s)
+{
+    if (n_live < 0 || n_live > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(clear_step_kernel, dim3(1), dim3(64), 0, s, err_step, live, n_live);
     return hipGetLastError();
 }
