@@ -470,12 +470,24 @@ __device__ __forceinline__ double entropy_density(const double *u, double gam)
 }
 
 // log1p(x): series x - x^2/2 + ... + x^9/9 for |x| < 1e-2 (omitted term < 1e-20/10),
-// flog1p otherwise.
+// flog1p otherwise.  The relaxation arithmetic below fixes its fused
+// multiply-adds (no contraction left to the compiler), so that an evaluation
+// gives the same bits in every kernel that makes it (the last stage, the
+// launched passes, the completion kernel), whatever code surrounds it.
 __device__ __forceinline__ double log1p_small(double x)
 {
-    if (fabs(x) < 1.0e-2)
-        return x * (1.0 + x * (-1.0 / 2.0 + x * (1.0 / 3.0 + x * (-1.0 / 4.0 + x * (1.0 / 5.0 + x * (-1.0 / 6.0 +
-               x * (1.0 / 7.0 + x * (-1.0 / 8.0 + x * (1.0 / 9.0)))))))));
+#pragma clang fp contract(off)
+    if (fabs(x) < 1.0e-2) {
+        double P = fma(x, 1.0 / 9.0, -1.0 / 8.0);
+        P = fma(x, P, 1.0 / 7.0);
+        P = fma(x, P, -1.0 / 6.0);
+        P = fma(x, P, 1.0 / 5.0);
+        P = fma(x, P, -1.0 / 4.0);
+        P = fma(x, P, 1.0 / 3.0);
+        P = fma(x, P, -1.0 / 2.0);
+        P = fma(x, P, 1.0);
+        return x * P;
+    }
     return flog1p(x);
 }
 
@@ -489,35 +501,39 @@ template <int DIM>
 __device__ __forceinline__ void relax_node(const double *u, const double *dv, double g, double dt, double gam,
                                            double &ds, double &wd)
 {
+#pragma clang fp contract(off)
     const double rho = u[0];
+    const double gdt = g * dt;
     double du[DIM + 2];
 #pragma unroll
-    for (int v = 0; v < DIM + 2; ++v) du[v] = g * dt * dv[v];
+    for (int v = 0; v < DIM + 2; ++v) du[v] = gdt * dv[v];
     const double drho = du[0], rho1 = rho + drho;
     // reciprocals by rcp64 (within an ulp; a correctly rounded division costs
     // about three times as many instructions, and this runs per node and pass)
     const double ir = rcp64(rho), ir1 = rcp64(rho1);
-    double mdm = 0.0, dm2 = 0.0, m2 = 0.0;
+    double mdm = u[1] * du[1], dm2 = du[1] * du[1], m2 = u[1] * u[1];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        mdm += u[1 + k] * du[1 + k];
-        dm2 += du[1 + k] * du[1 + k];
-        m2 += u[1 + k] * u[1 + k];
+    for (int k = 1; k < DIM; ++k) {
+        mdm = fma(u[1 + k], du[1 + k], mdm);
+        dm2 = fma(du[1 + k], du[1 + k], dm2);
+        m2 = fma(u[1 + k], u[1 + k], m2);
     }
     const double g1 = gam - 1.0;
-    const double p = g1 * (u[DIM + 1] - 0.5 * m2 * ir);
-    const double dp = g1 * (du[DIM + 1] - (mdm + 0.5 * dm2) * ir1 + 0.5 * drho * m2 * ir * ir1);
+    // p = (gamma-1) (E - |m|^2 / (2 rho)),
+    // dp = (gamma-1) (dE - (m.dm + |dm|^2/2) / rho' + drho |m|^2 / (2 rho rho'))
+    const double p = g1 * fma(-0.5 * m2, ir, u[DIM + 1]);
+    const double dp = g1 * fma(0.5 * drho * m2, ir * ir1, fma(-fma(0.5, dm2, mdm), ir1, du[DIM + 1]));
     const double p1 = p + dp;
     const double lp = log1p_small(dp * rcp64(p)), lr = log1p_small(drho * ir);
-    const double sth0 = flog(p) - gam * flog(rho);
-    const double sth1 = sth0 + lp - gam * lr;
-    ds = -drho * sth1 - rho * (lp - gam * lr);
-    const double ip1 = rcp64(p1);
-    const double m12 = m2 + 2.0 * mdm + dm2;
-    double dot = (gam - sth1 - 0.5 * g1 * m12 * ir1 * ip1) * dv[0];
+    const double lpr = fma(-gam, lr, lp);                 // log1p(dp/p) - gamma log1p(drho/rho)
+    const double sth1 = fma(-gam, flog(rho), flog(p)) + lpr;  // log(p' rho'^-gamma)
+    ds = fma(-drho, sth1, -rho * lpr);
+    const double ip1 = rcp64(p1), gip = g1 * ip1;
+    const double m12 = fma(2.0, mdm, m2) + dm2;  // |m'|^2
+    double dot = fma(-0.5 * g1 * m12, ir1 * ip1, gam - sth1) * dv[0];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) dot += g1 * (u[1 + k] + du[1 + k]) * ip1 * dv[1 + k];
-    dot += -g1 * rho1 * ip1 * dv[DIM + 1];
+    for (int k = 0; k < DIM; ++k) dot = fma(gip * (u[1 + k] + du[1 + k]), dv[1 + k], dot);
+    dot = fma(-gip * rho1, dv[DIM + 1], dot);
     wd = dt * dot;
 }
 
@@ -2498,6 +2514,7 @@ __device__ __forceinline__ void case_sum(const double *part, int stride, int64_t
 __device__ __forceinline__ void relax_node_mhd(const double *u, const double *dv, double g, double dt, double gam,
                                                double &ds, double &wd)
 {
+#pragma clang fp contract(off)
     const double rho = u[0];
     double du[MHD_V];
 #pragma unroll
@@ -2545,36 +2562,23 @@ struct Sys {
 };
 
 // Per-element residual partials: J sum q Delta s at gamma, J sum q w(u + gamma dt d) . dt d,
-// J sum q Delta s at gamma_b (only while opening a bracket), sum |d|.
-template <int DIM, int SYS, bool PRELOAD = false>
-__device__ __forceinline__ void relax_element(const double *U, const double *dd, const ElemInfo *elem,
-                                              const CaseState *cs, double *partial, int64_t nelem,
-                                              double gam, int64_t e, int node, bool valid)
+// J sum q Delta s at gamma_b (only while opening a bracket), sum |d|.  Node
+// lane of element e of case C (jac: the element's Jacobian); u, dv: the node's
+// U_n and d, loaded by load() where the case needs an evaluation (a no-op where
+// the caller loaded them already).
+template <int DIM, int SYS, typename Load>
+__device__ __forceinline__ void relax_finish(const CaseState &C, double jac, double *partial, int64_t e, int node,
+                                             bool valid, double gam, const double *u, const double *dv, Load load)
 {
     constexpr int NPE = Sys<DIM, SYS>::NPE, V = Sys<DIM, SYS>::V;
-    const ElemInfo ei = elem[e];
-    const CaseState &C = cs[ei.case_id];
     const int st = C.state;
     const bool live = valid && st != RS_DONE && st != RS_FALLBACK && st != RS_EVAL1;
     const bool eval1 = valid && st == RS_EVAL1;
     double sr = 0.0, srp = 0.0, srb = 0.0, sabs = 0.0;
-    // PRELOAD (the first pass of a step, where every case is being solved): the
-    // node loads are issued with the case-state loads instead of after them
-    double u[V], dv[V];
-    const size_t field = (size_t)nelem * NPE;
-    const uint32_t o8 = ((uint32_t)e * NPE + (uint32_t)node) * 8u;
-    auto load_node = [&]() {
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            u[v] = bload<double>(field_rsrc<double>(U, v, field), o8);
-            dv[v] = bload<double>(field_rsrc<double>(dd, v, field), o8);
-        }
-    };
-    if (PRELOAD) load_node();
     if (live || eval1) {
         const double g = eval1 ? 1.0 : C.gamma;
         const double dt = C.dt;
-        if (!PRELOAD) load_node();
+        load();
 #pragma unroll
         for (int v = 0; v < V; ++v) sabs += fabs(dv[v]);
         const double q = node_weight<DIM>(node);
@@ -2598,11 +2602,42 @@ __device__ __forceinline__ void relax_element(const double *U, const double *dd,
     }
     if ((live || eval1) && node == 0) {
         double *pp = partial + (size_t)e * 4;
-        pp[0] = ei.jac * sr;
-        pp[1] = ei.jac * srp;
-        pp[2] = ei.jac * srb;
+        pp[0] = jac * sr;
+        pp[1] = jac * srp;
+        pp[2] = jac * srb;
         pp[3] = sabs;
     }
+}
+
+template <int DIM, int SYS>
+__device__ __forceinline__ void relax_load(const double *U, const double *dd, int64_t nelem, int64_t e, int node,
+                                           double *u, double *dv)
+{
+    constexpr int NPE = Sys<DIM, SYS>::NPE, V = Sys<DIM, SYS>::V;
+    const size_t field = (size_t)nelem * NPE;
+    const uint32_t o8 = ((uint32_t)e * NPE + (uint32_t)node) * 8u;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        u[v] = bload<double>(field_rsrc<double>(U, v, field), o8);
+        dv[v] = bload<double>(field_rsrc<double>(dd, v, field), o8);
+    }
+}
+
+// One element per call.  PRELOAD (the launched passes, whose blocks hold a case
+// being solved): the node loads go out with the element and case-state loads;
+// otherwise they are issued only where the case needs an evaluation.
+template <int DIM, int SYS, bool PRELOAD = false>
+__device__ __forceinline__ void relax_element(const double *U, const double *dd, const ElemInfo *elem,
+                                              const CaseState *cs, double *partial, int64_t nelem,
+                                              double gam, int64_t e, int node, bool valid)
+{
+    constexpr int V = Sys<DIM, SYS>::V;
+    const ElemInfo ei = elem[e];
+    double u[V], dv[V];
+    if constexpr (PRELOAD) relax_load<DIM, SYS>(U, dd, nelem, e, node, u, dv);
+    relax_finish<DIM, SYS>(cs[ei.case_id], ei.jac, partial, e, node, valid, gam, u, dv, [&]() {
+        if constexpr (!PRELOAD) relax_load<DIM, SYS>(U, dd, nelem, e, node, u, dv);
+    });
 }
 
 }  // namespace
@@ -2914,7 +2949,7 @@ relax_pass_kernel(const double *U, const double *d, const ElemInfo *elem, const 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t e0 = ((int64_t)blk * (blockDim.x >> 6) + wave) * EPW + lane / NPE;
     const bool valid = e0 < nelem;
-    relax_element<DIM, SYS, FIRST>(U, d, elem, cs, partial, nelem, gam, valid ? e0 : nelem - 1, lane % NPE, valid);
+    relax_element<DIM, SYS, true>(U, d, elem, cs, partial, nelem, gam, valid ? e0 : nelem - 1, lane % NPE, valid);
 }
 
 // Solver update of each case after a residual pass (live_in: the pass's word;
