@@ -231,20 +231,20 @@ __device__ __forceinline__ void make_prim_f32(const double *u, double gm1, Prim<
 template <typename T, int DIM>
 __device__ __forceinline__ void make_prim(const double *u, double gm1, Prim<T, DIM> &P, int &bad)
 {
+#pragma clang fp contract(off)
     if constexpr (sizeof(T) == 4) {
         make_prim_f32<DIM>(u, gm1, P, bad);
         return;
     }
     const double rho = u[0];
     const double ir = rcp64(rho);
-    double ke = 0.0;
     double v[DIM];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        v[k] = u[1 + k] * ir;
-        ke += u[1 + k] * v[k];
-    }
-    const double p = gm1 * (u[DIM + 1] - 0.5 * ke);
+    for (int k = 0; k < DIM; ++k) v[k] = u[1 + k] * ir;
+    double ke = u[1] * v[0];
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) ke = fma(u[1 + k], v[k], ke);
+    const double p = gm1 * fma(-0.5, ke, u[DIM + 1]);
     double sum = u[0];
 #pragma unroll
     for (int k = 1; k < DIM + 2; ++k) sum += u[k];
@@ -263,18 +263,18 @@ __device__ __forceinline__ void make_prim(const double *u, double gm1, Prim<T, D
 template <int DIM>
 __device__ __forceinline__ void prim_f32(const float *uf, double gm1, Prim<float, DIM> &P, int &bad)
 {
+#pragma clang fp contract(off)
     float sum = uf[0];
 #pragma unroll
     for (int k = 1; k < DIM + 2; ++k) sum += uf[k];
     const float rho = uf[0];
     const float ir = __builtin_amdgcn_rcpf(rho);
-    float ke = 0.0f;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        P.v[k] = uf[1 + k] * ir;
-        ke += uf[1 + k] * P.v[k];
-    }
-    const float p = (float)gm1 * (uf[DIM + 1] - 0.5f * ke);
+    for (int k = 0; k < DIM; ++k) P.v[k] = uf[1 + k] * ir;
+    float ke = uf[1] * P.v[0];
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) ke = fmaf(uf[1 + k], P.v[k], ke);
+    const float p = (float)gm1 * fmaf(-0.5f, ke, uf[DIM + 1]);
     if (!isfinite(sum)) bad |= 2;
     else if (!(rho > 0.0f) || !(p > 0.0f)) bad |= 1;
     P.rho = rho;
@@ -444,15 +444,16 @@ __device__ __forceinline__ void flux_diss(int kind, int d, const Prim<T, DIM> &L
 template <int DIM>
 __device__ __forceinline__ void entropy_vars(const double *u, double gam, double *w)
 {
+#pragma clang fp contract(off)
     const double rho = u[0];
     const double ir = rcp64(rho);
-    double m2 = 0.0;
+    double m2 = u[1] * u[1];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) m2 += u[1 + k] * u[1 + k];
-    const double p = (gam - 1.0) * (u[DIM + 1] - 0.5 * m2 * ir);
+    for (int k = 1; k < DIM; ++k) m2 = fma(u[1 + k], u[1 + k], m2);
+    const double p = (gam - 1.0) * fma(-0.5 * m2, ir, u[DIM + 1]);
     const double rp = rho * rcp64(p);
     const double g1rp = (gam - 1.0) * rp;
-    w[0] = gam - (flog(p) - gam * flog(rho)) - 0.5 * g1rp * m2 * ir * ir;
+    w[0] = fma(-0.5 * g1rp * m2, ir * ir, gam - fma(-gam, flog(rho), flog(p)));
 #pragma unroll
     for (int k = 0; k < DIM; ++k) w[1 + k] = g1rp * u[1 + k] * ir;
     w[DIM + 1] = -g1rp;
@@ -462,11 +463,12 @@ __device__ __forceinline__ void entropy_vars(const double *u, double gam, double
 template <int DIM>
 __device__ __forceinline__ double entropy_density(const double *u, double gam)
 {
-    double m2 = 0.0;
+#pragma clang fp contract(off)
+    double m2 = u[1] * u[1];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) m2 += u[1 + k] * u[1 + k];
+    for (int k = 1; k < DIM; ++k) m2 = fma(u[1 + k], u[1 + k], m2);
     const double p = (gam - 1.0) * (u[DIM + 1] - 0.5 * m2 / u[0]);
-    return -u[0] * (flog(p) - gam * flog(u[0]));
+    return -u[0] * fma(-gam, flog(u[0]), flog(p));
 }
 
 // log1p(x): series x - x^2/2 + ... + x^9/9 for |x| < 1e-2 (omitted term < 1e-20/10),
@@ -616,16 +618,22 @@ __device__ __forceinline__ void load_raw(const StageArgs &a, int e, int node, No
 }
 
 // U_{n,i} = U_n + dt (c1 K_1 + cp K_{i-1}) with the node's level coefficients.
+// This, the primitive variables and the entropy variables fix their fused
+// multiply-adds explicitly (contraction off): a lane forms its own state and,
+// for its face node, the neighbour's from the neighbour's data, and the two
+// must have the bits the neighbour's own lanes give them (both sides of a face
+// then form the same flux).
 template <int V, typename KT, int KIND>
 __device__ __forceinline__ void combine(const NodeRaw<V, KT> &r, double dt, double c1, double cp, double *u)
 {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         double x = r.u[v];
         if (KIND != SK_FIRST) {
             double s = c1 * (double)r.k1[v];
-            s += (cp != 0.0) ? cp * (double)r.kp[v] : 0.0;
-            x = x + dt * s;
+            s = (cp != 0.0) ? fma(cp, (double)r.kp[v], s) : s;
+            x = fma(dt, s, x);
         }
         u[v] = x;
     }
@@ -636,14 +644,15 @@ __device__ __forceinline__ void combine(const NodeRaw<V, KT> &r, double dt, doub
 template <int V, typename KT, int KIND, typename UT>
 __device__ __forceinline__ void combine_f32(const NodeRaw<V, KT, UT> &r, double dt, float c1, float cp, float *u)
 {
+#pragma clang fp contract(off)
     const float fdt = (float)dt, fc1 = c1, fcp = cp;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         float x = (float)r.u[v];
         if (KIND != SK_FIRST) {
             float s = fc1 * (float)r.k1[v];
-            s += (cp != 0.0f) ? fcp * (float)r.kp[v] : 0.0f;
-            x = x + fdt * s;
+            s = (cp != 0.0f) ? fmaf(fcp, (float)r.kp[v], s) : s;
+            x = fmaf(fdt, s, x);
         }
         u[v] = x;
     }
