@@ -315,7 +315,7 @@ def test_learned_guess_gain_on_held_out_cases(P):
     """The shipped network (trained on another seed's ensemble) against the
     previous-gamma guess on 128 held-out cases over 60 steps: both accept only
     certified roots, and the network saves at least 0.02 residual evaluations
-    per case and step (measured: 1.708 -> 1.665; the runs are deterministic)."""
+    per case and step (measured: 1.713 -> 1.660; the runs are deterministic)."""
     from paper_2507_04991_amd import learned_guess as L
     from paper_2507_04991_amd import problems
     prob = problems.ensemble(7, 128)
