@@ -1499,10 +1499,16 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             double dv = a.bs * k[v];
-            double ksm1 = (double)own.kp[v], k1 = (double)own.k1[v];
-            if constexpr (sizeof(T) == 8) {
-                if (a.k64_sm1) ksm1 = k64sm1[v];
-                if (a.k64_1) k1 = k64_1[v];
+            double ksm1, k1;
+            if constexpr (sizeof(T) == 8 && sizeof(KT) == 4) {
+                // mixed precision: the double copies, kept wherever the weight is nonzero
+                // (so the single-precision K_1, K_{S-1} need not stay live through the
+                // flux work: 16-20 fewer VGPRs, one more wavefront per SIMD on hexahedra)
+                ksm1 = k64sm1[v];
+                k1 = k64_1[v];
+            } else {
+                ksm1 = (double)own.kp[v];
+                k1 = (double)own.k1[v];
             }
             if (a.bsm1 != 0.0) dv += a.bsm1 * ksm1;
             if (a.b1 != 0.0) dv += a.b1 * k1;
