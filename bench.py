@@ -27,7 +27,9 @@ Variants on identical inputs (same mesh, dt, steps and initial state):
                        entropy production accumulated in double precision;
   fp64                 double precision throughout;
 "+learned": the first Newton point is the previous gamma plus the learned
-increment (otherwise the previous gamma).  The headline is mixed+learned
+increment (otherwise the previous gamma); "fp64+extrapolated" (ensemble only):
+fp64 starting from the linear extrapolation of the root history, beside the
+plain fp64 baseline (previous gamma).  The headline is mixed+learned
 (mixed where no network applies); mixed_all is faster but its states deviate
 from FP64 about ten times more, enough to miss "equal L2 error" on some cases.
 For the ensemble the L2 error of each case against the exact advected vortex at
@@ -337,15 +339,20 @@ def main():
     M = wl["U0"].size
     print(f"# workload {wl['name']}: {M} DOF, {len(wl['faces'])} case(s)", file=sys.stderr, flush=True)
 
-    # variants on identical inputs: name -> (precision, learned guess); the first is
-    # the headline (the learned guess needs the network trained on the ensemble)
+    # variants on identical inputs: name -> (precision, initial guess of the Newton
+    # iteration); the first is the headline (the learned guess needs the network
+    # trained on the ensemble).  fp64 is the plain baseline (previous gamma);
+    # fp64+extrapolated starts from the linear extrapolation of the root history.
     learned = wl["kind"] == "ensemble" and os.path.exists(LG.DEFAULT_MODEL)
-    plan = [("mixed+learned", P.MIXED, True), ("mixed", P.MIXED, False), ("mixed_all+learned", P.MIXED_ALL, True),
-            ("mixed_all", P.MIXED_ALL, False), ("fp64", P.FP64, False)]
+    MLP, PREV, EXTRAP = P.GUESS_MLP, P.GUESS_PREV, P.GUESS_EXTRAP
+    plan = [("mixed+learned", P.MIXED, MLP), ("mixed", P.MIXED, PREV), ("mixed_all+learned", P.MIXED_ALL, MLP),
+            ("mixed_all", P.MIXED_ALL, PREV), ("fp64", P.FP64, PREV)]
+    if wl["kind"] == "ensemble":
+        plan.append(("fp64+extrapolated", P.FP64, EXTRAP))
     if not learned:
-        plan = [(n, p, g) for n, p, g in plan if not g]
+        plan = [(n, p, g) for n, p, g in plan if g != MLP]
     if fp64_only:  # the GLM-MHD and viscous paths are double precision only
-        plan = [("fp64", P.FP64, False)]
+        plan = [("fp64", P.FP64, PREV)]
     if args.no_compare:
         plan = plan[:1]
     head_name = plan[0][0]
@@ -353,7 +360,7 @@ def main():
     model = LG.load(LG.DEFAULT_MODEL) if learned else None
     for k, (name, prec, guess) in enumerate(plan):
         runs[name] = run_variant(P, torch, wl, prec, args.steps, args.warmup, profile=(k == 0),
-                                 guess=P.GUESS_MLP if guess else P.GUESS_PREV, model=model if guess else None)
+                                 guess=guess, model=model if guess == MLP else None)
     extra = {"variants": {}}
     for name, r in runs.items():
         print(f"# {name}: {r['seconds'] / args.steps * 1e3:.3f} ms/step, passes {r['passes_mean']}",
@@ -443,7 +450,7 @@ def main():
         wl1 = dict(wl, lev=[np.full_like(np.asarray(lv), R - 1) for lv in wl["lev"]])
         head = plan[0]
         one = run_variant(P, torch, wl1, head[1], args.steps, args.warmup,
-                          guess=P.GUESS_MLP if head[2] else P.GUESS_PREV, model=model if head[2] else None)
+                          guess=head[2], model=model if head[2] == MLP else None)
         n_rhs1 = float(E[-1]) * M
         cmp = dict(variant=head_name, single_level_ms_per_step=one["seconds"] / args.steps * 1e3,
                    multirate_ms_per_step=mixed["seconds"] / args.steps * 1e3,

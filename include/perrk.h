@@ -101,8 +101,13 @@ enum { PERRK_FP64 = 0, PERRK_MIXED = 1, PERRK_MIXED_ALL = 2 };
  * part of the relaxation state, see perrk_get_relaxation_state). */
 enum { PERRK_ANCHOR_STEP = 0, PERRK_ANCHOR_INITIAL = 1 };
 /* Initial guess of the Newton iteration: previous accepted gamma (1 at the
- * first step), or the learned guess (perrk_set_guess_model). */
-enum { PERRK_GUESS_PREV = 0, PERRK_GUESS_MLP = 1 };
+ * first step), the learned guess (perrk_set_guess_model), or the linear
+ * extrapolation of the root history, 1 + 2 (gamma*_{n-1} - 1) - (gamma*_{n-2} - 1)
+ * (see perrk_get_relaxation_state), once a case has taken two steps; an
+ * extrapolation that is not finite, moves the previous root by 0.1 or more, or
+ * is <= 0 is ignored (the previous accepted gamma is used).  Not in the paper:
+ * Newton and bisection still decide the accepted gamma. */
+enum { PERRK_GUESS_PREV = 0, PERRK_GUESS_MLP = 1, PERRK_GUESS_EXTRAP = 2 };
 /* Per-case step flags (perrk_step_info.flags). */
 enum {
     PERRK_FLAG_BISECT = 1,   /* Newton failed, bisection was used */
@@ -168,7 +173,7 @@ typedef struct {
     int32_t anchor;            /* PERRK_ANCHOR_STEP or PERRK_ANCHOR_INITIAL */
     int32_t max_bisect;        /* bisection steps before gamma = 1 (>= 0) */
     double bisect_lo, bisect_hi; /* bracket, 0 < lo < 1 < hi; widened once to [lo/2, 2 hi] */
-    int32_t guess;             /* PERRK_GUESS_PREV or PERRK_GUESS_MLP */
+    int32_t guess;             /* PERRK_GUESS_PREV, PERRK_GUESS_MLP or PERRK_GUESS_EXTRAP */
     int32_t fast_passes;       /* residual passes launched without host involvement (1..16);
                                   further passes run in one per-case completion kernel */
     int32_t use_graph;         /* 1: capture each step's launch sequence into a hipGraph */

@@ -295,7 +295,8 @@ int validate(const perrk_mesh_desc *m, const perrk_partition_desc *p, const perr
         if (!(o->bisect_lo > 0.0 && o->bisect_lo < 1.0 && o->bisect_hi > 1.0))
             return ck.bad("bracket must satisfy 0 < lo < 1 < hi");
         if (o->anchor != PERRK_ANCHOR_STEP && o->anchor != PERRK_ANCHOR_INITIAL) return ck.bad("bad anchor");
-        if (o->guess != PERRK_GUESS_PREV && o->guess != PERRK_GUESS_MLP) return ck.bad("bad guess");
+        if (o->guess != PERRK_GUESS_PREV && o->guess != PERRK_GUESS_MLP && o->guess != PERRK_GUESS_EXTRAP)
+            return ck.bad("bad guess");
         if (o->fast_passes < 1 || o->fast_passes > 16) return ck.bad("fast_passes must be in 1..16");
         if (o->tune != 0 && o->tune != 1 && o->tune != -1 && o->tune != -2 && o->tune != -4 && o->tune != -8)
             return ck.bad("tune must be 1, 0, -1, -2, -4 or -8");

@@ -2919,6 +2919,11 @@ relax_prepare_kernel(CaseState *cs, const int64_t *case_off, const double *ep, i
         const double pred = (double)y * (double)oscale[0] + (double)oscale[1];
         const double base = 1.0 + C.ghist[0];
         if (isfinite(pred) && fabs(pred) < 0.1 && base + pred > 0.0) g0 = base + pred;
+    } else if (rp.guess == 2 && C.nsteps >= 2) {
+        // linear extrapolation of the root history
+        const double pred = C.ghist[0] - C.ghist[1];
+        const double base = 1.0 + C.ghist[0];
+        if (isfinite(pred) && fabs(pred) < 0.1 && base + pred > 0.0) g0 = base + pred;
     }
     C.gamma = g0;
     C.gamma_b = g0;

@@ -21,7 +21,7 @@ VOLUME_FLUX_DIFFERENCING, VOLUME_WEAK = 0, 1
 SYSTEM_EULER, SYSTEM_GLM_MHD = 0, 1
 FP64, MIXED, MIXED_ALL = 0, 1, 2
 ANCHOR_STEP, ANCHOR_INITIAL = 0, 1
-GUESS_PREV, GUESS_MLP = 0, 1
+GUESS_PREV, GUESS_MLP, GUESS_EXTRAP = 0, 1, 2
 TILES = 4  # PERRK_TILES
 FLAG_BISECT, FLAG_FALLBACK, FLAG_TRIVIAL = 1, 2, 4
 

@@ -124,6 +124,11 @@ def test_validate_viscous_descriptors():
     for phases in (-1, 3):
         st, msg = d.validate(P.default_options(phases=phases))
         assert st == P.EINVAL and "phases" in msg, msg
+    for guess in (P.GUESS_PREV, P.GUESS_MLP, P.GUESS_EXTRAP):
+        assert d.validate(P.default_options(guess=guess))[0] == P.OK
+    for guess in (-1, 3):
+        st, msg = d.validate(P.default_options(guess=guess))
+        assert st == P.EINVAL and "guess" in msg, msg
 
 
 def test_validate_node_limit_and_case_count():
