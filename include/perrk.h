@@ -188,14 +188,15 @@ typedef struct {
                                   2D tiles of 32 quadrilaterals (a full workgroup) 8x4, 4x8, 16x2,
                                   32x1; 3D cubes of 8^3, 4^3, 16^3 hexahedra, or whole rows.  Results
                                   do not depend on the tile. */
-    int32_t phases;            /* Euler with the EC surface flux and flux differencing: 0 = chosen per
-                                  stage with double-precision fluxes by the autotuner with tune = 1
-                                  (1 otherwise); 1 = a stage forms the pair fluxes of two directions
-                                  per phase (2D: x and y, faces in a round of their own; 3D: z with
-                                  the z faces, then x and y); 2 = one direction at a time, each with
-                                  its faces (2D: x, y; 3D: z, x, y; half the pair-flux LDS per
-                                  element).  Ignored by the other configurations.  Results do not
-                                  depend on the choice. */
+    int32_t phases;            /* Euler with the EC surface flux and flux differencing, and GLM-MHD:
+                                  0 = chosen per stage with double-precision fluxes by the autotuner
+                                  with tune = 1 (1 otherwise); 1 = a stage forms the pair fluxes of
+                                  two directions per phase (Euler 2D: x and y, faces in a round of
+                                  their own; 3D: z with the z faces, then x and y; GLM-MHD: x and y
+                                  after the faces); 2 = one direction at a time (Euler: each with its
+                                  faces, 2D: x, y; 3D: z, x, y; GLM-MHD: x, then y, after the faces),
+                                  with half the pair-flux LDS per element.  Ignored by the other
+                                  configurations.  Results do not depend on the choice. */
 } perrk_options;
 #define PERRK_TILES 4
 

@@ -36,7 +36,7 @@ struct perrk_ctx {
     perrk_options opt{};
     RelaxParams rp{};
     LaunchCfg cfg{4, 0};            // default stage launch shape
-    bool can_one_dir = false;       // Euler with the EC fluxes: stages may take one direction at a time
+    bool can_one_dir = false;       // Euler with the EC fluxes, GLM-MHD: stages may take one direction at a time
     std::vector<LaunchCfg> scfg;    // per stage (autotuned at the first step when opt.tune)
     bool tuned = false;
     std::string tune_report;
@@ -875,8 +875,11 @@ int perrk_init(const perrk_mesh_desc *m, const perrk_partition_desc *p, const pe
     c->rp = rp;
     // the Euler stage kernel's last stage evaluates the first residual of the solve
     c->fused_first = c->sys == PERRK_SYSTEM_EULER && !c->viscous;
-    c->can_one_dir = c->fused_first && c->flux == PERRK_FLUX_EC && c->volume == PERRK_VOLUME_FLUX_DIFFERENCING;
-    // GLM-MHD: 27 KB of LDS per wavefront; Navier-Stokes: 19 KB
+    // stages that may take the directions one at a time: Euler with the EC fluxes
+    // (pairs and faces of a direction together), GLM-MHD with any fluxes (pairs only)
+    c->can_one_dir = (c->fused_first && c->flux == PERRK_FLUX_EC && c->volume == PERRK_VOLUME_FLUX_DIFFERENCING) ||
+                     c->sys == PERRK_SYSTEM_GLM_MHD;
+    // GLM-MHD: 24 KB of LDS per wavefront (17 KB one direction at a time); Navier-Stokes: 19 KB
     c->cfg.epb_mult = c->sys == PERRK_SYSTEM_GLM_MHD ? 1 : (c->viscous ? 2 : 4);
     c->cfg.one_dir = c->can_one_dir && c->opt.phases == 2 ? 1 : 0;
     c->scfg.assign(c->S, c->cfg);

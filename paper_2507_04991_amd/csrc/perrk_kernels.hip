@@ -1603,7 +1603,16 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) stage_kernel(const StageAr
 constexpr int MHD_V = 9;
 constexpr int MHD_NC = 11;  // flux components + the means of B_d and psi
 constexpr int MHD_NQ = 9;   // primitives per node in LDS: rho, v_1..3, p, B_1..3, psi
-constexpr int MHD_SLOT = MHD_NQ * 16 + MHD_NC * (SG<2>::NFN + SG<2>::NPP);  // LDS doubles per element
+// LDS doubles per element: the primitives, the lifted face fluxes and face means
+// (MHD_NC per face node), the pair fluxes (MHD_V per pair; the gather forms the
+// pair means of B_d and psi from the primitives) of both directions, or of one
+// direction at a time (ONE_DIR: 584 instead of 752 doubles, 8 instead of 6
+// wavefronts per compute unit).
+template <bool ONE_DIR>
+constexpr int mhd_slot()
+{
+    return MHD_NQ * 16 + MHD_NC * SG<2>::NFN + MHD_V * (ONE_DIR ? SG<2>::NPD : SG<2>::NPP);
+}
 
 struct PrimM {
     double rho, v[3], p, B[3], psi;
@@ -1663,20 +1672,29 @@ __device__ __forceinline__ void mhd_get(const double *slot, int node, PrimM &P)
 __device__ __forceinline__ double sel2(int d, double a, double b) { return d == 0 ? a : b; }
 
 // Physical flux in direction d (0 or 1) from primitive variables.
+// The GLM-MHD fluxes fix their fused multiply-adds explicitly (contraction off),
+// as the Euler fluxes do: a pair flux then has the same bits whether its
+// direction is a compile-time constant (one direction at a time) or a per-lane
+// value (two directions per phase).
+__device__ __forceinline__ double dot3(const double *a, const double *b)
+{
+#pragma clang fp contract(off)
+    return fma(a[2], b[2], fma(a[1], b[1], a[0] * b[0]));
+}
+
 __device__ __forceinline__ void mhd_flux_phys(int d, const PrimM &P, double gam, double inv_gm1, double c_h, double *f)
 {
+#pragma clang fp contract(off)
     const double vn = sel2(d, P.v[0], P.v[1]), Bn = sel2(d, P.B[0], P.B[1]);
-    const double vB = P.v[0] * P.B[0] + P.v[1] * P.B[1] + P.v[2] * P.B[2];
-    const double B2 = P.B[0] * P.B[0] + P.B[1] * P.B[1] + P.B[2] * P.B[2];
-    const double v2 = P.v[0] * P.v[0] + P.v[1] * P.v[1] + P.v[2] * P.v[2];
-    const double ptot = P.p + 0.5 * B2;
+    const double vB = dot3(P.v, P.B), B2 = dot3(P.B, P.B), v2 = dot3(P.v, P.v);
+    const double ptot = fma(0.5, B2, P.p);
     const double mn = P.rho * vn;
     f[0] = mn;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) f[1 + k] = mn * P.v[k] - P.B[k] * Bn + (k == d ? ptot : 0.0);
-    f[4] = vn * (0.5 * P.rho * v2 + gam * inv_gm1 * P.p + B2) - Bn * vB + c_h * P.psi * Bn;
+    for (int k = 0; k < 3; ++k) f[1 + k] = fma(mn, P.v[k], fma(-P.B[k], Bn, k == d ? ptot : 0.0));
+    f[4] = fma(vn, fma(0.5 * P.rho, v2, fma(gam * inv_gm1, P.p, B2)), fma(-Bn, vB, c_h * P.psi * Bn));
 #pragma unroll
-    for (int k = 0; k < 3; ++k) f[5 + k] = vn * P.B[k] - P.v[k] * Bn + (k == d ? c_h * P.psi : 0.0);
+    for (int k = 0; k < 3; ++k) f[5 + k] = fma(vn, P.B[k], fma(-P.v[k], Bn, k == d ? c_h * P.psi : 0.0));
     f[8] = c_h * Bn;
 }
 
@@ -1690,38 +1708,39 @@ __device__ __forceinline__ void mhd_flux_phys(int d, const PrimM &P, double gam,
 __device__ __forceinline__ void mhd_flux_ec(int d, const PrimM &A, const PrimM &B, double inv_gm1, double c_h,
                                             double *f)
 {
+#pragma clang fp contract(off)
     const double ba = 0.5 * A.rho * rcp64(A.p), bb = 0.5 * B.rho * rcp64(B.p);
     const double rho_ln = lmean(A.rho, B.rho);
     const double ibeta_ln = inv_lmean(ba, bb);
     const double ptil = (A.rho + B.rho) * rcp64(2.0 * (ba + bb));
-    double va[3], Ba[3], BB = 0.0, v2a = 0.0, vBa = 0.0, vBb = 0.0, B2a = 0.0, B2b = 0.0;
+    double va[3], Ba[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         va[k] = 0.5 * (A.v[k] + B.v[k]);
         Ba[k] = 0.5 * (A.B[k] + B.B[k]);
-        BB += A.B[k] * B.B[k];
-        v2a += 0.5 * (A.v[k] * A.v[k] + B.v[k] * B.v[k]);
-        vBa += A.v[k] * A.B[k];
-        vBb += B.v[k] * B.B[k];
-        B2a += A.B[k] * A.B[k];
-        B2b += B.B[k] * B.B[k];
     }
+    const double BB = dot3(A.B, B.B), v2a = 0.5 * (dot3(A.v, A.v) + dot3(B.v, B.v));
+    const double vBa = dot3(A.v, A.B), vBb = dot3(B.v, B.B), B2a = dot3(A.B, A.B), B2b = dot3(B.B, B.B);
     const double Bna = sel2(d, A.B[0], A.B[1]), Bnb = sel2(d, B.B[0], B.B[1]);
     const double vna = sel2(d, A.v[0], A.v[1]), vnb = sel2(d, B.v[0], B.v[1]);
-    const double psa = 0.5 * (A.psi + B.psi);
-    const double f0 = rho_ln * 0.5 * (vna + vnb);
+    const double psa = 0.5 * (A.psi + B.psi), Bnm = 0.5 * (Bna + Bnb);
+    const double f0 = rho_ln * (0.5 * (vna + vnb));
     f[0] = f0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) f[1 + k] = f0 * va[k] - 0.5 * (Bna * B.B[k] + Bnb * A.B[k]) + (k == d ? ptil + 0.5 * BB : 0.0);
+    for (int k = 0; k < 3; ++k)
+        f[1 + k] = fma(f0, va[k], fma(-0.5, fma(Bna, B.B[k], Bnb * A.B[k]), k == d ? fma(0.5, BB, ptil) : 0.0));
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        f[5 + k] = 0.5 * (vna * A.B[k] - A.v[k] * Bna + vnb * B.B[k] - B.v[k] * Bnb) + (k == d ? c_h * psa : 0.0);
-    f[8] = c_h * 0.5 * (Bna + Bnb);
-    double fe = f0 * (0.5 * inv_gm1 * ibeta_ln - 0.5 * v2a);
+        f[5 + k] = fma(0.5, fma(vna, A.B[k], fma(-A.v[k], Bna, fma(vnb, B.B[k], -B.v[k] * Bnb))),
+                       k == d ? c_h * psa : 0.0);
+    f[8] = c_h * Bnm;
+    double fe = f0 * fma(0.5 * inv_gm1, ibeta_ln, -0.5 * v2a);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) fe += f[1 + k] * va[k] + f[5 + k] * Ba[k];
-    fe += f[8] * psa - 0.25 * (vna * B2a + vnb * B2b) + 0.5 * (Bna + Bnb) * 0.5 * (vBa + vBb)
-          - c_h * 0.5 * (A.psi * Bna + B.psi * Bnb);
+    for (int k = 0; k < 3; ++k) fe = fma(f[5 + k], Ba[k], fma(f[1 + k], va[k], fe));
+    fe = fma(f[8], psa, fe);
+    fe = fma(-0.25, fma(vna, B2a, vnb * B2b), fe);
+    fe = fma(Bnm, 0.5 * (vBa + vBb), fe);
+    fe = fma(-0.5 * c_h, fma(A.psi, Bna, B.psi * Bnb), fe);
     f[4] = fe;
 }
 
@@ -1754,6 +1773,7 @@ __device__ __forceinline__ void mhd_cons(const PrimM &P, double inv_gm1, double 
 __device__ __forceinline__ void mhd_flux_surface(int kind, int d, const PrimM &L, const PrimM &R, double gam,
                                                  double inv_gm1, double c_h, double *f)
 {
+#pragma clang fp contract(off)
     if (kind == PERRK_FLUX_EC) {
         mhd_flux_ec(d, L, R, inv_gm1, c_h, f);
         return;
@@ -1809,10 +1829,10 @@ __device__ __forceinline__ double mhd_entropy_density(const double *u, double ga
     return -rho * (flog(p) - gam * flog(rho));
 }
 
-template <int KIND>
+template <int KIND, bool ONE_DIR>
 __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) mhd_stage_kernel(const StageArgs a, const double *coef)
 {
-    constexpr int NPE = 16, V = MHD_V, NC = MHD_NC, EPW = 4, SLOT = MHD_SLOT;
+    constexpr int NPE = 16, V = MHD_V, NC = MHD_NC, EPW = 4, SLOT = mhd_slot<ONE_DIR>();
     constexpr int NFN = SG<2>::NFN, NPP = SG<2>::NPP, NPD = SG<2>::NPD, NLINE = SG<2>::NLINE;
     constexpr int FR = FaceRounds<2>::N;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1933,11 +1953,15 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) mhd_stage_kernel(const Sta
         sf[10 * NFN + F[r].q] = lift * 0.5 * (L.psi + R.psi);
     }
 
-    // ---- volume pairs: the two-point flux and the pair means of B_d and psi
-#pragma unroll
-    for (int rd = 0; rd < PairRounds<2, 2>::N; ++rd) {
-        int es, dd, l, k;
-        pair_of<2, 2>(rd, lane, es, dd, l, k);
+    // ---- volume pairs (the two-point flux), and the gather:
+    //      (2/h_d) [sum_m Dsplit f# + lifted face flux
+    //               + Phi (sum_m Dsplit {B_d} + lifted face mean) + Phi_d (... psi)]
+    // Two directions per phase (3 rounds of pairs, then both gathers), or one
+    // direction at a time (ONE_DIR: pairs k = 0..3 of the direction on every lane,
+    // then k = 4, 5 on lanes 0..31, its gather, then the other direction): the same
+    // fluxes and sums in the same order.
+    constexpr int VS = ONE_DIR ? NPD : NPP;  // pairs held per phase
+    auto pair_flux = [&](int dd, int es, int l, int k) {
         int ta, tb;
         pair_pos(k, ta, tb);
         double *ps = lds + (size_t)(wave * EPW + es) * SLOT;
@@ -1955,59 +1979,82 @@ __global__ void __launch_bounds__(64 * PERRK_MAX_WPB) mhd_stage_kernel(const Sta
             mhd_flux_ec(dd, A, B, inv_gm1, c_h, f);
         }
         double *vf = ps + MHD_NQ * NPE + NC * NFN;
-        const int p = dd * NPD + l * 6 + k;
+        const int p = (ONE_DIR ? 0 : dd * NPD) + l * 6 + k;
 #pragma unroll
-        for (int v = 0; v < V; ++v) vf[v * NPP + p] = f[v];
-        vf[9 * NPP + p] = 0.5 * (sel2(dd, A.B[0], A.B[1]) + sel2(dd, B.B[0], B.B[1]));
-        vf[10 * NPP + p] = 0.5 * (A.psi + B.psi);
-    }
-    wave_lds_sync();
-
-    // ---- gather: (2/h_d) [sum_m Dsplit f# + lifted face flux
-    //                        + Phi (sum_m Dsplit {B_d} + lifted face mean) + Phi_d (... psi)]
+        for (int v = 0; v < V; ++v) vf[v * VS + p] = f[v];
+    };
     const ElemInfo ei = elt(a.elem, (uint32_t)e);
     double du[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) du[v] = 0.0;
-    {
+    const double vB = me.v[0] * me.B[0] + me.v[1] * me.B[1] + me.v[2] * me.B[2];
+    auto gather_dir = [&](int d) {
         const double *sf = slot + MHD_NQ * NPE;
         const double *vf = sf + NC * NFN;
-        const double vB = me.v[0] * me.B[0] + me.v[1] * me.B[1] + me.v[2] * me.B[2];
+        const int t = node_pos(d, node);
+        const int l = node_line<2>(d, node);
+        double acc[NC];
+#pragma unroll
+        for (int v = 0; v < NC; ++v) acc[v] = 0.0;
+        const int pb = (ONE_DIR ? 0 : d * NPD) + l * 6;
+        const int p1 = pb + pair_k<1>(t), p2 = pb + pair_k<2>(t), p3 = pb + pair_k<3>(t);
+        const double w1 = dsplit_j<double, 1>(t), w2 = dsplit_j<double, 2>(t), w3 = dsplit_j<double, 3>(t);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            acc[v] += w1 * vf[v * VS + p1];
+            acc[v] += w2 * vf[v * VS + p2];
+            acc[v] += w3 * vf[v * VS + p3];
+        }
+        // pair means of B_d and psi with the partners (t + j) & 3 (a symmetric
+        // sum, so it does not matter which node of the pair it is formed on)
+        const double *q1 = slot + line_node<2>(d, l, (t + 1) & 3) * MHD_NQ;
+        const double *q2 = slot + line_node<2>(d, l, (t + 2) & 3) * MHD_NQ;
+        const double *q3 = slot + line_node<2>(d, l, (t + 3) & 3) * MHD_NQ;
+        const double bt = sel2(d, me.B[0], me.B[1]);
+        acc[9] += w1 * (0.5 * (bt + q1[5 + d]));
+        acc[9] += w2 * (0.5 * (bt + q2[5 + d]));
+        acc[9] += w3 * (0.5 * (bt + q3[5 + d]));
+        acc[10] += w1 * (0.5 * (me.psi + q1[8]));
+        acc[10] += w2 * (0.5 * (me.psi + q2[8]));
+        acc[10] += w3 * (0.5 * (me.psi + q3[8]));
+        if (t == 0 || t == 3) {
+            const int q = (2 * d + (t == 3 ? 1 : 0)) * NLINE + l;
+#pragma unroll
+            for (int v = 0; v < NC; ++v) acc[v] += sf[v * NFN + q];
+        }
+        // non-conservative terms of the node's own state
+        const double vn = sel2(d, me.v[0], me.v[1]);
+        acc[1] += me.B[0] * acc[9];
+        acc[2] += me.B[1] * acc[9];
+        acc[3] += me.B[2] * acc[9];
+        acc[4] += vB * acc[9] + vn * me.psi * acc[10];
+        acc[5] += me.v[0] * acc[9];
+        acc[6] += me.v[1] * acc[9];
+        acc[7] += me.v[2] * acc[9];
+        acc[8] += vn * acc[10];
+        const double h = d == 0 ? ei.metric[0] : ei.metric[1];
+#pragma unroll
+        for (int v = 0; v < V; ++v) du[v] += h * acc[v];
+    };
+    if constexpr (ONE_DIR) {
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
-            const int t = node_pos(d, node);
-            const int l = node_line<2>(d, node);
-            double acc[NC];
-#pragma unroll
-            for (int v = 0; v < NC; ++v) acc[v] = 0.0;
-            const int pb = d * NPD + l * 6;
-            const int p1 = pb + pair_k<1>(t), p2 = pb + pair_k<2>(t), p3 = pb + pair_k<3>(t);
-            const double w1 = dsplit_j<double, 1>(t), w2 = dsplit_j<double, 2>(t), w3 = dsplit_j<double, 3>(t);
-#pragma unroll
-            for (int v = 0; v < NC; ++v) {
-                acc[v] += w1 * vf[v * NPP + p1];
-                acc[v] += w2 * vf[v * NPP + p2];
-                acc[v] += w3 * vf[v * NPP + p3];
-            }
-            if (t == 0 || t == 3) {
-                const int q = (2 * d + (t == 3 ? 1 : 0)) * NLINE + l;
-#pragma unroll
-                for (int v = 0; v < NC; ++v) acc[v] += sf[v * NFN + q];
-            }
-            // non-conservative terms of the node's own state
-            const double vn = sel2(d, me.v[0], me.v[1]);
-            acc[1] += me.B[0] * acc[9];
-            acc[2] += me.B[1] * acc[9];
-            acc[3] += me.B[2] * acc[9];
-            acc[4] += vB * acc[9] + vn * me.psi * acc[10];
-            acc[5] += me.v[0] * acc[9];
-            acc[6] += me.v[1] * acc[9];
-            acc[7] += me.v[2] * acc[9];
-            acc[8] += vn * acc[10];
-            const double h = d == 0 ? ei.metric[0] : ei.metric[1];
-#pragma unroll
-            for (int v = 0; v < V; ++v) du[v] += h * acc[v];
+            pair_flux(d, lane >> 4, (lane >> 2) & 3, lane & 3);
+            if (lane < 32) pair_flux(d, lane >> 3, (lane >> 1) & 3, 4 + (lane & 1));
+            wave_lds_sync();
+            gather_dir(d);
+            wave_lds_sync();
         }
+    } else {
+#pragma unroll
+        for (int rd = 0; rd < PairRounds<2, 2>::N; ++rd) {
+            int es, dd, l, k;
+            pair_of<2, 2>(rd, lane, es, dd, l, k);
+            pair_flux(dd, es, l, k);
+        }
+        wave_lds_sync();
+        gather_dir(0);
+        gather_dir(1);
     }
 
     double k[V];
@@ -3226,8 +3273,13 @@ hipError_t launch_mhd_stage_t(const StageArgs &a, const double *coef, LaunchCfg 
     const int epb = wpb * 4;
     if (a.n_active <= 0) return hipSuccess;
     const int blocks = (a.n_active + epb - 1) / epb;
-    const size_t lds = (size_t)epb * MHD_SLOT * sizeof(double);
-    hipLaunchKernelGGL((mhd_stage_kernel<KIND>), dim3(blocks), dim3(64 * wpb), lds, s, a, coef);
+    if (cfg.one_dir) {
+        const size_t lds = (size_t)epb * mhd_slot<true>() * sizeof(double);
+        hipLaunchKernelGGL((mhd_stage_kernel<KIND, true>), dim3(blocks), dim3(64 * wpb), lds, s, a, coef);
+    } else {
+        const size_t lds = (size_t)epb * mhd_slot<false>() * sizeof(double);
+        hipLaunchKernelGGL((mhd_stage_kernel<KIND, false>), dim3(blocks), dim3(64 * wpb), lds, s, a, coef);
+    }
     return hipGetLastError();
 }
 
@@ -3258,7 +3310,7 @@ hipError_t launch_ns_stage_t(const StageArgs &a, const double *coef, LaunchCfg c
 
 size_t stage_lds_bytes(int dim, int variant, int wpb, int sys, bool one_dir)
 {
-    if (sys == 1) return (size_t)wpb * 4 * MHD_SLOT * sizeof(double);
+    if (sys == 1) return (size_t)wpb * 4 * (one_dir ? mhd_slot<true>() : mhd_slot<false>()) * sizeof(double);
     if (sys == 2) return (size_t)wpb * 4 * NS_SLOT * sizeof(double);
     const bool ec = one_dir;  // (quadrilaterals with the EC fluxes only)
     if (variant == 1) {  // element slots and the wavefronts' gather tables

@@ -1,8 +1,8 @@
 """Launch shapes through the C ABI: every stage launched with 1, 2, 4 or 8
 wavefronts per workgroup (options.tune = -w), the active lists built with
-every element tile (options.tile = 1..4), and the stages with the EC fluxes run
-with two directions per phase or one direction at a time (options.phases = 1,
-2), give bit-identical states; so does the autotuner's own choice (tune = 1,
+every element tile (options.tile = 1..4), and the Euler stages with the EC
+fluxes and the GLM-MHD stages run with two directions per phase or one direction
+at a time (options.phases = 1, 2), give bit-identical states; so does the autotuner's own choice (tune = 1,
 tile = 0, phases = 0), which the tuning report names.
 
 In 2D the active lists keep tiles of each case mesh together and a neighbour that
@@ -156,6 +156,35 @@ def test_3d_states_identical_for_both_phase_structures(P, precision):
     for k in res:
         assert np.array_equal(res[k][0], res[1, 1][0]), k
         assert np.array_equal(res[k][1], res[1, 1][1]), k
+
+
+@pytest.mark.parametrize("setup", ["alfven", "blast"])
+def test_glm_mhd_states_identical_for_both_phase_structures(P, setup):
+    """GLM-MHD stages with the pair fluxes of both directions per phase and one
+    direction at a time (half the pair-flux LDS), at 1 and 2 wavefronts per
+    workgroup: the same states and gammas bit for bit (Alfven wave: weak form with
+    LLF faces, random levels; 1.5D blast: EC fluxes)."""
+    from paper_2507_04991_amd import problems
+    prob = problems.alfven(n=16) if setup == "alfven" else problems.mhd_blast()
+    res = {}
+    for phases in (1, 2):
+        for w in (1, 2):
+            d = P.Descriptors(prob["faces"], prob["lev"], prob["tab"], gas_gamma=prob["gam"],
+                              surface_flux=prob["flux"], volume_integral=prob["volume"], system=1,
+                              glm_ch=prob["glm_ch"])
+            st = P.Stepper(d, P.default_options(tune=-w, phases=phases))
+            u = torch.tensor(prob["U0"], device="cuda").contiguous()
+            gam = []
+            for _ in range(3):
+                infos = st.step(u, prob["dt"])
+                assert all(i["flags"] == 0 for i in infos)
+                gam.append([i["gamma"] for i in infos])
+            od = int(phases == 2)
+            assert f"stage_one_direction_at_a_time=[{','.join([str(od)] * len(prob['tab']['c']))}]" in st.tuning()
+            res[(phases, w)] = (u.cpu().numpy(), np.array(gam))
+            st.close()
+    for key, (uu, gg) in res.items():
+        assert np.array_equal(uu, res[(1, 1)][0]) and np.array_equal(gg, res[(1, 1)][1]), key
 
 
 def test_phases_option_ignored_where_it_does_not_apply(P):
